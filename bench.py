@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Newton-step benchmark on one MI355X: assemble + block-Jacobi PCG to 1e-5.
+
+Workload (default "large"): five 50x50x30-cell Kuhn blocks (2.25M tets,
+403,155 nodes, 1.21M DoF) compressed 40 % between fixed planes, 600k
+point-triangle + 400k edge-edge constraints, kappa = 1e5; synthetic, seeded.
+
+One "step" is one bf_newton_step call with the state already in HBM:
+constraint linearization, merged BSR pattern, elastic/contact assembly,
+preconditioner, PCG to a relative residual of 1e-5, FP64 stats.  Prints one
+JSON line (see the fields below); progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def spmv_bytes(N, nnzb):
+    """Algorithmic bytes of one SpMV launch (k_spmv): the scaled off-diagonal
+    blocks are stored for both triangles, so each of the nnzb - N upper
+    off-diagonal blocks is read twice (2 x (36 B FP32 values + 4 B column));
+    one row pointer per row; p read once (12 B/node); q written once (12 B/node)."""
+    n_off = nnzb - N
+    return 80 * n_off + 4 * (N + 1) + 24 * N
+
+
+def spmv_bytes_upper_only(N, nnzb):
+    """The same product counted with upper-only storage (each upper block,
+    diagonal included, read once: 40 B), row pointers, p read and q read and
+    written: the least traffic any symmetric BSR SpMV of this matrix moves."""
+    return 40 * nnzb + 4 * (N + 1) + 24 * N
+
+
+def pcg_iteration_bytes(N, nnzb):
+    """SpMV + update (x, p, r, q read, x, r written, L read for the residual
+    check: 96 B/node) + direction (r, p read, p written: 36 B/node)."""
+    return spmv_bytes(N, nnzb) + 96 * N + 36 * N
+
+
+def cpu_baseline(sc, gpu_iters, frac):
+    """The FP64 oracle on a bounded sample of the workload, one thread.
+
+    Sample: the first `frac` of the tets and of each constraint type.  The
+    oracle assembles G and H for the sample (linearization, elasticity with
+    its numeric projection, inertia, AL terms, DBC) and times FP64
+    block-Jacobi PCG iterations on the sample's H; both are scaled by 1/frac
+    and the PCG time by the GPU's iteration count to give ms per Newton step
+    of the full workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    sub = dict(sc)
+    T = len(sc["tets"])
+    sub["tets"] = sc["tets"][: int(frac * T)]
+    for k in ("E", "nu", "rho"):
+        sub[k] = sc[k][: int(frac * T)]
+    npt, nee = int(frac * len(sc["pt"])), int(frac * len(sc["ee"]))
+    sub["pt"], sub["ee"] = sc["pt"][:npt], sc["ee"][:nee]
+    lam = np.concatenate([sc["lam"][:npt], sc["lam"][len(sc["pt"]):len(sc["pt"]) + nee]])
+    sub["lam"], sub["gamma"] = lam, np.ones(len(lam))
+    with threadpool_limits(1):
+        # per-mesh data of the full mesh (lumped mass over every tet), per-tet
+        # arrays restricted to the sample; not timed (per-mesh setup)
+        full = oracle.prepare(sc)
+        m = len(sub["tets"])
+        full.tets, full.Dminv, full.vol, full.A = full.tets[:m], full.Dminv[:m], full.vol[:m], full.A[:m]
+        full.mu_l, full.lam_l = full.mu_l[:m], full.lam_l[:m]
+        t0 = time.perf_counter()
+        st = oracle.assemble(sub, full)
+        t_asm = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.block_jacobi_pcg(st.H, st.G, 0.0, max_iter=4)
+        t_a = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.block_jacobi_pcg(st.H, st.G, 0.0, max_iter=24)
+        t_b = time.perf_counter() - t0
+    t_it = max(t_b - t_a, 0.0) / 20.0
+    ms = (t_asm + t_it * gpu_iters) / frac * 1e3
+    return {"value": round(ms, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": (f"first {frac:.0%} of tets and constraints ({len(sub['tets'])} tets, {npt}+{nee} PT+EE): "
+                       f"oracle assembly {t_asm:.2f} s and FP64 block-Jacobi PCG {t_it * 1e3:.1f} ms/iteration, "
+                       f"each scaled by 1/{frac:g}, PCG x {gpu_iters} GPU iterations")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large", choices=["large", "medium", "tiny"])
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--cpu-sample", type=float, default=0.05)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is described in "
+              "DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2512_12151_amd import bfal
+
+    log(f"generating workload {args.workload}")
+    sc = scenes.make_scene(args.workload)
+    N, T = len(sc["rest"]), len(sc["tets"])
+    n_c = len(sc["pt"]) + len(sc["ee"])
+    dev = torch.device("cuda:0")
+    t = {k: torch.from_numpy(np.ascontiguousarray(sc[k])).to(dev)
+         for k in ("tets", "rest", "E", "nu", "rho", "fixed", "x", "x_hat", "x_tilde", "pt", "ee", "lam", "gamma")}
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    ctx = bfal.Context(0, stream=stream.cuda_stream)
+    log(f"setup: {N} nodes, {T} tets, {n_c} constraints")
+    pb = bfal.Problem(ctx, t["tets"], t["rest"], t["E"], t["nu"], t["rho"], t["fixed"])
+    pb.set_state(t["x"], t["x_hat"], t["x_tilde"], sc["dt"])
+    pb.set_constraints(t["pt"], t["ee"], t["lam"], t["gamma"], sc["kappa"], sc["delta"])
+    out = torch.empty((N, 3), dtype=torch.float64, device=dev)
+    opts = dict(tol=args.tol, max_iter=200000, poll_every=64, check_every=1)
+    for w in range(args.warmup):
+        _, st, status = pb.newton_step(out=out, **opts)
+        log(f"warmup {w}: status {status}, {st['pcg_iters']} PCG iterations, rel residual {st['rel_residual']:.2e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    last = None
+    for k in range(args.steps):
+        _, last, status = pb.newton_step(out=out, **opts)
+        iters.append(last["pcg_iters"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = elapsed / args.steps * 1e3
+    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step, iterations {iters}")
+    # dominant kernel: time the SpMV launches of one more step with HIP events on the library's stream
+    _, tst, _ = pb.newton_step(out=out, time_spmv=256, **opts)
+    nnzb = int(last["nnzb"])
+    sb = spmv_bytes(N, nnzb)
+    spmv_ms = tst["ms_spmv_avg"]
+    achieved = sb / (spmv_ms * 1e-3) / 1e9
+    it_mean = float(np.mean(iters))
+    pcg_gbs = pcg_iteration_bytes(N, nnzb) * last["pcg_iters"] / (last["ms_pcg"] * 1e-3) / 1e9
+    line = {
+        "metric": "Newton-step assemble+PCG ms @1e-5 rel residual",
+        "value": round(ms_step, 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {T} tets, {N} nodes, {3 * N} DoF, {len(sc['pt'])} PT + "
+                               f"{len(sc['ee'])} EE constraints, kappa {sc['kappa']:g}, PCG tol {args.tol:g}",
+                   "parallelism": "single GPU"},
+        "pcg_iters": it_mean,
+        "pcg_iters_per_s": round(last["pcg_iters"] / (last["ms_pcg"] * 1e-3), 1),
+        "phase_ms": {k: round(last[k], 3) for k in ("ms_lin", "ms_pattern", "ms_assemble", "ms_pcg")},
+        "pcg_hbm_gbs": round(pcg_gbs, 1),
+        "nnzb": nnzb,
+        "rel_residual": last["rel_residual"],
+        "roofline": {"bound": "hbm", "kernel": "k_spmv", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": sb, "avg_ms": round(spmv_ms, 5), "launches_timed": tst["spmv_timed"],
+                     "upper_only_gbs": round(spmv_bytes_upper_only(N, nnzb) / (spmv_ms * 1e-3) / 1e9, 1)},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        line["cpu_baseline"] = cpu_baseline(sc, int(round(it_mean)), args.cpu_sample)
+    print(json.dumps(line), flush=True)
+    pb.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * bfal.h -- C-ABI of libbfal: one Newton step of the barrier-free
+ * augmented-Lagrangian (AL) contact subproblem on one MI355X (gfx950).
+ *
+ * The operation (paper: Algorithm 2, the body of the Newton loop; Section 4.2
+ * "Augmented Lagrangian-based Subproblem Solver"):
+ *
+ *   G = grad E(x_hat, x_tilde) + sum_i kappa*gamma_i*(c_i - lambda_i/kappa - s_i) grad d_i(x)
+ *   H = SPDProject(hess E(x_hat, x_tilde)) + sum_i kappa*gamma_i grad d_i(x) grad d_i(x)^T
+ *   p = -H^{-1} G                     (block-Jacobi preconditioned CG)
+ *
+ * with E the incremental potential 1/2|x - x_tilde|_M^2 + h^2 U(x) of Section 3
+ * (lumped mass M, Neo-Hookean U on linear tetrahedra), the linearized
+ * constraints c_i(x_hat) = d_i(x) + grad d_i(x)^T (x_hat - x) - delta of
+ * Section 4.2, slacks s_i = max(0, c_i - lambda_i/kappa), the per-element
+ * SPD projection of Section 5.1 (eigenvalues of d2Psi/dF2 clamped at zero),
+ * and moving-boundary (Dirichlet) nodes eliminated as in Section 5.3.  The
+ * paper calls the penalty mu; this ABI calls it kappa to keep mu for the Lame
+ * parameter.  d_i is the unsigned distance of a point-triangle (PT) or
+ * edge-edge (EE) pair (Section 3).
+ *
+ * Conventions shared by every call:
+ *  - Status: every call returns a bf_status.  Negative values are errors and
+ *    leave the outputs unspecified; positive values are warnings and the
+ *    outputs are written.  Calls never throw and never abort across the ABI.
+ *    bf_last_error() returns a message for the last failing call on a context.
+ *  - Memory: array arguments are plain pointers.  `mem` says where they live:
+ *    BF_MEM_HOST (pageable or pinned host memory) or BF_MEM_DEVICE (device
+ *    memory of the context's GPU, ordered on the context's stream).  Inputs
+ *    are borrowed for the duration of the call and copied; outputs are
+ *    caller-allocated.  Handles are owned by the caller and freed by the
+ *    matching _destroy call.  A context (and its problems) must be used from
+ *    one thread at a time.
+ *  - Layouts: node arrays are [n_nodes][3] row-major doubles; index arrays are
+ *    [n][4] row-major int32.  Constraint arrays list all PT pairs first, then
+ *    all EE pairs.
+ */
+#ifndef BFAL_H
+#define BFAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BF_OK = 0,
+  BF_WARN_PCG_MAXITER = 1,          /* PCG stopped at max_iter; p is the last iterate */
+  BF_ERR_INVALID_ARG = -1,          /* null pointer, size, index out of range, non-finite value */
+  BF_ERR_OOM = -2,                  /* device allocation failed */
+  BF_ERR_HIP = -3,                  /* a HIP runtime call failed */
+  BF_ERR_INVERTED_ELEMENT = -4,     /* det F(x_hat) <= 0 in some tet (Neo-Hookean is non-invertible) */
+  BF_ERR_DEGENERATE_CONSTRAINT = -5,/* d_i(x) <= 0, repeated vertex, or (near-)parallel EE pair */
+  BF_ERR_NOT_SPD = -6,              /* a diagonal block is not SPD, or PCG breakdown p^T H p <= 0 */
+  BF_ERR_STATE = -7                 /* call order: state or constraints missing */
+} bf_status;
+
+enum { BF_MEM_HOST = 0, BF_MEM_DEVICE = 1 };
+enum { BF_PREC_FP32 = 0, BF_PREC_BF16_REFINE = 1 };
+
+typedef struct bf_context bf_context;
+typedef struct bf_problem bf_problem;
+
+/* Tetrahedral mesh and material (Section 3; Neo-Hookean per tet). */
+typedef struct {
+  int32_t n_nodes, n_tets;
+  const int32_t* tets;   /* [n_tets][4] vertex ids; positive orientation not required */
+  const double* rest;    /* [n_nodes][3] rest positions */
+  const double* E;       /* [n_tets] Young's modulus (Pa), > 0 */
+  const double* nu;      /* [n_tets] Poisson ratio in (-1, 0.5) */
+  const double* rho;     /* [n_tets] density (kg/m^3), > 0 */
+  const uint8_t* fixed;  /* [n_nodes] 1 = Dirichlet node (Section 5.3); may be NULL */
+} bf_mesh_desc;
+
+/* Active constraint set C = {(i, lambda_i, gamma_i)} (Algorithm 2 input). */
+typedef struct {
+  int32_t n_pt, n_ee;
+  const int32_t* pt;     /* [n_pt][4]: p, t0, t1, t2 (four distinct vertices) */
+  const int32_t* ee;     /* [n_ee][4]: a0, a1, b0, b1 (four distinct vertices) */
+  const double* lambda;  /* [n_pt + n_ee] multiplier estimates, >= 0 */
+  const double* gamma;   /* [n_pt + n_ee] decay factors in (0, 1]; NULL means all 1 */
+  double kappa;          /* AL penalty stiffness (the paper's mu), > 0 */
+  double delta;          /* surface separation offset (the paper's delta), >= 0 */
+} bf_constraint_desc;
+
+typedef struct {
+  double tol;            /* stop at |r|_2 <= tol |b|_2 (unpreconditioned, FP64 norms) */
+  int32_t max_iter;      /* PCG iteration cap (BF_WARN_PCG_MAXITER when hit) */
+  int32_t precision;     /* BF_PREC_FP32, or BF_PREC_BF16_REFINE */
+  double refine_tol;     /* BF16 mode: outer refinement stops at this relative residual */
+  int32_t poll_every;    /* host polls the device convergence flag every this many iterations */
+  int32_t check_every;   /* the true residual norm is formed every this many iterations */
+  int32_t time_spmv;     /* >0: time the SpMV launches of the first this-many PCG iterations
+                            with HIP events (reported in bf_step_stats); 0: no per-kernel events */
+} bf_solve_opts;
+
+typedef struct {
+  int32_t pcg_iters;         /* inner PCG iterations (summed over sweeps in BF16 mode) */
+  int32_t refine_sweeps;     /* outer refinement sweeps (BF16 mode), else 0 */
+  double rel_residual;       /* final |b - H p|_2 / |b|_2 as tracked by the solver (FP64) */
+  double newton_inf_over_h;  /* |p|_inf / h (Section 6.1 residual-style stat), FP64 */
+  double max_violation;      /* max_i max(0, -c_i(x_hat)), FP64 */
+  int64_t nnzb;              /* stored upper 3x3 blocks, diagonal included */
+  double ms_lin, ms_pattern, ms_assemble, ms_pcg;  /* device time per phase */
+  int32_t spmv_timed;        /* SpMV launches timed (see bf_solve_opts.time_spmv) */
+  double ms_spmv_avg;        /* their average duration (event to event, ms) */
+} bf_step_stats;
+
+/* ---------------------------------------------------------------- context */
+
+/* Open `device`.  `hip_stream` (a hipStream_t) is used for all work when
+ * non-NULL; otherwise the context creates and owns a default-priority stream. */
+bf_status bf_context_create(int32_t device, void* hip_stream, bf_context** out);
+void bf_context_destroy(bf_context* ctx);
+/* Message of the last failing call on this context ("" if none).  Owned by the
+ * context, valid until its next call. */
+const char* bf_last_error(const bf_context* ctx);
+
+/* ---------------------------------------------------------------- problem */
+
+/* Per-mesh setup: rest geometry (the constant row vectors A_a of Section 5.1),
+ * Lame parameters, lumped mass (Section 3), the static elastic 3x3-block
+ * pattern and its assembly order.  Copies the mesh.  Errors: INVALID_ARG for
+ * bad sizes/indices/values or a degenerate rest tet. */
+bf_status bf_problem_create(bf_context* ctx, const bf_mesh_desc* mesh, int32_t mem, bf_problem** out);
+void bf_problem_destroy(bf_problem* pb);
+
+/* x: intersection-free linearization point; x_hat: current iterate; x_tilde:
+ * inertia target x^t + h v^t + h^2 M^{-1} f_ext (Section 3); dt = h > 0.
+ * Each [n_nodes][3].  Copies them. */
+bf_status bf_set_state(bf_problem* pb, const double* x, const double* x_hat, const double* x_tilde,
+                       double dt, int32_t mem);
+
+/* Copies and validates the active set.  Host memory is validated on the host;
+ * device memory is validated by a kernel before any use. */
+bf_status bf_set_constraints(bf_problem* pb, const bf_constraint_desc* cons, int32_t mem);
+
+/* One Newton step: constraint linearization at x, merged BSR pattern,
+ * assembly of G and the SPD-projected H, block-Jacobi PCG for p = -H^{-1} G,
+ * and the FP64 stats.  p_out is [n_nodes][3] doubles in `mem`.  stats may be
+ * NULL.  Errors: INVERTED_ELEMENT, DEGENERATE_CONSTRAINT, NOT_SPD, STATE. */
+bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* opts, double* p_out, int32_t mem,
+                         bf_step_stats* stats);
+
+/* ----------------------------------------------- introspection (parity) */
+/* Valid after bf_newton_step.  All outputs are host memory. */
+
+/* Assembled gradient G after DBC, [n_nodes][3]. */
+bf_status bf_get_gradient(bf_problem* pb, double* g_out);
+/* Number of stored upper blocks (diagonal included) of the last step. */
+bf_status bf_get_nnzb(bf_problem* pb, int64_t* nnzb);
+/* Upper BSR pattern: row_ptr [n_nodes+1], col [nnzb]; emap [n_tets][10] and
+ * cmap [n_pt+n_ee][10] slots of the local vertex pairs (0,0),(0,1),(0,2),(0,3),
+ * (1,1),(1,2),(1,3),(2,2),(2,3),(3,3) (the block is transposed when the first
+ * vertex id is larger); diag [n_nodes] slot of (v,v).  Any pointer may be NULL. */
+bf_status bf_get_pattern(bf_problem* pb, int32_t* row_ptr, int32_t* col, int32_t* emap, int32_t* cmap,
+                         int32_t* diag);
+/* Assembled (unscaled) blocks after DBC, [nnzb][3][3] row-major FP32. */
+bf_status bf_get_blocks(bf_problem* pb, float* vals);
+
+/* Device bytes a problem of this size holds (mesh, state, constraints,
+ * pattern, blocks and solver vectors), for admission control. */
+bf_status bf_footprint_bytes(int32_t n_nodes, int32_t n_tets, int32_t n_constraints, size_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFAL_H */

@@ -1,0 +1,242 @@
+"""ctypes binding of libbfal (include/bfal.h): argument marshalling only.
+
+Every entry point of the C-ABI is exposed under its own name; the small
+Context / Problem classes only pack numpy arrays (host memory) or torch
+tensors (device memory) into pointers and raise on error statuses.  All of
+the Newton step runs in the library's HIP kernels; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbfal.so")
+
+BF_OK = 0
+BF_WARN_PCG_MAXITER = 1
+STATUS = {0: "OK", 1: "WARN_PCG_MAXITER", -1: "ERR_INVALID_ARG", -2: "ERR_OOM", -3: "ERR_HIP",
+          -4: "ERR_INVERTED_ELEMENT", -5: "ERR_DEGENERATE_CONSTRAINT", -6: "ERR_NOT_SPD", -7: "ERR_STATE"}
+BF_MEM_HOST, BF_MEM_DEVICE = 0, 1
+BF_PREC_FP32, BF_PREC_BF16_REFINE = 0, 1
+
+
+class bf_mesh_desc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_tets", C.c_int32), ("tets", C.c_void_p), ("rest", C.c_void_p),
+                ("E", C.c_void_p), ("nu", C.c_void_p), ("rho", C.c_void_p), ("fixed", C.c_void_p)]
+
+
+class bf_constraint_desc(C.Structure):
+    _fields_ = [("n_pt", C.c_int32), ("n_ee", C.c_int32), ("pt", C.c_void_p), ("ee", C.c_void_p),
+                ("lambda_", C.c_void_p), ("gamma", C.c_void_p), ("kappa", C.c_double), ("delta", C.c_double)]
+
+
+class bf_solve_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
+                ("refine_tol", C.c_double), ("poll_every", C.c_int32), ("check_every", C.c_int32),
+                ("time_spmv", C.c_int32)]
+
+
+class bf_step_stats(C.Structure):
+    _fields_ = [("pcg_iters", C.c_int32), ("refine_sweeps", C.c_int32), ("rel_residual", C.c_double),
+                ("newton_inf_over_h", C.c_double), ("max_violation", C.c_double), ("nnzb", C.c_int64),
+                ("ms_lin", C.c_double), ("ms_pattern", C.c_double), ("ms_assemble", C.c_double),
+                ("ms_pcg", C.c_double), ("spmv_timed", C.c_int32), ("ms_spmv_avg", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BfalError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point
+_PROTOS = [
+    ("bf_context_create", C.c_int, [C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("bf_context_destroy", None, [C.c_void_p]),
+    ("bf_last_error", C.c_char_p, [C.c_void_p]),
+    ("bf_problem_create", C.c_int, [C.c_void_p, C.POINTER(bf_mesh_desc), C.c_int32, C.POINTER(C.c_void_p)]),
+    ("bf_problem_destroy", None, [C.c_void_p]),
+    ("bf_set_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32]),
+    ("bf_set_constraints", C.c_int, [C.c_void_p, C.POINTER(bf_constraint_desc), C.c_int32]),
+    ("bf_newton_step", C.c_int, [C.c_void_p, C.POINTER(bf_solve_opts), C.c_void_p, C.c_int32,
+                                 C.POINTER(bf_step_stats)]),
+    ("bf_get_gradient", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("bf_get_nnzb", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("bf_get_pattern", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("bf_get_blocks", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("bf_footprint_bytes", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+]
+
+EXPORTED = [p[0] for p in _PROTOS]
+
+
+def lib():
+    """Load libbfal.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        # torch ships its own HIP runtime; importing it first makes libbfal bind
+        # to that same runtime (one HIP runtime per process, shared streams and
+        # device memory).  Without torch, libbfal uses the system ROCm runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in _PROTOS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    """Pointer of a numpy array (host) or a torch tensor (device); None stays NULL."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _mem(a):
+    return BF_MEM_HOST if isinstance(a, np.ndarray) else BF_MEM_DEVICE
+
+
+class Context:
+    """A device plus the HIP stream all work of its problems is ordered on."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.h = C.c_void_p()
+        st = lib().bf_context_create(int(device), stream, C.byref(self.h))
+        if st != BF_OK:
+            raise BfalError(st, "bf_context_create failed")
+
+    def check(self, st):
+        if st < 0:
+            raise BfalError(st, lib().bf_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if self.h:
+            lib().bf_context_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class Problem:
+    """One mesh on one context: state, constraints, Newton steps, introspection."""
+
+    def __init__(self, ctx: Context, tets, rest, E, nu, rho, fixed=None):
+        self.ctx = ctx
+        dev = not isinstance(tets, np.ndarray)
+        if not dev:
+            tets, rest = _host(tets, np.int32), _host(rest, np.float64)
+            E, nu, rho = _host(E, np.float64), _host(nu, np.float64), _host(rho, np.float64)
+            fixed = None if fixed is None else _host(fixed, np.uint8)
+        self.N, self.T = int(rest.shape[0]), int(tets.shape[0])
+        d = bf_mesh_desc(self.N, self.T, _ptr(tets), _ptr(rest), _ptr(E), _ptr(nu), _ptr(rho), _ptr(fixed))
+        self.h = C.c_void_p()
+        ctx.check(lib().bf_problem_create(ctx.h, C.byref(d), BF_MEM_DEVICE if dev else BF_MEM_HOST, C.byref(self.h)))
+        self.n_c = 0
+
+    @classmethod
+    def from_scene(cls, ctx, sc):
+        pb = cls(ctx, sc["tets"], sc["rest"], sc["E"], sc["nu"], sc["rho"], sc["fixed"])
+        pb.set_state(sc["x"], sc["x_hat"], sc["x_tilde"], sc["dt"])
+        pb.set_constraints(sc["pt"], sc["ee"], sc["lam"], sc["gamma"], sc["kappa"], sc["delta"])
+        return pb
+
+    def set_state(self, x, x_hat, x_tilde, dt):
+        if isinstance(x, np.ndarray):
+            x, x_hat, x_tilde = (_host(a, np.float64) for a in (x, x_hat, x_tilde))
+        self._keep_state = (x, x_hat, x_tilde)
+        self.dt = float(dt)
+        self.ctx.check(lib().bf_set_state(self.h, _ptr(x), _ptr(x_hat), _ptr(x_tilde), self.dt, _mem(x)))
+
+    def set_constraints(self, pt, ee, lam, gamma, kappa, delta):
+        if isinstance(lam, np.ndarray):
+            pt, ee = _host(pt, np.int32).reshape(-1, 4), _host(ee, np.int32).reshape(-1, 4)
+            lam = _host(lam, np.float64)
+            gamma = None if gamma is None else _host(gamma, np.float64)
+        d = bf_constraint_desc(int(pt.shape[0]), int(ee.shape[0]), _ptr(pt) if pt.shape[0] else None,
+                               _ptr(ee) if ee.shape[0] else None, _ptr(lam) if lam.shape[0] else None,
+                               _ptr(gamma) if gamma is not None and gamma.shape[0] else None,
+                               float(kappa), float(delta))
+        self.ctx.check(lib().bf_set_constraints(self.h, C.byref(d), _mem(lam)))
+        self.n_c = int(pt.shape[0] + ee.shape[0])
+
+    def newton_step(self, tol=1e-5, max_iter=20000, precision=BF_PREC_FP32, refine_tol=1e-6, poll_every=16,
+                    check_every=1, time_spmv=0, out=None):
+        """Returns (p [N,3] (numpy, or `out` when a device tensor is passed), stats dict, status)."""
+        o = bf_solve_opts(float(tol), int(max_iter), int(precision), float(refine_tol), int(poll_every),
+                          int(check_every), int(time_spmv))
+        p = np.empty((self.N, 3), dtype=np.float64) if out is None else out
+        s = bf_step_stats()
+        st = self.ctx.check(lib().bf_newton_step(self.h, C.byref(o), _ptr(p), _mem(p), C.byref(s)))
+        return p, s.as_dict(), st
+
+    def gradient(self):
+        g = np.empty((self.N, 3), dtype=np.float64)
+        self.ctx.check(lib().bf_get_gradient(self.h, g.ctypes.data))
+        return g
+
+    def nnzb(self):
+        n = C.c_int64()
+        self.ctx.check(lib().bf_get_nnzb(self.h, C.byref(n)))
+        return int(n.value)
+
+    def pattern(self):
+        nnzb = self.nnzb()
+        row_ptr = np.empty(self.N + 1, np.int32)
+        col = np.empty(nnzb, np.int32)
+        emap = np.empty((self.T, 10), np.int32)
+        cmap = np.empty((max(self.n_c, 1), 10), np.int32)
+        diag = np.empty(self.N, np.int32)
+        self.ctx.check(lib().bf_get_pattern(self.h, row_ptr.ctypes.data, col.ctypes.data, emap.ctypes.data,
+                                            cmap.ctypes.data, diag.ctypes.data))
+        return row_ptr, col, emap, cmap[: self.n_c], diag
+
+    def blocks(self):
+        v = np.empty((self.nnzb(), 3, 3), np.float32)
+        self.ctx.check(lib().bf_get_blocks(self.h, v.ctypes.data))
+        return v
+
+    def close(self):
+        if self.h:
+            lib().bf_problem_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def footprint_bytes(n_nodes, n_tets, n_constraints):
+    out = C.c_size_t()
+    st = lib().bf_footprint_bytes(int(n_nodes), int(n_tets), int(n_constraints), C.byref(out))
+    if st != BF_OK:
+        raise BfalError(st, "bf_footprint_bytes failed")
+    return int(out.value)

@@ -1,0 +1,646 @@
+// Host side of libbfal: the C-ABI declared in include/bfal.h.  Validates
+// arguments, owns device memory, and enqueues the per-mesh setup and the
+// per-Newton-step pipeline on the context's stream:
+//   linearize constraints -> merged BSR pattern -> element kernel -> row
+//   assembly (G, H, DBC, block-Jacobi factors) -> scaled off-diagonal blocks
+//   -> PCG (device-side convergence flag, polled every poll_every iterations)
+//   -> p = L^{-T} p_hat and FP64 stats.
+#include <cmath>
+#include <cstdio>
+#include <new>
+#include <vector>
+
+#include "common.h"
+
+using namespace bfal;
+
+struct bf_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+};
+
+struct bf_problem {
+  bf_context* ctx = nullptr;
+  int N = 0, T = 0;
+  // mesh (per-mesh setup)
+  DevBuf tets, rest, E, nu, rho, fixed, Dminv9, vol, mu, lam, mass;
+  int nnzb_e = 0;
+  DevBuf erow_ptr, ecol, emap, ecptr, elist, epos, staging;
+  // state
+  DevBuf x, xh, xt;
+  double dt = 0.0;
+  bool has_state = false;
+  // constraints
+  int n_pt = 0, n_ee = 0, n_c = 0;
+  DevBuf cids, clam, cgam;
+  double kappa = 1.0, delta = 0.0;
+  // per-step buffers
+  DevBuf cn, cw, cg, ch, viol_part;
+  DevBuf vcnt, vptr, vinc;
+  DevBuf ccount, cptr, cand, ucount, row_ptr, col, eslot;
+  DevBuf vals, grad, Lf, Linv, bhat, bb_part, ovals, ocol, orow_ptr, lcnt, lptr, lsrc;
+  DevBuf xs, r, p, q, part, scal, pout, flags, scan_tmp, scratch_int;
+  long long cap_nnzb = 0, cap_cand = 0;
+  PcgScalars* host_sc = nullptr;
+  bool stepped = false;
+  long long nnzb_last = 0;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> tev;   // SpMV timing events (pairs), created on demand
+};
+
+namespace {
+
+bf_status fail(bf_context* c, bf_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+#define HIPCHK(ctx, call)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((ctx), e_ == hipErrorOutOfMemory ? BF_ERR_OOM : BF_ERR_HIP,              \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                      \
+  } while (0)
+
+#define ALLOC(ctx, buf, bytes)                                                             \
+  do {                                                                                     \
+    hipError_t e_ = (buf).ensure(bytes);                                                   \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((ctx), BF_ERR_OOM, std::string("device allocation of ") +                \
+                  std::to_string((size_t)(bytes)) + " bytes failed");                      \
+  } while (0)
+
+hipMemcpyKind kind_in(int32_t mem) { return mem == BF_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
+hipMemcpyKind kind_out(int32_t mem) { return mem == BF_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
+
+bool finite_all(const double* a, long long n) {
+  for (long long i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+bf_status flags_to_status(bf_context* c, int flags) {
+  if (flags & FLAG_BAD_INDEX) return fail(c, BF_ERR_INVALID_ARG, "index out of range or repeated vertex in a tet");
+  if (flags & FLAG_BAD_VALUE) return fail(c, BF_ERR_INVALID_ARG, "invalid value (degenerate rest tet, material, lambda or gamma)");
+  if (flags & FLAG_DEGENERATE)
+    return fail(c, BF_ERR_DEGENERATE_CONSTRAINT, "degenerate constraint: d(x) <= 0, repeated vertex or parallel edge pair");
+  if (flags & FLAG_INVERTED) return fail(c, BF_ERR_INVERTED_ELEMENT, "inverted element: det F(x_hat) <= 0");
+  if (flags & (FLAG_NOT_SPD | FLAG_BREAKDOWN)) return fail(c, BF_ERR_NOT_SPD, "matrix not SPD (diagonal block or PCG breakdown)");
+  return BF_OK;
+}
+
+bf_status read_flags(bf_problem* pb, int* out) {
+  bf_context* c = pb->ctx;
+  HIPCHK(c, hipMemcpyAsync(out, pb->flags.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return BF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bf_status bf_context_create(int32_t device, void* hip_stream, bf_context** out) {
+  if (!out) return BF_ERR_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return BF_ERR_INVALID_ARG;
+  bf_context* c = new (std::nothrow) bf_context();
+  if (!c) return BF_ERR_OOM;
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess) { delete c; return BF_ERR_HIP; }
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { delete c; return BF_ERR_HIP; }
+    c->own_stream = true;
+  }
+  *out = c;
+  return BF_OK;
+}
+
+void bf_context_destroy(bf_context* c) {
+  if (!c) return;
+  if (c->own_stream && c->stream) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamDestroy(c->stream);
+  }
+  delete c;
+}
+
+const char* bf_last_error(const bf_context* c) { return c ? c->err.c_str() : "null context"; }
+
+bf_status bf_footprint_bytes(int32_t n_nodes, int32_t n_tets, int32_t n_constraints, size_t* out) {
+  if (!out || n_nodes <= 0 || n_tets <= 0 || n_constraints < 0) return BF_ERR_INVALID_ARG;
+  const size_t N = n_nodes, T = n_tets, C = n_constraints;
+  const size_t nnzb_e = N + 6 * T;                 // upper bound on the static pattern
+  const size_t cap = nnzb_e + 6 * C;
+  size_t b = 0;
+  b += T * (16 + 3 * 8 + 36 + 12 + 40 * 3 + 360);  // tets, E/nu/rho, Dm^-1, vol/mu/lam, emap/epos/elist, staging
+  b += nnzb_e * (4 + 4) + N * (4 * 3 + 24 + 4 + 1);
+  b += N * 24 * 3;                                 // x, x_hat, x_tilde
+  b += C * (16 + 16 + 12 + 16 + 8);                // ids, lambda/gamma, n, w, factors
+  b += N * 4 * 8 + C * 16 + cap * 4 * 2;           // incidence, candidates, pattern
+  b += cap * (36 + 36 + 4 + 4);                    // blocks, scaled blocks, ocol, eslot
+  b += N * (12 * 6 + 24 * 2 + 24);                 // grad, bhat, x, r, p, q, L, L^-1, p out
+  b += 1 << 20;                                    // partials, scalars, scan scratch
+  *out = b;
+  return BF_OK;
+}
+
+bf_status bf_problem_create(bf_context* c, const bf_mesh_desc* m, int32_t mem, bf_problem** out) {
+  if (!c) return BF_ERR_INVALID_ARG;
+  if (!out) return fail(c, BF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!m || !m->tets || !m->rest || !m->E || !m->nu || !m->rho)
+    return fail(c, BF_ERR_INVALID_ARG, "mesh descriptor or one of its arrays is NULL");
+  if (m->n_nodes <= 0 || m->n_tets <= 0) return fail(c, BF_ERR_INVALID_ARG, "n_nodes and n_tets must be positive");
+  if ((long long)m->n_tets * 10 >= (1LL << 31) || (long long)m->n_nodes * 3 >= (1LL << 31))
+    return fail(c, BF_ERR_INVALID_ARG, "mesh too large for 32-bit slot indices");
+  if (mem != BF_MEM_HOST && mem != BF_MEM_DEVICE) return fail(c, BF_ERR_INVALID_ARG, "mem must be BF_MEM_HOST or BF_MEM_DEVICE");
+  const int N = m->n_nodes, T = m->n_tets;
+  if (mem == BF_MEM_HOST) {
+    for (long long e = 0; e < T; ++e) {
+      const int32_t* t = m->tets + 4 * e;
+      for (int a = 0; a < 4; ++a)
+        if (t[a] < 0 || t[a] >= N) return fail(c, BF_ERR_INVALID_ARG, "tet vertex index out of range");
+      if (t[0] == t[1] || t[0] == t[2] || t[0] == t[3] || t[1] == t[2] || t[1] == t[3] || t[2] == t[3])
+        return fail(c, BF_ERR_INVALID_ARG, "tet with a repeated vertex");
+      if (!(m->E[e] > 0.0) || !std::isfinite(m->E[e]) || !(m->nu[e] > -1.0 && m->nu[e] < 0.5) ||
+          !(m->rho[e] > 0.0) || !std::isfinite(m->rho[e]))
+        return fail(c, BF_ERR_INVALID_ARG, "invalid material value");
+    }
+    if (!finite_all(m->rest, 3LL * N)) return fail(c, BF_ERR_INVALID_ARG, "non-finite rest position");
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  bf_problem* pb = new (std::nothrow) bf_problem();
+  if (!pb) return fail(c, BF_ERR_OOM, "host allocation failed");
+  pb->ctx = c;
+  pb->N = N;
+  pb->T = T;
+  bf_status st = BF_OK;
+  auto body = [&]() -> bf_status {
+    hipStream_t s = c->stream;
+    ALLOC(c, pb->tets, 16LL * T);
+    ALLOC(c, pb->rest, 24LL * N);
+    ALLOC(c, pb->E, 8LL * T);
+    ALLOC(c, pb->nu, 8LL * T);
+    ALLOC(c, pb->rho, 8LL * T);
+    ALLOC(c, pb->fixed, N);
+    ALLOC(c, pb->Dminv9, 36LL * T);
+    ALLOC(c, pb->vol, 4LL * T);
+    ALLOC(c, pb->mu, 4LL * T);
+    ALLOC(c, pb->lam, 4LL * T);
+    ALLOC(c, pb->mass, 4LL * N);
+    ALLOC(c, pb->flags, 64);
+    HIPCHK(c, hipMemcpyAsync(pb->tets.p, m->tets, 16LL * T, kind_in(mem), s));
+    HIPCHK(c, hipMemcpyAsync(pb->rest.p, m->rest, 24LL * N, kind_in(mem), s));
+    HIPCHK(c, hipMemcpyAsync(pb->E.p, m->E, 8LL * T, kind_in(mem), s));
+    HIPCHK(c, hipMemcpyAsync(pb->nu.p, m->nu, 8LL * T, kind_in(mem), s));
+    HIPCHK(c, hipMemcpyAsync(pb->rho.p, m->rho, 8LL * T, kind_in(mem), s));
+    if (m->fixed) {
+      HIPCHK(c, hipMemcpyAsync(pb->fixed.p, m->fixed, N, kind_in(mem), s));
+    } else {
+      std::vector<uint8_t> z(N, 0);
+      HIPCHK(c, hipMemcpyAsync(pb->fixed.p, z.data(), N, hipMemcpyHostToDevice, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+    }
+    int* flags = pb->flags.as<int>();
+    fill_int(flags, 0, 16, s);
+    const int4* tets = pb->tets.as<int4>();
+    launch_check_tets(tets, T, N, flags, s);
+    int hflags = 0;
+    bf_status r0 = read_flags(pb, &hflags);
+    if (r0 != BF_OK) return r0;
+    if (hflags) return flags_to_status(c, hflags);
+    launch_rest_geometry(tets, pb->rest.as<double>(), pb->E.as<double>(), pb->nu.as<double>(), T,
+                         pb->Dminv9.as<float>(), pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), flags, s);
+    // static elastic pattern: pair keys bucketed by row, sorted and unique per row
+    const long long npairs = 6LL * T;
+    const long long nslots_tmp = (long long)N + 1;
+    ALLOC(c, pb->scratch_int, 4LL * (3 * nslots_tmp + npairs + 16));
+    int* cnt = pb->scratch_int.as<int>();
+    int* kptr = cnt + nslots_tmp;
+    int* cursor = kptr + nslots_tmp;
+    int* keys = cursor + nslots_tmp;
+    ALLOC(c, pb->scan_tmp, 4LL * scan_tmp_ints(10LL * T + N + 16));
+    int* tmp = pb->scan_tmp.as<int>();
+    fill_int(cnt, 0, N, s);
+    launch_elastic_pair_count(tets, T, cnt, s);
+    scan_exclusive(cnt, kptr, N, kptr + N, tmp, s);
+    fill_int(cursor, 0, N, s);
+    launch_elastic_pair_fill(tets, T, kptr, cursor, keys, s);
+    ALLOC(c, pb->erow_ptr, 4LL * (N + 1));
+    int* ucount = cnt;  // reuse
+    launch_row_unique(keys, kptr, N, ucount, s);
+    int* erow = pb->erow_ptr.as<int>();
+    scan_exclusive(ucount, erow, N, erow + N, tmp, s);
+    int nnzb_e = 0;
+    HIPCHK(c, hipMemcpyAsync(&nnzb_e, erow + N, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    pb->nnzb_e = nnzb_e;
+    ALLOC(c, pb->ecol, 4LL * nnzb_e);
+    launch_row_write(keys, kptr, N, erow, pb->ecol.as<int>(), s);
+    // (tet, pair) -> elastic slot, and each slot's contributions in (tet, pair) order
+    ALLOC(c, pb->emap, 40LL * T);
+    launch_emap(tets, T, erow, pb->ecol.as<int>(), pb->emap.as<int>(), s);
+    ALLOC(c, pb->ecptr, 4LL * (nnzb_e + 1));
+    ALLOC(c, pb->elist, 40LL * T);
+    ALLOC(c, pb->epos, 40LL * T);
+    // nnzb_e <= N + 6T, so the scratch buffer already holds nnzb_e counters
+    int* scnt = pb->scratch_int.as<int>();
+    int* ecptr = pb->ecptr.as<int>();
+    fill_int(scnt, 0, nnzb_e, s);
+    launch_slot_count(pb->emap.as<int>(), 10LL * T, scnt, s);
+    scan_exclusive(scnt, ecptr, nnzb_e, ecptr + nnzb_e, tmp, s);
+    fill_int(scnt, 0, nnzb_e, s);
+    launch_slot_fill(pb->emap.as<int>(), 10LL * T, ecptr, scnt, pb->elist.as<int>(), s);
+    sort_segments(pb->elist.as<int>(), ecptr, nnzb_e, s);
+    launch_inverse_positions(pb->elist.as<int>(), 10LL * T, pb->epos.as<int>(), s);
+    launch_mass(ecptr, pb->elist.as<int>(), erow, pb->vol.as<float>(), pb->rho.as<double>(), N, pb->mass.as<float>(), s);
+    ALLOC(c, pb->staging, 360LL * T);
+    r0 = read_flags(pb, &hflags);
+    if (r0 != BF_OK) return r0;
+    if (hflags) return flags_to_status(c, hflags);
+    for (auto& e : pb->ev) HIPCHK(c, hipEventCreate(&e));
+    HIPCHK(c, hipHostMalloc((void**)&pb->host_sc, sizeof(PcgScalars), hipHostMallocDefault));
+    ALLOC(c, pb->scal, sizeof(PcgScalars));
+    HIPCHK(c, hipMemsetAsync(pb->scal.p, 0, sizeof(PcgScalars), s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return BF_OK;
+  };
+  st = body();
+  if (st != BF_OK) {
+    bf_problem_destroy(pb);
+    return st;
+  }
+  *out = pb;
+  c->err.clear();
+  return BF_OK;
+}
+
+void bf_problem_destroy(bf_problem* pb) {
+  if (!pb) return;
+  if (pb->ctx) (void)hipStreamSynchronize(pb->ctx->stream);
+  DevBuf* bufs[] = {&pb->tets, &pb->rest, &pb->E, &pb->nu, &pb->rho, &pb->fixed, &pb->Dminv9, &pb->vol, &pb->mu,
+                    &pb->lam, &pb->mass, &pb->erow_ptr, &pb->ecol, &pb->emap, &pb->ecptr, &pb->elist, &pb->epos,
+                    &pb->staging, &pb->x, &pb->xh, &pb->xt, &pb->cids, &pb->clam, &pb->cgam, &pb->cn, &pb->cw,
+                    &pb->cg, &pb->ch, &pb->viol_part, &pb->vcnt, &pb->vptr, &pb->vinc, &pb->ccount, &pb->cptr,
+                    &pb->cand, &pb->ucount, &pb->row_ptr, &pb->col, &pb->eslot, &pb->vals, &pb->grad, &pb->Lf,
+                    &pb->Linv, &pb->bhat, &pb->bb_part, &pb->ovals, &pb->ocol, &pb->orow_ptr, &pb->lcnt, &pb->lptr,
+                    &pb->lsrc, &pb->xs, &pb->r,
+                    &pb->p, &pb->q, &pb->part, &pb->scal, &pb->pout, &pb->flags, &pb->scan_tmp, &pb->scratch_int};
+  for (DevBuf* b : bufs) b->release();
+  for (auto& e : pb->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : pb->tev) (void)hipEventDestroy(e);
+  if (pb->host_sc) (void)hipHostFree(pb->host_sc);
+  delete pb;
+}
+
+bf_status bf_set_state(bf_problem* pb, const double* x, const double* x_hat, const double* x_tilde, double dt,
+                       int32_t mem) {
+  if (!pb) return BF_ERR_INVALID_ARG;
+  bf_context* c = pb->ctx;
+  if (!x || !x_hat || !x_tilde) return fail(c, BF_ERR_INVALID_ARG, "state array is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, BF_ERR_INVALID_ARG, "dt must be positive and finite");
+  if (mem != BF_MEM_HOST && mem != BF_MEM_DEVICE) return fail(c, BF_ERR_INVALID_ARG, "bad mem kind");
+  const long long n3 = 3LL * pb->N;
+  if (mem == BF_MEM_HOST && (!finite_all(x, n3) || !finite_all(x_hat, n3) || !finite_all(x_tilde, n3)))
+    return fail(c, BF_ERR_INVALID_ARG, "non-finite state value");
+  ALLOC(c, pb->x, 8 * n3);
+  ALLOC(c, pb->xh, 8 * n3);
+  ALLOC(c, pb->xt, 8 * n3);
+  HIPCHK(c, hipMemcpyAsync(pb->x.p, x, 8 * n3, kind_in(mem), c->stream));
+  HIPCHK(c, hipMemcpyAsync(pb->xh.p, x_hat, 8 * n3, kind_in(mem), c->stream));
+  HIPCHK(c, hipMemcpyAsync(pb->xt.p, x_tilde, 8 * n3, kind_in(mem), c->stream));
+  if (mem == BF_MEM_HOST) HIPCHK(c, hipStreamSynchronize(c->stream));
+  pb->dt = dt;
+  pb->has_state = true;
+  c->err.clear();
+  return BF_OK;
+}
+
+bf_status bf_set_constraints(bf_problem* pb, const bf_constraint_desc* cd, int32_t mem) {
+  if (!pb) return BF_ERR_INVALID_ARG;
+  bf_context* c = pb->ctx;
+  if (!cd) return fail(c, BF_ERR_INVALID_ARG, "constraint descriptor is NULL");
+  if (cd->n_pt < 0 || cd->n_ee < 0) return fail(c, BF_ERR_INVALID_ARG, "negative constraint count");
+  const long long nc = (long long)cd->n_pt + cd->n_ee;
+  if (nc * 10 >= (1LL << 31)) return fail(c, BF_ERR_INVALID_ARG, "too many constraints");
+  if ((cd->n_pt && !cd->pt) || (cd->n_ee && !cd->ee) || (nc && !cd->lambda))
+    return fail(c, BF_ERR_INVALID_ARG, "constraint array is NULL");
+  if (!(cd->kappa > 0.0) || !std::isfinite(cd->kappa)) return fail(c, BF_ERR_INVALID_ARG, "kappa must be positive");
+  if (!(cd->delta >= 0.0) || !std::isfinite(cd->delta)) return fail(c, BF_ERR_INVALID_ARG, "delta must be >= 0");
+  if (mem != BF_MEM_HOST && mem != BF_MEM_DEVICE) return fail(c, BF_ERR_INVALID_ARG, "bad mem kind");
+  const int N = pb->N;
+  if (mem == BF_MEM_HOST) {
+    for (int part = 0; part < 2; ++part) {
+      const int32_t* a = part ? cd->ee : cd->pt;
+      const long long n = part ? cd->n_ee : cd->n_pt;
+      for (long long i = 0; i < n; ++i) {
+        const int32_t* t = a + 4 * i;
+        for (int k = 0; k < 4; ++k)
+          if (t[k] < 0 || t[k] >= N) return fail(c, BF_ERR_INVALID_ARG, "constraint vertex index out of range");
+        if (t[0] == t[1] || t[0] == t[2] || t[0] == t[3] || t[1] == t[2] || t[1] == t[3] || t[2] == t[3])
+          return fail(c, BF_ERR_DEGENERATE_CONSTRAINT, "constraint with a repeated vertex");
+      }
+    }
+    for (long long i = 0; i < nc; ++i) {
+      if (!(cd->lambda[i] >= 0.0) || !std::isfinite(cd->lambda[i]))
+        return fail(c, BF_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+      if (cd->gamma && !(cd->gamma[i] > 0.0 && cd->gamma[i] <= 1.0))
+        return fail(c, BF_ERR_INVALID_ARG, "gamma must lie in (0, 1]");
+    }
+  }
+  hipStream_t s = c->stream;
+  const int n = (int)nc;
+  ALLOC(c, pb->cids, 16LL * n + 16);
+  ALLOC(c, pb->clam, 8LL * n + 8);
+  ALLOC(c, pb->cgam, 8LL * n + 8);
+  if (cd->n_pt) HIPCHK(c, hipMemcpyAsync(pb->cids.p, cd->pt, 16LL * cd->n_pt, kind_in(mem), s));
+  if (cd->n_ee)
+    HIPCHK(c, hipMemcpyAsync(pb->cids.as<char>() + 16LL * cd->n_pt, cd->ee, 16LL * cd->n_ee, kind_in(mem), s));
+  if (n) HIPCHK(c, hipMemcpyAsync(pb->clam.p, cd->lambda, 8LL * n, kind_in(mem), s));
+  if (n && cd->gamma) {
+    HIPCHK(c, hipMemcpyAsync(pb->cgam.p, cd->gamma, 8LL * n, kind_in(mem), s));
+  } else if (n) {
+    std::vector<double> ones(n, 1.0);
+    HIPCHK(c, hipMemcpyAsync(pb->cgam.p, ones.data(), 8LL * n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  if (mem == BF_MEM_DEVICE && n) {
+    fill_int(pb->flags.as<int>(), 0, 16, s);
+    launch_check_constraints(pb->cids.as<int4>(), n, N, pb->clam.as<double>(), pb->cgam.as<double>(),
+                             pb->flags.as<int>(), s);
+    int hflags = 0;
+    bf_status r0 = read_flags(pb, &hflags);
+    if (r0 != BF_OK) return r0;
+    if (hflags) return flags_to_status(c, hflags);
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  pb->n_pt = cd->n_pt;
+  pb->n_ee = cd->n_ee;
+  pb->n_c = n;
+  pb->kappa = cd->kappa;
+  pb->delta = cd->delta;
+  // size the per-step buffers for this constraint count
+  const long long cap = (long long)pb->nnzb_e + 6LL * n;
+  const long long capc = (long long)pb->nnzb_e - N + 6LL * n + 16;
+  ALLOC(c, pb->cn, 12LL * n + 16);
+  ALLOC(c, pb->cw, 16LL * n + 16);
+  ALLOC(c, pb->cg, 4LL * n + 16);
+  ALLOC(c, pb->ch, 4LL * n + 16);
+  ALLOC(c, pb->viol_part, 8LL * (div_up(n, kBlock) + 1));
+  ALLOC(c, pb->vcnt, 4LL * (N + 1));
+  ALLOC(c, pb->vptr, 4LL * (N + 1));
+  ALLOC(c, pb->vinc, 16LL * n + 16);
+  ALLOC(c, pb->ccount, 4LL * (N + 1));
+  ALLOC(c, pb->cptr, 4LL * (N + 1));
+  ALLOC(c, pb->cand, 4LL * capc);
+  ALLOC(c, pb->ucount, 4LL * (N + 1));
+  ALLOC(c, pb->row_ptr, 4LL * (N + 1));
+  ALLOC(c, pb->col, 4LL * cap);
+  ALLOC(c, pb->eslot, 4LL * cap);
+  ALLOC(c, pb->vals, 36LL * cap);
+  ALLOC(c, pb->ovals, 72LL * cap);     // scaled off-diagonal blocks of both triangles
+  ALLOC(c, pb->ocol, 8LL * cap);
+  ALLOC(c, pb->orow_ptr, 4LL * (N + 1));
+  ALLOC(c, pb->lcnt, 4LL * (N + 1));
+  ALLOC(c, pb->lptr, 4LL * (N + 1));
+  ALLOC(c, pb->lsrc, 4LL * cap);
+  ALLOC(c, pb->grad, 12LL * N);
+  ALLOC(c, pb->Lf, 24LL * N);
+  ALLOC(c, pb->Linv, 24LL * N);
+  ALLOC(c, pb->bhat, 12LL * N + 16);
+  ALLOC(c, pb->bb_part, 8LL * (div_up(N, kBlock) + 1));
+  ALLOC(c, pb->xs, 12LL * N + 16);
+  ALLOC(c, pb->r, 12LL * N + 16);
+  ALLOC(c, pb->p, 12LL * N + 16);
+  ALLOC(c, pb->q, 12LL * N + 16);
+  ALLOC(c, pb->part, 8LL * pcg_partials_needed(N));
+  ALLOC(c, pb->pout, 24LL * N);
+  ALLOC(c, pb->scan_tmp, 4LL * scan_tmp_ints((long long)10 * pb->T + N + 6LL * n + 16));
+  pb->cap_nnzb = cap;
+  pb->cap_cand = capc;
+  c->err.clear();
+  return BF_OK;
+}
+
+bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, int32_t mem, bf_step_stats* stats) {
+  if (!pb) return BF_ERR_INVALID_ARG;
+  bf_context* c = pb->ctx;
+  if (!o || !p_out) return fail(c, BF_ERR_INVALID_ARG, "opts or p_out is NULL");
+  if (!pb->has_state) return fail(c, BF_ERR_STATE, "bf_set_state must be called before bf_newton_step");
+  if (pb->cap_nnzb == 0) return fail(c, BF_ERR_STATE, "bf_set_constraints must be called before bf_newton_step");
+  if (!(o->tol > 0.0) || o->max_iter < 0) return fail(c, BF_ERR_INVALID_ARG, "tol must be > 0 and max_iter >= 0");
+  if (o->precision != BF_PREC_FP32) return fail(c, BF_ERR_INVALID_ARG, "unsupported precision mode");
+  if (mem != BF_MEM_HOST && mem != BF_MEM_DEVICE) return fail(c, BF_ERR_INVALID_ARG, "bad mem kind");
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  const int N = pb->N, T = pb->T, n = pb->n_c;
+  int* flags = pb->flags.as<int>();
+  int* tmp = pb->scan_tmp.as<int>();
+  const int4* ids = pb->cids.as<int4>();
+  fill_int(flags, 0, 16, s);
+  HIPCHK(c, hipEventRecord(pb->ev[0], s));
+  // (1) constraint linearization at x and AL factors at x_hat
+  fill_int(reinterpret_cast<int*>(pb->viol_part.p), 0, 2, s);
+  launch_contact_lin(ids, pb->n_pt, n, pb->x.as<double>(), pb->xh.as<double>(), pb->clam.as<double>(),
+                     pb->cgam.as<double>(), pb->kappa, pb->delta, pb->cn.as<float>(), pb->cw.as<float>(),
+                     pb->cg.as<float>(), pb->ch.as<float>(), pb->viol_part.as<double>(), flags, s);
+  HIPCHK(c, hipEventRecord(pb->ev[1], s));
+  // (2) merged pattern: vertex -> constraint incidence, candidates, unique rows
+  int* vcnt = pb->vcnt.as<int>();
+  int* vptr = pb->vptr.as<int>();
+  fill_int(vcnt, 0, N, s);
+  launch_vertex_incidence_count(ids, n, vcnt, s);
+  scan_exclusive(vcnt, vptr, N, vptr + N, tmp, s);
+  fill_int(vcnt, 0, N, s);
+  launch_vertex_incidence_fill(ids, n, vptr, vcnt, pb->vinc.as<int>(), s);
+  sort_segments(pb->vinc.as<int>(), vptr, N, s);
+  int* cptr = pb->cptr.as<int>();
+  launch_candidate_count(pb->erow_ptr.as<int>(), vptr, pb->vinc.as<int>(), ids, N, pb->ccount.as<int>(), s);
+  scan_exclusive(pb->ccount.as<int>(), cptr, N, cptr + N, tmp, s);
+  launch_candidate_fill(pb->erow_ptr.as<int>(), pb->ecol.as<int>(), vptr, pb->vinc.as<int>(), ids, N, cptr,
+                        pb->cand.as<int>(), pb->ucount.as<int>(), s);
+  int* row_ptr = pb->row_ptr.as<int>();
+  scan_exclusive(pb->ucount.as<int>(), row_ptr, N, row_ptr + N, tmp, s);
+  launch_merged_write(pb->cand.as<int>(), cptr, row_ptr, pb->erow_ptr.as<int>(), pb->ecol.as<int>(), N,
+                      pb->col.as<int>(), pb->eslot.as<int>(), s);
+  HIPCHK(c, hipEventRecord(pb->ev[2], s));
+  // (3) assembly
+  const float h2 = (float)(pb->dt * pb->dt);
+  launch_elastic(pb->tets.as<int4>(), T, pb->rest.as<double>(), pb->xh.as<double>(), pb->Dminv9.as<float>(),
+                 pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), h2, pb->epos.as<int>(),
+                 pb->staging.as<float>(), flags, s);
+  launch_assemble_rows(N, row_ptr, pb->col.as<int>(), pb->eslot.as<int>(), pb->ecptr.as<int>(), pb->staging.as<float>(),
+                       vptr, pb->vinc.as<int>(), ids, n, pb->cn.as<float>(), pb->cw.as<float>(), pb->cg.as<float>(),
+                       pb->ch.as<float>(), pb->mass.as<float>(), pb->xh.as<double>(), pb->xt.as<double>(),
+                       pb->fixed.as<uint8_t>(), pb->vals.as<float>(), pb->grad.as<float>(), pb->Lf.as<float>(),
+                       pb->Linv.as<float>(), pb->bhat.as<float>(), pb->bb_part.as<double>(), flags, s);
+  // scaled blocks of both triangles for the gather-only SpMV
+  const long long fstride = 2 * pb->cap_nnzb;
+  int* lcnt = pb->lcnt.as<int>();
+  int* lptr = pb->lptr.as<int>();
+  fill_int(lcnt, 0, N, s);
+  launch_lower_count(N, row_ptr, pb->col.as<int>(), lcnt, s);
+  scan_exclusive(lcnt, lptr, N, lptr + N, tmp, s);
+  fill_int(lcnt, 0, N, s);
+  launch_lower_fill(N, row_ptr, pb->col.as<int>(), lptr, lcnt, pb->lsrc.as<int>(), s);
+  sort_segments(pb->lsrc.as<int>(), lptr, N, s);
+  launch_scale_full(N, row_ptr, pb->col.as<int>(), pb->vals.as<float>(), pb->Linv.as<float>(), lptr,
+                    pb->lsrc.as<int>(), pb->ovals.as<float>(), pb->ocol.as<int>(), pb->orow_ptr.as<int>(), fstride, s);
+  HIPCHK(c, hipEventRecord(pb->ev[3], s));
+  // (4) PCG
+  PcgScalars* sc = pb->scal.as<PcgScalars>();
+  double* part = pb->part.as<double>();
+  launch_pcg_init(N, pb->bhat.as<float>(), pb->xs.as<float>(), pb->r.as<float>(), pb->p.as<float>(), part,
+                  pb->bb_part.as<double>(), div_up(N, kBlock), sc, o->tol, o->max_iter, o->check_every, s);
+  const int poll = o->poll_every > 0 ? o->poll_every : 16;
+  const int ntime = o->time_spmv > 0 ? (o->time_spmv < 4096 ? o->time_spmv : 4096) : 0;
+  while ((int)pb->tev.size() < 2 * ntime) {
+    hipEvent_t e;
+    HIPCHK(c, hipEventCreate(&e));
+    pb->tev.push_back(e);
+  }
+  int launched = 0;
+  bool assembly_checked = false;
+  for (;;) {
+    const int batch = poll;
+    for (int k = 0; k < batch; ++k) {
+      const int it = launched + k;
+      if (it < ntime) HIPCHK(c, hipEventRecord(pb->tev[2 * it], s));
+      launch_pcg_spmv(N, pb->orow_ptr.as<int>(), pb->ocol.as<int>(), pb->ovals.as<float>(), fstride,
+                      pb->p.as<float>(), pb->q.as<float>(), part, sc, s);
+      if (it < ntime) HIPCHK(c, hipEventRecord(pb->tev[2 * it + 1], s));
+      launch_pcg_vector_ops(N, pb->Lf.as<float>(), pb->xs.as<float>(), pb->r.as<float>(), pb->p.as<float>(),
+                            pb->q.as<float>(), part, sc, s);
+    }
+    launched += batch;
+    HIPCHK(c, hipMemcpyAsync(pb->host_sc, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (!assembly_checked) {
+      int hf = 0;
+      bf_status r0 = read_flags(pb, &hf);
+      if (r0 != BF_OK) return r0;
+      if (hf) return flags_to_status(c, hf);
+      assembly_checked = true;
+    }
+    if (pb->host_sc->done) break;
+    if (launched > o->max_iter + poll) break;   // cannot happen: the device stops at max_iter
+  }
+  launch_pcg_finish(N, pb->Linv.as<float>(), pb->xs.as<float>(), pb->pout.as<double>(), part, sc,
+                    pb->viol_part.as<double>(), div_up(n, kBlock) > 0 ? div_up(n, kBlock) : 1, s);
+  HIPCHK(c, hipEventRecord(pb->ev[4], s));
+  HIPCHK(c, hipMemcpyAsync(p_out, pb->pout.p, 24LL * N, kind_out(mem), s));
+  HIPCHK(c, hipMemcpyAsync(pb->host_sc, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+  int nnzb = 0, hflags = 0;
+  HIPCHK(c, hipMemcpyAsync(&nnzb, row_ptr + N, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  pb->nnzb_last = nnzb;
+  pb->stepped = true;
+  const PcgScalars& h = *pb->host_sc;
+  if (stats) {
+    float t01 = 0.f, t12 = 0.f, t23 = 0.f, t34 = 0.f;
+    (void)hipEventElapsedTime(&t01, pb->ev[0], pb->ev[1]);
+    (void)hipEventElapsedTime(&t12, pb->ev[1], pb->ev[2]);
+    (void)hipEventElapsedTime(&t23, pb->ev[2], pb->ev[3]);
+    (void)hipEventElapsedTime(&t34, pb->ev[3], pb->ev[4]);
+    stats->pcg_iters = h.iter3;
+    stats->refine_sweeps = 0;
+    stats->rel_residual = h.bb > 0.0 ? std::sqrt(h.rr_true / h.bb) : 0.0;
+    stats->newton_inf_over_h = h.stat_pinf / pb->dt;
+    stats->max_violation = h.stat_viol;
+    stats->nnzb = nnzb;
+    stats->ms_lin = t01;
+    stats->ms_pattern = t12;
+    stats->ms_assemble = t23;
+    stats->ms_pcg = t34;
+    // only launches made before convergence did the full SpMV
+    const int nt = ntime < h.iter3 ? ntime : h.iter3;
+    double tot = 0.0;
+    for (int k = 0; k < nt; ++k) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, pb->tev[2 * k], pb->tev[2 * k + 1]);
+      tot += ms;
+    }
+    stats->spmv_timed = nt;
+    stats->ms_spmv_avg = nt > 0 ? tot / nt : 0.0;
+  }
+  if (hflags | h.flags) return flags_to_status(c, hflags | h.flags);
+  c->err.clear();
+  if (h.done == 2) {
+    c->err = "PCG reached max_iter";
+    return BF_WARN_PCG_MAXITER;
+  }
+  return BF_OK;
+}
+
+bf_status bf_get_gradient(bf_problem* pb, double* g_out) {
+  if (!pb) return BF_ERR_INVALID_ARG;
+  bf_context* c = pb->ctx;
+  if (!g_out) return fail(c, BF_ERR_INVALID_ARG, "g_out is NULL");
+  if (!pb->stepped) return fail(c, BF_ERR_STATE, "no Newton step has been run");
+  std::vector<float> g(3LL * pb->N);
+  HIPCHK(c, hipMemcpyAsync(g.data(), pb->grad.p, 12LL * pb->N, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (size_t i = 0; i < g.size(); ++i) g_out[i] = g[i];
+  return BF_OK;
+}
+
+bf_status bf_get_nnzb(bf_problem* pb, int64_t* nnzb) {
+  if (!pb) return BF_ERR_INVALID_ARG;
+  if (!nnzb) return fail(pb->ctx, BF_ERR_INVALID_ARG, "nnzb is NULL");
+  if (!pb->stepped) return fail(pb->ctx, BF_ERR_STATE, "no Newton step has been run");
+  *nnzb = pb->nnzb_last;
+  return BF_OK;
+}
+
+bf_status bf_get_pattern(bf_problem* pb, int32_t* row_ptr, int32_t* col, int32_t* emap, int32_t* cmap, int32_t* diag) {
+  if (!pb) return BF_ERR_INVALID_ARG;
+  bf_context* c = pb->ctx;
+  if (!pb->stepped) return fail(c, BF_ERR_STATE, "no Newton step has been run");
+  hipStream_t s = c->stream;
+  const int N = pb->N, T = pb->T, n = pb->n_c;
+  const int* rp = pb->row_ptr.as<int>();
+  const int* cl = pb->col.as<int>();
+  if (row_ptr) HIPCHK(c, hipMemcpyAsync(row_ptr, rp, 4LL * (N + 1), hipMemcpyDeviceToHost, s));
+  if (col) HIPCHK(c, hipMemcpyAsync(col, cl, 4LL * pb->nnzb_last, hipMemcpyDeviceToHost, s));
+  DevBuf tmp;
+  const long long need = 4LL * ((long long)10 * T > 10LL * n ? 10LL * T : 10LL * n) + 4LL * N + 64;
+  ALLOC(c, tmp, need);
+  if (emap) {
+    launch_emap(pb->tets.as<int4>(), T, rp, cl, tmp.as<int>(), s);
+    HIPCHK(c, hipMemcpyAsync(emap, tmp.p, 40LL * T, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  if (cmap && n) {
+    launch_cmap(pb->cids.as<int4>(), n, rp, cl, tmp.as<int>(), s);
+    HIPCHK(c, hipMemcpyAsync(cmap, tmp.p, 40LL * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  if (diag) {
+    launch_row_diag_slots(N, rp, tmp.as<int>(), s);
+    HIPCHK(c, hipMemcpyAsync(diag, tmp.p, 4LL * N, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  tmp.release();
+  return BF_OK;
+}
+
+bf_status bf_get_blocks(bf_problem* pb, float* vals) {
+  if (!pb) return BF_ERR_INVALID_ARG;
+  bf_context* c = pb->ctx;
+  if (!vals) return fail(c, BF_ERR_INVALID_ARG, "vals is NULL");
+  if (!pb->stepped) return fail(c, BF_ERR_STATE, "no Newton step has been run");
+  HIPCHK(c, hipMemcpyAsync(vals, pb->vals.p, 36LL * pb->nnzb_last, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return BF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,264 @@
+// Row-owner assembly of G and of the upper 3x3-block matrix H, one thread per
+// row, in a fixed order (no atomics on the matrix, bitwise reproducible):
+//   - elastic blocks: sum of the per-tet contributions of each static slot, in
+//     the slot's precomputed (tet, pair) order;
+//   - inertia (Section 3): diagonal += m_v I, G_v += m_v (x_hat_v - x_tilde_v);
+//   - AL contact terms of the contact loop of Algorithm 2, for every incident
+//     constraint in increasing id: G_a += gfac w_a n and block(a, b) +=
+//     hfac w_a w_b n n^T (hfac = kappa gamma, kept also for inactive pairs);
+//   - moving-boundary elimination (Section 5.3): G_v = 0 and every entry in
+//     the rows and columns of a fixed node zeroed except its scalar diagonals.
+// Then the block-Jacobi preconditioner (the paper's 3x3 block-Jacobi PCG) is
+// applied symmetrically: each diagonal block is factored D_v = L_v L_v^T and
+// the off-diagonal blocks are scaled to L_r^{-1} H_rc L_c^{-T}, so the solver
+// runs CG on a matrix whose diagonal blocks are identities.  The scaled blocks
+// are stored for both triangles so that the SpMV is a pure row gather.
+#include "common.h"
+
+namespace bfal {
+
+namespace {
+
+__device__ inline int vtx(const int4& t, int a) { return a == 0 ? t.x : a == 1 ? t.y : a == 2 ? t.z : t.w; }
+
+__device__ inline int find_slot(const int* __restrict__ col, int lo, int hi, int c) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (col[mid] < c) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_assemble_rows(int N, const int* __restrict__ row_ptr, const int* __restrict__ col, const int* __restrict__ eslot,
+                const int* __restrict__ ecptr, const float* __restrict__ staging, const int* __restrict__ vptr,
+                const int* __restrict__ vinc, const int4* __restrict__ ids, int n_c, const float* __restrict__ cn,
+                const float* __restrict__ cw, const float* __restrict__ cg, const float* __restrict__ ch,
+                const float* __restrict__ mass, const double* __restrict__ xh, const double* __restrict__ xt,
+                const uint8_t* __restrict__ fixed, float* __restrict__ vals, float* __restrict__ grad,
+                float* __restrict__ Lf, float* __restrict__ Linv, float* __restrict__ bhat,
+                double* __restrict__ bb_part, int* flags) {
+  __shared__ double red[kBlock / kWave];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  double bb = 0.0;
+  if (r < N) {
+    const int o = row_ptr[r], n = row_ptr[r + 1] - o;
+    // diagonal: elastic sum (symmetric 6 + gradient 3 per contribution)
+    float d[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, g[3] = {0.f, 0.f, 0.f};
+    {
+      const int es = eslot[o];
+      for (int j = ecptr[es]; j < ecptr[es + 1]; ++j) {
+        const float* s = staging + 9LL * j;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) d[k] += s[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g[k] += s[6 + k];
+      }
+    }
+    // off-diagonal elastic sums
+    for (int j = 1; j < n; ++j) {
+      float b[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      const int es = eslot[o + j];
+      if (es >= 0) {
+        for (int q = ecptr[es]; q < ecptr[es + 1]; ++q) {
+          const float* s = staging + 9LL * q;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) b[k] += s[k];
+        }
+      }
+      float* v = vals + 9LL * (o + j);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) v[k] = b[k];
+    }
+    // inertia
+    const float m = mass[r];
+    d[0] += m; d[3] += m; d[5] += m;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g[k] += m * (float)(xh[3LL * r + k] - xt[3LL * r + k]);
+    // AL contact terms of the incident constraints
+    for (int j = vptr[r]; j < vptr[r + 1]; ++j) {
+      const int ci = vinc[j] >> 2, a = vinc[j] & 3;
+      const int4 t = ids[ci];
+      const float n0 = cn[ci], n1 = cn[n_c + ci], n2 = cn[2LL * n_c + ci];
+      const float w[4] = {cw[ci], cw[n_c + ci], cw[2LL * n_c + ci], cw[3LL * n_c + ci]};
+      const float gf = cg[ci], hf = ch[ci];
+      const float wa = w[a];
+      g[0] += gf * wa * n0; g[1] += gf * wa * n1; g[2] += gf * wa * n2;
+      const float saa = hf * wa * wa;
+      d[0] += saa * n0 * n0; d[1] += saa * n0 * n1; d[2] += saa * n0 * n2;
+      d[3] += saa * n1 * n1; d[4] += saa * n1 * n2; d[5] += saa * n2 * n2;
+      for (int b = 0; b < 4; ++b) {
+        const int vb = vtx(t, b);
+        if (b == a || vb < r) continue;
+        const int s = find_slot(col, o + 1, o + n - 1, vb);
+        const float sab = hf * wa * w[b];
+        float* v = vals + 9LL * s;
+        v[0] += sab * n0 * n0; v[1] += sab * n0 * n1; v[2] += sab * n0 * n2;
+        v[3] += sab * n1 * n0; v[4] += sab * n1 * n1; v[5] += sab * n1 * n2;
+        v[6] += sab * n2 * n0; v[7] += sab * n2 * n1; v[8] += sab * n2 * n2;
+      }
+    }
+    // moving-boundary elimination
+    const bool fr = fixed[r] != 0;
+    if (fr) {
+      g[0] = g[1] = g[2] = 0.f;
+      d[1] = d[2] = d[4] = 0.f;
+    }
+    for (int j = 1; j < n; ++j) {
+      if (fr || fixed[col[o + j]]) {
+        float* v = vals + 9LL * (o + j);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v[k] = 0.f;
+      }
+    }
+    float* v = vals + 9LL * o;
+    v[0] = d[0]; v[1] = d[1]; v[2] = d[2];
+    v[3] = d[1]; v[4] = d[3]; v[5] = d[4];
+    v[6] = d[2]; v[7] = d[4]; v[8] = d[5];
+    grad[3LL * r] = g[0]; grad[3LL * r + 1] = g[1]; grad[3LL * r + 2] = g[2];
+    bb = (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
+    // Cholesky D = L L^T and M = L^{-1} (both lower triangular, 6 entries)
+    const float q00 = d[0];
+    bool ok = q00 > 0.f;
+    const float L00 = ok ? sqrtf(q00) : 1.f;
+    const float L10 = d[1] / L00, L20 = d[2] / L00;
+    const float q11 = d[3] - L10 * L10;
+    ok = ok && q11 > 0.f;
+    const float L11 = q11 > 0.f ? sqrtf(q11) : 1.f;
+    const float L21 = (d[4] - L20 * L10) / L11;
+    const float q22 = d[5] - L20 * L20 - L21 * L21;
+    ok = ok && q22 > 0.f;
+    const float L22 = q22 > 0.f ? sqrtf(q22) : 1.f;
+    if (!ok) atomicOr(flags, FLAG_NOT_SPD);
+    const float M00 = 1.f / L00, M11 = 1.f / L11, M22 = 1.f / L22;
+    const float M10 = -L10 * M00 * M11;
+    const float M21 = -L21 * M11 * M22;
+    const float M20 = -(L20 * M00 + L21 * M10) * M22;
+    float* lf = Lf + 6LL * r;
+    lf[0] = L00; lf[1] = L10; lf[2] = L11; lf[3] = L20; lf[4] = L21; lf[5] = L22;
+    float* li = Linv + 6LL * r;
+    li[0] = M00; li[1] = M10; li[2] = M11; li[3] = M20; li[4] = M21; li[5] = M22;
+    // b_hat = L^{-1} b with b = -G
+    bhat[3LL * r] = -(M00 * g[0]);
+    bhat[3LL * r + 1] = -(M10 * g[0] + M11 * g[1]);
+    bhat[3LL * r + 2] = -(M20 * g[0] + M21 * g[1] + M22 * g[2]);
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) bb += __shfl_xor(bb, off, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = bb;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) s += red[w];
+    bb_part[blockIdx.x] = s;
+  }
+}
+
+// Transpose index of the upper off-diagonal pattern: for every column c the
+// rows r < c holding a block (r, c), sorted (after sort_segments) by r.
+__global__ void k_lower_count(int N, const int* __restrict__ row_ptr, const int* __restrict__ col, int* lcnt) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  for (int s = row_ptr[r] + 1; s < row_ptr[r + 1]; ++s) atomicAdd(&lcnt[col[s]], 1);
+}
+
+__global__ void k_lower_fill(int N, const int* __restrict__ row_ptr, const int* __restrict__ col,
+                             const int* __restrict__ lptr, int* lcur, int* lsrc) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  for (int s = row_ptr[r] + 1; s < row_ptr[r + 1]; ++s) {
+    const int c = col[s];
+    lsrc[lptr[c] + atomicAdd(&lcur[c], 1)] = r;
+  }
+}
+
+__device__ inline void scaled_block(const float* __restrict__ mr, const float* __restrict__ b,
+                                    const float* __restrict__ mc, float out[3][3]) {
+  const float R[3][3] = {{mr[0], 0.f, 0.f}, {mr[1], mr[2], 0.f}, {mr[3], mr[4], mr[5]}};
+  const float Cm[3][3] = {{mc[0], 0.f, 0.f}, {mc[1], mc[2], 0.f}, {mc[3], mc[4], mc[5]}};
+  float T1[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) T1[i][k] = R[i][0] * b[k] + R[i][1] * b[3 + k] + R[i][2] * b[6 + k];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out[i][k] = T1[i][0] * Cm[k][0] + T1[i][1] * Cm[k][1] + T1[i][2] * Cm[k][2];
+}
+
+// H_hat_rc = M_r H_rc M_c^T for every off-diagonal block of both triangles,
+// row-major with columns ascending (lower part, then upper part), SoA
+// [9][stride].  The diagonal blocks of H_hat are identities and not stored.
+__global__ void k_scale_full(int N, const int* __restrict__ row_ptr, const int* __restrict__ col,
+                             const float* __restrict__ vals, const float* __restrict__ Linv,
+                             const int* __restrict__ lptr, const int* __restrict__ lsrc, float* __restrict__ fv,
+                             int* __restrict__ fcol, int* __restrict__ frow_ptr, long long st) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  long long pos = (long long)(row_ptr[r] - r) + lptr[r];
+  frow_ptr[r] = (int)pos;
+  if (r == N - 1) frow_ptr[N] = (row_ptr[N] - N) + lptr[N];
+  const float* mr = Linv + 6LL * r;
+  float h[3][3];
+  for (int j = lptr[r]; j < lptr[r + 1]; ++j) {
+    const int rs = lsrc[j];
+    const int s = find_slot(col, row_ptr[rs] + 1, row_ptr[rs + 1] - 1, r);
+    scaled_block(Linv + 6LL * rs, vals + 9LL * s, mr, h);   // block (rs, r); row r stores its transpose
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) fv[(3 * i + k) * st + pos] = h[k][i];
+    fcol[pos] = rs;
+    ++pos;
+  }
+  for (int s = row_ptr[r] + 1; s < row_ptr[r + 1]; ++s) {
+    const int c = col[s];
+    scaled_block(mr, vals + 9LL * s, Linv + 6LL * c, h);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) fv[(3 * i + k) * st + pos] = h[i][k];
+    fcol[pos] = c;
+    ++pos;
+  }
+}
+
+__global__ void k_row_diag_slots(int N, const int* __restrict__ row_ptr, int* diag) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < N) diag[r] = row_ptr[r];
+}
+
+}  // namespace
+
+void launch_assemble_rows(int N, const int* row_ptr, const int* col, const int* eslot, const int* ecptr,
+                          const float* staging, const int* vptr, const int* vinc, const int4* ids, int n_c,
+                          const float* cn, const float* cw, const float* cg, const float* ch, const float* mass,
+                          const double* xh, const double* xt, const uint8_t* fixed, float* vals, float* grad,
+                          float* Lf, float* Linv, float* bhat, double* bb_part, int* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_assemble_rows, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, eslot, ecptr,
+                     staging, vptr, vinc, ids, n_c, cn, cw, cg, ch, mass, xh, xt, fixed, vals, grad, Lf, Linv, bhat,
+                     bb_part, flags);
+}
+
+void launch_lower_count(int N, const int* row_ptr, const int* col, int* lcnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_lower_count, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, lcnt);
+}
+
+void launch_lower_fill(int N, const int* row_ptr, const int* col, const int* lptr, int* lcur, int* lsrc,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_lower_fill, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, lptr, lcur, lsrc);
+}
+
+void launch_scale_full(int N, const int* row_ptr, const int* col, const float* vals, const float* Linv,
+                       const int* lptr, const int* lsrc, float* fvals, int* fcol, int* frow_ptr, long long fstride,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_full, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, vals, Linv, lptr,
+                     lsrc, fvals, fcol, frow_ptr, fstride);
+}
+
+void launch_row_diag_slots(int N, const int* row_ptr, int* diag, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_diag_slots, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, diag);
+}
+
+}  // namespace bfal

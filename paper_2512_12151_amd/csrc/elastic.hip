@@ -1,0 +1,328 @@
+// Neo-Hookean element kernel: one thread per tet.
+//
+// Per tet it forms F (from FP64 displacement differences, then FP32), the
+// stress P, the element gradient h^2 V P A_a^T, and the ten upper 3x3 blocks
+// of the SPD-projected element Hessian by the vertex-block identity of
+// Section 5.1:
+//
+//   H_ab = h^2 V  U [ sum_k omega_k^+ D_k (A_a V)^T (A_b V) D_k^T ] U^T
+//
+// where F = U Sigma V^T is a rotation-preserving SVD and (omega_k, D_k) are
+// the analytic eigenpairs of d2Psi/dF2 in the SVD frame: three scaling modes
+// (eigenvectors e_k of the 3x3 Hessian of Psi in the singular values, D_k =
+// diag(e_k)), three twist and three flip modes (D = (E_ij -+ E_ji)/sqrt 2).
+// Exploiting the sparsity of D_k, the bracket is the Hadamard product of the
+// projected 3x3 scaling Hessian with (A_a V)^T (A_b V), plus four terms per
+// singular-value pair.  Blocks are written to the fixed assembly order
+// (staging position of each (tet, pair)), so no atomics touch the matrix.
+//
+// Energy (reading of the paper, which names Neo-Hookean without printing it):
+//   Psi = mu/2 (tr F^T F - 3) - mu ln J + lam/2 (ln J)^2.
+// Cancellation-free forms near rest: with G = F - I,
+//   J - 1 = tr G + ((tr G)^2 - tr(G^2))/2 + det G,  ln J = log1p(J - 1),
+//   P = F^{-T} [ mu (G + G^T + G^T G) + lam ln J I ].
+#include "common.h"
+
+namespace bfal {
+
+namespace {
+
+__constant__ int c_pa[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+__constant__ int c_pb[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+
+// Cyclic Jacobi eigen-decomposition of a symmetric 3x3 matrix (A is destroyed).
+// On return A's diagonal holds the eigenvalues and V's columns the eigenvectors.
+__device__ inline void jacobi3(float A[3][3], float V[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? 1.f : 0.f;
+  for (int sweep = 0; sweep < 8; ++sweep) {
+    const float off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const float dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (off <= 1e-14f * dia || off == 0.f) break;
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0;
+      const int q = pq == 0 ? 1 : 2;
+      const float apq = A[p][q];
+      if (apq == 0.f) continue;
+      const float theta = (A[q][q] - A[p][p]) / (2.f * apq);
+      const float t = copysignf(1.f, theta) / (fabsf(theta) + sqrtf(theta * theta + 1.f));
+      const float c = 1.f / sqrtf(t * t + 1.f), s = t * c;
+      const int r = 3 - p - q;
+      const float arp = A[r][p], arq = A[r][q];
+      A[p][p] -= t * apq;
+      A[q][q] += t * apq;
+      A[p][q] = A[q][p] = 0.f;
+      A[r][p] = A[p][r] = c * arp - s * arq;
+      A[r][q] = A[q][r] = s * arp + c * arq;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float vkp = V[k][p], vkq = V[k][q];
+        V[k][p] = c * vkp - s * vkq;
+        V[k][q] = s * vkp + c * vkq;
+      }
+    }
+  }
+}
+
+__device__ inline float det3(const float M[3][3]) {
+  return M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+         M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+}
+
+// Rotation-preserving SVD F = U diag(S) V^T with det U = det V = +1 (S[2]
+// carries the sign of det F).  V from the Jacobi eigenvectors of F^T F, U and
+// S from a Givens QR of F V (McAdams et al. 2011, "Computing the singular
+// value decomposition of 3x3 matrices with minimal branching and elementary
+// floating point operations", steps: symmetric eigenanalysis, sorting, QR).
+__device__ inline void svd3(const float F[3][3], float U[3][3], float S[3], float V[3][3]) {
+  float A[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) A[i][j] = F[0][i] * F[0][j] + F[1][i] * F[1][j] + F[2][i] * F[2][j];
+  float W[3][3];
+  jacobi3(A, W);
+  float ev[3] = {A[0][0], A[1][1], A[2][2]};
+  int o[3] = {0, 1, 2};
+  // sort eigenvalues descending
+  if (ev[o[0]] < ev[o[1]]) { int t = o[0]; o[0] = o[1]; o[1] = t; }
+  if (ev[o[1]] < ev[o[2]]) { int t = o[1]; o[1] = o[2]; o[2] = t; }
+  if (ev[o[0]] < ev[o[1]]) { int t = o[0]; o[0] = o[1]; o[1] = t; }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) V[i][k] = W[i][o[k]];
+  if (det3(V) < 0.f) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) V[i][2] = -V[i][2];
+  }
+  float B[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) B[i][k] = F[i][0] * V[0][k] + F[i][1] * V[1][k] + F[i][2] * V[2][k];
+  // Q^T accumulates the Givens rotations: Q^T B = R
+  float Qt[3][3] = {{1.f, 0.f, 0.f}, {0.f, 1.f, 0.f}, {0.f, 0.f, 1.f}};
+  const int gi[3] = {0, 0, 1}, gj[3] = {1, 2, 2}, gc[3] = {0, 0, 1};
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    const int i = gi[g], j = gj[g], col = gc[g];
+    const float a = B[i][col], b = B[j][col];
+    const float r = sqrtf(a * a + b * b);
+    float c = 1.f, s = 0.f;
+    if (r > 0.f) { c = a / r; s = b / r; }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float bi = B[i][k], bj = B[j][k];
+      B[i][k] = c * bi + s * bj;
+      B[j][k] = -s * bi + c * bj;
+      const float qi = Qt[i][k], qj = Qt[j][k];
+      Qt[i][k] = c * qi + s * qj;
+      Qt[j][k] = -s * qi + c * qj;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) U[i][k] = Qt[k][i];
+  S[0] = B[0][0]; S[1] = B[1][1]; S[2] = B[2][2];
+  // make S[0], S[1] non-negative, pushing signs into column 2 to keep det U = +1
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (S[k] < 0.f) {
+      S[k] = -S[k]; S[2] = -S[2];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) { U[i][k] = -U[i][k]; U[i][2] = -U[i][2]; }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest, const double* __restrict__ xh,
+          const float* __restrict__ Dminv9, const float* __restrict__ vol, const float* __restrict__ mu_,
+          const float* __restrict__ lam_, float h2, const int* __restrict__ epos, float* __restrict__ staging,
+          int* flags) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= T) return;
+  const int4 t = tets[e];
+  const int v[4] = {t.x, t.y, t.z, t.w};
+  // displacement differences in FP64, then FP32
+  double u0[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) u0[i] = xh[3LL * v[0] + i] - rest[3LL * v[0] + i];
+  float Du[3][3];  // column k = u_{k+1} - u_0
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      Du[i][k] = (float)((xh[3LL * v[k + 1] + i] - rest[3LL * v[k + 1] + i]) - u0[i]);
+  float Dm[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Dm[i][j] = Dminv9[(long long)(3 * i + j) * T + e];
+  float Gm[3][3], F[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Gm[i][j] = Du[i][0] * Dm[0][j] + Du[i][1] * Dm[1][j] + Du[i][2] * Dm[2][j];
+      F[i][j] = Gm[i][j] + (i == j ? 1.f : 0.f);
+    }
+  const float trG = Gm[0][0] + Gm[1][1] + Gm[2][2];
+  float trG2 = 0.f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) trG2 += Gm[i][j] * Gm[j][i];
+  const float Jm1 = trG + 0.5f * (trG * trG - trG2) + det3(Gm);
+  const float J = 1.f + Jm1;
+  const float w = h2 * vol[e];
+  const long long pbase = 10LL * e;
+  if (!(J > 0.f)) {
+    atomicOr(flags, FLAG_INVERTED);
+    for (int k = 0; k < 10; ++k) {
+      float* o = staging + 9LL * epos[pbase + k];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) o[q] = 0.f;
+    }
+    return;
+  }
+  const float mu = mu_[e], lam = lam_[e];
+  const float lnJ = log1pf(Jm1);
+  // P = F^{-T} Sp with Sp = mu (G + G^T + G^T G) + lam lnJ I; F^{-T} = cof(F) / J
+  float Sp[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const float gtg = Gm[0][i] * Gm[0][j] + Gm[1][i] * Gm[1][j] + Gm[2][i] * Gm[2][j];
+      Sp[i][j] = mu * (Gm[i][j] + Gm[j][i] + gtg) + (i == j ? lam * lnJ : 0.f);
+    }
+  float C[3][3];
+  C[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+  C[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+  C[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+  C[1][0] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
+  C[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
+  C[1][2] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
+  C[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
+  C[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
+  C[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  const float iJ = 1.f / J;
+  float P[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) P[i][j] = (C[i][0] * Sp[0][j] + C[i][1] * Sp[1][j] + C[i][2] * Sp[2][j]) * iJ;
+  // rows A_a (A_1..A_3 = rows of Dm^{-1}, A_0 = -their sum)
+  float A[4][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    A[1][j] = Dm[0][j]; A[2][j] = Dm[1][j]; A[3][j] = Dm[2][j];
+    A[0][j] = -(Dm[0][j] + Dm[1][j] + Dm[2][j]);
+  }
+  // SVD and the analytic eigensystem
+  float U[3][3], S[3], V[3][3];
+  svd3(F, U, S, V);
+  const float lnJs = lnJ;
+  float Ah[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Ah[i][j] = (i == j) ? mu + (mu + lam - lam * lnJs) / (S[i] * S[i]) : lam / (S[i] * S[j]);
+  if (mu - lam * lnJs < 0.f) {
+    // Ah = mu I + (mu - lam lnJ) diag(1/S^2) + lam s s^T can be indefinite only here: clamp its eigenvalues
+    float E3[3][3], Q[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) E3[i][j] = Ah[i][j];
+    jacobi3(E3, Q);
+    const float l0 = fmaxf(E3[0][0], 0.f), l1 = fmaxf(E3[1][1], 0.f), l2 = fmaxf(E3[2][2], 0.f);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Ah[i][j] = l0 * Q[i][0] * Q[j][0] + l1 * Q[i][1] * Q[j][1] + l2 * Q[i][2] * Q[j][2];
+  }
+  // twist / flip eigenvalues per singular-value pair (0,1), (0,2), (1,2)
+  float c1[3], c2[3];
+  const int pi[3] = {0, 0, 1}, pj[3] = {1, 2, 2};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float ss = S[pi[k]] * S[pj[k]];
+    const float wt = fmaxf(mu + (lam * lnJs - mu) / ss, 0.f);
+    const float wf = fmaxf(mu + (mu - lam * lnJs) / ss, 0.f);
+    c1[k] = 0.5f * (wt + wf);
+    c2[k] = 0.5f * (wf - wt);
+  }
+  float AV[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) AV[a][k] = A[a][0] * V[0][k] + A[a][1] * V[1][k] + A[a][2] * V[2][k];
+
+  for (int pr = 0; pr < 10; ++pr) {
+    const int a = c_pa[pr], b = c_pb[pr];
+    float Sm[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Sm[i][j] = Ah[i][j] * AV[a][i] * AV[b][j];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int i = pi[k], j = pj[k];
+      Sm[i][i] += c1[k] * AV[a][j] * AV[b][j];
+      Sm[j][j] += c1[k] * AV[a][i] * AV[b][i];
+      Sm[i][j] += c2[k] * AV[a][j] * AV[b][i];
+      Sm[j][i] += c2[k] * AV[a][i] * AV[b][j];
+    }
+    float T1[3][3], Hb[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) T1[i][j] = U[i][0] * Sm[0][j] + U[i][1] * Sm[1][j] + U[i][2] * Sm[2][j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Hb[i][j] = w * (T1[i][0] * U[j][0] + T1[i][1] * U[j][1] + T1[i][2] * U[j][2]);
+    float* o = staging + 9LL * epos[pbase + pr];
+    if (a == b) {
+      // symmetric diagonal block: 6 entries, then the vertex gradient h^2 V P A_a^T
+      o[0] = Hb[0][0];
+      o[1] = 0.5f * (Hb[0][1] + Hb[1][0]);
+      o[2] = 0.5f * (Hb[0][2] + Hb[2][0]);
+      o[3] = Hb[1][1];
+      o[4] = 0.5f * (Hb[1][2] + Hb[2][1]);
+      o[5] = Hb[2][2];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) o[6 + i] = w * (P[i][0] * A[a][0] + P[i][1] * A[a][1] + P[i][2] * A[a][2]);
+    } else if (v[a] < v[b]) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) o[3 * i + j] = Hb[i][j];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) o[3 * i + j] = Hb[j][i];
+    }
+  }
+}
+
+}  // namespace
+
+void launch_elastic(const int4* tets, int T, const double* rest, const double* xh, const float* Dminv9,
+                    const float* vol, const float* mu, const float* lam, float h2, const int* epos, float* staging,
+                    int* flags, hipStream_t s) {
+  if (T > 0)
+    hipLaunchKernelGGL(k_elastic, dim3(div_up(T, kBlock)), dim3(kBlock), 0, s, tets, T, rest, xh, Dminv9, vol, mu,
+                       lam, h2, epos, staging, flags);
+}
+
+}  // namespace bfal

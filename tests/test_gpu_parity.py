@@ -1,0 +1,196 @@
+"""GPU parity through the C-ABI against the FP64 CPU oracle.
+
+Bars: the BSR pattern and its maps bit-exact; the FP32 gradient within 1e-5
+relative (2-norm over free DoFs); assembled blocks within 1e-5 relative
+(Frobenius over all blocks); the PCG solution within 1e-4 relative in the
+energy norm of the oracle's FP64 H against the FP64 direct/reference solve
+when the tolerance allows it, and otherwise no worse than the FP64 oracle PCG
+at the same tolerance (whose own error is reported beside it)."""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bf():
+    from paper_2512_12151_amd import bfal
+    return bfal
+
+
+@pytest.fixture(scope="module")
+def ctx(bf):
+    return bf.Context(0)
+
+
+CASES = {
+    "tiny": lambda: scenes.tiny(),
+    "tiny_shifted": lambda: scenes.tiny(lateral=(0.37, 0.21)),
+    "two_8cubes": lambda: scenes.tiny(n=8, n_pt=300, n_ee=200, lateral=(0.3, 0.6)),
+    "serve3": lambda: scenes.serve_request(3),
+}
+
+_cache = {}
+
+
+def ref(name):
+    if name not in _cache:
+        sc = CASES[name]() if name in CASES else scenes.medium()
+        st = oracle.assemble(sc)
+        _cache[name] = (sc, st)
+    return _cache[name]
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("name", list(CASES) + ["medium"])
+def test_pattern_and_maps_bit_exact(ctx, bf, name):
+    sc, st = ref(name)
+    print(f"case {name}", flush=True)
+    pb = bf.Problem.from_scene(ctx, sc)
+    pb.newton_step(tol=1e-5)
+    row_ptr, col, emap, cmap, diag = pb.pattern()
+    r_ptr, r_col, r_emap, r_cmap, r_diag = oracle.pattern(len(sc["rest"]), sc["tets"], sc["pt"], sc["ee"])
+    assert np.array_equal(row_ptr, r_ptr)
+    assert np.array_equal(col, r_col)
+    assert np.array_equal(emap, r_emap)
+    assert np.array_equal(cmap, r_cmap)
+    assert np.array_equal(diag, r_diag)
+
+
+@pytest.mark.parametrize("name", list(CASES) + ["medium"])
+def test_gradient_and_blocks(ctx, bf, name):
+    sc, st = ref(name)
+    print(f"case {name}", flush=True)
+    pb = bf.Problem.from_scene(ctx, sc)
+    pb.newton_step(tol=1e-5)
+    g = pb.gradient()
+    free = ~sc["fixed"].astype(bool)
+    assert rel(g[free], st.G[free]) <= 1e-5
+    assert np.all(g[~free] == 0.0)
+    row_ptr, col, *_ = pb.pattern()
+    B = pb.blocks().astype(np.float64)
+    Bref = oracle.upper_blocks(st.H, row_ptr.astype(np.int64), col)
+    assert rel(B, Bref) <= 1e-5
+
+
+@pytest.mark.parametrize("name,tol,bar", [("tiny", 1e-7, 1e-4), ("tiny_shifted", 1e-7, 1e-4),
+                                          ("two_8cubes", 1e-7, 1e-4), ("serve3", 1e-7, 1e-4),
+                                          ("medium", 1e-7, 1e-4)])
+def test_solution_energy_norm(ctx, bf, name, tol, bar):
+    sc, st = ref(name)
+    print(f"case {name}", flush=True)
+    pb = bf.Problem.from_scene(ctx, sc)
+    p, stats, status = pb.newton_step(tol=tol, max_iter=50000)
+    assert status == bf.BF_OK
+    p_ref = oracle.solve_reference(st.H, st.G)
+    err = oracle.energy_norm_rel(st.H, p, p_ref)
+    p64, it64 = oracle.block_jacobi_pcg(st.H, st.G, tol)
+    err64 = oracle.energy_norm_rel(st.H, p64, p_ref)
+    print(f"{name}: tol={tol:g} gpu iters={stats['pcg_iters']} err={err:.3e} | fp64 pcg iters={it64} "
+          f"err={err64:.3e}", flush=True)
+    assert err <= bar
+    assert np.all(p[sc["fixed"].astype(bool)] == 0.0)
+    assert stats["rel_residual"] <= tol
+
+
+@pytest.mark.parametrize("name", ["tiny_shifted", "medium"])
+def test_solution_at_bench_tolerance_matches_fp64_pcg(ctx, bf, name):
+    sc, st = ref(name)
+    print(f"case {name}", flush=True)
+    pb = bf.Problem.from_scene(ctx, sc)
+    p, stats, status = pb.newton_step(tol=1e-5, max_iter=50000)
+    p_ref = oracle.solve_reference(st.H, st.G)
+    err = oracle.energy_norm_rel(st.H, p, p_ref)
+    p64, it64 = oracle.block_jacobi_pcg(st.H, st.G, 1e-5)
+    err64 = oracle.energy_norm_rel(st.H, p64, p_ref)
+    print(f"{name}: tol=1e-5 gpu iters={stats['pcg_iters']} err={err:.3e} | fp64 pcg iters={it64} err={err64:.3e}",
+          flush=True)
+    assert err <= 2.0 * err64 + 1e-5
+    # the true residual of the returned p in FP64
+    r = st.H @ p.ravel() + st.G.ravel()
+    assert np.linalg.norm(r) <= 1.5e-5 * np.linalg.norm(st.G)
+
+
+def test_stats_and_determinism(ctx, bf):
+    sc, st = ref("tiny_shifted")
+    pb = bf.Problem.from_scene(ctx, sc)
+    p1, s1, _ = pb.newton_step(tol=1e-6)
+    g1, b1 = pb.gradient(), pb.blocks()
+    p2, s2, _ = pb.newton_step(tol=1e-6)
+    g2, b2 = pb.gradient(), pb.blocks()
+    assert np.array_equal(g1, g2) and np.array_equal(b1, b2)      # assembly is atomic-free
+    # the SpMV scatters with FP32 atomics: runs agree to the solve tolerance, not bitwise
+    assert oracle.energy_norm_rel(st.H, p1, p2) <= 1e-4
+    assert abs(s1["max_violation"] - float(np.maximum(0, -st.c).max())) <= 1e-12 * max(1.0, s1["max_violation"])
+    assert np.isclose(s1["newton_inf_over_h"], np.abs(p1).max() / sc["dt"], rtol=1e-12)
+    assert s1["nnzb"] == pb.nnzb()
+
+
+def test_device_pointer_path_matches_host_path(ctx, bf):
+    import torch
+    sc, st = ref("tiny_shifted")
+    pb = bf.Problem.from_scene(ctx, sc)
+    p_host, _, _ = pb.newton_step(tol=1e-7)
+    dev = torch.device("cuda:0")
+    t = {k: torch.from_numpy(np.ascontiguousarray(sc[k])).to(dev)
+         for k in ("tets", "rest", "E", "nu", "rho", "fixed", "x", "x_hat", "x_tilde", "pt", "ee", "lam", "gamma")}
+    torch.cuda.synchronize()
+    pd = bf.Problem(ctx, t["tets"], t["rest"], t["E"], t["nu"], t["rho"], t["fixed"])
+    pd.set_state(t["x"], t["x_hat"], t["x_tilde"], sc["dt"])
+    pd.set_constraints(t["pt"], t["ee"], t["lam"], t["gamma"], sc["kappa"], sc["delta"])
+    out = torch.empty((len(sc["rest"]), 3), dtype=torch.float64, device=dev)
+    pd.newton_step(tol=1e-7, out=out)
+    torch.cuda.synchronize()
+    p_dev = out.cpu().numpy()
+    assert np.array_equal(pd.gradient(), pb.gradient())          # same bits up to the solve
+    assert oracle.energy_norm_rel(st.H, p_dev, p_host) <= 1e-4
+
+
+def test_error_statuses(ctx, bf):
+    sc = dict(ref("tiny")[0])
+    # an inverted element in x_hat
+    bad = dict(sc)
+    xh = sc["x_hat"].copy()
+    t0 = sc["tets"][100]
+    xh[t0[0]] = xh[t0[1]] + 2.0 * (xh[t0[1]] - xh[t0[0]])
+    bad["x_hat"] = xh
+    pb = bf.Problem.from_scene(ctx, bad)
+    with pytest.raises(bf.BfalError) as e:
+        pb.newton_step()
+    assert e.value.status == -4
+    # a constraint whose primitives touch at x (d = 0: the point sits on a triangle vertex)
+    bad = dict(sc)
+    x = sc["x"].copy()
+    p_, a, b, c = sc["pt"][0]
+    x[p_] = x[a]
+    bad["x"] = x
+    pb = bf.Problem.from_scene(ctx, bad)
+    with pytest.raises(bf.BfalError) as e:
+        pb.newton_step()
+    assert e.value.status == -5
+    # a parallel edge-edge pair at x
+    bad = dict(sc)
+    x = sc["x"].copy()
+    a0, a1, b0, b1 = sc["ee"][0]
+    x[b1] = x[b0] + (x[a1] - x[a0])
+    bad["x"] = x
+    pb = bf.Problem.from_scene(ctx, bad)
+    with pytest.raises(bf.BfalError) as e:
+        pb.newton_step()
+    assert e.value.status == -5
+    # out-of-range index and repeated vertex are rejected on the host
+    bad = dict(sc)
+    pt = sc["pt"].copy()
+    pt[0, 1] = len(sc["rest"])
+    bad["pt"] = pt
+    with pytest.raises(bf.BfalError) as e:
+        bf.Problem.from_scene(ctx, bad)
+    assert e.value.status == -1
+    with pytest.raises(bf.BfalError):
+        pb.set_state(sc["x"], sc["x_hat"], sc["x_tilde"], -1.0)
