@@ -30,25 +30,21 @@ def log(msg):
 
 
 def spmv_bytes(N, nnzb):
-    """Algorithmic bytes of one SpMV launch (k_spmv): the scaled off-diagonal
-    blocks are stored for both triangles, so each of the nnzb - N upper
-    off-diagonal blocks is read twice (2 x (36 B FP32 values + 4 B column));
-    one row pointer per row; p read once (12 B/node); q written once (12 B/node)."""
+    """Algorithmic bytes of one launch of k_spmv, the first phase of the
+    symmetric product: each of the nnzb - N stored upper off-diagonal blocks
+    is read once (36 B FP32 values + 4 B column) and its transposed product
+    written once (12 B); one row pointer per row; p read once (12 B/node);
+    q_row written once (12 B/node)."""
     n_off = nnzb - N
-    return 80 * n_off + 4 * (N + 1) + 24 * N
-
-
-def spmv_bytes_upper_only(N, nnzb):
-    """The same product counted with upper-only storage (each upper block,
-    diagonal included, read once: 40 B), row pointers, p read and q read and
-    written: the least traffic any symmetric BSR SpMV of this matrix moves."""
-    return 40 * nnzb + 4 * (N + 1) + 24 * N
+    return 52 * n_off + 4 * (N + 1) + 24 * N
 
 
 def pcg_iteration_bytes(N, nnzb):
-    """SpMV + update (x, p, r, q read, x, r written, L read for the residual
-    check: 96 B/node) + direction (r, p read, p written: 36 B/node)."""
-    return spmv_bytes(N, nnzb) + 96 * N + 36 * N
+    """k_spmv + k_update (q_row, transpose pointer, x, p, r, L read, x and r
+    written: 100 B/node; transpose index and transposed products read:
+    16 B/block) + k_direction (r, p read, p written: 36 B/node)."""
+    n_off = nnzb - N
+    return spmv_bytes(N, nnzb) + 16 * n_off + 100 * N + 36 * N
 
 
 def cpu_baseline(sc, gpu_iters, frac):
@@ -106,6 +102,11 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--cpu-sample", type=float, default=0.05)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=200000,
+                    help="PCG iteration cap (lower it only for counter-collection runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time a plain device-to-device copy of 512 MiB (bandwidth ceiling and the reference "
+                         "for scaling HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is described in "
@@ -117,6 +118,24 @@ def main():
 
     import scenes
     from paper_2512_12151_amd import bfal
+
+    if args.copy_probe:
+        n = 128 * 1024 * 1024   # floats: 512 MiB per buffer
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "ms": ms,
+                          "gbs_read_plus_write": 8 * n / (ms * 1e-3) / 1e9}), flush=True)
+        return
 
     log(f"generating workload {args.workload}")
     sc = scenes.make_scene(args.workload)
@@ -133,7 +152,7 @@ def main():
     pb.set_state(t["x"], t["x_hat"], t["x_tilde"], sc["dt"])
     pb.set_constraints(t["pt"], t["ee"], t["lam"], t["gamma"], sc["kappa"], sc["delta"])
     out = torch.empty((N, 3), dtype=torch.float64, device=dev)
-    opts = dict(tol=args.tol, max_iter=200000, poll_every=64, check_every=1)
+    opts = dict(tol=args.tol, max_iter=args.max_iter, poll_every=64, check_every=1)
     for w in range(args.warmup):
         _, st, status = pb.newton_step(out=out, **opts)
         log(f"warmup {w}: status {status}, {st['pcg_iters']} PCG iterations, rel residual {st['rel_residual']:.2e}")
@@ -180,8 +199,7 @@ def main():
         "rel_residual": last["rel_residual"],
         "roofline": {"bound": "hbm", "kernel": "k_spmv", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_launch": sb, "avg_ms": round(spmv_ms, 5), "launches_timed": tst["spmv_timed"],
-                     "upper_only_gbs": round(spmv_bytes_upper_only(N, nnzb) / (spmv_ms * 1e-3) / 1e9, 1)},
+                     "bytes_per_launch": sb, "avg_ms": round(spmv_ms, 5), "launches_timed": tst["spmv_timed"]},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")

@@ -40,7 +40,7 @@ struct bf_problem {
   DevBuf cn, cw, cg, ch, viol_part;
   DevBuf vcnt, vptr, vinc;
   DevBuf ccount, cptr, cand, ucount, row_ptr, col, eslot;
-  DevBuf vals, grad, Lf, Linv, bhat, bb_part, ovals, ocol, orow_ptr, lcnt, lptr, lsrc;
+  DevBuf vals, grad, Lf, Linv, bhat, bb_part, ovals, ocol, orow_ptr, lcnt, lptr, lsrc, tidx, tbuf;
   DevBuf xs, r, p, q, part, scal, pout, flags, scan_tmp, scratch_int;
   long long cap_nnzb = 0, cap_cand = 0;
   PcgScalars* host_sc = nullptr;
@@ -291,7 +291,7 @@ void bf_problem_destroy(bf_problem* pb) {
                     &pb->cg, &pb->ch, &pb->viol_part, &pb->vcnt, &pb->vptr, &pb->vinc, &pb->ccount, &pb->cptr,
                     &pb->cand, &pb->ucount, &pb->row_ptr, &pb->col, &pb->eslot, &pb->vals, &pb->grad, &pb->Lf,
                     &pb->Linv, &pb->bhat, &pb->bb_part, &pb->ovals, &pb->ocol, &pb->orow_ptr, &pb->lcnt, &pb->lptr,
-                    &pb->lsrc, &pb->xs, &pb->r,
+                    &pb->lsrc, &pb->tidx, &pb->tbuf, &pb->xs, &pb->r,
                     &pb->p, &pb->q, &pb->part, &pb->scal, &pb->pout, &pb->flags, &pb->scan_tmp, &pb->scratch_int};
   for (DevBuf* b : bufs) b->release();
   for (auto& e : pb->ev)
@@ -406,21 +406,29 @@ bf_status bf_set_constraints(bf_problem* pb, const bf_constraint_desc* cd, int32
   ALLOC(c, pb->col, 4LL * cap);
   ALLOC(c, pb->eslot, 4LL * cap);
   ALLOC(c, pb->vals, 36LL * cap);
-  ALLOC(c, pb->ovals, 72LL * cap);     // scaled off-diagonal blocks of both triangles
-  ALLOC(c, pb->ocol, 8LL * cap);
+  ALLOC(c, pb->ovals, 36LL * cap);     // scaled upper off-diagonal blocks, SoA [9][cap]
+  ALLOC(c, pb->ocol, 4LL * cap);
   ALLOC(c, pb->orow_ptr, 4LL * (N + 1));
   ALLOC(c, pb->lcnt, 4LL * (N + 1));
   ALLOC(c, pb->lptr, 4LL * (N + 1));
   ALLOC(c, pb->lsrc, 4LL * cap);
+  ALLOC(c, pb->tidx, 4LL * cap);
+  ALLOC(c, pb->tbuf, 12LL * cap);
+  // solver vectors and the factor L are padded to a multiple of 4 nodes (float4
+  // access); the pads are zeroed here and never written with nonzeros
+  const long long N4 = (N + 3) & ~3LL;
   ALLOC(c, pb->grad, 12LL * N);
-  ALLOC(c, pb->Lf, 24LL * N);
-  ALLOC(c, pb->Linv, 24LL * N);
-  ALLOC(c, pb->bhat, 12LL * N + 16);
+  ALLOC(c, pb->Lf, 24LL * N4);
+  ALLOC(c, pb->Linv, 24LL * N4);
+  ALLOC(c, pb->bhat, 12LL * N4);
   ALLOC(c, pb->bb_part, 8LL * (div_up(N, kBlock) + 1));
-  ALLOC(c, pb->xs, 12LL * N + 16);
-  ALLOC(c, pb->r, 12LL * N + 16);
-  ALLOC(c, pb->p, 12LL * N + 16);
-  ALLOC(c, pb->q, 12LL * N + 16);
+  ALLOC(c, pb->xs, 12LL * N4);
+  ALLOC(c, pb->r, 12LL * N4);
+  ALLOC(c, pb->p, 12LL * N4);
+  ALLOC(c, pb->q, 12LL * N4);
+  for (DevBuf* b : {&pb->Lf, &pb->Linv, &pb->bhat, &pb->xs, &pb->r, &pb->p, &pb->q})
+    HIPCHK(c, hipMemsetAsync(b->p, 0, b->bytes, s));
+  HIPCHK(c, hipStreamSynchronize(s));
   ALLOC(c, pb->part, 8LL * pcg_partials_needed(N));
   ALLOC(c, pb->pout, 24LL * N);
   ALLOC(c, pb->scan_tmp, 4LL * scan_tmp_ints((long long)10 * pb->T + N + 6LL * n + 16));
@@ -482,8 +490,8 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
                        pb->ch.as<float>(), pb->mass.as<float>(), pb->xh.as<double>(), pb->xt.as<double>(),
                        pb->fixed.as<uint8_t>(), pb->vals.as<float>(), pb->grad.as<float>(), pb->Lf.as<float>(),
                        pb->Linv.as<float>(), pb->bhat.as<float>(), pb->bb_part.as<double>(), flags, s);
-  // scaled blocks of both triangles for the gather-only SpMV
-  const long long fstride = 2 * pb->cap_nnzb;
+  // scaled upper blocks and the transpose index of the two-phase SpMV
+  const long long ustride = pb->cap_nnzb;
   int* lcnt = pb->lcnt.as<int>();
   int* lptr = pb->lptr.as<int>();
   fill_int(lcnt, 0, N, s);
@@ -492,8 +500,9 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
   fill_int(lcnt, 0, N, s);
   launch_lower_fill(N, row_ptr, pb->col.as<int>(), lptr, lcnt, pb->lsrc.as<int>(), s);
   sort_segments(pb->lsrc.as<int>(), lptr, N, s);
-  launch_scale_full(N, row_ptr, pb->col.as<int>(), pb->vals.as<float>(), pb->Linv.as<float>(), lptr,
-                    pb->lsrc.as<int>(), pb->ovals.as<float>(), pb->ocol.as<int>(), pb->orow_ptr.as<int>(), fstride, s);
+  launch_transpose_index(N, row_ptr, pb->col.as<int>(), lptr, pb->lsrc.as<int>(), pb->tidx.as<int>(), s);
+  launch_scale_upper(N, row_ptr, pb->col.as<int>(), pb->vals.as<float>(), pb->Linv.as<float>(), pb->ovals.as<float>(),
+                     pb->ocol.as<int>(), pb->orow_ptr.as<int>(), ustride, s);
   HIPCHK(c, hipEventRecord(pb->ev[3], s));
   // (4) PCG
   PcgScalars* sc = pb->scal.as<PcgScalars>();
@@ -514,11 +523,11 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
     for (int k = 0; k < batch; ++k) {
       const int it = launched + k;
       if (it < ntime) HIPCHK(c, hipEventRecord(pb->tev[2 * it], s));
-      launch_pcg_spmv(N, pb->orow_ptr.as<int>(), pb->ocol.as<int>(), pb->ovals.as<float>(), fstride,
-                      pb->p.as<float>(), pb->q.as<float>(), part, sc, s);
+      launch_pcg_spmv(N, pb->orow_ptr.as<int>(), pb->ocol.as<int>(), pb->ovals.as<float>(), ustride,
+                      pb->p.as<float>(), pb->q.as<float>(), pb->tbuf.as<float>(), part, sc, s);
       if (it < ntime) HIPCHK(c, hipEventRecord(pb->tev[2 * it + 1], s));
       launch_pcg_vector_ops(N, pb->Lf.as<float>(), pb->xs.as<float>(), pb->r.as<float>(), pb->p.as<float>(),
-                            pb->q.as<float>(), part, sc, s);
+                            pb->q.as<float>(), pb->tbuf.as<float>(), lptr, pb->tidx.as<int>(), part, sc, s);
     }
     launched += batch;
     HIPCHK(c, hipMemcpyAsync(pb->host_sc, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));

@@ -11,8 +11,9 @@
 // Then the block-Jacobi preconditioner (the paper's 3x3 block-Jacobi PCG) is
 // applied symmetrically: each diagonal block is factored D_v = L_v L_v^T and
 // the off-diagonal blocks are scaled to L_r^{-1} H_rc L_c^{-T}, so the solver
-// runs CG on a matrix whose diagonal blocks are identities.  The scaled blocks
-// are stored for both triangles so that the SpMV is a pure row gather.
+// runs CG on a matrix whose diagonal blocks are identities.  Only the upper
+// off-diagonal scaled blocks are stored, plus a transpose index (for every
+// column, the blocks above the diagonal in it) used by the SpMV's second phase.
 #include "common.h"
 
 namespace bfal {
@@ -187,40 +188,41 @@ __device__ inline void scaled_block(const float* __restrict__ mr, const float* _
     for (int k = 0; k < 3; ++k) out[i][k] = T1[i][0] * Cm[k][0] + T1[i][1] * Cm[k][1] + T1[i][2] * Cm[k][2];
 }
 
-// H_hat_rc = M_r H_rc M_c^T for every off-diagonal block of both triangles,
-// row-major with columns ascending (lower part, then upper part), SoA
-// [9][stride].  The diagonal blocks of H_hat are identities and not stored.
-__global__ void k_scale_full(int N, const int* __restrict__ row_ptr, const int* __restrict__ col,
-                             const float* __restrict__ vals, const float* __restrict__ Linv,
-                             const int* __restrict__ lptr, const int* __restrict__ lsrc, float* __restrict__ fv,
-                             int* __restrict__ fcol, int* __restrict__ frow_ptr, long long st) {
+// H_hat_rc = M_r H_rc M_c^T for every upper off-diagonal block, SoA [9][stride];
+// row r's blocks start at row_ptr[r] - r (the diagonal slots are dropped: the
+// diagonal blocks of H_hat are identities).
+__global__ void k_scale_upper(int N, const int* __restrict__ row_ptr, const int* __restrict__ col,
+                              const float* __restrict__ vals, const float* __restrict__ Linv, float* __restrict__ uv,
+                              int* __restrict__ ucol, int* __restrict__ urow_ptr, long long st) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= N) return;
-  long long pos = (long long)(row_ptr[r] - r) + lptr[r];
-  frow_ptr[r] = (int)pos;
-  if (r == N - 1) frow_ptr[N] = (row_ptr[N] - N) + lptr[N];
+  const int o = row_ptr[r], n = row_ptr[r + 1] - o;
+  urow_ptr[r] = o - r;
+  if (r == N - 1) urow_ptr[N] = row_ptr[N] - N;
   const float* mr = Linv + 6LL * r;
   float h[3][3];
-  for (int j = lptr[r]; j < lptr[r + 1]; ++j) {
-    const int rs = lsrc[j];
-    const int s = find_slot(col, row_ptr[rs] + 1, row_ptr[rs + 1] - 1, r);
-    scaled_block(Linv + 6LL * rs, vals + 9LL * s, mr, h);   // block (rs, r); row r stores its transpose
+  for (int j = 1; j < n; ++j) {
+    const int c = col[o + j];
+    scaled_block(mr, vals + 9LL * (o + j), Linv + 6LL * c, h);
+    const long long oj = (long long)(o - r) + j - 1;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) fv[(3 * i + k) * st + pos] = h[k][i];
-    fcol[pos] = rs;
-    ++pos;
+      for (int k = 0; k < 3; ++k) uv[(3 * i + k) * st + oj] = h[i][k];
+    ucol[oj] = c;
   }
-  for (int s = row_ptr[r] + 1; s < row_ptr[r + 1]; ++s) {
-    const int c = col[s];
-    scaled_block(mr, vals + 9LL * s, Linv + 6LL * c, h);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) fv[(3 * i + k) * st + pos] = h[i][k];
-    fcol[pos] = c;
-    ++pos;
+}
+
+// For every node c, the upper off-diagonal block indices j with column c, in
+// increasing source row (the order the SpMV sums their transposed products).
+__global__ void k_transpose_index(int N, const int* __restrict__ row_ptr, const int* __restrict__ col,
+                                  const int* __restrict__ lptr, const int* __restrict__ lsrc, int* __restrict__ tidx) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  for (int i = lptr[c]; i < lptr[c + 1]; ++i) {
+    const int rs = lsrc[i];
+    const int s = find_slot(col, row_ptr[rs] + 1, row_ptr[rs + 1] - 1, c);
+    tidx[i] = s - rs - 1;
   }
 }
 
@@ -250,11 +252,16 @@ void launch_lower_fill(int N, const int* row_ptr, const int* col, const int* lpt
   hipLaunchKernelGGL(k_lower_fill, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, lptr, lcur, lsrc);
 }
 
-void launch_scale_full(int N, const int* row_ptr, const int* col, const float* vals, const float* Linv,
-                       const int* lptr, const int* lsrc, float* fvals, int* fcol, int* frow_ptr, long long fstride,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_full, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, vals, Linv, lptr,
-                     lsrc, fvals, fcol, frow_ptr, fstride);
+void launch_scale_upper(int N, const int* row_ptr, const int* col, const float* vals, const float* Linv, float* uvals,
+                        int* ucol, int* urow_ptr, long long ustride, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_upper, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, vals, Linv, uvals,
+                     ucol, urow_ptr, ustride);
+}
+
+void launch_transpose_index(int N, const int* row_ptr, const int* col, const int* lptr, const int* lsrc, int* tidx,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose_index, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, lptr, lsrc,
+                     tidx);
 }
 
 void launch_row_diag_slots(int N, const int* row_ptr, int* diag, hipStream_t s) {

@@ -122,14 +122,16 @@ void launch_assemble_rows(int N, const int* row_ptr, const int* col, const int* 
                           const float* mass, const double* xh, const double* xt, const uint8_t* fixed,
                           float* vals, float* grad, float* Lf, float* Linv, float* bhat, double* bb_part,
                           int* flags, hipStream_t s);
-// Both triangles of the scaled off-diagonal blocks, row-major, as SoA [9][stride]:
-// lower_count/lower_fill build the transpose (column -> source rows) index.
+// Scaled upper off-diagonal blocks as SoA [9][stride] and the transpose index
+// (lower_count / lower_fill / sort_segments give, per column, the source rows;
+// transpose_index turns them into upper block indices).
 void launch_lower_count(int N, const int* row_ptr, const int* col, int* lcnt, hipStream_t s);
 void launch_lower_fill(int N, const int* row_ptr, const int* col, const int* lptr, int* lcur, int* lsrc,
                        hipStream_t s);
-void launch_scale_full(int N, const int* row_ptr, const int* col, const float* vals, const float* Linv,
-                       const int* lptr, const int* lsrc, float* fvals, int* fcol, int* frow_ptr, long long fstride,
-                       hipStream_t s);
+void launch_scale_upper(int N, const int* row_ptr, const int* col, const float* vals, const float* Linv, float* uvals,
+                        int* ucol, int* urow_ptr, long long ustride, hipStream_t s);
+void launch_transpose_index(int N, const int* row_ptr, const int* col, const int* lptr, const int* lsrc, int* tidx,
+                            hipStream_t s);
 void launch_row_diag_slots(int N, const int* row_ptr, int* diag, hipStream_t s);
 
 // pcg.hip
@@ -138,10 +140,14 @@ void launch_pcg_init(int N, const float* bhat, float* x, float* r, float* p, dou
                      const double* bb_part, int nbb, PcgScalars* sc, double tol, int max_iter,
                      int check_every, hipStream_t s);
 // One PCG iteration = launch_pcg_spmv then launch_pcg_vector_ops (update + direction).
-void launch_pcg_spmv(int N, const int* frow_ptr, const int* fcol, const float* fvals, long long fstride,
-                     const float* p, float* q, double* part, PcgScalars* sc, hipStream_t s);
-void launch_pcg_vector_ops(int N, const float* Lf, float* x, float* r, float* p, const float* q, double* part,
-                           PcgScalars* sc, hipStream_t s);
+// The SpMV's first phase writes q_row = p + (upper part) p and, for every upper
+// block j, its transposed product B_j^T p_r into tbuf; launch_pcg_vector_ops
+// completes q = q_row + sum of tbuf over the transpose index, then updates.
+void launch_pcg_spmv(int N, const int* urow_ptr, const int* ucol, const float* uvals, long long ustride,
+                     const float* p, float* qrow, float* tbuf, double* part, PcgScalars* sc, hipStream_t s);
+void launch_pcg_vector_ops(int N, const float* Lf, float* x, float* r, float* p, const float* qrow,
+                           const float* tbuf, const int* tptr, const int* tidx, double* part, PcgScalars* sc,
+                           hipStream_t s);
 void launch_pcg_finish(int N, const float* Linv, const float* x, double* pout, double* part,
                        PcgScalars* sc, const double* viol_part, int nviol, hipStream_t s);
 

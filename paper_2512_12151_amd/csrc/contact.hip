@@ -188,32 +188,101 @@ __global__ void k_cand_count(const int* __restrict__ erow_ptr, const int* __rest
   ccount[r] = n;
 }
 
-__global__ void k_cand_fill(const int* __restrict__ erow_ptr, const int* __restrict__ ecol,
-                            const int* __restrict__ vptr, const int* __restrict__ vinc,
-                            const int4* __restrict__ ids, int N, const int* __restrict__ cptr, int* cand,
-                            int* ucount) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= N) return;
-  const int b = cptr[r];
-  int n = 0;
-  for (int j = erow_ptr[r] + 1; j < erow_ptr[r + 1]; ++j) cand[b + n++] = ecol[j];
-  for (int j = vptr[r]; j < vptr[r + 1]; ++j) {
-    const int4 t = ids[vinc[j] >> 2];
-    if (t.x > r) cand[b + n++] = t.x;
-    if (t.y > r) cand[b + n++] = t.y;
-    if (t.z > r) cand[b + n++] = t.z;
-    if (t.w > r) cand[b + n++] = t.w;
+// One wave per row: gather the row's candidate columns into LDS, sort them by
+// rank (stable: rank = #smaller + #equal with a lower index), keep the first
+// of each run of equal keys, and write the sorted unique columns back to the
+// row's candidate segment.  Rows longer than kCandLds fall back to one lane.
+constexpr int kCandLds = 1024;
+
+__device__ inline int wave_excl_scan(int v, int* total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int inc = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int t = __shfl_up(inc, off, kWave);
+    if (lane >= off) inc += t;
   }
-  for (int j = b + 1; j < b + n; ++j) {
-    int key = cand[j];
-    int k = j - 1;
-    while (k >= b && cand[k] > key) { cand[k + 1] = cand[k]; --k; }
-    cand[k + 1] = key;
+  *total = __shfl(inc, kWave - 1, kWave);
+  return inc - v;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_cand_fill(const int* __restrict__ erow_ptr, const int* __restrict__ ecol, const int* __restrict__ vptr,
+            const int* __restrict__ vinc, const int4* __restrict__ ids, int N, const int* __restrict__ cptr,
+            int* __restrict__ cand, int* __restrict__ ucount) {
+  __shared__ int keys[kBlock / kWave][kCandLds];
+  __shared__ int sorted[kBlock / kWave][kCandLds];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int r = blockIdx.x * (kBlock / kWave) + w;
+  if (r >= N) return;   // whole wave leaves together
+  const int b = cptr[r], n = cptr[r + 1] - b;
+  int* K = keys[w];
+  int* S = sorted[w];
+  if (n > kCandLds) {
+    // rare very long row: one lane, in global memory
+    if (lane == 0) {
+      int m = 0;
+      for (int j = erow_ptr[r] + 1; j < erow_ptr[r + 1]; ++j) cand[b + m++] = ecol[j];
+      for (int j = vptr[r]; j < vptr[r + 1]; ++j) {
+        const int4 t = ids[vinc[j] >> 2];
+        if (t.x > r) cand[b + m++] = t.x;
+        if (t.y > r) cand[b + m++] = t.y;
+        if (t.z > r) cand[b + m++] = t.z;
+        if (t.w > r) cand[b + m++] = t.w;
+      }
+      for (int j = b + 1; j < b + m; ++j) {
+        int key = cand[j];
+        int k = j - 1;
+        while (k >= b && cand[k] > key) { cand[k + 1] = cand[k]; --k; }
+        cand[k + 1] = key;
+      }
+      int u = 0;
+      for (int j = b; j < b + m; ++j)
+        if (j == b || cand[j] != cand[j - 1]) cand[b + u++] = cand[j];
+      ucount[r] = 1 + u;
+    }
+    return;
   }
+  // gather: elastic columns, then the partners of every incident constraint
+  const int e0 = erow_ptr[r] + 1, ne = erow_ptr[r + 1] - e0;
+  for (int j = lane; j < ne; j += kWave) K[j] = ecol[e0 + j];
+  int m = ne;
+  for (int j0 = vptr[r]; j0 < vptr[r + 1]; j0 += kWave) {
+    const int j = j0 + lane;
+    int4 t = make_int4(-1, -1, -1, -1);
+    if (j < vptr[r + 1]) t = ids[vinc[j] >> 2];
+    const int cnt = (t.x > r) + (t.y > r) + (t.z > r) + (t.w > r);
+    int tot;
+    int o = m + wave_excl_scan(cnt, &tot);
+    if (t.x > r) K[o++] = t.x;
+    if (t.y > r) K[o++] = t.y;
+    if (t.z > r) K[o++] = t.z;
+    if (t.w > r) K[o++] = t.w;
+    m += tot;
+  }
+  __builtin_amdgcn_wave_barrier();
+  // stable rank sort
+  for (int i = lane; i < m; i += kWave) {
+    const int key = K[i];
+    int rank = 0;
+    for (int j = 0; j < m; ++j) {
+      const int kj = K[j];
+      rank += (kj < key) || (kj == key && j < i);
+    }
+    S[rank] = key;
+  }
+  __builtin_amdgcn_wave_barrier();
+  // unique, in order
   int u = 0;
-  for (int j = b; j < b + n; ++j)
-    if (j == b || cand[j] != cand[j - 1]) cand[b + u++] = cand[j];
-  ucount[r] = 1 + u;
+  for (int i0 = 0; i0 < m; i0 += kWave) {
+    const int i = i0 + lane;
+    const int keep = (i < m) && (i == 0 || S[i] != S[i - 1]);
+    int tot;
+    const int o = u + wave_excl_scan(keep, &tot);
+    if (keep) cand[b + o] = S[i];
+    u += tot;
+  }
+  if (lane == 0) ucount[r] = 1 + u;
 }
 
 // Write the merged row (diagonal first) and, for each slot, the static elastic
@@ -293,8 +362,8 @@ void launch_candidate_count(const int* erow_ptr, const int* vptr, const int* vin
 
 void launch_candidate_fill(const int* erow_ptr, const int* ecol, const int* vptr, const int* vinc, const int4* ids,
                            int N, const int* cptr, int* cand, int* ucount, hipStream_t s) {
-  hipLaunchKernelGGL(k_cand_fill, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, erow_ptr, ecol, vptr, vinc, ids, N,
-                     cptr, cand, ucount);
+  hipLaunchKernelGGL(k_cand_fill, dim3(div_up(N, kBlock / kWave)), dim3(kBlock), 0, s, erow_ptr, ecol, vptr, vinc, ids,
+                     N, cptr, cand, ucount);
 }
 
 void launch_merged_write(const int* cand, const int* cptr, const int* row_ptr, const int* erow_ptr, const int* ecol,

@@ -4,13 +4,18 @@
 // diagonal blocks are identities.  In exact arithmetic its iterates are those
 // of PCG with z = D^{-1} r on H: p = L^{-T} p_hat, r = L r_hat.
 //
-// One iteration is three kernels on one stream, with no host round trip:
-//   spmv      q = H_hat p = p + sum_c B_rc p_c over the stored off-diagonal
-//             blocks of each row (both triangles: a pure gather, no atomics),
-//             and p^T q (FP64).
-//   update    alpha = rho / p^T q; x += alpha p, r -= alpha q; rho' = r^T r
-//             (FP64); every check_every iterations also |L r|^2, the
-//             unscaled residual norm squared.
+// Only the upper off-diagonal blocks of H_hat are stored and each is read once
+// per iteration.  The symmetric product q = H_hat p runs in two phases with no
+// atomics: the SpMV kernel forms, per row r, q_row = p_r + sum_{c>r} B_rc p_c
+// and writes every block's transposed product t_j = B_rc^T p_r to its own slot
+// of tbuf; the update kernel completes q_c = q_row_c + sum of t_j over the
+// blocks j in column c (the transpose index, in increasing source row).
+// p^T H_hat p = sum_r p_r.(p_r + 2 sum_{c>r} B_rc p_c) is formed in the first
+// phase.  One iteration is three kernels on one stream, with no host round trip:
+//   spmv      q_row, tbuf, p^T q (FP64)
+//   update    q = q_row + transposed sums; alpha = rho / p^T q; x += alpha p,
+//             r -= alpha q; rho' = r^T r (FP64); every check_every iterations
+//             also |L r|^2, the unscaled residual norm squared.
 //   direction beta = rho' / rho, convergence test, p = r + beta p.
 // Grid-wide sums: every workgroup writes one FP64 partial per quantity, and
 // every workgroup of the *next* kernel re-sums all partials in the same fixed
@@ -26,14 +31,17 @@ namespace bfal {
 
 namespace {
 
-constexpr int kGridVec = 1024;                     // workgroups of the vector kernels (partials per sum)
+constexpr int kVecBlock = 1024;                    // threads per workgroup of the vector kernels
+constexpr int kGridVec = 256;                      // workgroups of the vector kernels (partials per sum)
+constexpr int kSpmvBlock = 512;                    // threads per workgroup of the SpMV
 constexpr int kGridSpmv = 1024;                    // workgroups of the SpMV (multiple of 8 XCDs)
-constexpr int kGroup = 16;                         // lanes per BSR row in the SpMV
-constexpr int kRowsPerPass = kBlock / kGroup;      // rows per workgroup pass in the SpMV
+constexpr int kGroup = 8;                          // lanes per BSR row in the SpMV
+constexpr int kRowsPerPass = kSpmvBlock / kGroup;  // rows per workgroup pass in the SpMV
 
-// Sum of v over the workgroup, returned to every thread (fixed shuffle/LDS order).
+// Sum of v over a workgroup of NT threads, returned to every thread (fixed shuffle/LDS order).
+template <int NT>
 __device__ inline double block_sum_all(double v) {
-  __shared__ double red[kBlock / kWave];
+  __shared__ double red[NT / kWave];
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
   __syncthreads();
@@ -41,12 +49,13 @@ __device__ inline double block_sum_all(double v) {
   __syncthreads();
   double s = 0.0;
 #pragma unroll
-  for (int w = 0; w < kBlock / kWave; ++w) s += red[w];
+  for (int w = 0; w < NT / kWave; ++w) s += red[w];
   return s;
 }
 
+template <int NT>
 __device__ inline double block_max_all(double v) {
-  __shared__ double red[kBlock / kWave];
+  __shared__ double red[NT / kWave];
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
   __syncthreads();
@@ -54,15 +63,16 @@ __device__ inline double block_max_all(double v) {
   __syncthreads();
   double s = 0.0;
 #pragma unroll
-  for (int w = 0; w < kBlock / kWave; ++w) s = fmax(s, red[w]);
+  for (int w = 0; w < NT / kWave; ++w) s = fmax(s, red[w]);
   return s;
 }
 
 // Fixed-order sum of part[0..n) by the whole workgroup (same value in every workgroup).
+template <int NT>
 __device__ inline double sum_parts(const double* __restrict__ part, int n) {
   double s = 0.0;
-  for (int k = threadIdx.x; k < n; k += kBlock) s += part[k];
-  return block_sum_all(s);
+  for (int k = threadIdx.x; k < n; k += NT) s += part[k];
+  return block_sum_all<NT>(s);
 }
 
 // Write this workgroup's partial (thread 0).
@@ -78,28 +88,48 @@ __device__ inline int xcd_block() {
   return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
 }
 
-__global__ void __launch_bounds__(kBlock)
-k_spmv(int N, const int* __restrict__ frow_ptr, const int* __restrict__ fcol, const float* __restrict__ fv,
-       long long st, const float* __restrict__ p, float* __restrict__ q, double* __restrict__ part_pq,
-       const PcgScalars* __restrict__ sc) {
+// Smallest row r with frow_ptr[r] >= target (N when none); the last range ends at N.
+__device__ inline int first_row_at(const int* __restrict__ frow_ptr, int N, long long target) {
+  int lo = 0, hi = N;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (frow_ptr[mid] < target) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(kSpmvBlock)
+k_spmv(int N, const int* __restrict__ urow_ptr, const int* __restrict__ ucol, const float* __restrict__ uv,
+       long long st, const float* __restrict__ p, float* __restrict__ qrow, float* __restrict__ tbuf,
+       double* __restrict__ part_pq, const PcgScalars* __restrict__ sc) {
   if (sc->done) return;
+  // rows [r0, r1) hold about 1/gridDim.x of the stored blocks (rows with
+  // contact blocks are longer, and they cluster at the interfaces)
   const int lb = xcd_block();
-  const int rows_per_block = div_up(div_up(N, gridDim.x), kRowsPerPass) * kRowsPerPass;
-  const int r0 = lb * rows_per_block;
-  const int r1 = min(N, r0 + rows_per_block);
+  const long long nnz = urow_ptr[N];
+  const int r0 = first_row_at(urow_ptr, N, (nnz * lb) / gridDim.x);
+  const int r1 = (lb == (int)gridDim.x - 1) ? N : first_row_at(urow_ptr, N, (nnz * (lb + 1)) / gridDim.x);
   const int g = threadIdx.x / kGroup, k = threadIdx.x % kGroup;
   double dot = 0.0;
   for (int rb = r0; rb < r1; rb += kRowsPerPass) {
     const int r = rb + g;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, pr0 = 0.f, pr1 = 0.f, pr2 = 0.f;
     if (r < r1) {
-      const int je = frow_ptr[r + 1];
-      for (int j = frow_ptr[r] + k; j < je; j += kGroup) {
-        const int c = fcol[j];
+      pr0 = p[3LL * r]; pr1 = p[3LL * r + 1]; pr2 = p[3LL * r + 2];
+      const int je = urow_ptr[r + 1];
+      for (int j = urow_ptr[r] + k; j < je; j += kGroup) {
+        const int c = ucol[j];
+        float b[9];
+#pragma unroll
+        for (int m = 0; m < 9; ++m) b[m] = uv[m * st + j];
         const float pc0 = p[3LL * c], pc1 = p[3LL * c + 1], pc2 = p[3LL * c + 2];
-        a0 += fv[j] * pc0 + fv[st + j] * pc1 + fv[2 * st + j] * pc2;
-        a1 += fv[3 * st + j] * pc0 + fv[4 * st + j] * pc1 + fv[5 * st + j] * pc2;
-        a2 += fv[6 * st + j] * pc0 + fv[7 * st + j] * pc1 + fv[8 * st + j] * pc2;
+        a0 += b[0] * pc0 + b[1] * pc1 + b[2] * pc2;
+        a1 += b[3] * pc0 + b[4] * pc1 + b[5] * pc2;
+        a2 += b[6] * pc0 + b[7] * pc1 + b[8] * pc2;
+        float* t = tbuf + 3LL * j;
+        t[0] = b[0] * pr0 + b[3] * pr1 + b[6] * pr2;
+        t[1] = b[1] * pr0 + b[4] * pr1 + b[7] * pr2;
+        t[2] = b[2] * pr0 + b[5] * pr1 + b[8] * pr2;
       }
     }
 #pragma unroll
@@ -109,25 +139,25 @@ k_spmv(int N, const int* __restrict__ frow_ptr, const int* __restrict__ fcol, co
       a2 += __shfl_xor(a2, off, kGroup);
     }
     if (r < r1 && k == 0) {
-      const float pr0 = p[3LL * r], pr1 = p[3LL * r + 1], pr2 = p[3LL * r + 2];
-      const float q0 = pr0 + a0, q1 = pr1 + a1, q2 = pr2 + a2;   // identity diagonal block
-      q[3LL * r] = q0;
-      q[3LL * r + 1] = q1;
-      q[3LL * r + 2] = q2;
-      dot += (double)pr0 * q0 + (double)pr1 * q1 + (double)pr2 * q2;
+      qrow[3LL * r] = pr0 + a0;   // identity diagonal block + upper part
+      qrow[3LL * r + 1] = pr1 + a1;
+      qrow[3LL * r + 2] = pr2 + a2;
+      dot += (double)pr0 * pr0 + (double)pr1 * pr1 + (double)pr2 * pr2 +
+             2.0 * ((double)pr0 * a0 + (double)pr1 * a1 + (double)pr2 * a2);
     }
   }
-  put_part(part_pq, block_sum_all(dot));
+  put_part(part_pq, block_sum_all<kSpmvBlock>(dot));
 }
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kVecBlock)
 k_update(int N, const float* __restrict__ Lf, float* __restrict__ x, float* __restrict__ r,
-         const float* __restrict__ p, const float* __restrict__ q, const double* __restrict__ part_pq, int n_pq,
+         const float* __restrict__ p, const float* __restrict__ qrow, const float* __restrict__ tbuf,
+         const int* __restrict__ tptr, const int* __restrict__ tidx, const double* __restrict__ part_pq, int n_pq,
          double* __restrict__ part_rr, double* __restrict__ part_rt, PcgScalars* __restrict__ sc) {
   if (sc->done) return;
   const int k = sc->iter3;
-  const double rho = sum_parts(part_rr + (k & 1) * kGridVec, gridDim.x);
-  const double pq = sum_parts(part_pq, n_pq);
+  const double rho = sum_parts<kVecBlock>(part_rr + (k & 1) * kGridVec, gridDim.x);
+  const double pq = sum_parts<kVecBlock>(part_pq, n_pq);
   if (blockIdx.x == 0 && threadIdx.x == 0) sc->iter2 = k;
   if (!(pq > 0.0)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -139,9 +169,16 @@ k_update(int N, const float* __restrict__ Lf, float* __restrict__ x, float* __re
   const float alpha = (float)(rho / pq);
   const bool check = ((k + 1) % sc->check_every) == 0;
   double rr = 0.0, rt = 0.0;
-  for (int v = blockIdx.x * kBlock + threadIdx.x; v < N; v += gridDim.x * kBlock) {
+  for (int v = blockIdx.x * kVecBlock + threadIdx.x; v < N; v += gridDim.x * kVecBlock) {
     const long long o = 3LL * v;
-    const float r0 = r[o] - alpha * q[o], r1 = r[o + 1] - alpha * q[o + 1], r2 = r[o + 2] - alpha * q[o + 2];
+    float q0 = qrow[o], q1 = qrow[o + 1], q2 = qrow[o + 2];
+    for (int i = tptr[v]; i < tptr[v + 1]; ++i) {
+      const float* t = tbuf + 3LL * tidx[i];
+      q0 += t[0];
+      q1 += t[1];
+      q2 += t[2];
+    }
+    const float r0 = r[o] - alpha * q0, r1 = r[o + 1] - alpha * q1, r2 = r[o + 2] - alpha * q2;
     x[o] += alpha * p[o];
     x[o + 1] += alpha * p[o + 1];
     x[o + 2] += alpha * p[o + 2];
@@ -157,19 +194,19 @@ k_update(int N, const float* __restrict__ Lf, float* __restrict__ x, float* __re
       rt += t0 * t0 + t1 * t1 + t2 * t2;
     }
   }
-  put_part(part_rr + ((k + 1) & 1) * kGridVec, block_sum_all(rr));
-  put_part(part_rt, block_sum_all(rt));
+  put_part(part_rr + ((k + 1) & 1) * kGridVec, block_sum_all<kVecBlock>(rr));
+  put_part(part_rt, block_sum_all<kVecBlock>(rt));
 }
 
-__global__ void __launch_bounds__(kBlock)
-k_direction(int N, const float* __restrict__ r, float* __restrict__ p, const double* __restrict__ part_rr,
+__global__ void __launch_bounds__(kVecBlock)
+k_direction(int N4, const float* __restrict__ r, float* __restrict__ p, const double* __restrict__ part_rr,
             const double* __restrict__ part_rt, PcgScalars* __restrict__ sc) {
   if (sc->done) return;
   const int k = sc->iter2;
-  const double rho_old = sum_parts(part_rr + (k & 1) * kGridVec, gridDim.x);
-  const double rho_new = sum_parts(part_rr + ((k + 1) & 1) * kGridVec, gridDim.x);
+  const double rho_old = sum_parts<kVecBlock>(part_rr + (k & 1) * kGridVec, gridDim.x);
+  const double rho_new = sum_parts<kVecBlock>(part_rr + ((k + 1) & 1) * kGridVec, gridDim.x);
   const bool check = ((k + 1) % sc->check_every) == 0;
-  const double rt = check ? sum_parts(part_rt, gridDim.x) : 0.0;
+  const double rt = check ? sum_parts<kVecBlock>(part_rt, gridDim.x) : 0.0;
   const bool converged = (check && rt <= sc->tol2 * sc->bb) || rho_new == 0.0;
   const bool capped = (k + 1) >= sc->max_iter;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -181,30 +218,36 @@ k_direction(int N, const float* __restrict__ r, float* __restrict__ p, const dou
   }
   if (converged || capped) return;
   const float beta = (float)(rho_new / rho_old);
-  const long long n3 = 3LL * N;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n3; i += (long long)gridDim.x * kBlock)
-    p[i] = r[i] + beta * p[i];
+  const int nf4 = 3 * (N4 / 4);
+  const float4* r4 = reinterpret_cast<const float4*>(r);
+  float4* p4 = reinterpret_cast<float4*>(p);
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < nf4; i += gridDim.x * kVecBlock) {
+    const float4 rv = r4[i];
+    float4 pv = p4[i];
+    pv.x = rv.x + beta * pv.x; pv.y = rv.y + beta * pv.y; pv.z = rv.z + beta * pv.z; pv.w = rv.w + beta * pv.w;
+    p4[i] = pv;
+  }
 }
 
-__global__ void __launch_bounds__(kBlock)
-k_init(int N, const float* __restrict__ bhat, float* __restrict__ x, float* __restrict__ r, float* __restrict__ p,
+__global__ void __launch_bounds__(kVecBlock)
+k_init(int N4, const float* __restrict__ bhat, float* __restrict__ x, float* __restrict__ r, float* __restrict__ p,
        double* __restrict__ part_rr) {
   double rr = 0.0;
-  const long long n3 = 3LL * N;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n3; i += (long long)gridDim.x * kBlock) {
+  const long long n3 = 3LL * N4;
+  for (long long i = (long long)blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += (long long)gridDim.x * kVecBlock) {
     const float b = bhat[i];
     x[i] = 0.f;
     r[i] = b;
     p[i] = b;
     rr += (double)b * b;
   }
-  put_part(part_rr, block_sum_all(rr));   // iteration 0 reads slot (0 & 1) = 0
+  put_part(part_rr, block_sum_all<kVecBlock>(rr));   // iteration 0 reads slot (0 & 1) = 0
 }
 
 __global__ void __launch_bounds__(kBlock)
 k_init_scalars(const double* __restrict__ bb_part, int nbb, PcgScalars* sc, double tol, int max_iter,
                int check_every) {
-  const double bb = sum_parts(bb_part, nbb);
+  const double bb = sum_parts<kBlock>(bb_part, nbb);
   if (threadIdx.x == 0) {
     sc->bb = bb;
     sc->rr_true = bb;
@@ -220,11 +263,11 @@ k_init_scalars(const double* __restrict__ bb_part, int nbb, PcgScalars* sc, doub
 }
 
 // p = L^{-T} p_hat in FP64 and the per-workgroup max |p|.
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kVecBlock)
 k_finish(int N, const float* __restrict__ Linv, const float* __restrict__ x, double* __restrict__ pout,
          double* __restrict__ part) {
   double m = 0.0;
-  for (int v = blockIdx.x * kBlock + threadIdx.x; v < N; v += gridDim.x * kBlock) {
+  for (int v = blockIdx.x * kVecBlock + threadIdx.x; v < N; v += gridDim.x * kVecBlock) {
     const float* l = Linv + 6LL * v;
     const double x0 = x[3LL * v], x1 = x[3LL * v + 1], x2 = x[3LL * v + 2];
     const double p0 = (double)l[0] * x0 + (double)l[1] * x1 + (double)l[3] * x2;
@@ -235,7 +278,7 @@ k_finish(int N, const float* __restrict__ Linv, const float* __restrict__ x, dou
     pout[3LL * v + 2] = p2;
     m = fmax(m, fmax(fabs(p0), fmax(fabs(p1), fabs(p2))));
   }
-  const double s = block_max_all(m);
+  const double s = block_max_all<kVecBlock>(m);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
@@ -245,16 +288,18 @@ k_finish_scalars(const double* __restrict__ part, int n, const double* __restric
   double m = 0.0, vm = 0.0;
   for (int k = threadIdx.x; k < n; k += kBlock) m = fmax(m, part[k]);
   for (int k = threadIdx.x; k < nviol; k += kBlock) vm = fmax(vm, viol_part[k]);
-  m = block_max_all(m);
-  vm = block_max_all(vm);
+  m = block_max_all<kBlock>(m);
+  vm = block_max_all<kBlock>(vm);
   if (threadIdx.x == 0) {
     sc->stat_pinf = m;
     sc->stat_viol = vm;
   }
 }
 
+inline int pad4(int N) { return (N + 3) & ~3; }
+
 inline int vec_grid(int N) {
-  int g = div_up(N, kBlock);
+  int g = div_up(N, kVecBlock);
   return g < 1 ? 1 : (g > kGridVec ? kGridVec : g);
 }
 
@@ -266,6 +311,8 @@ inline int spmv_grid(int N) {
 
 }  // namespace
 
+// Vectors x, r, p, q, b_hat and the factor L hold pad4(N) nodes; the pad
+// entries are zero and stay zero (the SpMV writes q for the N real rows only).
 // Partials layout: [0, 2*kGridVec) r^T r of two consecutive iterations,
 // [2k, 3k) |L r|^2, [3k, 3k + kGridSpmv) p^T q  (k = kGridVec).
 int pcg_partials_needed(int N) {
@@ -275,29 +322,30 @@ int pcg_partials_needed(int N) {
 
 void launch_pcg_init(int N, const float* bhat, float* x, float* r, float* p, double* part, const double* bb_part,
                      int nbb, PcgScalars* sc, double tol, int max_iter, int check_every, hipStream_t s) {
-  hipLaunchKernelGGL(k_init, dim3(vec_grid(N)), dim3(kBlock), 0, s, N, bhat, x, r, p, part);
+  hipLaunchKernelGGL(k_init, dim3(vec_grid(N)), dim3(kVecBlock), 0, s, pad4(N), bhat, x, r, p, part);
   hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kBlock), 0, s, bb_part, nbb, sc, tol, max_iter, check_every);
 }
 
-void launch_pcg_spmv(int N, const int* frow_ptr, const int* fcol, const float* fvals, long long fstride,
-                     const float* p, float* q, double* part, PcgScalars* sc, hipStream_t s) {
-  hipLaunchKernelGGL(k_spmv, dim3(spmv_grid(N)), dim3(kBlock), 0, s, N, frow_ptr, fcol, fvals, fstride, p, q,
-                     part + 3 * kGridVec, (const PcgScalars*)sc);
+void launch_pcg_spmv(int N, const int* urow_ptr, const int* ucol, const float* uvals, long long ustride,
+                     const float* p, float* qrow, float* tbuf, double* part, PcgScalars* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_spmv, dim3(spmv_grid(N)), dim3(kSpmvBlock), 0, s, N, urow_ptr, ucol, uvals, ustride, p, qrow,
+                     tbuf, part + 3 * kGridVec, (const PcgScalars*)sc);
 }
 
-void launch_pcg_vector_ops(int N, const float* Lf, float* x, float* r, float* p, const float* q, double* part,
-                           PcgScalars* sc, hipStream_t s) {
+void launch_pcg_vector_ops(int N, const float* Lf, float* x, float* r, float* p, const float* qrow,
+                           const float* tbuf, const int* tptr, const int* tidx, double* part, PcgScalars* sc,
+                           hipStream_t s) {
   const int gv = vec_grid(N);
-  hipLaunchKernelGGL(k_update, dim3(gv), dim3(kBlock), 0, s, N, Lf, x, r, (const float*)p, q,
+  hipLaunchKernelGGL(k_update, dim3(gv), dim3(kVecBlock), 0, s, N, Lf, x, r, (const float*)p, qrow, tbuf, tptr, tidx,
                      (const double*)(part + 3 * kGridVec), spmv_grid(N), part, part + 2 * kGridVec, sc);
-  hipLaunchKernelGGL(k_direction, dim3(gv), dim3(kBlock), 0, s, N, (const float*)r, p, (const double*)part,
+  hipLaunchKernelGGL(k_direction, dim3(gv), dim3(kVecBlock), 0, s, pad4(N), (const float*)r, p, (const double*)part,
                      (const double*)(part + 2 * kGridVec), sc);
 }
 
 void launch_pcg_finish(int N, const float* Linv, const float* x, double* pout, double* part, PcgScalars* sc,
                        const double* viol_part, int nviol, hipStream_t s) {
   const int g = vec_grid(N);
-  hipLaunchKernelGGL(k_finish, dim3(g), dim3(kBlock), 0, s, N, Linv, x, pout, part);
+  hipLaunchKernelGGL(k_finish, dim3(g), dim3(kVecBlock), 0, s, N, Linv, x, pout, part);
   hipLaunchKernelGGL(k_finish_scalars, dim3(1), dim3(kBlock), 0, s, (const double*)part, g, viol_part, nviol, sc);
 }
 
