@@ -14,6 +14,8 @@ from __future__ import annotations
 
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -30,21 +32,21 @@ def log(msg):
 
 
 def spmv_bytes(N, nnzb):
-    """Algorithmic bytes of one launch of k_spmv, the first phase of the
-    symmetric product: each of the nnzb - N stored upper off-diagonal blocks
-    is read once (36 B FP32 values + 4 B column) and its transposed product
-    written once (12 B); one row pointer per row; p read once (12 B/node);
-    q_row written once (12 B/node)."""
+    """Algorithmic bytes of one launch of k_spmv (symmetric SpMV with the
+    direction update fused in): each of the n_off = nnzb - N stored upper
+    off-diagonal blocks once (36 B FP32 values + 4 B column) and its entry of
+    the transpose index (8 B: block index, source row); two row pointers per
+    row (8 B); r and the previous p read once (24 B/node); the new p and q
+    written once (24 B/node).  The second read of each block (the lower half,
+    gathered through the transpose index) is not counted."""
     n_off = nnzb - N
-    return 52 * n_off + 4 * (N + 1) + 24 * N
+    return 48 * n_off + 8 * (N + 1) + 48 * N
 
 
 def pcg_iteration_bytes(N, nnzb):
-    """k_spmv + k_update (q_row, transpose pointer, x, p, r, L read, x and r
-    written: 100 B/node; transpose index and transposed products read:
-    16 B/block) + k_direction (r, p read, p written: 36 B/node)."""
-    n_off = nnzb - N
-    return spmv_bytes(N, nnzb) + 16 * n_off + 100 * N + 36 * N
+    """k_spmv + k_update (p, q, x, r and the factor L read, x and r written:
+    96 B/node)."""
+    return spmv_bytes(N, nnzb) + 96 * N
 
 
 def cpu_baseline(sc, gpu_iters, frac):
@@ -93,6 +95,74 @@ def cpu_baseline(sc, gpu_iters, frac):
                        f"each scaled by 1/{frac:g}, PCG x {gpu_iters} GPU iterations")}
 
 
+def serve_trace(server, reqs, arrivals, timeout=600.0):
+    """Submit reqs[i] at arrivals[i] seconds after the start (Poisson trace),
+    poll completions; returns per-request latency (done - submit, s), the
+    span from the first submit to the last completion, and statuses."""
+    from paper_2512_12151_amd import bfal
+    n = len(reqs)
+    lat = np.zeros(n)
+    status = np.zeros(n, dtype=int)
+    first, last = None, 0.0
+    done = 0
+    k = 0
+    t0 = time.perf_counter()
+    while done < n:
+        now = time.perf_counter() - t0
+        while k < n and arrivals[k] <= now:
+            server.submit(k, reqs[k])
+            k += 1
+        for i in server.poll():
+            _, st, times, rs = server.result(i)
+            lat[i] = times["t_done"] - times["t_submit"]
+            status[i] = rs
+            first = times["t_submit"] if first is None else min(first, times["t_submit"])
+            last = max(last, times["t_done"])
+            done += 1
+        if now > timeout:
+            raise RuntimeError("serving trace did not finish")
+        nxt = arrivals[k] - (time.perf_counter() - t0) if k < n else 2e-4
+        time.sleep(min(max(nxt, 0.0), 2e-4))
+    return lat, last - first, status
+
+
+def run_serve(n_req, seed=5):
+    """C5: requests of two stacked cubes (tets ~ LogU[2k, 300k]), Poisson
+    arrivals at 0.8 x the one-at-a-time service rate (measured first on the
+    first 32 requests), served by the continuous-batching server and by the
+    same engine one request at a time, on the same trace."""
+    import torch
+
+    import scenes
+    from paper_2512_12151_amd import bfal
+    log(f"serve: generating {n_req} requests")
+    reqs = [scenes.serve_request(i) for i in range(n_req)]
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.9 * free)
+    # service time one at a time (back to back, no queueing delay counted)
+    cal = min(32, n_req)
+    sv = bfal.Server(0, hbm_budget=budget, max_active=1, iters_per_round=8)
+    lat, span, _ = serve_trace(sv, reqs[:cal], np.zeros(cal))
+    sv.close()
+    service = span / cal
+    rate = 0.8 / service
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    arrivals -= arrivals[0]
+    out = {"requests": n_req, "arrival_rate_per_s": round(rate, 2),
+           "one_at_a_time_service_ms": round(service * 1e3, 3), "hbm_budget_bytes": budget}
+    for name, max_active in (("batched", 64), ("one_at_a_time", 1)):
+        sv = bfal.Server(0, hbm_budget=budget, max_active=max_active, iters_per_round=8)
+        lat, span, status = serve_trace(sv, reqs, arrivals)
+        sv.close()
+        out[name] = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                     "mean_ms": round(float(lat.mean()) * 1e3, 3),
+                     "steps_per_s": round(n_req / span, 2), "errors": int((status < 0).sum())}
+        log(f"serve {name}: {out[name]}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +174,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-iter", type=int, default=200000,
                     help="PCG iteration cap (lower it only for counter-collection runs)")
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="requests of the serving trace (0 skips the serving measurement)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain device-to-device copy of 512 MiB (bandwidth ceiling and the reference "
                          "for scaling HBM counters) and exit")
@@ -201,11 +273,13 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": sb, "avg_ms": round(spmv_ms, 5), "launches_timed": tst["spmv_timed"]},
     }
+    pb.close()
+    if args.serve_requests > 0:
+        line["serve"] = run_serve(args.serve_requests)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         line["cpu_baseline"] = cpu_baseline(sc, int(round(it_mean)), args.cpu_sample)
     print(json.dumps(line), flush=True)
-    pb.close()
     ctx.close()
 
 

@@ -86,26 +86,34 @@ typedef struct {
 } bf_constraint_desc;
 
 typedef struct {
-  double tol;            /* stop at |r|_2 <= tol |b|_2 (unpreconditioned, FP64 norms) */
+  double tol;            /* stop at |r|_2 <= tol |b|_2 (unpreconditioned, FP64 norms); in BF16 mode the
+                            relative tolerance of each inner solve against its own right-hand side */
   int32_t max_iter;      /* PCG iteration cap (BF_WARN_PCG_MAXITER when hit) */
-  int32_t precision;     /* BF_PREC_FP32, or BF_PREC_BF16_REFINE */
-  double refine_tol;     /* BF16 mode: outer refinement stops at this relative residual */
+  int32_t precision;     /* BF_PREC_FP32, or BF_PREC_BF16_REFINE: the scaled blocks are also stored
+                            in BF16 (round to nearest even); each inner PCG runs on them with FP32
+                            vectors and FP64 dot products; the outer loop keeps x in FP64 and forms
+                            r = b - H x with the FP32 blocks in FP64 (iterative refinement) */
+  double refine_tol;     /* BF16 mode: outer refinement stops at |b - H p|_2 <= refine_tol |b|_2 */
   int32_t poll_every;    /* host polls the device convergence flag every this many iterations */
   int32_t check_every;   /* the true residual norm is formed every this many iterations */
   int32_t time_spmv;     /* >0: time the SpMV launches of the first this-many PCG iterations
                             with HIP events (reported in bf_step_stats); 0: no per-kernel events */
+  int32_t max_sweeps;    /* BF16 mode: at most this many inner solves (0 means 30) */
 } bf_solve_opts;
 
 typedef struct {
   int32_t pcg_iters;         /* inner PCG iterations (summed over sweeps in BF16 mode) */
-  int32_t refine_sweeps;     /* outer refinement sweeps (BF16 mode), else 0 */
-  double rel_residual;       /* final |b - H p|_2 / |b|_2 as tracked by the solver (FP64) */
+  int32_t refine_sweeps;     /* inner solves of the refinement (BF16 mode), else 0 */
+  double rel_residual;       /* final |b - H p|_2 / |b|_2 as tracked by the solver (FP64); in BF16
+                                mode the FP64 residual of the FP32-stored system */
   double newton_inf_over_h;  /* |p|_inf / h (Section 6.1 residual-style stat), FP64 */
   double max_violation;      /* max_i max(0, -c_i(x_hat)), FP64 */
   int64_t nnzb;              /* stored upper 3x3 blocks, diagonal included */
   double ms_lin, ms_pattern, ms_assemble, ms_pcg;  /* device time per phase */
   int32_t spmv_timed;        /* SpMV launches timed (see bf_solve_opts.time_spmv) */
   double ms_spmv_avg;        /* their average duration (event to event, ms) */
+  double sweep_rel_residual[16]; /* BF16 mode: |b - H x_s|_2 / |b|_2 before inner solve s (FP64;
+                                    entry 0 is 1), then after the last; unused entries 0 */
 } bf_step_stats;
 
 /* ---------------------------------------------------------------- context */
@@ -163,6 +171,54 @@ bf_status bf_get_blocks(bf_problem* pb, float* vals);
 /* Device bytes a problem of this size holds (mesh, state, constraints,
  * pattern, blocks and solver vectors), for admission control. */
 bf_status bf_footprint_bytes(int32_t n_nodes, int32_t n_tets, int32_t n_constraints, size_t* out);
+
+/* ---------------------------------------------------------------- serving */
+/* A server solves independent Newton-step requests (each: a mesh, its state
+ * and its active constraint set; the same operation as bf_newton_step, FP32
+ * mode) with continuous batching on one device.  Two threads of the library
+ * work in the background: an admission thread takes submitted requests in
+ * arrival order and admits the head of the queue when its footprint
+ * (bf_footprint_bytes) fits beside the admitted ones in hbm_budget and fewer
+ * than max_active are admitted, then assembles it on its own stream; a batch
+ * thread runs the PCG of all admitted requests in shared launches (a
+ * block-diagonal system with per-request scalars, iters_per_round iterations
+ * between scheduling points), retires finished requests and frees their
+ * budget.  Requests arriving while others are on the GPU join the batch as
+ * slots and memory free up.  max_active = 1 serves one request at a time.
+ * Threads: submit, poll, result and stats may be called from any one thread;
+ * the server uses its own streams, so the calling thread's context is free. */
+typedef struct bf_server bf_server;
+typedef struct {
+  size_t hbm_budget;         /* device bytes the admitted requests may hold (footprint estimates), > 0 */
+  int32_t max_active;        /* at most this many admitted requests, >= 1 */
+  int32_t iters_per_round;   /* batched PCG iterations between scheduling points, >= 1 */
+} bf_server_opts;
+typedef struct {
+  double t_submit, t_admit, t_done;  /* seconds on bf_clock_now()'s clock */
+} bf_request_times;
+
+/* A monotonic clock (seconds) shared with the request time stamps. */
+double bf_clock_now(void);
+bf_status bf_server_create(int32_t device, const bf_server_opts* opts, bf_server** out);
+/* Copies the request (host memory only) and queues it; returns at once.
+ * req_id must not be queued or finished-but-untaken already.  opts->precision
+ * must be BF_PREC_FP32.  Invalid meshes or constraints are reported through
+ * the request's status (bf_server_result), not here. */
+bf_status bf_server_submit(bf_server* srv, int64_t req_id, const bf_mesh_desc* mesh, const double* x,
+                           const double* x_hat, const double* x_tilde, double dt,
+                           const bf_constraint_desc* cons, const bf_solve_opts* opts);
+/* Non-blocking: writes up to cap ids of requests finished since the last poll. */
+bf_status bf_server_poll(bf_server* srv, int64_t* done_ids, int32_t cap, int32_t* n_done);
+/* Takes a finished request's result: p_out [n_nodes][3] host doubles, stats,
+ * times and its status (a bf_status: BF_OK, a warning or an error such as
+ * BF_ERR_OOM when its footprint exceeds the budget).  Any output may be NULL.
+ * BF_ERR_STATE if the id is not finished. */
+bf_status bf_server_result(bf_server* srv, int64_t req_id, double* p_out, bf_step_stats* stats,
+                           bf_request_times* times, int32_t* req_status);
+/* Queue length, admitted requests and their footprint sum. */
+bf_status bf_server_stats(bf_server* srv, int32_t* n_pending, int32_t* n_active, size_t* used_bytes);
+/* Stops the threads (requests still queued or running are dropped) and frees everything. */
+void bf_server_destroy(bf_server* srv);
 
 #ifdef __cplusplus
 }

@@ -36,23 +36,34 @@ class bf_constraint_desc(C.Structure):
 class bf_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
                 ("refine_tol", C.c_double), ("poll_every", C.c_int32), ("check_every", C.c_int32),
-                ("time_spmv", C.c_int32)]
+                ("time_spmv", C.c_int32), ("max_sweeps", C.c_int32)]
 
 
 class bf_step_stats(C.Structure):
     _fields_ = [("pcg_iters", C.c_int32), ("refine_sweeps", C.c_int32), ("rel_residual", C.c_double),
                 ("newton_inf_over_h", C.c_double), ("max_violation", C.c_double), ("nnzb", C.c_int64),
                 ("ms_lin", C.c_double), ("ms_pattern", C.c_double), ("ms_assemble", C.c_double),
-                ("ms_pcg", C.c_double), ("spmv_timed", C.c_int32), ("ms_spmv_avg", C.c_double)]
+                ("ms_pcg", C.c_double), ("spmv_timed", C.c_int32), ("ms_spmv_avg", C.c_double),
+                ("sweep_rel_residual", C.c_double * 16)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["sweep_rel_residual"] = [float(v) for v in self.sweep_rel_residual][: self.refine_sweeps + 1]
+        return d
 
 
 class BfalError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+class bf_server_opts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int32), ("iters_per_round", C.c_int32)]
+
+
+class bf_request_times(C.Structure):
+    _fields_ = [("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
 
 
 _lib = None
@@ -73,6 +84,17 @@ _PROTOS = [
     ("bf_get_pattern", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("bf_get_blocks", C.c_int, [C.c_void_p, C.c_void_p]),
     ("bf_footprint_bytes", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    ("bf_clock_now", C.c_double, []),
+    ("bf_server_create", C.c_int, [C.c_int32, C.POINTER(bf_server_opts), C.POINTER(C.c_void_p)]),
+    ("bf_server_submit", C.c_int, [C.c_void_p, C.c_int64, C.POINTER(bf_mesh_desc), C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_double, C.POINTER(bf_constraint_desc),
+                                   C.POINTER(bf_solve_opts)]),
+    ("bf_server_poll", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)]),
+    ("bf_server_result", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(bf_step_stats),
+                                   C.POINTER(bf_request_times), C.POINTER(C.c_int32)]),
+    ("bf_server_stats", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_size_t)]),
+    ("bf_server_destroy", None, [C.c_void_p]),
 ]
 
 EXPORTED = [p[0] for p in _PROTOS]
@@ -187,10 +209,10 @@ class Problem:
         self.n_c = int(pt.shape[0] + ee.shape[0])
 
     def newton_step(self, tol=1e-5, max_iter=20000, precision=BF_PREC_FP32, refine_tol=1e-6, poll_every=16,
-                    check_every=1, time_spmv=0, out=None):
+                    check_every=1, time_spmv=0, max_sweeps=0, out=None):
         """Returns (p [N,3] (numpy, or `out` when a device tensor is passed), stats dict, status)."""
         o = bf_solve_opts(float(tol), int(max_iter), int(precision), float(refine_tol), int(poll_every),
-                          int(check_every), int(time_spmv))
+                          int(check_every), int(time_spmv), int(max_sweeps))
         p = np.empty((self.N, 3), dtype=np.float64) if out is None else out
         s = bf_step_stats()
         st = self.ctx.check(lib().bf_newton_step(self.h, C.byref(o), _ptr(p), _mem(p), C.byref(s)))
@@ -240,3 +262,77 @@ def footprint_bytes(n_nodes, n_tets, n_constraints):
     if st != BF_OK:
         raise BfalError(st, "bf_footprint_bytes failed")
     return int(out.value)
+
+
+def clock_now():
+    """The library's monotonic clock (seconds), the one request times use."""
+    return float(lib().bf_clock_now())
+
+
+class Server:
+    """Continuous-batching server (bf_server_*): submit host-memory requests,
+    poll for finished ids, take results.  Arguments are marshalled only."""
+
+    def __init__(self, device=0, hbm_budget=8 << 30, max_active=64, iters_per_round=8):
+        o = bf_server_opts(int(hbm_budget), int(max_active), int(iters_per_round))
+        self.h = C.c_void_p()
+        st = lib().bf_server_create(int(device), C.byref(o), C.byref(self.h))
+        if st != BF_OK:
+            raise BfalError(st, "bf_server_create failed")
+        self._n = {}
+
+    def submit(self, req_id, sc, tol=1e-5, max_iter=20000, check_every=1):
+        """Queue the scene dict `sc` (the scenes module's layout) as request req_id."""
+        tets, rest = _host(sc["tets"], np.int32), _host(sc["rest"], np.float64)
+        E, nu, rho = (_host(sc[k], np.float64) for k in ("E", "nu", "rho"))
+        fixed = None if sc.get("fixed") is None else _host(sc["fixed"], np.uint8)
+        x, xh, xt = (_host(sc[k], np.float64) for k in ("x", "x_hat", "x_tilde"))
+        pt, ee = _host(sc["pt"], np.int32).reshape(-1, 4), _host(sc["ee"], np.int32).reshape(-1, 4)
+        lam = _host(sc["lam"], np.float64)
+        gamma = None if sc.get("gamma") is None else _host(sc["gamma"], np.float64)
+        m = bf_mesh_desc(len(rest), len(tets), _ptr(tets), _ptr(rest), _ptr(E), _ptr(nu), _ptr(rho), _ptr(fixed))
+        d = bf_constraint_desc(len(pt), len(ee), _ptr(pt) if len(pt) else None, _ptr(ee) if len(ee) else None,
+                               _ptr(lam) if len(lam) else None,
+                               _ptr(gamma) if gamma is not None and len(gamma) else None,
+                               float(sc["kappa"]), float(sc["delta"]))
+        o = bf_solve_opts(float(tol), int(max_iter), BF_PREC_FP32, 1e-6, 16, int(check_every), 0, 0)
+        st = lib().bf_server_submit(self.h, int(req_id), C.byref(m), _ptr(x), _ptr(xh), _ptr(xt),
+                                    float(sc["dt"]), C.byref(d), C.byref(o))
+        if st != BF_OK:
+            raise BfalError(st, "bf_server_submit failed")
+        self._n[int(req_id)] = len(rest)
+
+    def poll(self, cap=1024):
+        ids = (C.c_int64 * cap)()
+        n = C.c_int32()
+        st = lib().bf_server_poll(self.h, ids, int(cap), C.byref(n))
+        if st != BF_OK:
+            raise BfalError(st, "bf_server_poll failed")
+        return [int(ids[i]) for i in range(n.value)]
+
+    def result(self, req_id):
+        """(p [N,3], stats dict, times dict, status) of a finished request."""
+        n = self._n.pop(int(req_id))
+        p = np.empty((n, 3), np.float64)
+        s, t, rs = bf_step_stats(), bf_request_times(), C.c_int32()
+        st = lib().bf_server_result(self.h, int(req_id), p.ctypes.data, C.byref(s), C.byref(t), C.byref(rs))
+        if st != BF_OK:
+            raise BfalError(st, "bf_server_result failed")
+        times = {"t_submit": t.t_submit, "t_admit": t.t_admit, "t_done": t.t_done}
+        return p, s.as_dict(), times, int(rs.value)
+
+    def stats(self):
+        a, b, u = C.c_int32(), C.c_int32(), C.c_size_t()
+        lib().bf_server_stats(self.h, C.byref(a), C.byref(b), C.byref(u))
+        return {"pending": a.value, "active": b.value, "used_bytes": u.value}
+
+    def close(self):
+        if self.h:
+            lib().bf_server_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -5,101 +5,220 @@
 //   assembly (G, H, DBC, block-Jacobi factors) -> scaled off-diagonal blocks
 //   -> PCG (device-side convergence flag, polled every poll_every iterations)
 //   -> p = L^{-T} p_hat and FP64 stats.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <new>
 #include <vector>
 
-#include "common.h"
+#include "problem.h"
 
 using namespace bfal;
 
-struct bf_context {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  std::string err;
-};
+namespace bfal {
 
-struct bf_problem {
-  bf_context* ctx = nullptr;
-  int N = 0, T = 0;
-  // mesh (per-mesh setup)
-  DevBuf tets, rest, E, nu, rho, fixed, Dminv9, vol, mu, lam, mass;
+bf_status problem_init(bf_context* c, bf_problem* pb, const bf_mesh_desc* m, int32_t mem) {
+  if (!m || !m->tets || !m->rest || !m->E || !m->nu || !m->rho)
+    return fail(c, BF_ERR_INVALID_ARG, "mesh descriptor or one of its arrays is NULL");
+  if (m->n_nodes <= 0 || m->n_tets <= 0) return fail(c, BF_ERR_INVALID_ARG, "n_nodes and n_tets must be positive");
+  if ((long long)m->n_tets * 10 >= (1LL << 31) || (long long)m->n_nodes * 3 >= (1LL << 31))
+    return fail(c, BF_ERR_INVALID_ARG, "mesh too large for 32-bit slot indices");
+  if (mem != BF_MEM_HOST && mem != BF_MEM_DEVICE) return fail(c, BF_ERR_INVALID_ARG, "mem must be BF_MEM_HOST or BF_MEM_DEVICE");
+  const int N = m->n_nodes, T = m->n_tets;
+  if (mem == BF_MEM_HOST) {
+    for (long long e = 0; e < T; ++e) {
+      const int32_t* t = m->tets + 4 * e;
+      for (int a = 0; a < 4; ++a)
+        if (t[a] < 0 || t[a] >= N) return fail(c, BF_ERR_INVALID_ARG, "tet vertex index out of range");
+      if (t[0] == t[1] || t[0] == t[2] || t[0] == t[3] || t[1] == t[2] || t[1] == t[3] || t[2] == t[3])
+        return fail(c, BF_ERR_INVALID_ARG, "tet with a repeated vertex");
+      if (!(m->E[e] > 0.0) || !std::isfinite(m->E[e]) || !(m->nu[e] > -1.0 && m->nu[e] < 0.5) ||
+          !(m->rho[e] > 0.0) || !std::isfinite(m->rho[e]))
+        return fail(c, BF_ERR_INVALID_ARG, "invalid material value");
+    }
+    if (!finite_all(m->rest, 3LL * N)) return fail(c, BF_ERR_INVALID_ARG, "non-finite rest position");
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  pb->ctx = c;
+  pb->N = N;
+  pb->T = T;
+  pb->has_state = false;
+  pb->stepped = false;
+  pb->cap_nnzb = 0;
+  hipStream_t s = c->stream;
+  ALLOC(c, pb->tets, 16LL * T);
+  ALLOC(c, pb->rest, 24LL * N);
+  ALLOC(c, pb->E, 8LL * T);
+  ALLOC(c, pb->nu, 8LL * T);
+  ALLOC(c, pb->rho, 8LL * T);
+  ALLOC(c, pb->fixed, N);
+  ALLOC(c, pb->Dminv9, 36LL * T);
+  ALLOC(c, pb->vol, 4LL * T);
+  ALLOC(c, pb->mu, 4LL * T);
+  ALLOC(c, pb->lam, 4LL * T);
+  ALLOC(c, pb->mass, 4LL * N);
+  ALLOC(c, pb->flags, 64);
+  HIPCHK(c, hipMemcpyAsync(pb->tets.p, m->tets, 16LL * T, kind_in(mem), s));
+  HIPCHK(c, hipMemcpyAsync(pb->rest.p, m->rest, 24LL * N, kind_in(mem), s));
+  HIPCHK(c, hipMemcpyAsync(pb->E.p, m->E, 8LL * T, kind_in(mem), s));
+  HIPCHK(c, hipMemcpyAsync(pb->nu.p, m->nu, 8LL * T, kind_in(mem), s));
+  HIPCHK(c, hipMemcpyAsync(pb->rho.p, m->rho, 8LL * T, kind_in(mem), s));
+  if (m->fixed) {
+    HIPCHK(c, hipMemcpyAsync(pb->fixed.p, m->fixed, N, kind_in(mem), s));
+  } else {
+    std::vector<uint8_t> z(N, 0);
+    HIPCHK(c, hipMemcpyAsync(pb->fixed.p, z.data(), N, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  int* flags = pb->flags.as<int>();
+  fill_int(flags, 0, 16, s);
+  const int4* tets = pb->tets.as<int4>();
+  launch_check_tets(tets, T, N, flags, s);
+  int hflags = 0;
+  bf_status r0 = read_flags(pb, &hflags);
+  if (r0 != BF_OK) return r0;
+  if (hflags) return flags_to_status(c, hflags);
+  launch_rest_geometry(tets, pb->rest.as<double>(), pb->E.as<double>(), pb->nu.as<double>(), T,
+                       pb->Dminv9.as<float>(), pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), flags, s);
+  // static elastic pattern: pair keys bucketed by row, sorted and unique per row
+  const long long npairs = 6LL * T;
+  const long long nslots_tmp = (long long)N + 1;
+  ALLOC(c, pb->scratch_int, 4LL * (3 * nslots_tmp + npairs + 16));
+  int* cnt = pb->scratch_int.as<int>();
+  int* kptr = cnt + nslots_tmp;
+  int* cursor = kptr + nslots_tmp;
+  int* keys = cursor + nslots_tmp;
+  ALLOC(c, pb->scan_tmp, 4LL * scan_tmp_ints(10LL * T + N + 16));
+  int* tmp = pb->scan_tmp.as<int>();
+  fill_int(cnt, 0, N, s);
+  launch_elastic_pair_count(tets, T, cnt, s);
+  scan_exclusive(cnt, kptr, N, kptr + N, tmp, s);
+  fill_int(cursor, 0, N, s);
+  launch_elastic_pair_fill(tets, T, kptr, cursor, keys, s);
+  ALLOC(c, pb->erow_ptr, 4LL * (N + 1));
+  int* ucount = cnt;  // reuse
+  launch_row_unique(keys, kptr, N, ucount, s);
+  int* erow = pb->erow_ptr.as<int>();
+  scan_exclusive(ucount, erow, N, erow + N, tmp, s);
   int nnzb_e = 0;
-  DevBuf erow_ptr, ecol, emap, ecptr, elist, epos, staging;
-  // state
-  DevBuf x, xh, xt;
-  double dt = 0.0;
-  bool has_state = false;
-  // constraints
-  int n_pt = 0, n_ee = 0, n_c = 0;
-  DevBuf cids, clam, cgam;
-  double kappa = 1.0, delta = 0.0;
-  // per-step buffers
-  DevBuf cn, cw, cg, ch, viol_part;
-  DevBuf vcnt, vptr, vinc;
-  DevBuf ccount, cptr, cand, ucount, row_ptr, col, eslot;
-  DevBuf vals, grad, Lf, Linv, bhat, bb_part, ovals, ocol, orow_ptr, lcnt, lptr, lsrc, tidx, tbuf;
-  DevBuf xs, r, p, q, part, scal, pout, flags, scan_tmp, scratch_int;
-  long long cap_nnzb = 0, cap_cand = 0;
-  PcgScalars* host_sc = nullptr;
-  bool stepped = false;
-  long long nnzb_last = 0;
-  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  std::vector<hipEvent_t> tev;   // SpMV timing events (pairs), created on demand
-};
-
-namespace {
-
-bf_status fail(bf_context* c, bf_status st, const std::string& msg) {
-  if (c) c->err = msg;
-  return st;
-}
-
-#define HIPCHK(ctx, call)                                                                  \
-  do {                                                                                     \
-    hipError_t e_ = (call);                                                                \
-    if (e_ != hipSuccess)                                                                  \
-      return fail((ctx), e_ == hipErrorOutOfMemory ? BF_ERR_OOM : BF_ERR_HIP,              \
-                  std::string(#call) + ": " + hipGetErrorString(e_));                      \
-  } while (0)
-
-#define ALLOC(ctx, buf, bytes)                                                             \
-  do {                                                                                     \
-    hipError_t e_ = (buf).ensure(bytes);                                                   \
-    if (e_ != hipSuccess)                                                                  \
-      return fail((ctx), BF_ERR_OOM, std::string("device allocation of ") +                \
-                  std::to_string((size_t)(bytes)) + " bytes failed");                      \
-  } while (0)
-
-hipMemcpyKind kind_in(int32_t mem) { return mem == BF_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
-hipMemcpyKind kind_out(int32_t mem) { return mem == BF_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
-
-bool finite_all(const double* a, long long n) {
-  for (long long i = 0; i < n; ++i)
-    if (!std::isfinite(a[i])) return false;
-  return true;
-}
-
-bf_status flags_to_status(bf_context* c, int flags) {
-  if (flags & FLAG_BAD_INDEX) return fail(c, BF_ERR_INVALID_ARG, "index out of range or repeated vertex in a tet");
-  if (flags & FLAG_BAD_VALUE) return fail(c, BF_ERR_INVALID_ARG, "invalid value (degenerate rest tet, material, lambda or gamma)");
-  if (flags & FLAG_DEGENERATE)
-    return fail(c, BF_ERR_DEGENERATE_CONSTRAINT, "degenerate constraint: d(x) <= 0, repeated vertex or parallel edge pair");
-  if (flags & FLAG_INVERTED) return fail(c, BF_ERR_INVERTED_ELEMENT, "inverted element: det F(x_hat) <= 0");
-  if (flags & (FLAG_NOT_SPD | FLAG_BREAKDOWN)) return fail(c, BF_ERR_NOT_SPD, "matrix not SPD (diagonal block or PCG breakdown)");
+  HIPCHK(c, hipMemcpyAsync(&nnzb_e, erow + N, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  pb->nnzb_e = nnzb_e;
+  ALLOC(c, pb->ecol, 4LL * nnzb_e);
+  launch_row_write(keys, kptr, N, erow, pb->ecol.as<int>(), s);
+  // (tet, pair) -> elastic slot, and each slot's contributions in (tet, pair) order
+  ALLOC(c, pb->emap, 40LL * T);
+  launch_emap(tets, T, erow, pb->ecol.as<int>(), pb->emap.as<int>(), s);
+  ALLOC(c, pb->ecptr, 4LL * (nnzb_e + 1));
+  ALLOC(c, pb->elist, 40LL * T);
+  ALLOC(c, pb->epos, 40LL * T);
+  // nnzb_e <= N + 6T, so the scratch buffer already holds nnzb_e counters
+  int* scnt = pb->scratch_int.as<int>();
+  int* ecptr = pb->ecptr.as<int>();
+  fill_int(scnt, 0, nnzb_e, s);
+  launch_slot_count(pb->emap.as<int>(), 10LL * T, scnt, s);
+  scan_exclusive(scnt, ecptr, nnzb_e, ecptr + nnzb_e, tmp, s);
+  fill_int(scnt, 0, nnzb_e, s);
+  launch_slot_fill(pb->emap.as<int>(), 10LL * T, ecptr, scnt, pb->elist.as<int>(), s);
+  sort_segments(pb->elist.as<int>(), ecptr, nnzb_e, s);
+  launch_inverse_positions(pb->elist.as<int>(), 10LL * T, pb->epos.as<int>(), s);
+  launch_mass(ecptr, pb->elist.as<int>(), erow, pb->vol.as<float>(), pb->rho.as<double>(), N, pb->mass.as<float>(), s);
+  ALLOC(c, pb->staging, 360LL * T);
+  r0 = read_flags(pb, &hflags);
+  if (r0 != BF_OK) return r0;
+  if (hflags) return flags_to_status(c, hflags);
+  for (auto& e : pb->ev)
+    if (!e) HIPCHK(c, hipEventCreate(&e));
+  if (!pb->host_sc) HIPCHK(c, hipHostMalloc((void**)&pb->host_sc, sizeof(PcgScalars), hipHostMallocDefault));
+  ALLOC(c, pb->scal, sizeof(PcgScalars));
+  HIPCHK(c, hipMemsetAsync(pb->scal.p, 0, sizeof(PcgScalars), s));
+  HIPCHK(c, hipStreamSynchronize(s));
   return BF_OK;
 }
 
-bf_status read_flags(bf_problem* pb, int* out) {
+}  // namespace bfal
+
+namespace bfal {
+
+bf_status step_assemble(bf_problem* pb, bool bf16) {
   bf_context* c = pb->ctx;
-  HIPCHK(c, hipMemcpyAsync(out, pb->flags.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  const int N = pb->N, T = pb->T, n = pb->n_c;
+  int* flags = pb->flags.as<int>();
+  int* tmp = pb->scan_tmp.as<int>();
+  const int4* ids = pb->cids.as<int4>();
+  fill_int(flags, 0, 16, s);
+  HIPCHK(c, hipEventRecord(pb->ev[0], s));
+  // (1) constraint linearization at x and AL factors at x_hat
+  fill_int(reinterpret_cast<int*>(pb->viol_part.p), 0, 2, s);
+  launch_contact_lin(ids, pb->n_pt, n, pb->x.as<double>(), pb->xh.as<double>(), pb->clam.as<double>(),
+                     pb->cgam.as<double>(), pb->kappa, pb->delta, pb->cn.as<float>(), pb->cw.as<float>(),
+                     pb->cg.as<float>(), pb->ch.as<float>(), pb->viol_part.as<double>(), flags, s);
+  HIPCHK(c, hipEventRecord(pb->ev[1], s));
+  // (2) merged pattern: vertex -> constraint incidence, candidates, unique rows
+  int* vcnt = pb->vcnt.as<int>();
+  int* vptr = pb->vptr.as<int>();
+  fill_int(vcnt, 0, N, s);
+  launch_vertex_incidence_count(ids, n, vcnt, s);
+  scan_exclusive(vcnt, vptr, N, vptr + N, tmp, s);
+  fill_int(vcnt, 0, N, s);
+  launch_vertex_incidence_fill(ids, n, vptr, vcnt, pb->vinc.as<int>(), s);
+  sort_segments(pb->vinc.as<int>(), vptr, N, s);
+  int* cptr = pb->cptr.as<int>();
+  launch_candidate_count(pb->erow_ptr.as<int>(), vptr, pb->vinc.as<int>(), ids, N, pb->ccount.as<int>(), s);
+  scan_exclusive(pb->ccount.as<int>(), cptr, N, cptr + N, tmp, s);
+  launch_candidate_fill(pb->erow_ptr.as<int>(), pb->ecol.as<int>(), vptr, pb->vinc.as<int>(), ids, N, cptr,
+                        pb->cand.as<int>(), pb->ucount.as<int>(), s);
+  int* row_ptr = pb->row_ptr.as<int>();
+  scan_exclusive(pb->ucount.as<int>(), row_ptr, N, row_ptr + N, tmp, s);
+  launch_merged_write(pb->cand.as<int>(), cptr, row_ptr, pb->erow_ptr.as<int>(), pb->ecol.as<int>(), N,
+                      pb->col.as<int>(), pb->eslot.as<int>(), s);
+  HIPCHK(c, hipEventRecord(pb->ev[2], s));
+  // (3) assembly
+  const float h2 = (float)(pb->dt * pb->dt);
+  launch_elastic(pb->tets.as<int4>(), T, pb->rest.as<double>(), pb->xh.as<double>(), pb->Dminv9.as<float>(),
+                 pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), h2, pb->epos.as<int>(),
+                 pb->staging.as<float>(), flags, s);
+  launch_assemble_rows(N, row_ptr, pb->col.as<int>(), pb->eslot.as<int>(), pb->ecptr.as<int>(), pb->staging.as<float>(),
+                       vptr, pb->vinc.as<int>(), ids, n, pb->cn.as<float>(), pb->cw.as<float>(), pb->cg.as<float>(),
+                       pb->ch.as<float>(), pb->mass.as<float>(), pb->xh.as<double>(), pb->xt.as<double>(),
+                       pb->fixed.as<uint8_t>(), pb->vals.as<float>(), pb->grad.as<float>(), pb->Lf.as<float>(),
+                       pb->Linv.as<float>(), pb->bhat.as<float>(), pb->bb_part.as<double>(), flags, s);
+  // sliced storage of the scaled matrix: per column the source rows of its
+  // upper blocks, slot counts per slice, then the slots themselves
+  int* lcnt = pb->lcnt.as<int>();
+  int* lptr = pb->lptr.as<int>();
+  fill_int(lcnt, 0, N, s);
+  launch_lower_count(N, row_ptr, pb->col.as<int>(), lcnt, s);
+  scan_exclusive(lcnt, lptr, N, lptr + N, tmp, s);
+  fill_int(lcnt, 0, N, s);
+  launch_lower_fill(N, row_ptr, pb->col.as<int>(), lptr, lcnt, pb->lsrc.as<int>(), s);
+  sort_segments(pb->lsrc.as<int>(), lptr, N, s);
+  const int nslices = div_up(N, kSlice);
+  int* sbu = pb->sbu.as<int>();
+  int* sbl = pb->sbl.as<int>();
+  launch_slice_widths(N, nslices, row_ptr, lptr, sbu, sbl, s);
+  scan_exclusive(sbu, sbu, nslices, sbu + nslices, tmp, s);
+  scan_exclusive(sbl, sbl, nslices, sbl + nslices, tmp, s);
+  int tot[2] = {0, 0};
+  HIPCHK(c, hipMemcpyAsync(&tot[0], sbu + nslices, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(&tot[1], sbl + nslices, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  pb->nslot_u = tot[0];
+  pb->nslot_l = tot[1];
+  ALLOC(c, pb->sblk, 36LL * (tot[0] + 1));
+  if (bf16) ALLOC(c, pb->sblk16, 20LL * (tot[0] + 1));
+  ALLOC(c, pb->scol, 4LL * tot[0] + 4);
+  ALLOC(c, pb->sent, 8LL * tot[1] + 8);
+  launch_sell_fill(N, nslices, row_ptr, pb->col.as<int>(), pb->vals.as<float>(), pb->Linv.as<float>(), lptr,
+                   pb->lsrc.as<int>(), sbu, sbl, pb->sblk.as<float>(), bf16 ? pb->sblk16.as<uint32_t>() : nullptr,
+                   pb->scol.as<int>(),
+                   pb->sent.as<int2>(), s);
   return BF_OK;
 }
 
-}  // namespace
+}  // namespace bfal
 
 extern "C" {
 
@@ -144,7 +263,7 @@ bf_status bf_footprint_bytes(int32_t n_nodes, int32_t n_tets, int32_t n_constrai
   b += N * 24 * 3;                                 // x, x_hat, x_tilde
   b += C * (16 + 16 + 12 + 16 + 8);                // ids, lambda/gamma, n, w, factors
   b += N * 4 * 8 + C * 16 + cap * 4 * 2;           // incidence, candidates, pattern
-  b += cap * (36 + 36 + 4 + 4);                    // blocks, scaled blocks, ocol, eslot
+  b += cap * (36 + 36 + 4 + 4 + 8 + 4);            // blocks, scaled blocks, ucol, eslot, transpose index, lsrc
   b += N * (12 * 6 + 24 * 2 + 24);                 // grad, bhat, x, r, p, q, L, L^-1, p out
   b += 1 << 20;                                    // partials, scalars, scan scratch
   *out = b;
@@ -155,124 +274,10 @@ bf_status bf_problem_create(bf_context* c, const bf_mesh_desc* m, int32_t mem, b
   if (!c) return BF_ERR_INVALID_ARG;
   if (!out) return fail(c, BF_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  if (!m || !m->tets || !m->rest || !m->E || !m->nu || !m->rho)
-    return fail(c, BF_ERR_INVALID_ARG, "mesh descriptor or one of its arrays is NULL");
-  if (m->n_nodes <= 0 || m->n_tets <= 0) return fail(c, BF_ERR_INVALID_ARG, "n_nodes and n_tets must be positive");
-  if ((long long)m->n_tets * 10 >= (1LL << 31) || (long long)m->n_nodes * 3 >= (1LL << 31))
-    return fail(c, BF_ERR_INVALID_ARG, "mesh too large for 32-bit slot indices");
-  if (mem != BF_MEM_HOST && mem != BF_MEM_DEVICE) return fail(c, BF_ERR_INVALID_ARG, "mem must be BF_MEM_HOST or BF_MEM_DEVICE");
-  const int N = m->n_nodes, T = m->n_tets;
-  if (mem == BF_MEM_HOST) {
-    for (long long e = 0; e < T; ++e) {
-      const int32_t* t = m->tets + 4 * e;
-      for (int a = 0; a < 4; ++a)
-        if (t[a] < 0 || t[a] >= N) return fail(c, BF_ERR_INVALID_ARG, "tet vertex index out of range");
-      if (t[0] == t[1] || t[0] == t[2] || t[0] == t[3] || t[1] == t[2] || t[1] == t[3] || t[2] == t[3])
-        return fail(c, BF_ERR_INVALID_ARG, "tet with a repeated vertex");
-      if (!(m->E[e] > 0.0) || !std::isfinite(m->E[e]) || !(m->nu[e] > -1.0 && m->nu[e] < 0.5) ||
-          !(m->rho[e] > 0.0) || !std::isfinite(m->rho[e]))
-        return fail(c, BF_ERR_INVALID_ARG, "invalid material value");
-    }
-    if (!finite_all(m->rest, 3LL * N)) return fail(c, BF_ERR_INVALID_ARG, "non-finite rest position");
-  }
-  HIPCHK(c, hipSetDevice(c->device));
   bf_problem* pb = new (std::nothrow) bf_problem();
   if (!pb) return fail(c, BF_ERR_OOM, "host allocation failed");
   pb->ctx = c;
-  pb->N = N;
-  pb->T = T;
-  bf_status st = BF_OK;
-  auto body = [&]() -> bf_status {
-    hipStream_t s = c->stream;
-    ALLOC(c, pb->tets, 16LL * T);
-    ALLOC(c, pb->rest, 24LL * N);
-    ALLOC(c, pb->E, 8LL * T);
-    ALLOC(c, pb->nu, 8LL * T);
-    ALLOC(c, pb->rho, 8LL * T);
-    ALLOC(c, pb->fixed, N);
-    ALLOC(c, pb->Dminv9, 36LL * T);
-    ALLOC(c, pb->vol, 4LL * T);
-    ALLOC(c, pb->mu, 4LL * T);
-    ALLOC(c, pb->lam, 4LL * T);
-    ALLOC(c, pb->mass, 4LL * N);
-    ALLOC(c, pb->flags, 64);
-    HIPCHK(c, hipMemcpyAsync(pb->tets.p, m->tets, 16LL * T, kind_in(mem), s));
-    HIPCHK(c, hipMemcpyAsync(pb->rest.p, m->rest, 24LL * N, kind_in(mem), s));
-    HIPCHK(c, hipMemcpyAsync(pb->E.p, m->E, 8LL * T, kind_in(mem), s));
-    HIPCHK(c, hipMemcpyAsync(pb->nu.p, m->nu, 8LL * T, kind_in(mem), s));
-    HIPCHK(c, hipMemcpyAsync(pb->rho.p, m->rho, 8LL * T, kind_in(mem), s));
-    if (m->fixed) {
-      HIPCHK(c, hipMemcpyAsync(pb->fixed.p, m->fixed, N, kind_in(mem), s));
-    } else {
-      std::vector<uint8_t> z(N, 0);
-      HIPCHK(c, hipMemcpyAsync(pb->fixed.p, z.data(), N, hipMemcpyHostToDevice, s));
-      HIPCHK(c, hipStreamSynchronize(s));
-    }
-    int* flags = pb->flags.as<int>();
-    fill_int(flags, 0, 16, s);
-    const int4* tets = pb->tets.as<int4>();
-    launch_check_tets(tets, T, N, flags, s);
-    int hflags = 0;
-    bf_status r0 = read_flags(pb, &hflags);
-    if (r0 != BF_OK) return r0;
-    if (hflags) return flags_to_status(c, hflags);
-    launch_rest_geometry(tets, pb->rest.as<double>(), pb->E.as<double>(), pb->nu.as<double>(), T,
-                         pb->Dminv9.as<float>(), pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), flags, s);
-    // static elastic pattern: pair keys bucketed by row, sorted and unique per row
-    const long long npairs = 6LL * T;
-    const long long nslots_tmp = (long long)N + 1;
-    ALLOC(c, pb->scratch_int, 4LL * (3 * nslots_tmp + npairs + 16));
-    int* cnt = pb->scratch_int.as<int>();
-    int* kptr = cnt + nslots_tmp;
-    int* cursor = kptr + nslots_tmp;
-    int* keys = cursor + nslots_tmp;
-    ALLOC(c, pb->scan_tmp, 4LL * scan_tmp_ints(10LL * T + N + 16));
-    int* tmp = pb->scan_tmp.as<int>();
-    fill_int(cnt, 0, N, s);
-    launch_elastic_pair_count(tets, T, cnt, s);
-    scan_exclusive(cnt, kptr, N, kptr + N, tmp, s);
-    fill_int(cursor, 0, N, s);
-    launch_elastic_pair_fill(tets, T, kptr, cursor, keys, s);
-    ALLOC(c, pb->erow_ptr, 4LL * (N + 1));
-    int* ucount = cnt;  // reuse
-    launch_row_unique(keys, kptr, N, ucount, s);
-    int* erow = pb->erow_ptr.as<int>();
-    scan_exclusive(ucount, erow, N, erow + N, tmp, s);
-    int nnzb_e = 0;
-    HIPCHK(c, hipMemcpyAsync(&nnzb_e, erow + N, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    pb->nnzb_e = nnzb_e;
-    ALLOC(c, pb->ecol, 4LL * nnzb_e);
-    launch_row_write(keys, kptr, N, erow, pb->ecol.as<int>(), s);
-    // (tet, pair) -> elastic slot, and each slot's contributions in (tet, pair) order
-    ALLOC(c, pb->emap, 40LL * T);
-    launch_emap(tets, T, erow, pb->ecol.as<int>(), pb->emap.as<int>(), s);
-    ALLOC(c, pb->ecptr, 4LL * (nnzb_e + 1));
-    ALLOC(c, pb->elist, 40LL * T);
-    ALLOC(c, pb->epos, 40LL * T);
-    // nnzb_e <= N + 6T, so the scratch buffer already holds nnzb_e counters
-    int* scnt = pb->scratch_int.as<int>();
-    int* ecptr = pb->ecptr.as<int>();
-    fill_int(scnt, 0, nnzb_e, s);
-    launch_slot_count(pb->emap.as<int>(), 10LL * T, scnt, s);
-    scan_exclusive(scnt, ecptr, nnzb_e, ecptr + nnzb_e, tmp, s);
-    fill_int(scnt, 0, nnzb_e, s);
-    launch_slot_fill(pb->emap.as<int>(), 10LL * T, ecptr, scnt, pb->elist.as<int>(), s);
-    sort_segments(pb->elist.as<int>(), ecptr, nnzb_e, s);
-    launch_inverse_positions(pb->elist.as<int>(), 10LL * T, pb->epos.as<int>(), s);
-    launch_mass(ecptr, pb->elist.as<int>(), erow, pb->vol.as<float>(), pb->rho.as<double>(), N, pb->mass.as<float>(), s);
-    ALLOC(c, pb->staging, 360LL * T);
-    r0 = read_flags(pb, &hflags);
-    if (r0 != BF_OK) return r0;
-    if (hflags) return flags_to_status(c, hflags);
-    for (auto& e : pb->ev) HIPCHK(c, hipEventCreate(&e));
-    HIPCHK(c, hipHostMalloc((void**)&pb->host_sc, sizeof(PcgScalars), hipHostMallocDefault));
-    ALLOC(c, pb->scal, sizeof(PcgScalars));
-    HIPCHK(c, hipMemsetAsync(pb->scal.p, 0, sizeof(PcgScalars), s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    return BF_OK;
-  };
-  st = body();
+  const bf_status st = problem_init(c, pb, m, mem);
   if (st != BF_OK) {
     bf_problem_destroy(pb);
     return st;
@@ -290,9 +295,10 @@ void bf_problem_destroy(bf_problem* pb) {
                     &pb->staging, &pb->x, &pb->xh, &pb->xt, &pb->cids, &pb->clam, &pb->cgam, &pb->cn, &pb->cw,
                     &pb->cg, &pb->ch, &pb->viol_part, &pb->vcnt, &pb->vptr, &pb->vinc, &pb->ccount, &pb->cptr,
                     &pb->cand, &pb->ucount, &pb->row_ptr, &pb->col, &pb->eslot, &pb->vals, &pb->grad, &pb->Lf,
-                    &pb->Linv, &pb->bhat, &pb->bb_part, &pb->ovals, &pb->ocol, &pb->orow_ptr, &pb->lcnt, &pb->lptr,
-                    &pb->lsrc, &pb->tidx, &pb->tbuf, &pb->xs, &pb->r,
-                    &pb->p, &pb->q, &pb->part, &pb->scal, &pb->pout, &pb->flags, &pb->scan_tmp, &pb->scratch_int};
+                    &pb->Linv, &pb->bhat, &pb->bb_part, &pb->lcnt, &pb->lptr, &pb->lsrc, &pb->sbu, &pb->sbl,
+                    &pb->sblk, &pb->sblk16, &pb->scol, &pb->sent, &pb->xs, &pb->r, &pb->p0, &pb->p1, &pb->q,
+                    &pb->part, &pb->scal, &pb->pout, &pb->flags, &pb->scan_tmp, &pb->scratch_int,
+                    &pb->xd, &pb->rd, &pb->rpart};
   for (DevBuf* b : bufs) b->release();
   for (auto& e : pb->ev)
     if (e) (void)hipEventDestroy(e);
@@ -406,14 +412,17 @@ bf_status bf_set_constraints(bf_problem* pb, const bf_constraint_desc* cd, int32
   ALLOC(c, pb->col, 4LL * cap);
   ALLOC(c, pb->eslot, 4LL * cap);
   ALLOC(c, pb->vals, 36LL * cap);
-  ALLOC(c, pb->ovals, 36LL * cap);     // scaled upper off-diagonal blocks, SoA [9][cap]
-  ALLOC(c, pb->ocol, 4LL * cap);
-  ALLOC(c, pb->orow_ptr, 4LL * (N + 1));
   ALLOC(c, pb->lcnt, 4LL * (N + 1));
   ALLOC(c, pb->lptr, 4LL * (N + 1));
   ALLOC(c, pb->lsrc, 4LL * cap);
-  ALLOC(c, pb->tidx, 4LL * cap);
-  ALLOC(c, pb->tbuf, 12LL * cap);
+  const long long nsl = div_up(N, kSlice);
+  ALLOC(c, pb->sbu, 4LL * (nsl + 1));
+  ALLOC(c, pb->sbl, 4LL * (nsl + 1));
+  // sliced storage: sized here for about 25 % padding, grown in the step if needed
+  const long long slots0 = (cap - N) + (cap - N) / 4 + kSlice;
+  ALLOC(c, pb->sblk, 36LL * (slots0 + 1));
+  ALLOC(c, pb->scol, 4LL * slots0);
+  ALLOC(c, pb->sent, 8LL * slots0);
   // solver vectors and the factor L are padded to a multiple of 4 nodes (float4
   // access); the pads are zeroed here and never written with nonzeros
   const long long N4 = (N + 3) & ~3LL;
@@ -424,12 +433,13 @@ bf_status bf_set_constraints(bf_problem* pb, const bf_constraint_desc* cd, int32
   ALLOC(c, pb->bb_part, 8LL * (div_up(N, kBlock) + 1));
   ALLOC(c, pb->xs, 12LL * N4);
   ALLOC(c, pb->r, 12LL * N4);
-  ALLOC(c, pb->p, 12LL * N4);
+  ALLOC(c, pb->p0, 12LL * N4);
+  ALLOC(c, pb->p1, 12LL * N4);
   ALLOC(c, pb->q, 12LL * N4);
-  for (DevBuf* b : {&pb->Lf, &pb->Linv, &pb->bhat, &pb->xs, &pb->r, &pb->p, &pb->q})
+  for (DevBuf* b : {&pb->Lf, &pb->Linv, &pb->bhat, &pb->xs, &pb->r, &pb->p0, &pb->p1, &pb->q})
     HIPCHK(c, hipMemsetAsync(b->p, 0, b->bytes, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  ALLOC(c, pb->part, 8LL * pcg_partials_needed(N));
+  ALLOC(c, pb->part, 8LL * kPartsPerSystem);
   ALLOC(c, pb->pout, 24LL * N);
   ALLOC(c, pb->scan_tmp, 4LL * scan_tmp_ints((long long)10 * pb->T + N + 6LL * n + 16));
   pb->cap_nnzb = cap;
@@ -445,70 +455,25 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
   if (!pb->has_state) return fail(c, BF_ERR_STATE, "bf_set_state must be called before bf_newton_step");
   if (pb->cap_nnzb == 0) return fail(c, BF_ERR_STATE, "bf_set_constraints must be called before bf_newton_step");
   if (!(o->tol > 0.0) || o->max_iter < 0) return fail(c, BF_ERR_INVALID_ARG, "tol must be > 0 and max_iter >= 0");
-  if (o->precision != BF_PREC_FP32) return fail(c, BF_ERR_INVALID_ARG, "unsupported precision mode");
+  if (o->precision != BF_PREC_FP32 && o->precision != BF_PREC_BF16_REFINE)
+    return fail(c, BF_ERR_INVALID_ARG, "unsupported precision mode");
+  if (o->precision == BF_PREC_BF16_REFINE && !(o->refine_tol > 0.0))
+    return fail(c, BF_ERR_INVALID_ARG, "refine_tol must be > 0");
+  const bool bf16 = o->precision == BF_PREC_BF16_REFINE;
   if (mem != BF_MEM_HOST && mem != BF_MEM_DEVICE) return fail(c, BF_ERR_INVALID_ARG, "bad mem kind");
   HIPCHK(c, hipSetDevice(c->device));
   hipStream_t s = c->stream;
-  const int N = pb->N, T = pb->T, n = pb->n_c;
+  const int N = pb->N, n = pb->n_c;
   int* flags = pb->flags.as<int>();
-  int* tmp = pb->scan_tmp.as<int>();
-  const int4* ids = pb->cids.as<int4>();
-  fill_int(flags, 0, 16, s);
-  HIPCHK(c, hipEventRecord(pb->ev[0], s));
-  // (1) constraint linearization at x and AL factors at x_hat
-  fill_int(reinterpret_cast<int*>(pb->viol_part.p), 0, 2, s);
-  launch_contact_lin(ids, pb->n_pt, n, pb->x.as<double>(), pb->xh.as<double>(), pb->clam.as<double>(),
-                     pb->cgam.as<double>(), pb->kappa, pb->delta, pb->cn.as<float>(), pb->cw.as<float>(),
-                     pb->cg.as<float>(), pb->ch.as<float>(), pb->viol_part.as<double>(), flags, s);
-  HIPCHK(c, hipEventRecord(pb->ev[1], s));
-  // (2) merged pattern: vertex -> constraint incidence, candidates, unique rows
-  int* vcnt = pb->vcnt.as<int>();
-  int* vptr = pb->vptr.as<int>();
-  fill_int(vcnt, 0, N, s);
-  launch_vertex_incidence_count(ids, n, vcnt, s);
-  scan_exclusive(vcnt, vptr, N, vptr + N, tmp, s);
-  fill_int(vcnt, 0, N, s);
-  launch_vertex_incidence_fill(ids, n, vptr, vcnt, pb->vinc.as<int>(), s);
-  sort_segments(pb->vinc.as<int>(), vptr, N, s);
-  int* cptr = pb->cptr.as<int>();
-  launch_candidate_count(pb->erow_ptr.as<int>(), vptr, pb->vinc.as<int>(), ids, N, pb->ccount.as<int>(), s);
-  scan_exclusive(pb->ccount.as<int>(), cptr, N, cptr + N, tmp, s);
-  launch_candidate_fill(pb->erow_ptr.as<int>(), pb->ecol.as<int>(), vptr, pb->vinc.as<int>(), ids, N, cptr,
-                        pb->cand.as<int>(), pb->ucount.as<int>(), s);
   int* row_ptr = pb->row_ptr.as<int>();
-  scan_exclusive(pb->ucount.as<int>(), row_ptr, N, row_ptr + N, tmp, s);
-  launch_merged_write(pb->cand.as<int>(), cptr, row_ptr, pb->erow_ptr.as<int>(), pb->ecol.as<int>(), N,
-                      pb->col.as<int>(), pb->eslot.as<int>(), s);
-  HIPCHK(c, hipEventRecord(pb->ev[2], s));
-  // (3) assembly
-  const float h2 = (float)(pb->dt * pb->dt);
-  launch_elastic(pb->tets.as<int4>(), T, pb->rest.as<double>(), pb->xh.as<double>(), pb->Dminv9.as<float>(),
-                 pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), h2, pb->epos.as<int>(),
-                 pb->staging.as<float>(), flags, s);
-  launch_assemble_rows(N, row_ptr, pb->col.as<int>(), pb->eslot.as<int>(), pb->ecptr.as<int>(), pb->staging.as<float>(),
-                       vptr, pb->vinc.as<int>(), ids, n, pb->cn.as<float>(), pb->cw.as<float>(), pb->cg.as<float>(),
-                       pb->ch.as<float>(), pb->mass.as<float>(), pb->xh.as<double>(), pb->xt.as<double>(),
-                       pb->fixed.as<uint8_t>(), pb->vals.as<float>(), pb->grad.as<float>(), pb->Lf.as<float>(),
-                       pb->Linv.as<float>(), pb->bhat.as<float>(), pb->bb_part.as<double>(), flags, s);
-  // scaled upper blocks and the transpose index of the two-phase SpMV
-  const long long ustride = pb->cap_nnzb;
-  int* lcnt = pb->lcnt.as<int>();
-  int* lptr = pb->lptr.as<int>();
-  fill_int(lcnt, 0, N, s);
-  launch_lower_count(N, row_ptr, pb->col.as<int>(), lcnt, s);
-  scan_exclusive(lcnt, lptr, N, lptr + N, tmp, s);
-  fill_int(lcnt, 0, N, s);
-  launch_lower_fill(N, row_ptr, pb->col.as<int>(), lptr, lcnt, pb->lsrc.as<int>(), s);
-  sort_segments(pb->lsrc.as<int>(), lptr, N, s);
-  launch_transpose_index(N, row_ptr, pb->col.as<int>(), lptr, pb->lsrc.as<int>(), pb->tidx.as<int>(), s);
-  launch_scale_upper(N, row_ptr, pb->col.as<int>(), pb->vals.as<float>(), pb->Linv.as<float>(), pb->ovals.as<float>(),
-                     pb->ocol.as<int>(), pb->orow_ptr.as<int>(), ustride, s);
+  {
+    const bf_status r0 = step_assemble(pb, bf16);
+    if (r0 != BF_OK) return r0;
+  }
+  PcgSystem S = system_of(pb);
   HIPCHK(c, hipEventRecord(pb->ev[3], s));
-  // (4) PCG
-  PcgScalars* sc = pb->scal.as<PcgScalars>();
-  double* part = pb->part.as<double>();
-  launch_pcg_init(N, pb->bhat.as<float>(), pb->xs.as<float>(), pb->r.as<float>(), pb->p.as<float>(), part,
-                  pb->bb_part.as<double>(), div_up(N, kBlock), sc, o->tol, o->max_iter, o->check_every, s);
+  // (4) PCG: one solve on the FP32 blocks, or iterative refinement around
+  // solves on the BF16 copy
   const int poll = o->poll_every > 0 ? o->poll_every : 16;
   const int ntime = o->time_spmv > 0 ? (o->time_spmv < 4096 ? o->time_spmv : 4096) : 0;
   while ((int)pb->tev.size() < 2 * ntime) {
@@ -516,37 +481,91 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
     HIPCHK(c, hipEventCreate(&e));
     pb->tev.push_back(e);
   }
-  int launched = 0;
+  int launched = 0, total_iters = 0, timed = 0;
   bool assembly_checked = false;
-  for (;;) {
-    const int batch = poll;
-    for (int k = 0; k < batch; ++k) {
-      const int it = launched + k;
-      if (it < ntime) HIPCHK(c, hipEventRecord(pb->tev[2 * it], s));
-      launch_pcg_spmv(N, pb->orow_ptr.as<int>(), pb->ocol.as<int>(), pb->ovals.as<float>(), ustride,
-                      pb->p.as<float>(), pb->q.as<float>(), pb->tbuf.as<float>(), part, sc, s);
-      if (it < ntime) HIPCHK(c, hipEventRecord(pb->tev[2 * it + 1], s));
-      launch_pcg_vector_ops(N, pb->Lf.as<float>(), pb->xs.as<float>(), pb->r.as<float>(), pb->p.as<float>(),
-                            pb->q.as<float>(), pb->tbuf.as<float>(), lptr, pb->tidx.as<int>(), part, sc, s);
+  // Runs the solve set up on S to its device-side stop; the first poll also
+  // checks the assembly's error flags.
+  auto run_solve = [&](const PcgSystem& Sx, bool use_bf16) -> bf_status {
+    int mine = 0;
+    for (;;) {
+      for (int k = 0; k < poll; ++k) {
+        const bool t = launched + k < ntime;
+        if (t) HIPCHK(c, hipEventRecord(pb->tev[2 * (launched + k)], s));
+        launch_pcg_iteration(Sx, use_bf16, s);
+        if (t) HIPCHK(c, hipEventRecord(pb->tev[2 * (launched + k) + 1], s));
+      }
+      launched += poll;
+      mine += poll;
+      HIPCHK(c, hipMemcpyAsync(pb->host_sc, Sx.sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      if (!assembly_checked) {
+        int hf = 0;
+        bf_status r0 = read_flags(pb, &hf);
+        if (r0 != BF_OK) return r0;
+        if (hf) return flags_to_status(c, hf);
+        assembly_checked = true;
+      }
+      if (pb->host_sc->done || pb->host_sc->brk) break;
+      if (mine > o->max_iter + poll) break;   // cannot happen: the device stops at max_iter
     }
-    launched += batch;
-    HIPCHK(c, hipMemcpyAsync(pb->host_sc, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    if (!assembly_checked) {
-      int hf = 0;
-      bf_status r0 = read_flags(pb, &hf);
+    // launches after the device-side stop returned early: only the first
+    // iter of this solve's timed launches did a full SpMV
+    const int first = launched - mine;
+    const int full_end = first + pb->host_sc->iter;
+    timed = std::max(timed, std::min(ntime, full_end));
+    total_iters += pb->host_sc->iter;
+    return BF_OK;
+  };
+  const int nviol = div_up(n, kBlock) > 0 ? div_up(n, kBlock) : 1;
+  double sweep_res[16] = {0.0};
+  int sweeps = 0;
+  bool refine_capped = false;
+  if (!bf16) {
+    launch_pcg_init(S, pb->bhat.as<float>(), pb->bb_part.as<double>(), div_up(N, kBlock), o->tol, o->max_iter,
+                    o->check_every, s);
+    bf_status r0 = run_solve(S, false);
+    if (r0 != BF_OK) return r0;
+    launch_pcg_finish(S, pb->Linv.as<float>(), pb->pout.as<double>(), pb->viol_part.as<double>(), nviol, s);
+  } else {
+    const long long n3 = 3LL * S.N4;
+    ALLOC(c, pb->xd, 8 * n3);
+    ALLOC(c, pb->rd, 8 * n3);
+    ALLOC(c, pb->rpart, 8LL * (kMaxSpmvParts + 8));
+    HIPCHK(c, hipMemsetAsync(pb->xd.p, 0, 8 * n3, s));
+    HIPCHK(c, hipMemsetAsync(pb->rd.p, 0, 8 * n3, s));
+    double* rpart = pb->rpart.as<double>();
+    double* rsum = rpart + kMaxSpmvParts;   // [0] residual^2, [1] |b|^2
+    launch_sum_to(pb->bb_part.as<double>(), div_up(N, kBlock), rsum + 1, s);
+    PcgSystem S16 = S;
+    S16.blk = pb->sblk16.p;
+    const int max_sweeps = o->max_sweeps > 0 ? o->max_sweeps : 30;
+    double bb = 0.0;
+    for (int sw = 0;; ++sw) {
+      launch_residual64(S, pb->bhat.as<float>(), pb->xd.as<double>(), pb->rd.as<double>(), rpart, rsum, s);
+      double hs[2] = {0.0, 0.0};
+      HIPCHK(c, hipMemcpyAsync(hs, rsum, sizeof(hs), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      bb = hs[1];
+      const double rel = bb > 0.0 ? std::sqrt(hs[0] / bb) : 0.0;
+      if (sw < 16) sweep_res[sw] = rel;
+      pb->host_sc->rr_true = hs[0];
+      if (rel <= o->refine_tol) break;
+      if (sw >= max_sweeps) { refine_capped = true; break; }
+      launch_pcg_init_from64(S16, pb->rd.as<double>(), rpart, S.spmv_nwg, o->tol, o->max_iter, o->check_every, s);
+      bf_status r0 = run_solve(S16, true);
       if (r0 != BF_OK) return r0;
-      if (hf) return flags_to_status(c, hf);
-      assembly_checked = true;
+      if (pb->host_sc->brk) break;
+      launch_axpy64(S16, pb->xd.as<double>(), s);
+      ++sweeps;
     }
-    if (pb->host_sc->done) break;
-    if (launched > o->max_iter + poll) break;   // cannot happen: the device stops at max_iter
+    pb->host_sc->bb = bb;
+    launch_pcg_finish64(S, pb->Linv.as<float>(), pb->xd.as<double>(), pb->pout.as<double>(),
+                        pb->viol_part.as<double>(), nviol, s);
   }
-  launch_pcg_finish(N, pb->Linv.as<float>(), pb->xs.as<float>(), pb->pout.as<double>(), part, sc,
-                    pb->viol_part.as<double>(), div_up(n, kBlock) > 0 ? div_up(n, kBlock) : 1, s);
   HIPCHK(c, hipEventRecord(pb->ev[4], s));
   HIPCHK(c, hipMemcpyAsync(p_out, pb->pout.p, 24LL * N, kind_out(mem), s));
-  HIPCHK(c, hipMemcpyAsync(pb->host_sc, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+  const double refine_rr = pb->host_sc->rr_true, refine_bb = pb->host_sc->bb;
+  HIPCHK(c, hipMemcpyAsync(pb->host_sc, S.sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
   int nnzb = 0, hflags = 0;
   HIPCHK(c, hipMemcpyAsync(&nnzb, row_ptr + N, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -560,9 +579,13 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
     (void)hipEventElapsedTime(&t12, pb->ev[1], pb->ev[2]);
     (void)hipEventElapsedTime(&t23, pb->ev[2], pb->ev[3]);
     (void)hipEventElapsedTime(&t34, pb->ev[3], pb->ev[4]);
-    stats->pcg_iters = h.iter3;
-    stats->refine_sweeps = 0;
-    stats->rel_residual = h.bb > 0.0 ? std::sqrt(h.rr_true / h.bb) : 0.0;
+    stats->pcg_iters = total_iters;
+    stats->refine_sweeps = sweeps;
+    if (bf16)
+      stats->rel_residual = refine_bb > 0.0 ? std::sqrt(refine_rr / refine_bb) : 0.0;
+    else
+      stats->rel_residual = h.bb > 0.0 ? std::sqrt(h.rr_true / h.bb) : 0.0;
+    for (int k = 0; k < 16; ++k) stats->sweep_rel_residual[k] = sweep_res[k];
     stats->newton_inf_over_h = h.stat_pinf / pb->dt;
     stats->max_violation = h.stat_viol;
     stats->nnzb = nnzb;
@@ -571,7 +594,7 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
     stats->ms_assemble = t23;
     stats->ms_pcg = t34;
     // only launches made before convergence did the full SpMV
-    const int nt = ntime < h.iter3 ? ntime : h.iter3;
+    const int nt = timed;
     double tot = 0.0;
     for (int k = 0; k < nt; ++k) {
       float ms = 0.f;
@@ -583,8 +606,8 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
   }
   if (hflags | h.flags) return flags_to_status(c, hflags | h.flags);
   c->err.clear();
-  if (h.done == 2) {
-    c->err = "PCG reached max_iter";
+  if ((!bf16 && h.done == 2 && !h.brk) || refine_capped) {
+    c->err = refine_capped ? "refinement reached max_sweeps" : "PCG reached max_iter";
     return BF_WARN_PCG_MAXITER;
   }
   return BF_OK;

@@ -12,8 +12,9 @@
 // applied symmetrically: each diagonal block is factored D_v = L_v L_v^T and
 // the off-diagonal blocks are scaled to L_r^{-1} H_rc L_c^{-T}, so the solver
 // runs CG on a matrix whose diagonal blocks are identities.  Only the upper
-// off-diagonal scaled blocks are stored, plus a transpose index (for every
-// column, the blocks above the diagonal in it) used by the SpMV's second phase.
+// off-diagonal scaled blocks are stored (in slices of 64 rows, see
+// k_slice_widths), plus, per row, references to the upper blocks of its column
+// through which the SpMV gathers the lower half.
 #include "common.h"
 
 namespace bfal {
@@ -135,14 +136,16 @@ k_assemble_rows(int N, const int* __restrict__ row_ptr, const int* __restrict__ 
     const float M10 = -L10 * M00 * M11;
     const float M21 = -L21 * M11 * M22;
     const float M20 = -(L20 * M00 + L21 * M10) * M22;
-    float* lf = Lf + 6LL * r;
-    lf[0] = L00; lf[1] = L10; lf[2] = L11; lf[3] = L20; lf[4] = L21; lf[5] = L22;
+    // L as SoA [6][N4] for the solver's residual check
+    const long long N4 = (N + 3) & ~3;
+    Lf[r] = L00; Lf[N4 + r] = L10; Lf[2 * N4 + r] = L11; Lf[3 * N4 + r] = L20; Lf[4 * N4 + r] = L21;
+    Lf[5 * N4 + r] = L22;
     float* li = Linv + 6LL * r;
     li[0] = M00; li[1] = M10; li[2] = M11; li[3] = M20; li[4] = M21; li[5] = M22;
-    // b_hat = L^{-1} b with b = -G
-    bhat[3LL * r] = -(M00 * g[0]);
-    bhat[3LL * r + 1] = -(M10 * g[0] + M11 * g[1]);
-    bhat[3LL * r + 2] = -(M20 * g[0] + M21 * g[1] + M22 * g[2]);
+    // b_hat = L^{-1} b with b = -G, SoA [3][N4]
+    bhat[r] = -(M00 * g[0]);
+    bhat[N4 + r] = -(M10 * g[0] + M11 * g[1]);
+    bhat[2 * N4 + r] = -(M20 * g[0] + M21 * g[1] + M22 * g[2]);
   }
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) bb += __shfl_xor(bb, off, kWave);
@@ -188,41 +191,100 @@ __device__ inline void scaled_block(const float* __restrict__ mr, const float* _
     for (int k = 0; k < 3; ++k) out[i][k] = T1[i][0] * Cm[k][0] + T1[i][1] * Cm[k][1] + T1[i][2] * Cm[k][2];
 }
 
-// H_hat_rc = M_r H_rc M_c^T for every upper off-diagonal block, SoA [9][stride];
-// row r's blocks start at row_ptr[r] - r (the diagonal slots are dropped: the
-// diagonal blocks of H_hat are identities).
-__global__ void k_scale_upper(int N, const int* __restrict__ row_ptr, const int* __restrict__ col,
-                              const float* __restrict__ vals, const float* __restrict__ Linv, float* __restrict__ uv,
-                              int* __restrict__ ucol, int* __restrict__ urow_ptr, long long st) {
+// FP32 -> BF16, round to nearest even (NaN kept quiet).
+__device__ inline uint32_t bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// Sliced storage of the scaled matrix (slices of kSlice consecutive rows, one
+// lane per row).  Slice s stores wu(s) = max upper off-diagonal count of its
+// rows upper slots and wl(s) = max lower count lower slots, slot k of the row
+// in lane l at base + k * kSlice + l (so a wavefront reads slot k of its 64 rows
+// contiguously).  Shorter rows are padded: an upper pad has a zero block and
+// its own row as column; a lower pad points at the zero block stored after
+// the last upper slot.
+__global__ void k_slice_widths(int N, int nslices, const int* __restrict__ row_ptr, const int* __restrict__ lptr,
+                               int* __restrict__ cu, int* __restrict__ cl) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= nslices) return;
+  int wu = 0, wl = 0;
+  const int r1 = min(N, (sl + 1) * kSlice);
+  for (int r = sl * kSlice; r < r1; ++r) {
+    wu = max(wu, row_ptr[r + 1] - row_ptr[r] - 1);
+    wl = max(wl, lptr[r + 1] - lptr[r]);
+  }
+  cu[sl] = wu * kSlice;
+  cl[sl] = wl * kSlice;
+}
+
+// Upper slots: H_hat_rc = M_r H_rc M_c^T (M = L^{-1}) for every upper
+// off-diagonal block, FP32 row-major 9 floats per slot, and when blk16 is set a
+// BF16 copy (10 half-words packed two per word, the last one zero).
+__global__ void k_sell_upper(int N, int nslices, const int* __restrict__ row_ptr, const int* __restrict__ col,
+                             const float* __restrict__ vals, const float* __restrict__ Linv,
+                             const int* __restrict__ sbu, float* __restrict__ blk, uint32_t* __restrict__ blk16,
+                             int* __restrict__ scol) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= N) return;
-  const int o = row_ptr[r], n = row_ptr[r + 1] - o;
-  urow_ptr[r] = o - r;
-  if (r == N - 1) urow_ptr[N] = row_ptr[N] - N;
-  const float* mr = Linv + 6LL * r;
-  float h[3][3];
-  for (int j = 1; j < n; ++j) {
-    const int c = col[o + j];
-    scaled_block(mr, vals + 9LL * (o + j), Linv + 6LL * c, h);
-    const long long oj = (long long)(o - r) + j - 1;
+  if (r >= nslices * kSlice) return;
+  const int sl = r / kSlice, lane = r % kSlice;
+  const int base = sbu[sl], wu = (sbu[sl + 1] - base) / kSlice;
+  const int o = r < N ? row_ptr[r] : 0;
+  const int nu = r < N ? row_ptr[r + 1] - o - 1 : 0;
+  const float* mr = Linv + 6LL * (r < N ? r : 0);
+  for (int k = 0; k < wu; ++k) {
+    const long long e = base + (long long)k * kSlice + lane;
+    float h[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    int c = r < N ? r : N - 1;
+    if (k < nu) {
+      c = col[o + 1 + k];
+      scaled_block(mr, vals + 9LL * (o + 1 + k), Linv + 6LL * c, h);
+    }
+    float* d = blk + 9 * e;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) uv[(3 * i + k) * st + oj] = h[i][k];
-    ucol[oj] = c;
+      for (int m = 0; m < 3; ++m) d[3 * i + m] = h[i][m];
+    if (blk16) {
+      uint32_t* w = blk16 + 5 * e;
+      w[0] = bf16_rne(h[0][0]) | (bf16_rne(h[0][1]) << 16);
+      w[1] = bf16_rne(h[0][2]) | (bf16_rne(h[1][0]) << 16);
+      w[2] = bf16_rne(h[1][1]) | (bf16_rne(h[1][2]) << 16);
+      w[3] = bf16_rne(h[2][0]) | (bf16_rne(h[2][1]) << 16);
+      w[4] = bf16_rne(h[2][2]);
+    }
+    scol[e] = c;
+  }
+  if (r == 0) {   // the zero block the lower pads point at
+    const long long z = sbu[nslices];
+    for (int m = 0; m < 9; ++m) blk[9 * z + m] = 0.f;
+    if (blk16)
+      for (int m = 0; m < 5; ++m) blk16[5 * z + m] = 0u;
   }
 }
 
-// For every node c, the upper off-diagonal block indices j with column c, in
-// increasing source row (the order the SpMV sums their transposed products).
-__global__ void k_transpose_index(int N, const int* __restrict__ row_ptr, const int* __restrict__ col,
-                                  const int* __restrict__ lptr, const int* __restrict__ lsrc, int* __restrict__ tidx) {
+// Lower slots of row c: for every upper block (src, c), src < c, in increasing
+// src, the pair (upper slot of the block, src).
+__global__ void k_sell_lower(int N, int nslices, const int* __restrict__ row_ptr, const int* __restrict__ col,
+                             const int* __restrict__ lptr, const int* __restrict__ lsrc, const int* __restrict__ sbu,
+                             const int* __restrict__ sbl, int2* __restrict__ sent) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
-  for (int i = lptr[c]; i < lptr[c + 1]; ++i) {
-    const int rs = lsrc[i];
-    const int s = find_slot(col, row_ptr[rs] + 1, row_ptr[rs + 1] - 1, c);
-    tidx[i] = s - rs - 1;
+  if (c >= nslices * kSlice) return;
+  const int sl = c / kSlice, lane = c % kSlice;
+  const int base = sbl[sl], wl = (sbl[sl + 1] - base) / kSlice;
+  const int o = c < N ? lptr[c] : 0;
+  const int nl = c < N ? lptr[c + 1] - o : 0;
+  const int zero = sbu[nslices];
+  for (int k = 0; k < wl; ++k) {
+    int2 t = make_int2(zero, c < N ? c : N - 1);
+    if (k < nl) {
+      const int src = lsrc[o + k];
+      const int s = find_slot(col, row_ptr[src] + 1, row_ptr[src + 1] - 1, c);
+      const int ks = s - row_ptr[src] - 1;
+      t = make_int2(sbu[src / kSlice] + ks * kSlice + src % kSlice, src);
+    }
+    sent[base + (long long)k * kSlice + lane] = t;
   }
 }
 
@@ -252,16 +314,18 @@ void launch_lower_fill(int N, const int* row_ptr, const int* col, const int* lpt
   hipLaunchKernelGGL(k_lower_fill, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, lptr, lcur, lsrc);
 }
 
-void launch_scale_upper(int N, const int* row_ptr, const int* col, const float* vals, const float* Linv, float* uvals,
-                        int* ucol, int* urow_ptr, long long ustride, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_upper, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, vals, Linv, uvals,
-                     ucol, urow_ptr, ustride);
+void launch_slice_widths(int N, int nslices, const int* row_ptr, const int* lptr, int* cu, int* cl, hipStream_t s) {
+  hipLaunchKernelGGL(k_slice_widths, dim3(div_up(nslices, kBlock)), dim3(kBlock), 0, s, N, nslices, row_ptr, lptr, cu,
+                     cl);
 }
 
-void launch_transpose_index(int N, const int* row_ptr, const int* col, const int* lptr, const int* lsrc, int* tidx,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_transpose_index, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, lptr, lsrc,
-                     tidx);
+void launch_sell_fill(int N, int nslices, const int* row_ptr, const int* col, const float* vals, const float* Linv,
+                      const int* lptr, const int* lsrc, const int* sbu, const int* sbl, float* blk, uint32_t* blk16,
+                      int* scol, int2* sent, hipStream_t s) {
+  const int g = div_up((long long)nslices * kSlice, kBlock);
+  hipLaunchKernelGGL(k_sell_upper, dim3(g), dim3(kBlock), 0, s, N, nslices, row_ptr, col, vals, Linv, sbu, blk, blk16,
+                     scol);
+  hipLaunchKernelGGL(k_sell_lower, dim3(g), dim3(kBlock), 0, s, N, nslices, row_ptr, col, lptr, lsrc, sbu, sbl, sent);
 }
 
 void launch_row_diag_slots(int N, const int* row_ptr, int* diag, hipStream_t s) {

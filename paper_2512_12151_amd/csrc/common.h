@@ -28,21 +28,58 @@ constexpr int kBlock = 256;        // default workgroup size (4 waves)
 
 // Device-resident scalars of one PCG solve (see pcg.hip for who writes what).
 struct PcgScalars {
-  double rho;        // r^T r of the scaled system (= r^T M^{-1} r of the original)
-  double pp;         // p^T p
-  double pq;         // p^T H p
-  double alpha, beta;
+  double rho;        // r^T r of the scaled system (= r^T D^{-1} r of the original)
   double rr_true;    // |L r|^2 = unscaled residual norm squared (when checked)
   double bb;         // |b|^2 (unscaled)
   double tol2;       // tol^2
   double stat_pinf;  // max |p_i| of the result
   double stat_viol;  // max_i max(0, -c_i)
-  int iter2;         // iteration index seen by the update kernel (written by its workgroup 0)
-  int iter3;         // completed iterations (written by workgroup 0 of the direction kernel)
-  int done;          // 1: converged, 2: max_iter, 3: breakdown
+  int iter;          // completed iterations (written by workgroup 0 of the update kernel)
+  int ks;            // iteration index of the last SpMV (written by its workgroup 0)
+  int done;          // 1: converged, 2: max_iter (written by workgroup 0 of the SpMV)
+  int brk;           // 1: breakdown p^T H p <= 0 (written by workgroup 0 of the update kernel)
   int max_iter;
   int check_every;
   int flags;         // FLAG_* bits
+};
+
+// Partials of one PCG system: every workgroup writes one FP64 value per sum.
+constexpr int kMaxVecParts = 1024;    // workgroups of the update kernel per system
+constexpr int kMaxSpmvParts = 2048;   // workgroups of the SpMV per system
+constexpr int kPartRR = 0;                              // r^T r, two slots (iterations k, k+1)
+constexpr int kPartRT = 2 * kMaxVecParts;               // |L r|^2
+constexpr int kPartPQ = 3 * kMaxVecParts;               // p^T H p
+constexpr int kPartsPerSystem = 3 * kMaxVecParts + kMaxSpmvParts;
+
+constexpr int kSlice = 64;         // rows per slice of the sliced block storage (one wavefront)
+
+// One symmetric block system of the PCG, H_hat = L^{-1} H L^{-T} with identity
+// diagonal blocks, in sliced storage (kSlice consecutive rows per slice, slot k
+// of the row in lane l of slice s at sbu[s] + k * kSlice + l):
+//   upper slots  blk (FP32 9 floats, or BF16 5 words) and scol: the upper
+//                off-diagonal blocks of the row and their columns;
+//   lower slots  sent = (upper slot, source row r) of every upper block (r, c)
+//                of the row's column c, by increasing r;
+// padded slots hold a zero block.  Vectors are FP32 SoA [3][N4] (N4 = N
+// rounded up to 4; pads are zero), Lf is SoA [6][N4].  The SpMV grid gives this
+// system spmv_nwg workgroups of 4 slices each; the update grid vec_nwg.
+struct PcgSystem {
+  int N, N4, nslices;
+  const int* sbu;    // [nslices + 1]
+  const int* sbl;    // [nslices + 1]
+  const int* scol;
+  const void* blk;
+  const int2* sent;
+  const float* Lf;
+  float* x;
+  float* r;
+  float* P0;
+  float* P1;
+  float* q;
+  double* part;      // kPartsPerSystem
+  PcgScalars* sc;
+  int spmv_wg0, spmv_nwg;
+  int vec_wg0, vec_nwg;
 };
 
 __host__ __device__ inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
@@ -122,33 +159,49 @@ void launch_assemble_rows(int N, const int* row_ptr, const int* col, const int* 
                           const float* mass, const double* xh, const double* xt, const uint8_t* fixed,
                           float* vals, float* grad, float* Lf, float* Linv, float* bhat, double* bb_part,
                           int* flags, hipStream_t s);
-// Scaled upper off-diagonal blocks as SoA [9][stride] and the transpose index
-// (lower_count / lower_fill / sort_segments give, per column, the source rows;
-// transpose_index turns them into upper block indices).
+// Sliced storage of the scaled matrix: lower_count / lower_fill /
+// sort_segments give, per column, the source rows of its upper blocks;
+// slice_widths gives the slot counts per slice (64 x the widest row), whose
+// exclusive scans are sbu / sbl; sell_fill writes the upper slots (FP32 and,
+// when blk16 is set, BF16) and the lower references.
 void launch_lower_count(int N, const int* row_ptr, const int* col, int* lcnt, hipStream_t s);
 void launch_lower_fill(int N, const int* row_ptr, const int* col, const int* lptr, int* lcur, int* lsrc,
                        hipStream_t s);
-void launch_scale_upper(int N, const int* row_ptr, const int* col, const float* vals, const float* Linv, float* uvals,
-                        int* ucol, int* urow_ptr, long long ustride, hipStream_t s);
-void launch_transpose_index(int N, const int* row_ptr, const int* col, const int* lptr, const int* lsrc, int* tidx,
-                            hipStream_t s);
+void launch_slice_widths(int N, int nslices, const int* row_ptr, const int* lptr, int* cu, int* cl, hipStream_t s);
+void launch_sell_fill(int N, int nslices, const int* row_ptr, const int* col, const float* vals, const float* Linv,
+                      const int* lptr, const int* lsrc, const int* sbu, const int* sbl, float* blk, uint32_t* blk16,
+                      int* scol, int2* sent, hipStream_t s);
 void launch_row_diag_slots(int N, const int* row_ptr, int* diag, hipStream_t s);
 
 // pcg.hip
-int pcg_partials_needed(int N);
-void launch_pcg_init(int N, const float* bhat, float* x, float* r, float* p, double* part,
-                     const double* bb_part, int nbb, PcgScalars* sc, double tol, int max_iter,
+// Workgroup counts of one system.
+int pcg_spmv_groups(int N);
+int pcg_vec_groups(int N);
+// x = 0, r = b_hat, |b|^2 from the assembly's partials, scalars reset.
+void launch_pcg_init(const PcgSystem& S, const float* bhat, const double* bb_part, int nbb, double tol, int max_iter,
                      int check_every, hipStream_t s);
-// One PCG iteration = launch_pcg_spmv then launch_pcg_vector_ops (update + direction).
-// The SpMV's first phase writes q_row = p + (upper part) p and, for every upper
-// block j, its transposed product B_j^T p_r into tbuf; launch_pcg_vector_ops
-// completes q = q_row + sum of tbuf over the transpose index, then updates.
-void launch_pcg_spmv(int N, const int* urow_ptr, const int* ucol, const float* uvals, long long ustride,
-                     const float* p, float* qrow, float* tbuf, double* part, PcgScalars* sc, hipStream_t s);
-void launch_pcg_vector_ops(int N, const float* Lf, float* x, float* r, float* p, const float* qrow,
-                           const float* tbuf, const int* tptr, const int* tidx, double* part, PcgScalars* sc,
-                           hipStream_t s);
-void launch_pcg_finish(int N, const float* Linv, const float* x, double* pout, double* part,
-                       PcgScalars* sc, const double* viol_part, int nviol, hipStream_t s);
+// One PCG iteration of one system: the SpMV kernel (direction p = r + beta p
+// fused in, q = H_hat p, p^T q) then the update kernel (x, r, r^T r, |L r|^2).
+// bf16 selects the BF16 block copy.
+void launch_pcg_iteration(const PcgSystem& S, bool bf16, hipStream_t s);
+// The same iteration for several systems in one launch pair: sys[] (device)
+// lists them, wg_sys_spmv / wg_sys_vec map each workgroup to its system.
+void launch_pcg_iteration_batched(const PcgSystem* sys, const int* wg_sys_spmv, int nwg_spmv, const int* wg_sys_vec,
+                                  int nwg_vec, bool bf16, hipStream_t s);
+// p = L^{-T} x in FP64 and the stats (max |p|, max violation).
+void launch_pcg_finish(const PcgSystem& S, const float* Linv, double* pout, const double* viol_part, int nviol,
+                       hipStream_t s);
+// Iterative refinement around BF16 inner solves: rd = b_hat - H_hat xd in FP64
+// with the FP32 blocks (S.blk must be the FP32 storage), partials of |L rd|^2
+// into rpart[spmv_nwg] and their sum into *rsum; an inner solve started from
+// rd with bb = the sum of rpart; xd += the inner solution; p = L^{-T} xd.
+void launch_residual64(const PcgSystem& S, const float* bhat, const double* xd, double* rd, double* rpart,
+                       double* rsum, hipStream_t s);
+void launch_sum_to(const double* part, int n, double* out, hipStream_t s);
+void launch_pcg_init_from64(const PcgSystem& S, const double* rd, const double* rpart, int nparts, double tol,
+                            int max_iter, int check_every, hipStream_t s);
+void launch_axpy64(const PcgSystem& S, double* xd, hipStream_t s);
+void launch_pcg_finish64(const PcgSystem& S, const float* Linv, const double* xd, double* pout,
+                         const double* viol_part, int nviol, hipStream_t s);
 
 }  // namespace bfal

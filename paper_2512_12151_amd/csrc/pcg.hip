@@ -1,42 +1,52 @@
 // Block-Jacobi preconditioned CG (the paper's linear solver: CG with a 3x3
-// block-Jacobi preconditioner on the symmetric BSR matrix), run on the
-// symmetrically scaled system H_hat = L^{-1} H L^{-T} (D_v = L_v L_v^T), whose
-// diagonal blocks are identities.  In exact arithmetic its iterates are those
-// of PCG with z = D^{-1} r on H: p = L^{-T} p_hat, r = L r_hat.
+// block-Jacobi preconditioner on the symmetric BSR matrix, Section 5.1), run on
+// the symmetrically scaled system H_hat = L^{-1} H L^{-T} (D_v = L_v L_v^T),
+// whose diagonal blocks are identities.  In exact arithmetic its iterates are
+// those of PCG with z = D^{-1} r on H: p = L^{-T} p_hat, r = L r_hat.
 //
-// Only the upper off-diagonal blocks of H_hat are stored and each is read once
-// per iteration.  The symmetric product q = H_hat p runs in two phases with no
-// atomics: the SpMV kernel forms, per row r, q_row = p_r + sum_{c>r} B_rc p_c
-// and writes every block's transposed product t_j = B_rc^T p_r to its own slot
-// of tbuf; the update kernel completes q_c = q_row_c + sum of t_j over the
-// blocks j in column c (the transpose index, in increasing source row).
-// p^T H_hat p = sum_r p_r.(p_r + 2 sum_{c>r} B_rc p_c) is formed in the first
-// phase.  One iteration is three kernels on one stream, with no host round trip:
-//   spmv      q_row, tbuf, p^T q (FP64)
-//   update    q = q_row + transposed sums; alpha = rho / p^T q; x += alpha p,
-//             r -= alpha q; rho' = r^T r (FP64); every check_every iterations
-//             also |L r|^2, the unscaled residual norm squared.
-//   direction beta = rho' / rho, convergence test, p = r + beta p.
+// One iteration is two kernels on one stream, with no host round trip:
+//   spmv    convergence test on r_k; beta = rho_k / rho_{k-1};
+//           p_k = r_k + beta p_{k-1} (formed on the fly wherever p is read and
+//           stored by the row owner into the other buffer of a pair);
+//           q = H_hat p_k = p_k + sum over the stored upper blocks of the row
+//           (B_rc p_c) + sum over the upper blocks of its column (B_cr^T p_c);
+//           p^T q (FP64).
+//   update  alpha = rho_k / p^T q; x += alpha p, r -= alpha q; rho_{k+1} =
+//           r^T r (FP64); every check_every iterations also |L r|^2, the
+//           unscaled residual norm squared.
+// The upper blocks are stored once, in slices of 64 rows with one lane per row
+// (slot k of all 64 rows contiguous), and read twice per iteration: streamed
+// for the upper part, and gathered through per-row references for the lower
+// part.  On a structured mesh the rows of a slice have the same stencil, so the
+// lower references of slot k point at consecutive slots of the source slice
+// and the p gathers of a slot are consecutive nodes: every access of the SpMV
+// is a contiguous run per wavefront.  Workgroups are mapped so each XCD owns
+// one contiguous range of slices; the whole upper matrix of the large workload
+// (~150 MB) fits the 256 MB Infinity Cache.
+//
 // Grid-wide sums: every workgroup writes one FP64 partial per quantity, and
 // every workgroup of the *next* kernel re-sums all partials in the same fixed
 // order, so every workgroup derives bit-identical scalars without any device
 // fence or atomic (kernel boundaries make the partials visible).  Scalars the
-// host polls (iteration count, convergence flag, residual) are written by
-// workgroup 0 only, into fields no other workgroup of that kernel reads.
-// After the flag is set every kernel returns at entry, so the host enqueues
-// iterations in batches and polls between batches.
+// host polls are written by workgroup 0 of a system only, into fields that no
+// workgroup of the same kernel reads: the SpMV writes `done` and `ks` and reads
+// `iter` and `brk`; the update kernel writes `iter` and `brk` and reads `done`
+// and `ks`.  Once a system has converged its SpMV workgroups re-derive that
+// from the unchanged partials and return, and its update workgroups see
+// `done`; so the host enqueues iterations in batches and polls between them.
+//
+// The same kernels serve a batch of independent systems: each workgroup looks
+// up its system in a table, so a batch is a block-diagonal system whose
+// scalars (alpha, beta, convergence) are kept per system.
 #include "common.h"
 
 namespace bfal {
 
 namespace {
 
-constexpr int kVecBlock = 1024;                    // threads per workgroup of the vector kernels
-constexpr int kGridVec = 256;                      // workgroups of the vector kernels (partials per sum)
-constexpr int kSpmvBlock = 512;                    // threads per workgroup of the SpMV
-constexpr int kGridSpmv = 1024;                    // workgroups of the SpMV (multiple of 8 XCDs)
-constexpr int kGroup = 8;                          // lanes per BSR row in the SpMV
-constexpr int kRowsPerPass = kSpmvBlock / kGroup;  // rows per workgroup pass in the SpMV
+constexpr int kSpmvBlock = 256;                    // threads per SpMV workgroup (4 slices)
+constexpr int kSlicesPerGroup = kSpmvBlock / kSlice;
+constexpr int kVecBlock = 256;                     // threads per update workgroup (4 nodes per thread)
 
 // Sum of v over a workgroup of NT threads, returned to every thread (fixed shuffle/LDS order).
 template <int NT>
@@ -75,173 +85,239 @@ __device__ inline double sum_parts(const double* __restrict__ part, int n) {
   return block_sum_all<NT>(s);
 }
 
-// Write this workgroup's partial (thread 0).
-__device__ inline void put_part(double* part, double v) {
-  if (threadIdx.x == 0) part[blockIdx.x] = v;
+// Dispatch ids go round-robin over the 8 XCDs: give each XCD one contiguous
+// range of logical workgroups.
+__device__ inline int xcd_block(int b, int nb) { return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b; }
+
+__device__ inline void load_block(const float* __restrict__ u, int j, float b[9]) {
+  const float* s = u + 9LL * j;
+#pragma unroll
+  for (int m = 0; m < 9; ++m) b[m] = s[m];
 }
 
-// XCD-aware workgroup index: dispatch ids round-robin over the 8 XCDs, so give
-// each XCD one contiguous range of rows (better L2 reuse of the gathered p).
-__device__ inline int xcd_block() {
-  const int nb = gridDim.x;
-  const int b = blockIdx.x;
-  return (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
-}
-
-// Smallest row r with frow_ptr[r] >= target (N when none); the last range ends at N.
-__device__ inline int first_row_at(const int* __restrict__ frow_ptr, int N, long long target) {
-  int lo = 0, hi = N;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (frow_ptr[mid] < target) lo = mid + 1; else hi = mid;
+// BF16 block: 10 half-words in 5 words, element 2i in the low half of word i.
+__device__ inline void load_block(const uint32_t* __restrict__ u, int j, float b[9]) {
+  const uint32_t* s = u + 5LL * j;
+  uint32_t w[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) w[m] = s[m];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    b[2 * m] = __uint_as_float(w[m] << 16);
+    b[2 * m + 1] = __uint_as_float(w[m] & 0xffff0000u);
   }
-  return lo;
+  b[8] = __uint_as_float(w[4] << 16);
 }
 
-__global__ void __launch_bounds__(kSpmvBlock)
-k_spmv(int N, const int* __restrict__ urow_ptr, const int* __restrict__ ucol, const float* __restrict__ uv,
-       long long st, const float* __restrict__ p, float* __restrict__ qrow, float* __restrict__ tbuf,
-       double* __restrict__ part_pq, const PcgScalars* __restrict__ sc) {
-  if (sc->done) return;
-  // rows [r0, r1) hold about 1/gridDim.x of the stored blocks (rows with
-  // contact blocks are longer, and they cluster at the interfaces)
-  const int lb = xcd_block();
-  const long long nnz = urow_ptr[N];
-  const int r0 = first_row_at(urow_ptr, N, (nnz * lb) / gridDim.x);
-  const int r1 = (lb == (int)gridDim.x - 1) ? N : first_row_at(urow_ptr, N, (nnz * (lb + 1)) / gridDim.x);
-  const int g = threadIdx.x / kGroup, k = threadIdx.x % kGroup;
+// Scalars at the start of SpMV k: returns false when the system is finished
+// (converged, capped) and the workgroup must return.  Called by the whole workgroup.
+__device__ inline bool spmv_scalars(const PcgSystem& S, bool leader, int& k, float& beta) {
+  PcgScalars* sc = S.sc;
+  if (sc->brk) return false;
+  k = sc->iter;
+  const double* part = S.part;
+  const double rho = sum_parts<kSpmvBlock>(part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg);
+  beta = 0.f;
+  if (k > 0) {
+    const bool check = (k % sc->check_every) == 0;
+    const double rt = check ? sum_parts<kSpmvBlock>(part + kPartRT, S.vec_nwg) : 0.0;
+    const bool converged = (check && rt <= sc->tol2 * sc->bb) || rho == 0.0;
+    const bool capped = k >= sc->max_iter;
+    if (leader) {
+      sc->rho = rho;
+      if (check) sc->rr_true = rt;
+      if (converged) sc->done = 1;
+      else if (capped) sc->done = 2;
+    }
+    if (converged || capped) return false;
+    const double rho_old = sum_parts<kSpmvBlock>(part + kPartRR + ((k + 1) & 1) * kMaxVecParts, S.vec_nwg);
+    beta = (float)(rho / rho_old);
+  }
+  if (leader) sc->ks = k;
+  return true;
+}
+
+// q = H_hat p_k for the slices of workgroup lb (of nwg) of one system, p_k
+// formed on the fly; returns this thread's share of p^T q.
+template <class BT>
+__device__ inline double spmv_slices(const PcgSystem& S, int lb, int nwg, int k, float beta) {
+  const int wave = threadIdx.x / kSlice, lane = threadIdx.x % kSlice;
+  const long long n4 = S.N4;
+  const float* __restrict__ r0 = S.r;
+  const float* __restrict__ r1 = S.r + n4;
+  const float* __restrict__ r2 = S.r + 2 * n4;
+  const float* __restrict__ pold = (k & 1) ? S.P0 : S.P1;
+  const float* __restrict__ o0 = pold;
+  const float* __restrict__ o1 = pold + n4;
+  const float* __restrict__ o2 = pold + 2 * n4;
+  float* __restrict__ pn = (k & 1) ? S.P1 : S.P0;
+  const BT* __restrict__ blk = static_cast<const BT*>(S.blk);
+  const int* __restrict__ scol = S.scol;
+  const int2* __restrict__ sent = S.sent;
+  const bool first = (k == 0);
   double dot = 0.0;
-  for (int rb = r0; rb < r1; rb += kRowsPerPass) {
-    const int r = rb + g;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, pr0 = 0.f, pr1 = 0.f, pr2 = 0.f;
-    if (r < r1) {
-      pr0 = p[3LL * r]; pr1 = p[3LL * r + 1]; pr2 = p[3LL * r + 2];
-      const int je = urow_ptr[r + 1];
-      for (int j = urow_ptr[r] + k; j < je; j += kGroup) {
-        const int c = ucol[j];
-        float b[9];
-#pragma unroll
-        for (int m = 0; m < 9; ++m) b[m] = uv[m * st + j];
-        const float pc0 = p[3LL * c], pc1 = p[3LL * c + 1], pc2 = p[3LL * c + 2];
-        a0 += b[0] * pc0 + b[1] * pc1 + b[2] * pc2;
-        a1 += b[3] * pc0 + b[4] * pc1 + b[5] * pc2;
-        a2 += b[6] * pc0 + b[7] * pc1 + b[8] * pc2;
-        float* t = tbuf + 3LL * j;
-        t[0] = b[0] * pr0 + b[3] * pr1 + b[6] * pr2;
-        t[1] = b[1] * pr0 + b[4] * pr1 + b[7] * pr2;
-        t[2] = b[2] * pr0 + b[5] * pr1 + b[8] * pr2;
+  for (int sl = lb * kSlicesPerGroup + wave; sl < S.nslices; sl += nwg * kSlicesPerGroup) {
+    const int bu = S.sbu[sl], wu = (S.sbu[sl + 1] - bu) / kSlice;
+    const int bl = S.sbl[sl], wl = (S.sbl[sl + 1] - bl) / kSlice;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    for (int kk = 0; kk < wu; ++kk) {
+      const int e = bu + kk * kSlice + lane;
+      const int c = scol[e];
+      float b[9];
+      load_block(blk, e, b);
+      float p0 = r0[c], p1 = r1[c], p2 = r2[c];
+      if (!first) {
+        p0 = __fmaf_rn(beta, o0[c], p0);
+        p1 = __fmaf_rn(beta, o1[c], p1);
+        p2 = __fmaf_rn(beta, o2[c], p2);
       }
+      a0 += b[0] * p0 + b[1] * p1 + b[2] * p2;
+      a1 += b[3] * p0 + b[4] * p1 + b[5] * p2;
+      a2 += b[6] * p0 + b[7] * p1 + b[8] * p2;
     }
-#pragma unroll
-    for (int off = kGroup / 2; off > 0; off >>= 1) {
-      a0 += __shfl_xor(a0, off, kGroup);
-      a1 += __shfl_xor(a1, off, kGroup);
-      a2 += __shfl_xor(a2, off, kGroup);
+    for (int kk = 0; kk < wl; ++kk) {
+      const int2 t = sent[bl + kk * kSlice + lane];
+      const int c = t.y;
+      float b[9];
+      load_block(blk, t.x, b);
+      float p0 = r0[c], p1 = r1[c], p2 = r2[c];
+      if (!first) {
+        p0 = __fmaf_rn(beta, o0[c], p0);
+        p1 = __fmaf_rn(beta, o1[c], p1);
+        p2 = __fmaf_rn(beta, o2[c], p2);
+      }
+      a0 += b[0] * p0 + b[3] * p1 + b[6] * p2;
+      a1 += b[1] * p0 + b[4] * p1 + b[7] * p2;
+      a2 += b[2] * p0 + b[5] * p1 + b[8] * p2;
     }
-    if (r < r1 && k == 0) {
-      qrow[3LL * r] = pr0 + a0;   // identity diagonal block + upper part
-      qrow[3LL * r + 1] = pr1 + a1;
-      qrow[3LL * r + 2] = pr2 + a2;
-      dot += (double)pr0 * pr0 + (double)pr1 * pr1 + (double)pr2 * pr2 +
-             2.0 * ((double)pr0 * a0 + (double)pr1 * a1 + (double)pr2 * a2);
+    const int row = sl * kSlice + lane;
+    if (row < S.N) {
+      float s0 = r0[row], s1 = r1[row], s2 = r2[row];
+      if (!first) {
+        s0 = __fmaf_rn(beta, o0[row], s0);
+        s1 = __fmaf_rn(beta, o1[row], s1);
+        s2 = __fmaf_rn(beta, o2[row], s2);
+      }
+      const float q0 = s0 + a0, q1 = s1 + a1, q2 = s2 + a2;
+      pn[row] = s0; pn[n4 + row] = s1; pn[2 * n4 + row] = s2;
+      S.q[row] = q0; S.q[n4 + row] = q1; S.q[2 * n4 + row] = q2;
+      dot += (double)s0 * q0 + (double)s1 * q1 + (double)s2 * q2;
     }
   }
-  put_part(part_pq, block_sum_all<kSpmvBlock>(dot));
+  return dot;
 }
 
-__global__ void __launch_bounds__(kVecBlock)
-k_update(int N, const float* __restrict__ Lf, float* __restrict__ x, float* __restrict__ r,
-         const float* __restrict__ p, const float* __restrict__ qrow, const float* __restrict__ tbuf,
-         const int* __restrict__ tptr, const int* __restrict__ tidx, const double* __restrict__ part_pq, int n_pq,
-         double* __restrict__ part_rr, double* __restrict__ part_rt, PcgScalars* __restrict__ sc) {
+template <class BT>
+__global__ void __launch_bounds__(kSpmvBlock) k_spmv(PcgSystem S) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  int k;
+  float beta;
+  if (!spmv_scalars(S, lb == 0 && threadIdx.x == 0, k, beta)) return;
+  const double dot = spmv_slices<BT>(S, lb, gridDim.x, k, beta);
+  const double s = block_sum_all<kSpmvBlock>(dot);
+  if (threadIdx.x == 0) S.part[kPartPQ + lb] = s;
+}
+
+template <class BT>
+__global__ void __launch_bounds__(kSpmvBlock) k_spmv_batched(const PcgSystem* __restrict__ sys,
+                                                              const int* __restrict__ wg_sys) {
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const PcgSystem S = sys[wg_sys[b]];
+  const int lb = b - S.spmv_wg0;
+  int k;
+  float beta;
+  if (!spmv_scalars(S, lb == 0 && threadIdx.x == 0, k, beta)) return;
+  const double dot = spmv_slices<BT>(S, lb, S.spmv_nwg, k, beta);
+  const double s = block_sum_all<kSpmvBlock>(dot);
+  if (threadIdx.x == 0) S.part[kPartPQ + lb] = s;
+}
+
+// alpha, then x += alpha p, r -= alpha q over the nodes of workgroup lb of nwg.
+__device__ inline void update_nodes(const PcgSystem& S, int lb) {
+  PcgScalars* sc = S.sc;
   if (sc->done) return;
-  const int k = sc->iter3;
-  const double rho = sum_parts<kVecBlock>(part_rr + (k & 1) * kGridVec, gridDim.x);
-  const double pq = sum_parts<kVecBlock>(part_pq, n_pq);
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc->iter2 = k;
+  const int k = sc->ks;
+  double* part = S.part;
+  const double rho = sum_parts<kVecBlock>(part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg);
+  const double pq = sum_parts<kVecBlock>(part + kPartPQ, S.spmv_nwg);
+  const bool leader = lb == 0 && threadIdx.x == 0;
   if (!(pq > 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (leader) {
       sc->flags |= FLAG_BREAKDOWN;
-      sc->done = 3;
+      sc->brk = 1;
     }
     return;
   }
   const float alpha = (float)(rho / pq);
   const bool check = ((k + 1) % sc->check_every) == 0;
+  const long long n4 = S.N4 / 4;   // float4 per component
+  const float4* __restrict__ p4 = reinterpret_cast<const float4*>((k & 1) ? S.P1 : S.P0);
+  const float4* __restrict__ q4 = reinterpret_cast<const float4*>(S.q);
+  float4* __restrict__ x4 = reinterpret_cast<float4*>(S.x);
+  float4* __restrict__ r4 = reinterpret_cast<float4*>(S.r);
+  const float4* __restrict__ l4 = reinterpret_cast<const float4*>(S.Lf);
   double rr = 0.0, rt = 0.0;
-  for (int v = blockIdx.x * kVecBlock + threadIdx.x; v < N; v += gridDim.x * kVecBlock) {
-    const long long o = 3LL * v;
-    float q0 = qrow[o], q1 = qrow[o + 1], q2 = qrow[o + 2];
-    for (int i = tptr[v]; i < tptr[v + 1]; ++i) {
-      const float* t = tbuf + 3LL * tidx[i];
-      q0 += t[0];
-      q1 += t[1];
-      q2 += t[2];
+  for (long long i = (long long)lb * kVecBlock + threadIdx.x; i < n4; i += (long long)S.vec_nwg * kVecBlock) {
+    float4 rn[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const float4 p = p4[m * n4 + i], q = q4[m * n4 + i];
+      float4 x = x4[m * n4 + i], r = r4[m * n4 + i];
+      x.x = __fmaf_rn(alpha, p.x, x.x); x.y = __fmaf_rn(alpha, p.y, x.y);
+      x.z = __fmaf_rn(alpha, p.z, x.z); x.w = __fmaf_rn(alpha, p.w, x.w);
+      r.x = __fmaf_rn(-alpha, q.x, r.x); r.y = __fmaf_rn(-alpha, q.y, r.y);
+      r.z = __fmaf_rn(-alpha, q.z, r.z); r.w = __fmaf_rn(-alpha, q.w, r.w);
+      x4[m * n4 + i] = x;
+      r4[m * n4 + i] = r;
+      rn[m] = r;
+      rr += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
     }
-    const float r0 = r[o] - alpha * q0, r1 = r[o + 1] - alpha * q1, r2 = r[o + 2] - alpha * q2;
-    x[o] += alpha * p[o];
-    x[o + 1] += alpha * p[o + 1];
-    x[o + 2] += alpha * p[o + 2];
-    r[o] = r0;
-    r[o + 1] = r1;
-    r[o + 2] = r2;
-    rr += (double)r0 * r0 + (double)r1 * r1 + (double)r2 * r2;
     if (check) {
-      const float* l = Lf + 6LL * v;
-      const double t0 = (double)l[0] * r0;
-      const double t1 = (double)l[1] * r0 + (double)l[2] * r1;
-      const double t2 = (double)l[3] * r0 + (double)l[4] * r1 + (double)l[5] * r2;
-      rt += t0 * t0 + t1 * t1 + t2 * t2;
+      float4 l[6];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) l[m] = l4[m * n4 + i];
+      const float lx[6][4] = {{l[0].x, l[0].y, l[0].z, l[0].w}, {l[1].x, l[1].y, l[1].z, l[1].w},
+                              {l[2].x, l[2].y, l[2].z, l[2].w}, {l[3].x, l[3].y, l[3].z, l[3].w},
+                              {l[4].x, l[4].y, l[4].z, l[4].w}, {l[5].x, l[5].y, l[5].z, l[5].w}};
+      const float rx[3][4] = {{rn[0].x, rn[0].y, rn[0].z, rn[0].w}, {rn[1].x, rn[1].y, rn[1].z, rn[1].w},
+                              {rn[2].x, rn[2].y, rn[2].z, rn[2].w}};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double t0 = (double)lx[0][v] * rx[0][v];
+        const double t1 = (double)lx[1][v] * rx[0][v] + (double)lx[2][v] * rx[1][v];
+        const double t2 = (double)lx[3][v] * rx[0][v] + (double)lx[4][v] * rx[1][v] + (double)lx[5][v] * rx[2][v];
+        rt += t0 * t0 + t1 * t1 + t2 * t2;
+      }
     }
   }
-  put_part(part_rr + ((k + 1) & 1) * kGridVec, block_sum_all<kVecBlock>(rr));
-  put_part(part_rt, block_sum_all<kVecBlock>(rt));
+  const double srr = block_sum_all<kVecBlock>(rr);
+  const double srt = block_sum_all<kVecBlock>(rt);
+  if (threadIdx.x == 0) {
+    part[kPartRR + ((k + 1) & 1) * kMaxVecParts + lb] = srr;
+    part[kPartRT + lb] = srt;
+  }
+  if (leader) sc->iter = k + 1;
+}
+
+__global__ void __launch_bounds__(kVecBlock) k_update(PcgSystem S) { update_nodes(S, blockIdx.x); }
+
+__global__ void __launch_bounds__(kVecBlock) k_update_batched(const PcgSystem* __restrict__ sys,
+                                                             const int* __restrict__ wg_sys) {
+  const PcgSystem S = sys[wg_sys[blockIdx.x]];
+  update_nodes(S, blockIdx.x - S.vec_wg0);
 }
 
 __global__ void __launch_bounds__(kVecBlock)
-k_direction(int N4, const float* __restrict__ r, float* __restrict__ p, const double* __restrict__ part_rr,
-            const double* __restrict__ part_rt, PcgScalars* __restrict__ sc) {
-  if (sc->done) return;
-  const int k = sc->iter2;
-  const double rho_old = sum_parts<kVecBlock>(part_rr + (k & 1) * kGridVec, gridDim.x);
-  const double rho_new = sum_parts<kVecBlock>(part_rr + ((k + 1) & 1) * kGridVec, gridDim.x);
-  const bool check = ((k + 1) % sc->check_every) == 0;
-  const double rt = check ? sum_parts<kVecBlock>(part_rt, gridDim.x) : 0.0;
-  const bool converged = (check && rt <= sc->tol2 * sc->bb) || rho_new == 0.0;
-  const bool capped = (k + 1) >= sc->max_iter;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc->iter3 = k + 1;
-    sc->rho = rho_new;
-    if (check) sc->rr_true = rt;
-    if (converged) sc->done = 1;
-    else if (capped) sc->done = 2;
-  }
-  if (converged || capped) return;
-  const float beta = (float)(rho_new / rho_old);
-  const int nf4 = 3 * (N4 / 4);
-  const float4* r4 = reinterpret_cast<const float4*>(r);
-  float4* p4 = reinterpret_cast<float4*>(p);
-  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < nf4; i += gridDim.x * kVecBlock) {
-    const float4 rv = r4[i];
-    float4 pv = p4[i];
-    pv.x = rv.x + beta * pv.x; pv.y = rv.y + beta * pv.y; pv.z = rv.z + beta * pv.z; pv.w = rv.w + beta * pv.w;
-    p4[i] = pv;
-  }
-}
-
-__global__ void __launch_bounds__(kVecBlock)
-k_init(int N4, const float* __restrict__ bhat, float* __restrict__ x, float* __restrict__ r, float* __restrict__ p,
-       double* __restrict__ part_rr) {
+k_init(int n3, const float* __restrict__ bhat, float* __restrict__ x, float* __restrict__ r, double* __restrict__ part) {
   double rr = 0.0;
-  const long long n3 = 3LL * N4;
-  for (long long i = (long long)blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += (long long)gridDim.x * kVecBlock) {
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) {
     const float b = bhat[i];
     x[i] = 0.f;
     r[i] = b;
-    p[i] = b;
     rr += (double)b * b;
   }
-  put_part(part_rr, block_sum_all<kVecBlock>(rr));   // iteration 0 reads slot (0 & 1) = 0
+  const double s = block_sum_all<kVecBlock>(rr);
+  if (threadIdx.x == 0) part[kPartRR + blockIdx.x] = s;   // iteration 0 reads slot 0
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -253,23 +329,25 @@ k_init_scalars(const double* __restrict__ bb_part, int nbb, PcgScalars* sc, doub
     sc->rr_true = bb;
     sc->rho = 0.0;
     sc->tol2 = tol * tol;
-    sc->iter2 = 0;
-    sc->iter3 = 0;
+    sc->iter = 0;
+    sc->ks = 0;
     sc->max_iter = max_iter;
     sc->check_every = check_every > 0 ? check_every : 1;
     sc->flags = 0;
+    sc->brk = 0;
     sc->done = (bb == 0.0) ? 1 : (max_iter <= 0 ? 2 : 0);
   }
 }
 
-// p = L^{-T} p_hat in FP64 and the per-workgroup max |p|.
+// p = L^{-T} x in FP64 (x FP32 or FP64, SoA [3][N4]) and the per-workgroup max |p|.
+template <class XT>
 __global__ void __launch_bounds__(kVecBlock)
-k_finish(int N, const float* __restrict__ Linv, const float* __restrict__ x, double* __restrict__ pout,
+k_finish(int N, int N4, const float* __restrict__ Linv, const XT* __restrict__ x, double* __restrict__ pout,
          double* __restrict__ part) {
   double m = 0.0;
   for (int v = blockIdx.x * kVecBlock + threadIdx.x; v < N; v += gridDim.x * kVecBlock) {
     const float* l = Linv + 6LL * v;
-    const double x0 = x[3LL * v], x1 = x[3LL * v + 1], x2 = x[3LL * v + 2];
+    const double x0 = x[v], x1 = x[N4 + v], x2 = x[2LL * N4 + v];
     const double p0 = (double)l[0] * x0 + (double)l[1] * x1 + (double)l[3] * x2;
     const double p1 = (double)l[2] * x1 + (double)l[4] * x2;
     const double p2 = (double)l[5] * x2;
@@ -280,6 +358,88 @@ k_finish(int N, const float* __restrict__ Linv, const float* __restrict__ x, dou
   }
   const double s = block_max_all<kVecBlock>(m);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// ------------------------------------------------ iterative refinement
+// The outer loop of the BF16 mode keeps the solution x_hat in FP64 and forms
+// the residual of the FP32-stored system in FP64: r = b_hat - H_hat x_hat,
+// with the FP32 blocks widened to FP64 (the same sliced storage and access
+// pattern as the SpMV), plus the per-workgroup partials of |L r|^2.
+__global__ void __launch_bounds__(kSpmvBlock)
+k_residual64(PcgSystem S, const float* __restrict__ bhat, const double* __restrict__ xd, double* __restrict__ rd,
+             double* __restrict__ part) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int wave = threadIdx.x / kSlice, lane = threadIdx.x % kSlice;
+  const long long n4 = S.N4;
+  const float* __restrict__ blk = static_cast<const float*>(S.blk);
+  double rt = 0.0;
+  for (int sl = lb * kSlicesPerGroup + wave; sl < S.nslices; sl += gridDim.x * kSlicesPerGroup) {
+    const int bu = S.sbu[sl], wu = (S.sbu[sl + 1] - bu) / kSlice;
+    const int bl = S.sbl[sl], wl = (S.sbl[sl + 1] - bl) / kSlice;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int kk = 0; kk < wu; ++kk) {
+      const int e = bu + kk * kSlice + lane;
+      const int c = S.scol[e];
+      float b[9];
+      load_block(blk, e, b);
+      const double x0 = xd[c], x1 = xd[n4 + c], x2 = xd[2 * n4 + c];
+      a0 += (double)b[0] * x0 + (double)b[1] * x1 + (double)b[2] * x2;
+      a1 += (double)b[3] * x0 + (double)b[4] * x1 + (double)b[5] * x2;
+      a2 += (double)b[6] * x0 + (double)b[7] * x1 + (double)b[8] * x2;
+    }
+    for (int kk = 0; kk < wl; ++kk) {
+      const int2 t = S.sent[bl + kk * kSlice + lane];
+      const int c = t.y;
+      float b[9];
+      load_block(blk, t.x, b);
+      const double x0 = xd[c], x1 = xd[n4 + c], x2 = xd[2 * n4 + c];
+      a0 += (double)b[0] * x0 + (double)b[3] * x1 + (double)b[6] * x2;
+      a1 += (double)b[1] * x0 + (double)b[4] * x1 + (double)b[7] * x2;
+      a2 += (double)b[2] * x0 + (double)b[5] * x1 + (double)b[8] * x2;
+    }
+    const int row = sl * kSlice + lane;
+    if (row < S.N) {
+      const double r0 = (double)bhat[row] - (xd[row] + a0);
+      const double r1 = (double)bhat[n4 + row] - (xd[n4 + row] + a1);
+      const double r2 = (double)bhat[2 * n4 + row] - (xd[2 * n4 + row] + a2);
+      rd[row] = r0;
+      rd[n4 + row] = r1;
+      rd[2 * n4 + row] = r2;
+      const float* L = S.Lf;
+      const double t0 = (double)L[row] * r0;
+      const double t1 = (double)L[n4 + row] * r0 + (double)L[2 * n4 + row] * r1;
+      const double t2 = (double)L[3 * n4 + row] * r0 + (double)L[4 * n4 + row] * r1 + (double)L[5 * n4 + row] * r2;
+      rt += t0 * t0 + t1 * t1 + t2 * t2;
+    }
+  }
+  const double s = block_sum_all<kSpmvBlock>(rt);
+  if (threadIdx.x == 0) part[lb] = s;
+}
+
+// Inner solve start: r = (float) r_outer, x = 0, partials of r^T r.
+__global__ void __launch_bounds__(kVecBlock)
+k_init_from64(int n3, const double* __restrict__ rd, float* __restrict__ x, float* __restrict__ r,
+              double* __restrict__ part) {
+  double rr = 0.0;
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) {
+    const float b = (float)rd[i];
+    x[i] = 0.f;
+    r[i] = b;
+    rr += (double)b * b;
+  }
+  const double s = block_sum_all<kVecBlock>(rr);
+  if (threadIdx.x == 0) part[kPartRR + blockIdx.x] = s;
+}
+
+// x_outer += d (FP64 accumulation of the FP32 correction).
+__global__ void __launch_bounds__(kVecBlock)
+k_axpy64(int n3, const float* __restrict__ d, double* __restrict__ xd) {
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) xd[i] += (double)d[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_sum_to(const double* __restrict__ part, int n, double* out) {
+  const double s = sum_parts<kBlock>(part, n);
+  if (threadIdx.x == 0) *out = s;
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -296,57 +456,80 @@ k_finish_scalars(const double* __restrict__ part, int n, const double* __restric
   }
 }
 
-inline int pad4(int N) { return (N + 3) & ~3; }
+}  // namespace
 
-inline int vec_grid(int N) {
-  int g = div_up(N, kVecBlock);
-  return g < 1 ? 1 : (g > kGridVec ? kGridVec : g);
-}
-
-inline int spmv_grid(int N) {
-  int g = div_up(N, kRowsPerPass);
-  if (g > kGridSpmv) g = kGridSpmv;
+int pcg_spmv_groups(int N) {
+  const int nslices = div_up(N, kSlice);
+  int g = div_up(nslices, kSlicesPerGroup);
+  if (g > kMaxSpmvParts) g = kMaxSpmvParts;
   return ((g + 7) / 8) * 8;
 }
 
-}  // namespace
-
-// Vectors x, r, p, q, b_hat and the factor L hold pad4(N) nodes; the pad
-// entries are zero and stay zero (the SpMV writes q for the N real rows only).
-// Partials layout: [0, 2*kGridVec) r^T r of two consecutive iterations,
-// [2k, 3k) |L r|^2, [3k, 3k + kGridSpmv) p^T q  (k = kGridVec).
-int pcg_partials_needed(int N) {
-  (void)N;
-  return 3 * kGridVec + kGridSpmv + 64;
+int pcg_vec_groups(int N) {
+  const int ng = ((N + 3) & ~3) / 4;
+  int g = div_up(ng, kVecBlock);
+  if (g > kMaxVecParts) g = kMaxVecParts;
+  return g < 1 ? 1 : g;
 }
 
-void launch_pcg_init(int N, const float* bhat, float* x, float* r, float* p, double* part, const double* bb_part,
-                     int nbb, PcgScalars* sc, double tol, int max_iter, int check_every, hipStream_t s) {
-  hipLaunchKernelGGL(k_init, dim3(vec_grid(N)), dim3(kVecBlock), 0, s, pad4(N), bhat, x, r, p, part);
-  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kBlock), 0, s, bb_part, nbb, sc, tol, max_iter, check_every);
+void launch_pcg_init(const PcgSystem& S, const float* bhat, const double* bb_part, int nbb, double tol, int max_iter,
+                     int check_every, hipStream_t s) {
+  hipLaunchKernelGGL(k_init, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, bhat, S.x, S.r, S.part);
+  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kBlock), 0, s, bb_part, nbb, S.sc, tol, max_iter, check_every);
 }
 
-void launch_pcg_spmv(int N, const int* urow_ptr, const int* ucol, const float* uvals, long long ustride,
-                     const float* p, float* qrow, float* tbuf, double* part, PcgScalars* sc, hipStream_t s) {
-  hipLaunchKernelGGL(k_spmv, dim3(spmv_grid(N)), dim3(kSpmvBlock), 0, s, N, urow_ptr, ucol, uvals, ustride, p, qrow,
-                     tbuf, part + 3 * kGridVec, (const PcgScalars*)sc);
+void launch_pcg_iteration(const PcgSystem& S, bool bf16, hipStream_t s) {
+  if (bf16)
+    hipLaunchKernelGGL(k_spmv<uint32_t>, dim3(S.spmv_nwg), dim3(kSpmvBlock), 0, s, S);
+  else
+    hipLaunchKernelGGL(k_spmv<float>, dim3(S.spmv_nwg), dim3(kSpmvBlock), 0, s, S);
+  hipLaunchKernelGGL(k_update, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, S);
 }
 
-void launch_pcg_vector_ops(int N, const float* Lf, float* x, float* r, float* p, const float* qrow,
-                           const float* tbuf, const int* tptr, const int* tidx, double* part, PcgScalars* sc,
-                           hipStream_t s) {
-  const int gv = vec_grid(N);
-  hipLaunchKernelGGL(k_update, dim3(gv), dim3(kVecBlock), 0, s, N, Lf, x, r, (const float*)p, qrow, tbuf, tptr, tidx,
-                     (const double*)(part + 3 * kGridVec), spmv_grid(N), part, part + 2 * kGridVec, sc);
-  hipLaunchKernelGGL(k_direction, dim3(gv), dim3(kVecBlock), 0, s, pad4(N), (const float*)r, p, (const double*)part,
-                     (const double*)(part + 2 * kGridVec), sc);
+void launch_pcg_iteration_batched(const PcgSystem* sys, const int* wg_sys_spmv, int nwg_spmv, const int* wg_sys_vec,
+                                  int nwg_vec, bool bf16, hipStream_t s) {
+  if (bf16)
+    hipLaunchKernelGGL(k_spmv_batched<uint32_t>, dim3(nwg_spmv), dim3(kSpmvBlock), 0, s, sys, wg_sys_spmv);
+  else
+    hipLaunchKernelGGL(k_spmv_batched<float>, dim3(nwg_spmv), dim3(kSpmvBlock), 0, s, sys, wg_sys_spmv);
+  hipLaunchKernelGGL(k_update_batched, dim3(nwg_vec), dim3(kVecBlock), 0, s, sys, wg_sys_vec);
 }
 
-void launch_pcg_finish(int N, const float* Linv, const float* x, double* pout, double* part, PcgScalars* sc,
-                       const double* viol_part, int nviol, hipStream_t s) {
-  const int g = vec_grid(N);
-  hipLaunchKernelGGL(k_finish, dim3(g), dim3(kVecBlock), 0, s, N, Linv, x, pout, part);
-  hipLaunchKernelGGL(k_finish_scalars, dim3(1), dim3(kBlock), 0, s, (const double*)part, g, viol_part, nviol, sc);
+void launch_pcg_finish(const PcgSystem& S, const float* Linv, double* pout, const double* viol_part, int nviol,
+                       hipStream_t s) {
+  const int g = pcg_vec_groups(S.N);
+  // the max |p| partials reuse the p^T q slots, which the solve no longer needs
+  double* part = S.part + kPartPQ;
+  hipLaunchKernelGGL(k_finish<float>, dim3(g), dim3(kVecBlock), 0, s, S.N, S.N4, Linv, (const float*)S.x, pout, part);
+  hipLaunchKernelGGL(k_finish_scalars, dim3(1), dim3(kBlock), 0, s, (const double*)part, g, viol_part, nviol, S.sc);
+}
+
+void launch_pcg_init_from64(const PcgSystem& S, const double* rd, const double* rpart, int nparts, double tol,
+                            int max_iter, int check_every, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_from64, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, rd, S.x, S.r, S.part);
+  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kBlock), 0, s, rpart, nparts, S.sc, tol, max_iter, check_every);
+}
+
+void launch_residual64(const PcgSystem& S, const float* bhat, const double* xd, double* rd, double* rpart,
+                       double* rsum, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual64, dim3(S.spmv_nwg), dim3(kSpmvBlock), 0, s, S, bhat, xd, rd, rpart);
+  hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(kBlock), 0, s, (const double*)rpart, S.spmv_nwg, rsum);
+}
+
+void launch_sum_to(const double* part, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(kBlock), 0, s, part, n, out);
+}
+
+void launch_axpy64(const PcgSystem& S, double* xd, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy64, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, (const float*)S.x, xd);
+}
+
+void launch_pcg_finish64(const PcgSystem& S, const float* Linv, const double* xd, double* pout,
+                         const double* viol_part, int nviol, hipStream_t s) {
+  const int g = pcg_vec_groups(S.N);
+  double* part = S.part + kPartPQ;
+  hipLaunchKernelGGL(k_finish<double>, dim3(g), dim3(kVecBlock), 0, s, S.N, S.N4, Linv, xd, pout, part);
+  hipLaunchKernelGGL(k_finish_scalars, dim3(1), dim3(kBlock), 0, s, (const double*)part, g, viol_part, nviol, S.sc);
 }
 
 }  // namespace bfal

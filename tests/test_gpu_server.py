@@ -1,0 +1,108 @@
+"""Continuous-batching server (bf_server_*) through the C-ABI.
+
+Every request's result must be the same alone and in the mix: the batched
+kernels give each request its own workgroups, partial sums and scalars, in the
+same order as a lone bf_newton_step, so the bar is bitwise equality with the
+single-request path (same p, same iteration count).  Each result is also held
+to the FP64 oracle at the solve tolerance, and the HBM budget is enforced."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+# small requests of different sizes (two stacked cubes, the serving recipe)
+IDS = [3, 7, 11, 19, 23, 31]
+_scenes = {}
+
+
+def scene(i):
+    if i not in _scenes:
+        _scenes[i] = scenes.serve_request(i)
+    return _scenes[i]
+
+
+@pytest.fixture(scope="module")
+def bf():
+    from paper_2512_12151_amd import bfal
+    return bfal
+
+
+@pytest.fixture(scope="module")
+def alone(bf):
+    ctx = bf.Context(0)
+    out = {}
+    for i in IDS:
+        pb = bf.Problem.from_scene(ctx, scene(i))
+        p, st, status = pb.newton_step(tol=1e-5, max_iter=20000)
+        out[i] = (p, st)
+        pb.close()
+    ctx.close()
+    return out
+
+
+def run_server(bf, server, ids, stagger=0.0, timeout=120.0):
+    for k, i in enumerate(ids):
+        server.submit(i, scene(i), tol=1e-5, max_iter=20000)
+        if stagger:
+            time.sleep(stagger)
+    got = {}
+    t0 = time.time()
+    while len(got) < len(ids):
+        for i in server.poll():
+            got[i] = server.result(i)
+        assert time.time() - t0 < timeout, "server did not finish"
+        time.sleep(0.002)
+    return got
+
+
+@pytest.mark.parametrize("max_active,stagger", [(64, 0.0), (3, 0.002), (1, 0.0)])
+def test_results_same_alone_and_in_the_mix(bf, alone, max_active, stagger):
+    print(f"case max_active={max_active} stagger={stagger}", flush=True)
+    sv = bf.Server(0, hbm_budget=4 << 30, max_active=max_active, iters_per_round=8)
+    got = run_server(bf, sv, IDS, stagger)
+    sv.close()
+    for i in IDS:
+        p, st, times, status = got[i]
+        assert status == bf.BF_OK
+        p1, st1 = alone[i]
+        assert st["pcg_iters"] == st1["pcg_iters"]
+        assert np.array_equal(p, p1), f"request {i} differs from its lone solve"
+        assert times["t_submit"] <= times["t_admit"] <= times["t_done"]
+
+
+def test_results_against_oracle(bf, alone):
+    for i in IDS[:3]:
+        sc = scene(i)
+        st = oracle.assemble(sc)
+        p_ref = oracle.solve_reference(st.H, st.G)
+        p64, _ = oracle.block_jacobi_pcg(st.H, st.G, 1e-5)
+        err = oracle.energy_norm_rel(st.H, alone[i][0], p_ref)
+        err64 = oracle.energy_norm_rel(st.H, p64, p_ref)
+        print(f"serve request {i}: N={len(sc['rest'])} err={err:.3e} fp64 pcg err={err64:.3e}", flush=True)
+        assert err <= 2.0 * err64 + 1e-5
+
+
+def test_budget_admission_and_rejection(bf, alone):
+    sizes = {i: bf.footprint_bytes(len(scene(i)["rest"]), len(scene(i)["tets"]),
+                                   len(scene(i)["pt"]) + len(scene(i)["ee"])) for i in IDS}
+    # room for the largest request only: requests run one or two at a time
+    budget = max(sizes.values()) + 1
+    sv = bf.Server(0, hbm_budget=budget, max_active=64, iters_per_round=4)
+    got = run_server(bf, sv, IDS)
+    for i in IDS:
+        assert got[i][3] == bf.BF_OK
+        assert np.array_equal(got[i][0], alone[i][0])
+    assert sv.stats()["used_bytes"] == 0
+    sv.close()
+    # a request larger than the whole budget is rejected with ERR_OOM
+    small = min(sizes.values())
+    sv = bf.Server(0, hbm_budget=small, max_active=4, iters_per_round=4)
+    big = max(sizes, key=sizes.get)
+    got = run_server(bf, sv, [big])
+    assert got[big][3] == -2   # BF_ERR_OOM
+    sv.close()
