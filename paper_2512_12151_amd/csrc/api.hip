@@ -298,7 +298,7 @@ void bf_problem_destroy(bf_problem* pb) {
                     &pb->Linv, &pb->bhat, &pb->bb_part, &pb->lcnt, &pb->lptr, &pb->lsrc, &pb->sbu, &pb->sbl,
                     &pb->sblk, &pb->sblk16, &pb->scol, &pb->sent, &pb->xs, &pb->r, &pb->p0, &pb->p1, &pb->q,
                     &pb->part, &pb->scal, &pb->pout, &pb->flags, &pb->scan_tmp, &pb->scratch_int,
-                    &pb->xd, &pb->rd, &pb->rpart};
+                    &pb->xd, &pb->rd, &pb->zd, &pb->fcg, &pb->rpart};
   for (DevBuf* b : bufs) b->release();
   for (auto& e : pb->ev)
     if (e) (void)hipEventDestroy(e);
@@ -527,35 +527,87 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
     if (r0 != BF_OK) return r0;
     launch_pcg_finish(S, pb->Linv.as<float>(), pb->pout.as<double>(), pb->viol_part.as<double>(), nviol, s);
   } else {
+    // Flexible CG on the FP32-stored system in FP64 vectors (the refinement):
+    // every sweep forms the true residual r = b_hat - H_hat x in FP64, solves
+    // H_bf16 z = r by the two-kernel PCG on the BF16 blocks to the relative
+    // tolerance tol (a BF16 breakdown ends that inner solve early: BF16
+    // rounding can make the scaled matrix indefinite in its lowest modes),
+    // makes z conjugate (in H_hat) to the last kFcgWindow directions, and
+    // takes the exact step along it.  The outer Krylov recurrence on the FP32
+    // operator recovers the modes the BF16 blocks cannot resolve.
+    constexpr int kFcgWindow = 4;
     const long long n3 = 3LL * S.N4;
     ALLOC(c, pb->xd, 8 * n3);
     ALLOC(c, pb->rd, 8 * n3);
-    ALLOC(c, pb->rpart, 8LL * (kMaxSpmvParts + 8));
+    ALLOC(c, pb->zd, 8 * n3);
+    ALLOC(c, pb->fcg, 8 * n3 * 2 * kFcgWindow);
+    ALLOC(c, pb->rpart, 8LL * (kMaxSpmvParts + 8 + 6 * 256 + 8));
     HIPCHK(c, hipMemsetAsync(pb->xd.p, 0, 8 * n3, s));
     HIPCHK(c, hipMemsetAsync(pb->rd.p, 0, 8 * n3, s));
+    HIPCHK(c, hipMemsetAsync(pb->zd.p, 0, 8 * n3, s));
+    HIPCHK(c, hipMemsetAsync(pb->fcg.p, 0, 8 * n3 * 2 * kFcgWindow, s));
     double* rpart = pb->rpart.as<double>();
-    double* rsum = rpart + kMaxSpmvParts;   // [0] residual^2, [1] |b|^2
+    double* rsum = rpart + kMaxSpmvParts;        // [0] residual^2, [1] |b|^2
+    double* dpart = rsum + 8;                    // partials of the dot products
+    double* dots = dpart + 6 * 256;              // their sums
+    double* xd = pb->xd.as<double>();
+    double* rd = pb->rd.as<double>();
+    double* zd = pb->zd.as<double>();
+    auto Pv = [&](int j) { return pb->fcg.as<double>() + n3 * (2 * (j % kFcgWindow)); };
+    auto Qv = [&](int j) { return pb->fcg.as<double>() + n3 * (2 * (j % kFcgWindow) + 1); };
+    double pq_hist[kFcgWindow] = {0.0};
     launch_sum_to(pb->bb_part.as<double>(), div_up(N, kBlock), rsum + 1, s);
     PcgSystem S16 = S;
     S16.blk = pb->sblk16.p;
-    const int max_sweeps = o->max_sweeps > 0 ? o->max_sweeps : 30;
+    const int max_sweeps = o->max_sweeps > 0 ? o->max_sweeps : 100;
     double bb = 0.0;
     for (int sw = 0;; ++sw) {
-      launch_residual64(S, pb->bhat.as<float>(), pb->xd.as<double>(), pb->rd.as<double>(), rpart, rsum, s);
+      launch_residual64(S, pb->bhat.as<float>(), xd, rd, rpart, rsum, s);
       double hs[2] = {0.0, 0.0};
       HIPCHK(c, hipMemcpyAsync(hs, rsum, sizeof(hs), hipMemcpyDeviceToHost, s));
       HIPCHK(c, hipStreamSynchronize(s));
       bb = hs[1];
       const double rel = bb > 0.0 ? std::sqrt(hs[0] / bb) : 0.0;
       if (sw < 16) sweep_res[sw] = rel;
+      if (sw >= 16) sweep_res[15] = rel;
       pb->host_sc->rr_true = hs[0];
       if (rel <= o->refine_tol) break;
       if (sw >= max_sweeps) { refine_capped = true; break; }
-      launch_pcg_init_from64(S16, pb->rd.as<double>(), rpart, S.spmv_nwg, o->tol, o->max_iter, o->check_every, s);
+      // inner BF16 solve z ~ H_bf16^{-1} r
+      launch_pcg_init_from64(S16, rd, rpart, S.spmv_nwg, o->tol, o->max_iter, o->check_every, s);
       bf_status r0 = run_solve(S16, true);
       if (r0 != BF_OK) return r0;
-      if (pb->host_sc->brk) break;
-      launch_axpy64(S16, pb->xd.as<double>(), s);
+      if (pb->host_sc->iter == 0) {
+        HIPCHK(c, hipMemcpyAsync(zd, rd, 8 * n3, hipMemcpyDeviceToDevice, s));   // no progress: steepest descent
+      } else {
+        launch_copy_f2d((int)n3, S16.x, zd, s);
+      }
+      // p = z - sum_j (z.q_j / p_j.q_j) p_j over the window
+      const int nwin = std::min(sweeps, kFcgWindow);
+      double* P = Pv(sweeps);
+      double* Q = Qv(sweeps);
+      HIPCHK(c, hipMemcpyAsync(P, zd, 8 * n3, hipMemcpyDeviceToDevice, s));
+      if (nwin > 0) {
+        const double* qs[kFcgWindow];
+        for (int j = 0; j < nwin; ++j) qs[j] = Qv(sweeps - 1 - j);
+        launch_dots64((int)n3, zd, qs, nwin, dpart, dots, s);
+        double hz[kFcgWindow];
+        HIPCHK(c, hipMemcpyAsync(hz, dots, 8 * nwin, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        for (int j = 0; j < nwin; ++j) {
+          const double pqj = pq_hist[(sweeps - 1 - j) % kFcgWindow];
+          if (pqj > 0.0) launch_axpy_d((int)n3, -hz[j] / pqj, Pv(sweeps - 1 - j), P, s);
+        }
+      }
+      launch_apply64(S, P, Q, s);
+      const double* pr[2] = {rd, Q};
+      launch_dots64((int)n3, P, pr, 2, dpart, dots, s);
+      double hd[2];
+      HIPCHK(c, hipMemcpyAsync(hd, dots, sizeof(hd), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      if (!(hd[1] > 0.0)) return fail(c, BF_ERR_NOT_SPD, "refinement direction with p^T H p <= 0");
+      pq_hist[sweeps % kFcgWindow] = hd[1];
+      launch_axpy_d((int)n3, hd[0] / hd[1], P, xd, s);
       ++sweeps;
     }
     pb->host_sc->bb = bb;
@@ -604,7 +656,9 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
     stats->spmv_timed = nt;
     stats->ms_spmv_avg = nt > 0 ? tot / nt : 0.0;
   }
-  if (hflags | h.flags) return flags_to_status(c, hflags | h.flags);
+  // in BF16 mode an inner breakdown only ends that inner solve
+  const int sflags = bf16 ? (h.flags & ~FLAG_BREAKDOWN) : h.flags;
+  if (hflags | sflags) return flags_to_status(c, hflags | sflags);
   c->err.clear();
   if ((!bf16 && h.done == 2 && !h.brk) || refine_capped) {
     c->err = refine_capped ? "refinement reached max_sweeps" : "PCG reached max_iter";

@@ -201,6 +201,14 @@ void launch_sum_to(const double* part, int n, double* out, hipStream_t s);
 void launch_pcg_init_from64(const PcgSystem& S, const double* rd, const double* rpart, int nparts, double tol,
                             int max_iter, int check_every, hipStream_t s);
 void launch_axpy64(const PcgSystem& S, double* xd, hipStream_t s);
+// Outer flexible-CG pieces (FP64 vectors of 3 * N4): yd = H_hat xd (FP32
+// blocks, FP64 sums); out[j] = a . b[j] for nb <= 6 vectors (part holds
+// 6 * 256 partials); y += alpha x; y = (double) x.
+void launch_apply64(const PcgSystem& S, const double* xd, double* yd, hipStream_t s);
+void launch_dots64(int n3, const double* a, const double* const* b, int nb, double* part, double* out,
+                   hipStream_t s);
+void launch_axpy_d(int n3, double alpha, const double* x, double* y, hipStream_t s);
+void launch_copy_f2d(int n3, const float* x, double* y, hipStream_t s);
 void launch_pcg_finish64(const PcgSystem& S, const float* Linv, const double* xd, double* pout,
                          const double* viol_part, int nviol, hipStream_t s);
 

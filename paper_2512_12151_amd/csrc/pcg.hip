@@ -77,6 +77,39 @@ __device__ inline double block_max_all(double v) {
   return s;
 }
 
+// Three fixed-order sums of part arrays (lengths n0, n1, n2; n = 0 gives 0) in
+// one pass: one load per array per thread and one LDS round, so a kernel's
+// preamble waits for one memory round trip instead of three.
+template <int NT>
+__device__ inline void sum_parts3(const double* __restrict__ a, int na, const double* __restrict__ b, int nb,
+                                  const double* __restrict__ c, int nc, double& sa, double& sb, double& sc) {
+  __shared__ double red[3][NT / kWave];
+  double va = 0.0, vb = 0.0, vc = 0.0;
+  for (int k = threadIdx.x; k < na; k += NT) va += a[k];
+  for (int k = threadIdx.x; k < nb; k += NT) vb += b[k];
+  for (int k = threadIdx.x; k < nc; k += NT) vc += c[k];
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    va += __shfl_xor(va, off, kWave);
+    vb += __shfl_xor(vb, off, kWave);
+    vc += __shfl_xor(vc, off, kWave);
+  }
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    red[0][threadIdx.x / kWave] = va;
+    red[1][threadIdx.x / kWave] = vb;
+    red[2][threadIdx.x / kWave] = vc;
+  }
+  __syncthreads();
+  sa = sb = sc = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / kWave; ++w) {
+    sa += red[0][w];
+    sb += red[1][w];
+    sc += red[2][w];
+  }
+}
+
 // Fixed-order sum of part[0..n) by the whole workgroup (same value in every workgroup).
 template <int NT>
 __device__ inline double sum_parts(const double* __restrict__ part, int n) {
@@ -116,11 +149,13 @@ __device__ inline bool spmv_scalars(const PcgSystem& S, bool leader, int& k, flo
   if (sc->brk) return false;
   k = sc->iter;
   const double* part = S.part;
-  const double rho = sum_parts<kSpmvBlock>(part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg);
+  const bool check = k > 0 && (k % sc->check_every) == 0;
+  double rho, rho_old, rt;
+  sum_parts3<kSpmvBlock>(part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg,
+                         part + kPartRR + ((k + 1) & 1) * kMaxVecParts, k > 0 ? S.vec_nwg : 0,
+                         part + kPartRT, check ? S.vec_nwg : 0, rho, rho_old, rt);
   beta = 0.f;
   if (k > 0) {
-    const bool check = (k % sc->check_every) == 0;
-    const double rt = check ? sum_parts<kSpmvBlock>(part + kPartRT, S.vec_nwg) : 0.0;
     const bool converged = (check && rt <= sc->tol2 * sc->bb) || rho == 0.0;
     const bool capped = k >= sc->max_iter;
     if (leader) {
@@ -130,11 +165,106 @@ __device__ inline bool spmv_scalars(const PcgSystem& S, bool leader, int& k, flo
       else if (capped) sc->done = 2;
     }
     if (converged || capped) return false;
-    const double rho_old = sum_parts<kSpmvBlock>(part + kPartRR + ((k + 1) & 1) * kMaxVecParts, S.vec_nwg);
     beta = (float)(rho / rho_old);
   }
   if (leader) sc->ks = k;
   return true;
+}
+
+#ifndef BFAL_SPMV_UNROLL
+#define BFAL_SPMV_UNROLL 4
+#endif
+constexpr int kUnroll = BFAL_SPMV_UNROLL;   // slots per step of a lane (independent loads in flight)
+
+// Vector entries of p_k at node c, formed on the fly: p_k = r + beta p_{k-1}
+// (the same rounding as the row owner's, so every reader sees the same p_k).
+struct PView {
+  const float* __restrict__ r0;
+  const float* __restrict__ r1;
+  const float* __restrict__ r2;
+  const float* __restrict__ o0;
+  const float* __restrict__ o1;
+  const float* __restrict__ o2;
+  float beta;
+  bool first;
+  __device__ inline void at(int c, float& p0, float& p1, float& p2) const {
+    p0 = r0[c];
+    p1 = r1[c];
+    p2 = r2[c];
+    if (!first) {
+      p0 = __fmaf_rn(beta, o0[c], p0);
+      p1 = __fmaf_rn(beta, o1[c], p1);
+      p2 = __fmaf_rn(beta, o2[c], p2);
+    }
+  }
+};
+
+// Accumulates the w slots of one row starting at base (stride kSlice):
+// upper slots (B p_c, columns from scol) or lower slots (B^T p_r, block and
+// source row from sent), kUnroll slots per step with all their loads issued
+// before any is used.  The sum runs in slot order either way.
+template <bool kLower, class BT>
+__device__ inline void accumulate_slots(int base, int w, const int* __restrict__ scol,
+                                        const int2* __restrict__ sent, const BT* __restrict__ blk, const PView& pv,
+                                        float& a0, float& a1, float& a2) {
+  int kk = 0;
+  for (; kk + kUnroll <= w; kk += kUnroll) {
+    int bi[kUnroll], c[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int e = base + (kk + u) * kSlice;
+      if (kLower) {
+        const int2 t = sent[e];
+        bi[u] = t.x;
+        c[u] = t.y;
+      } else {
+        bi[u] = e;
+        c[u] = scol[e];
+      }
+    }
+    float b[kUnroll][9], p[kUnroll][3];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      load_block(blk, bi[u], b[u]);
+      pv.at(c[u], p[u][0], p[u][1], p[u][2]);
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (kLower) {
+        a0 += b[u][0] * p[u][0] + b[u][3] * p[u][1] + b[u][6] * p[u][2];
+        a1 += b[u][1] * p[u][0] + b[u][4] * p[u][1] + b[u][7] * p[u][2];
+        a2 += b[u][2] * p[u][0] + b[u][5] * p[u][1] + b[u][8] * p[u][2];
+      } else {
+        a0 += b[u][0] * p[u][0] + b[u][1] * p[u][1] + b[u][2] * p[u][2];
+        a1 += b[u][3] * p[u][0] + b[u][4] * p[u][1] + b[u][5] * p[u][2];
+        a2 += b[u][6] * p[u][0] + b[u][7] * p[u][1] + b[u][8] * p[u][2];
+      }
+    }
+  }
+  for (; kk < w; ++kk) {
+    const int e = base + kk * kSlice;
+    int bi, c;
+    if (kLower) {
+      const int2 t = sent[e];
+      bi = t.x;
+      c = t.y;
+    } else {
+      bi = e;
+      c = scol[e];
+    }
+    float b[9], p0, p1, p2;
+    load_block(blk, bi, b);
+    pv.at(c, p0, p1, p2);
+    if (kLower) {
+      a0 += b[0] * p0 + b[3] * p1 + b[6] * p2;
+      a1 += b[1] * p0 + b[4] * p1 + b[7] * p2;
+      a2 += b[2] * p0 + b[5] * p1 + b[8] * p2;
+    } else {
+      a0 += b[0] * p0 + b[1] * p1 + b[2] * p2;
+      a1 += b[3] * p0 + b[4] * p1 + b[5] * p2;
+      a2 += b[6] * p0 + b[7] * p1 + b[8] * p2;
+    }
+  }
 }
 
 // q = H_hat p_k for the slices of workgroup lb (of nwg) of one system, p_k
@@ -143,61 +273,21 @@ template <class BT>
 __device__ inline double spmv_slices(const PcgSystem& S, int lb, int nwg, int k, float beta) {
   const int wave = threadIdx.x / kSlice, lane = threadIdx.x % kSlice;
   const long long n4 = S.N4;
-  const float* __restrict__ r0 = S.r;
-  const float* __restrict__ r1 = S.r + n4;
-  const float* __restrict__ r2 = S.r + 2 * n4;
-  const float* __restrict__ pold = (k & 1) ? S.P0 : S.P1;
-  const float* __restrict__ o0 = pold;
-  const float* __restrict__ o1 = pold + n4;
-  const float* __restrict__ o2 = pold + 2 * n4;
+  const float* pold = (k & 1) ? S.P0 : S.P1;
   float* __restrict__ pn = (k & 1) ? S.P1 : S.P0;
+  const PView pv{S.r, S.r + n4, S.r + 2 * n4, pold, pold + n4, pold + 2 * n4, beta, k == 0};
   const BT* __restrict__ blk = static_cast<const BT*>(S.blk);
-  const int* __restrict__ scol = S.scol;
-  const int2* __restrict__ sent = S.sent;
-  const bool first = (k == 0);
   double dot = 0.0;
   for (int sl = lb * kSlicesPerGroup + wave; sl < S.nslices; sl += nwg * kSlicesPerGroup) {
     const int bu = S.sbu[sl], wu = (S.sbu[sl + 1] - bu) / kSlice;
     const int bl = S.sbl[sl], wl = (S.sbl[sl + 1] - bl) / kSlice;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-    for (int kk = 0; kk < wu; ++kk) {
-      const int e = bu + kk * kSlice + lane;
-      const int c = scol[e];
-      float b[9];
-      load_block(blk, e, b);
-      float p0 = r0[c], p1 = r1[c], p2 = r2[c];
-      if (!first) {
-        p0 = __fmaf_rn(beta, o0[c], p0);
-        p1 = __fmaf_rn(beta, o1[c], p1);
-        p2 = __fmaf_rn(beta, o2[c], p2);
-      }
-      a0 += b[0] * p0 + b[1] * p1 + b[2] * p2;
-      a1 += b[3] * p0 + b[4] * p1 + b[5] * p2;
-      a2 += b[6] * p0 + b[7] * p1 + b[8] * p2;
-    }
-    for (int kk = 0; kk < wl; ++kk) {
-      const int2 t = sent[bl + kk * kSlice + lane];
-      const int c = t.y;
-      float b[9];
-      load_block(blk, t.x, b);
-      float p0 = r0[c], p1 = r1[c], p2 = r2[c];
-      if (!first) {
-        p0 = __fmaf_rn(beta, o0[c], p0);
-        p1 = __fmaf_rn(beta, o1[c], p1);
-        p2 = __fmaf_rn(beta, o2[c], p2);
-      }
-      a0 += b[0] * p0 + b[3] * p1 + b[6] * p2;
-      a1 += b[1] * p0 + b[4] * p1 + b[7] * p2;
-      a2 += b[2] * p0 + b[5] * p1 + b[8] * p2;
-    }
+    accumulate_slots<false, BT>(bu + lane, wu, S.scol, S.sent, blk, pv, a0, a1, a2);
+    accumulate_slots<true, BT>(bl + lane, wl, S.scol, S.sent, blk, pv, a0, a1, a2);
     const int row = sl * kSlice + lane;
     if (row < S.N) {
-      float s0 = r0[row], s1 = r1[row], s2 = r2[row];
-      if (!first) {
-        s0 = __fmaf_rn(beta, o0[row], s0);
-        s1 = __fmaf_rn(beta, o1[row], s1);
-        s2 = __fmaf_rn(beta, o2[row], s2);
-      }
+      float s0, s1, s2;
+      pv.at(row, s0, s1, s2);
       const float q0 = s0 + a0, q1 = s1 + a1, q2 = s2 + a2;
       pn[row] = s0; pn[n4 + row] = s1; pn[2 * n4 + row] = s2;
       S.q[row] = q0; S.q[n4 + row] = q1; S.q[2 * n4 + row] = q2;
@@ -238,8 +328,9 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
   if (sc->done) return;
   const int k = sc->ks;
   double* part = S.part;
-  const double rho = sum_parts<kVecBlock>(part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg);
-  const double pq = sum_parts<kVecBlock>(part + kPartPQ, S.spmv_nwg);
+  double rho, pq, unused;
+  sum_parts3<kVecBlock>(part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg, part + kPartPQ, S.spmv_nwg, part, 0, rho,
+                        pq, unused);
   const bool leader = lb == 0 && threadIdx.x == 0;
   if (!(pq > 0.0)) {
     if (leader) {
@@ -368,6 +459,7 @@ k_finish(int N, int N4, const float* __restrict__ Linv, const XT* __restrict__ x
 __global__ void __launch_bounds__(kSpmvBlock)
 k_residual64(PcgSystem S, const float* __restrict__ bhat, const double* __restrict__ xd, double* __restrict__ rd,
              double* __restrict__ part) {
+  // with bhat == nullptr: rd = H_hat xd and no partials
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int wave = threadIdx.x / kSlice, lane = threadIdx.x % kSlice;
   const long long n4 = S.N4;
@@ -398,7 +490,11 @@ k_residual64(PcgSystem S, const float* __restrict__ bhat, const double* __restri
       a2 += (double)b[2] * x0 + (double)b[5] * x1 + (double)b[8] * x2;
     }
     const int row = sl * kSlice + lane;
-    if (row < S.N) {
+    if (row < S.N && !bhat) {
+      rd[row] = xd[row] + a0;
+      rd[n4 + row] = xd[n4 + row] + a1;
+      rd[2 * n4 + row] = xd[2 * n4 + row] + a2;
+    } else if (row < S.N) {
       const double r0 = (double)bhat[row] - (xd[row] + a0);
       const double r1 = (double)bhat[n4 + row] - (xd[n4 + row] + a1);
       const double r2 = (double)bhat[2 * n4 + row] - (xd[2 * n4 + row] + a2);
@@ -413,7 +509,52 @@ k_residual64(PcgSystem S, const float* __restrict__ bhat, const double* __restri
     }
   }
   const double s = block_sum_all<kSpmvBlock>(rt);
-  if (threadIdx.x == 0) part[lb] = s;
+  if (threadIdx.x == 0 && part) part[lb] = s;
+}
+
+// Up to kMaxDots FP64 dot products a . b_j in one pass: partials part[j][blockIdx].
+constexpr int kMaxDots = 6;
+constexpr int kDotGrid = 256;
+struct DotArgs {
+  const double* b[kMaxDots];
+  int nb;
+};
+
+__global__ void __launch_bounds__(kVecBlock)
+k_dots64(int n3, const double* __restrict__ a, DotArgs B, double* __restrict__ part) {
+  double acc[kMaxDots];
+#pragma unroll
+  for (int j = 0; j < kMaxDots; ++j) acc[j] = 0.0;
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) {
+    const double av = a[i];
+#pragma unroll
+    for (int j = 0; j < kMaxDots; ++j)
+      if (j < B.nb) acc[j] += av * B.b[j][i];
+  }
+#pragma unroll
+  for (int j = 0; j < kMaxDots; ++j) {
+    if (j >= B.nb) break;
+    const double s = block_sum_all<kVecBlock>(acc[j]);
+    if (threadIdx.x == 0) part[j * kDotGrid + blockIdx.x] = s;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_dots_sum(const double* __restrict__ part, int nb, double* out) {
+  for (int j = 0; j < nb; ++j) {
+    const double s = sum_parts<kBlock>(part + j * kDotGrid, kDotGrid);
+    if (threadIdx.x == 0) out[j] = s;
+  }
+}
+
+// y += alpha x (FP64), or y = x (FP32 source) when x32 is set.
+__global__ void __launch_bounds__(kVecBlock)
+k_axpy_d(int n3, double alpha, const double* __restrict__ x, double* __restrict__ y) {
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) y[i] += alpha * x[i];
+}
+
+__global__ void __launch_bounds__(kVecBlock)
+k_copy_f2d(int n3, const float* __restrict__ x, double* __restrict__ y) {
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) y[i] = (double)x[i];
 }
 
 // Inner solve start: r = (float) r_outer, x = 0, partials of r^T r.
@@ -518,6 +659,30 @@ void launch_residual64(const PcgSystem& S, const float* bhat, const double* xd, 
 
 void launch_sum_to(const double* part, int n, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(kBlock), 0, s, part, n, out);
+}
+
+void launch_apply64(const PcgSystem& S, const double* xd, double* yd, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual64, dim3(S.spmv_nwg), dim3(kSpmvBlock), 0, s, S, (const float*)nullptr, xd, yd,
+                     (double*)nullptr);
+}
+
+void launch_dots64(int n3, const double* a, const double* const* b, int nb, double* part, double* out,
+                   hipStream_t s) {
+  DotArgs B{};
+  for (int j = 0; j < nb && j < kMaxDots; ++j) B.b[j] = b[j];
+  B.nb = nb < kMaxDots ? nb : kMaxDots;
+  hipLaunchKernelGGL(k_dots64, dim3(kDotGrid), dim3(kVecBlock), 0, s, n3, a, B, part);
+  hipLaunchKernelGGL(k_dots_sum, dim3(1), dim3(kBlock), 0, s, (const double*)part, B.nb, out);
+}
+
+void launch_axpy_d(int n3, double alpha, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_d, dim3(div_up(n3, kVecBlock) < 1024 ? div_up(n3, kVecBlock) : 1024), dim3(kVecBlock), 0,
+                     s, n3, alpha, x, y);
+}
+
+void launch_copy_f2d(int n3, const float* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_f2d, dim3(div_up(n3, kVecBlock) < 1024 ? div_up(n3, kVecBlock) : 1024), dim3(kVecBlock),
+                     0, s, n3, x, y);
 }
 
 void launch_axpy64(const PcgSystem& S, double* xd, hipStream_t s) {

@@ -40,7 +40,7 @@ struct bf_problem {
   DevBuf ccount, cptr, cand, ucount, row_ptr, col, eslot;
   DevBuf vals, grad, Lf, Linv, bhat, bb_part, lcnt, lptr, lsrc, sbu, sbl, sblk, sblk16, scol, sent;
   DevBuf xs, r, p0, p1, q, part, scal, pout, flags, scan_tmp, scratch_int;
-  DevBuf xd, rd, rpart;   // refinement: FP64 solution and residual, residual partials
+  DevBuf xd, rd, zd, fcg, rpart;   // refinement: FP64 solution, residual, inner solution, directions, partials
   long long cap_nnzb = 0, cap_cand = 0;
   long long nslot_u = 0, nslot_l = 0;   // slots of the sliced storage of the last step
   PcgScalars* host_sc = nullptr;

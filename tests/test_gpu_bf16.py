@@ -2,8 +2,8 @@
 oracle (the precision variant of the medium workload).
 
 The scaled blocks are rounded to BF16 (nearest even) for the inner PCG; the
-outer loop keeps the solution in FP64 and forms the residual of the
-FP32-stored system in FP64.  Bars: the refined solution within 1e-4 relative in
+outer loop (flexible CG on the FP32-stored system) keeps the solution in FP64
+and forms the residual in FP64.  Bars: the refined solution within 1e-4 relative in
 the oracle's FP64 energy norm of the direct solution, and the FP64 residual
 reported by the library at or below the requested 1e-6.  The energy-norm error
 of every sweep is printed beside the FP32 baseline at the same tolerance."""
@@ -42,7 +42,7 @@ def test_bf16_refinement_matches_fp64(ctx, bf, name):
     sc, st, p_ref = ref(name)
     print(f"case {name}", flush=True)
     pb = bf.Problem.from_scene(ctx, sc)
-    p, stats, status = pb.newton_step(tol=1e-2, refine_tol=1e-6, precision=bf.BF_PREC_BF16_REFINE,
+    p, stats, status = pb.newton_step(tol=0.3, refine_tol=1e-6, precision=bf.BF_PREC_BF16_REFINE,
                                       max_iter=50000)
     assert status == bf.BF_OK
     err = oracle.energy_norm_rel(st.H, p, p_ref)
@@ -62,17 +62,22 @@ def test_bf16_refinement_matches_fp64(ctx, bf, name):
 
 
 def test_bf16_error_per_sweep(ctx, bf):
-    """Energy-norm error of each refinement sweep (max_sweeps = 1, 2, ...):
-    the error must fall until the refinement has converged."""
+    """Energy-norm error after s sweeps (max_sweeps = s): it falls with the
+    sweeps and ends inside the bar; the FP32 PCG at the same final residual is
+    printed beside it."""
     sc, st, p_ref = ref("medium")
     pb = bf.Problem.from_scene(ctx, sc)
-    _, full, _ = pb.newton_step(tol=1e-2, refine_tol=1e-6, precision=bf.BF_PREC_BF16_REFINE, max_iter=50000)
+    opts = dict(tol=0.3, refine_tol=1e-6, precision=bf.BF_PREC_BF16_REFINE, max_iter=50000)
+    _, full, _ = pb.newton_step(**opts)
+    n = full["refine_sweeps"]
     errs = []
-    for s in range(1, full["refine_sweeps"] + 1):
-        p, stats, status = pb.newton_step(tol=1e-2, refine_tol=1e-6, precision=bf.BF_PREC_BF16_REFINE,
-                                          max_iter=50000, max_sweeps=s)
+    for s in sorted(set([1, 2, 4, 8, 16, 32, n]) & set(range(1, n + 1))):
+        p, stats, status = pb.newton_step(max_sweeps=s, **opts)
         errs.append(oracle.energy_norm_rel(st.H, p, p_ref))
-        print(f"medium bf16 sweep {s}: rel residual {stats['rel_residual']:.3e} energy-norm error {errs[-1]:.3e}",
-              flush=True)
+        print(f"medium bf16 sweep {s}: rel residual {stats['rel_residual']:.3e} inner iterations "
+              f"{stats['pcg_iters']} energy-norm error {errs[-1]:.3e}", flush=True)
+    p32, s32, _ = pb.newton_step(tol=1e-6, max_iter=50000)
+    print(f"medium fp32 tol 1e-6: iterations {s32['pcg_iters']} energy-norm error "
+          f"{oracle.energy_norm_rel(st.H, p32, p_ref):.3e}", flush=True)
     assert errs[-1] <= 1e-4
     assert errs[-1] < errs[0]
