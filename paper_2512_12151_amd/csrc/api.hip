@@ -198,19 +198,29 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
   const int nslices = div_up(N, kSlice);
   int* sbu = pb->sbu.as<int>();
   int* sbl = pb->sbl.as<int>();
-  launch_slice_widths(N, nslices, row_ptr, lptr, sbu, sbl, s);
+  int* wmax = pb->scratch_int.as<int>();   // free after the per-mesh setup
+  fill_int(wmax, 0, 2, s);
+  launch_slice_widths(N, nslices, row_ptr, lptr, sbu, sbl, wmax, s);
   scan_exclusive(sbu, sbu, nslices, sbu + nslices, tmp, s);
   scan_exclusive(sbl, sbl, nslices, sbl + nslices, tmp, s);
-  int tot[2] = {0, 0};
+  int tot[4] = {0, 0, 0, 0};
   HIPCHK(c, hipMemcpyAsync(&tot[0], sbu + nslices, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipMemcpyAsync(&tot[1], sbl + nslices, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(&tot[2], wmax, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   pb->nslot_u = tot[0];
   pb->nslot_l = tot[1];
-  ALLOC(c, pb->sblk, 36LL * (tot[0] + 1));
-  if (bf16) ALLOC(c, pb->sblk16, 20LL * (tot[0] + 1));
-  ALLOC(c, pb->scol, 4LL * tot[0] + 4);
-  ALLOC(c, pb->sent, 8LL * tot[1] + 8);
+  // slot arrays with the zero block (upper) and the SpMV's read-ahead padding
+  const long long nu_alloc = tot[0] + slot_padding(tot[3]);
+  const long long nl_alloc = tot[1] + slot_padding(tot[2]);
+  ALLOC(c, pb->sblk, 36LL * nu_alloc);
+  if (bf16) ALLOC(c, pb->sblk16, 20LL * nu_alloc);
+  ALLOC(c, pb->scol, 4LL * nu_alloc);
+  ALLOC(c, pb->sent, 8LL * nl_alloc);
+  HIPCHK(c, hipMemsetAsync(pb->sblk.as<char>() + 36LL * tot[0], 0, 36LL * (nu_alloc - tot[0]), s));
+  if (bf16) HIPCHK(c, hipMemsetAsync(pb->sblk16.as<char>() + 20LL * tot[0], 0, 20LL * (nu_alloc - tot[0]), s));
+  HIPCHK(c, hipMemsetAsync(pb->scol.as<char>() + 4LL * tot[0], 0, 4LL * (nu_alloc - tot[0]), s));
+  HIPCHK(c, hipMemsetAsync(pb->sent.as<char>() + 8LL * tot[1], 0, 8LL * (nl_alloc - tot[1]), s));
   launch_sell_fill(N, nslices, row_ptr, pb->col.as<int>(), pb->vals.as<float>(), pb->Linv.as<float>(), lptr,
                    pb->lsrc.as<int>(), sbu, sbl, pb->sblk.as<float>(), bf16 ? pb->sblk16.as<uint32_t>() : nullptr,
                    pb->scol.as<int>(),

@@ -136,16 +136,14 @@ k_assemble_rows(int N, const int* __restrict__ row_ptr, const int* __restrict__ 
     const float M10 = -L10 * M00 * M11;
     const float M21 = -L21 * M11 * M22;
     const float M20 = -(L20 * M00 + L21 * M10) * M22;
-    // L as SoA [6][N4] for the solver's residual check
-    const long long N4 = (N + 3) & ~3;
-    Lf[r] = L00; Lf[N4 + r] = L10; Lf[2 * N4 + r] = L11; Lf[3 * N4 + r] = L20; Lf[4 * N4 + r] = L21;
-    Lf[5 * N4 + r] = L22;
+    float* lf = Lf + 6LL * r;
+    lf[0] = L00; lf[1] = L10; lf[2] = L11; lf[3] = L20; lf[4] = L21; lf[5] = L22;
     float* li = Linv + 6LL * r;
     li[0] = M00; li[1] = M10; li[2] = M11; li[3] = M20; li[4] = M21; li[5] = M22;
-    // b_hat = L^{-1} b with b = -G, SoA [3][N4]
-    bhat[r] = -(M00 * g[0]);
-    bhat[N4 + r] = -(M10 * g[0] + M11 * g[1]);
-    bhat[2 * N4 + r] = -(M20 * g[0] + M21 * g[1] + M22 * g[2]);
+    // b_hat = L^{-1} b with b = -G
+    bhat[3LL * r] = -(M00 * g[0]);
+    bhat[3LL * r + 1] = -(M10 * g[0] + M11 * g[1]);
+    bhat[3LL * r + 2] = -(M20 * g[0] + M21 * g[1] + M22 * g[2]);
   }
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) bb += __shfl_xor(bb, off, kWave);
@@ -202,11 +200,15 @@ __device__ inline uint32_t bf16_rne(float f) {
 // lane per row).  Slice s stores wu(s) = max upper off-diagonal count of its
 // rows upper slots and wl(s) = max lower count lower slots, slot k of the row
 // in lane l at base + k * kSlice + l (so a wavefront reads slot k of its 64 rows
-// contiguously).  Shorter rows are padded: an upper pad has a zero block and
-// its own row as column; a lower pad points at the zero block stored after
-// the last upper slot.
+// contiguously).  Upper slots hold a row's blocks by decreasing column, lower
+// slots its column's blocks by increasing source row: on a regular stencil the
+// k-th upper slot of row r and the k-th lower slot of row r + d then hold the
+// same block, so the SpMV, which visits upper and lower slot k together, reads
+// each block twice at nearly the same time.  Shorter rows are padded: an
+// upper pad has a zero block and its own row as column; a lower pad points at
+// the zero block stored after the last upper slot.
 __global__ void k_slice_widths(int N, int nslices, const int* __restrict__ row_ptr, const int* __restrict__ lptr,
-                               int* __restrict__ cu, int* __restrict__ cl) {
+                               int* __restrict__ cu, int* __restrict__ cl, int* __restrict__ wmax) {
   const int sl = blockIdx.x * blockDim.x + threadIdx.x;
   if (sl >= nslices) return;
   int wu = 0, wl = 0;
@@ -217,6 +219,8 @@ __global__ void k_slice_widths(int N, int nslices, const int* __restrict__ row_p
   }
   cu[sl] = wu * kSlice;
   cl[sl] = wl * kSlice;
+  atomicMax(&wmax[0], wu);
+  atomicMax(&wmax[1], wl);
 }
 
 // Upper slots: H_hat_rc = M_r H_rc M_c^T (M = L^{-1}) for every upper
@@ -237,9 +241,10 @@ __global__ void k_sell_upper(int N, int nslices, const int* __restrict__ row_ptr
     const long long e = base + (long long)k * kSlice + lane;
     float h[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
     int c = r < N ? r : N - 1;
-    if (k < nu) {
-      c = col[o + 1 + k];
-      scaled_block(mr, vals + 9LL * (o + 1 + k), Linv + 6LL * c, h);
+    if (k < nu) {   // decreasing column order
+      const int sk = o + nu - k;
+      c = col[sk];
+      scaled_block(mr, vals + 9LL * sk, Linv + 6LL * c, h);
     }
     float* d = blk + 9 * e;
 #pragma unroll
@@ -281,7 +286,7 @@ __global__ void k_sell_lower(int N, int nslices, const int* __restrict__ row_ptr
     if (k < nl) {
       const int src = lsrc[o + k];
       const int s = find_slot(col, row_ptr[src] + 1, row_ptr[src + 1] - 1, c);
-      const int ks = s - row_ptr[src] - 1;
+      const int ks = row_ptr[src + 1] - 1 - s;   // position in src's decreasing upper list
       t = make_int2(sbu[src / kSlice] + ks * kSlice + src % kSlice, src);
     }
     sent[base + (long long)k * kSlice + lane] = t;
@@ -314,9 +319,10 @@ void launch_lower_fill(int N, const int* row_ptr, const int* col, const int* lpt
   hipLaunchKernelGGL(k_lower_fill, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, lptr, lcur, lsrc);
 }
 
-void launch_slice_widths(int N, int nslices, const int* row_ptr, const int* lptr, int* cu, int* cl, hipStream_t s) {
+void launch_slice_widths(int N, int nslices, const int* row_ptr, const int* lptr, int* cu, int* cl, int* wmax,
+                         hipStream_t s) {
   hipLaunchKernelGGL(k_slice_widths, dim3(div_up(nslices, kBlock)), dim3(kBlock), 0, s, N, nslices, row_ptr, lptr, cu,
-                     cl);
+                     cl, wmax);
 }
 
 void launch_sell_fill(int N, int nslices, const int* row_ptr, const int* col, const float* vals, const float* Linv,

@@ -60,8 +60,9 @@ constexpr int kSlice = 64;         // rows per slice of the sliced block storage
 //                off-diagonal blocks of the row and their columns;
 //   lower slots  sent = (upper slot, source row r) of every upper block (r, c)
 //                of the row's column c, by increasing r;
-// padded slots hold a zero block.  Vectors are FP32 SoA [3][N4] (N4 = N
-// rounded up to 4; pads are zero), Lf is SoA [6][N4].  The SpMV grid gives this
+// padded slots hold a zero block, and zeroed padding follows the last slot of
+// each array (see slot_padding).  Vectors are FP32 AoS [N4][3] (N4 = N
+// rounded up to 4; pads are zero), Lf is [N4][6].  The SpMV grid gives this
 // system spmv_nwg workgroups of 4 slices each; the update grid vec_nwg.
 struct PcgSystem {
   int N, N4, nslices;
@@ -167,7 +168,16 @@ void launch_assemble_rows(int N, const int* row_ptr, const int* col, const int* 
 void launch_lower_count(int N, const int* row_ptr, const int* col, int* lcnt, hipStream_t s);
 void launch_lower_fill(int N, const int* row_ptr, const int* col, const int* lptr, int* lcur, int* lsrc,
                        hipStream_t s);
-void launch_slice_widths(int N, int nslices, const int* row_ptr, const int* lptr, int* cu, int* cl, hipStream_t s);
+void launch_slice_widths(int N, int nslices, const int* row_ptr, const int* lptr, int* cu, int* cl, int* wmax,
+                         hipStream_t s);
+// The SpMV visits upper and lower slots in pairs, kPairs per step, and reads
+// up to (max width + kPairs) * kSlice slots past the end of a slice's range;
+// the slot arrays carry that much zeroed padding after their last slot.
+#ifndef BFAL_SPMV_PAIRS
+#define BFAL_SPMV_PAIRS 2
+#endif
+constexpr int kPairs = BFAL_SPMV_PAIRS;
+inline long long slot_padding(int wmax_other) { return (long long)(wmax_other + kPairs + 1) * kSlice; }
 void launch_sell_fill(int N, int nslices, const int* row_ptr, const int* col, const float* vals, const float* Linv,
                       const int* lptr, const int* lsrc, const int* sbu, const int* sbl, float* blk, uint32_t* blk16,
                       int* scol, int2* sent, hipStream_t s);

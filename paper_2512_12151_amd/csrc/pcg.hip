@@ -171,47 +171,46 @@ __device__ inline bool spmv_scalars(const PcgSystem& S, bool leader, int& k, flo
   return true;
 }
 
-#ifndef BFAL_SPMV_UNROLL
-#define BFAL_SPMV_UNROLL 4
-#endif
-constexpr int kUnroll = BFAL_SPMV_UNROLL;   // slots per step of a lane (independent loads in flight)
-
 // Vector entries of p_k at node c, formed on the fly: p_k = r + beta p_{k-1}
 // (the same rounding as the row owner's, so every reader sees the same p_k).
+// Vectors are AoS [N4][3]: one 12-byte load per vector and node.
 struct PView {
-  const float* __restrict__ r0;
-  const float* __restrict__ r1;
-  const float* __restrict__ r2;
-  const float* __restrict__ o0;
-  const float* __restrict__ o1;
-  const float* __restrict__ o2;
+  const float* __restrict__ r;
+  const float* __restrict__ o;
   float beta;
   bool first;
   __device__ inline void at(int c, float& p0, float& p1, float& p2) const {
-    p0 = r0[c];
-    p1 = r1[c];
-    p2 = r2[c];
+    const float* rc = r + 3LL * c;
+    p0 = rc[0];
+    p1 = rc[1];
+    p2 = rc[2];
     if (!first) {
-      p0 = __fmaf_rn(beta, o0[c], p0);
-      p1 = __fmaf_rn(beta, o1[c], p1);
-      p2 = __fmaf_rn(beta, o2[c], p2);
+      const float* oc = o + 3LL * c;
+      p0 = __fmaf_rn(beta, oc[0], p0);
+      p1 = __fmaf_rn(beta, oc[1], p1);
+      p2 = __fmaf_rn(beta, oc[2], p2);
     }
   }
 };
 
+#ifndef BFAL_SPMV_PAIRED
+#define BFAL_SPMV_PAIRED 1
+#endif
+
 // Accumulates the w slots of one row starting at base (stride kSlice):
 // upper slots (B p_c, columns from scol) or lower slots (B^T p_r, block and
-// source row from sent), kUnroll slots per step with all their loads issued
-// before any is used.  The sum runs in slot order either way.
+// source row from sent), 4 slots per step with all their loads issued before
+// any is used.  The sum runs in slot order.
 template <bool kLower, class BT>
 __device__ inline void accumulate_slots(int base, int w, const int* __restrict__ scol,
                                         const int2* __restrict__ sent, const BT* __restrict__ blk, const PView& pv,
                                         float& a0, float& a1, float& a2) {
+  constexpr int U = 4;
   int kk = 0;
-  for (; kk + kUnroll <= w; kk += kUnroll) {
-    int bi[kUnroll], c[kUnroll];
+  for (; kk + U <= w; kk += U) {
+    int bi[U], c[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int e = base + (kk + u) * kSlice;
       if (kLower) {
         const int2 t = sent[e];
@@ -222,14 +221,14 @@ __device__ inline void accumulate_slots(int base, int w, const int* __restrict__
         c[u] = scol[e];
       }
     }
-    float b[kUnroll][9], p[kUnroll][3];
+    float b[U][9], p[U][3];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       load_block(blk, bi[u], b[u]);
       pv.at(c[u], p[u][0], p[u][1], p[u][2]);
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       if (kLower) {
         a0 += b[u][0] * p[u][0] + b[u][3] * p[u][1] + b[u][6] * p[u][2];
         a1 += b[u][1] * p[u][0] + b[u][4] * p[u][1] + b[u][7] * p[u][2];
@@ -267,30 +266,81 @@ __device__ inline void accumulate_slots(int base, int w, const int* __restrict__
   }
 }
 
+// Accumulates one row's slots as pairs (upper slot k: B p_c with the column
+// from scol; lower slot k: B^T p_r with block and source row from sent),
+// kPairs pairs per step with all their loads issued before any is used.  A
+// step may run past the row's widths: those slots are still read (the slot
+// arrays are padded, so every index read is in range) but not added, which
+// keeps the step free of branches.  The sum runs in pair order.
+template <class BT>
+__device__ inline void accumulate_pairs(int ubase, int wu, int lbase, int wl, const int* __restrict__ scol,
+                                        const int2* __restrict__ sent, const BT* __restrict__ blk, const PView& pv,
+                                        float& a0, float& a1, float& a2) {
+  const int w = wu > wl ? wu : wl;
+  for (int k = 0; k < w; k += kPairs) {
+    int ub[kPairs], uc[kPairs], lb[kPairs], lc[kPairs];
+#pragma unroll
+    for (int u = 0; u < kPairs; ++u) {
+      ub[u] = ubase + (k + u) * kSlice;
+      uc[u] = scol[ub[u]];
+      const int2 t = sent[lbase + (k + u) * kSlice];
+      lb[u] = t.x;
+      lc[u] = t.y;
+    }
+    float bu[kPairs][9], pu[kPairs][3], bl[kPairs][9], pl[kPairs][3];
+#pragma unroll
+    for (int u = 0; u < kPairs; ++u) {
+      load_block(blk, ub[u], bu[u]);
+      pv.at(uc[u], pu[u][0], pu[u][1], pu[u][2]);
+      load_block(blk, lb[u], bl[u]);
+      pv.at(lc[u], pl[u][0], pl[u][1], pl[u][2]);
+    }
+#pragma unroll
+    for (int u = 0; u < kPairs; ++u) {
+      const bool vu = k + u < wu, vl = k + u < wl;
+      const float y0 = bu[u][0] * pu[u][0] + bu[u][1] * pu[u][1] + bu[u][2] * pu[u][2];
+      const float y1 = bu[u][3] * pu[u][0] + bu[u][4] * pu[u][1] + bu[u][5] * pu[u][2];
+      const float y2 = bu[u][6] * pu[u][0] + bu[u][7] * pu[u][1] + bu[u][8] * pu[u][2];
+      a0 += vu ? y0 : 0.f;
+      a1 += vu ? y1 : 0.f;
+      a2 += vu ? y2 : 0.f;
+      const float z0 = bl[u][0] * pl[u][0] + bl[u][3] * pl[u][1] + bl[u][6] * pl[u][2];
+      const float z1 = bl[u][1] * pl[u][0] + bl[u][4] * pl[u][1] + bl[u][7] * pl[u][2];
+      const float z2 = bl[u][2] * pl[u][0] + bl[u][5] * pl[u][1] + bl[u][8] * pl[u][2];
+      a0 += vl ? z0 : 0.f;
+      a1 += vl ? z1 : 0.f;
+      a2 += vl ? z2 : 0.f;
+    }
+  }
+}
+
 // q = H_hat p_k for the slices of workgroup lb (of nwg) of one system, p_k
 // formed on the fly; returns this thread's share of p^T q.
 template <class BT>
 __device__ inline double spmv_slices(const PcgSystem& S, int lb, int nwg, int k, float beta) {
   const int wave = threadIdx.x / kSlice, lane = threadIdx.x % kSlice;
-  const long long n4 = S.N4;
   const float* pold = (k & 1) ? S.P0 : S.P1;
   float* __restrict__ pn = (k & 1) ? S.P1 : S.P0;
-  const PView pv{S.r, S.r + n4, S.r + 2 * n4, pold, pold + n4, pold + 2 * n4, beta, k == 0};
+  const PView pv{S.r, pold, beta, k == 0};
   const BT* __restrict__ blk = static_cast<const BT*>(S.blk);
   double dot = 0.0;
   for (int sl = lb * kSlicesPerGroup + wave; sl < S.nslices; sl += nwg * kSlicesPerGroup) {
     const int bu = S.sbu[sl], wu = (S.sbu[sl + 1] - bu) / kSlice;
     const int bl = S.sbl[sl], wl = (S.sbl[sl + 1] - bl) / kSlice;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#if BFAL_SPMV_PAIRED
+    accumulate_pairs<BT>(bu + lane, wu, bl + lane, wl, S.scol, S.sent, blk, pv, a0, a1, a2);
+#else
     accumulate_slots<false, BT>(bu + lane, wu, S.scol, S.sent, blk, pv, a0, a1, a2);
     accumulate_slots<true, BT>(bl + lane, wl, S.scol, S.sent, blk, pv, a0, a1, a2);
+#endif
     const int row = sl * kSlice + lane;
     if (row < S.N) {
       float s0, s1, s2;
       pv.at(row, s0, s1, s2);
       const float q0 = s0 + a0, q1 = s1 + a1, q2 = s2 + a2;
-      pn[row] = s0; pn[n4 + row] = s1; pn[2 * n4 + row] = s2;
-      S.q[row] = q0; S.q[n4 + row] = q1; S.q[2 * n4 + row] = q2;
+      pn[3LL * row] = s0; pn[3LL * row + 1] = s1; pn[3LL * row + 2] = s2;
+      S.q[3LL * row] = q0; S.q[3LL * row + 1] = q1; S.q[3LL * row + 2] = q2;
       dot += (double)s0 * q0 + (double)s1 * q1 + (double)s2 * q2;
     }
   }
@@ -341,42 +391,43 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
   }
   const float alpha = (float)(rho / pq);
   const bool check = ((k + 1) % sc->check_every) == 0;
-  const long long n4 = S.N4 / 4;   // float4 per component
+  const long long ng = S.N4 / 4;   // groups of 4 nodes: 3 float4 per vector, 6 float4 of L
   const float4* __restrict__ p4 = reinterpret_cast<const float4*>((k & 1) ? S.P1 : S.P0);
   const float4* __restrict__ q4 = reinterpret_cast<const float4*>(S.q);
   float4* __restrict__ x4 = reinterpret_cast<float4*>(S.x);
   float4* __restrict__ r4 = reinterpret_cast<float4*>(S.r);
   const float4* __restrict__ l4 = reinterpret_cast<const float4*>(S.Lf);
   double rr = 0.0, rt = 0.0;
-  for (long long i = (long long)lb * kVecBlock + threadIdx.x; i < n4; i += (long long)S.vec_nwg * kVecBlock) {
-    float4 rn[3];
+  for (long long i = (long long)lb * kVecBlock + threadIdx.x; i < ng; i += (long long)S.vec_nwg * kVecBlock) {
+    float rv[12];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      const float4 p = p4[m * n4 + i], q = q4[m * n4 + i];
-      float4 x = x4[m * n4 + i], r = r4[m * n4 + i];
+      const float4 p = p4[3 * i + m], q = q4[3 * i + m];
+      float4 x = x4[3 * i + m], r = r4[3 * i + m];
       x.x = __fmaf_rn(alpha, p.x, x.x); x.y = __fmaf_rn(alpha, p.y, x.y);
       x.z = __fmaf_rn(alpha, p.z, x.z); x.w = __fmaf_rn(alpha, p.w, x.w);
       r.x = __fmaf_rn(-alpha, q.x, r.x); r.y = __fmaf_rn(-alpha, q.y, r.y);
       r.z = __fmaf_rn(-alpha, q.z, r.z); r.w = __fmaf_rn(-alpha, q.w, r.w);
-      x4[m * n4 + i] = x;
-      r4[m * n4 + i] = r;
-      rn[m] = r;
-      rr += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
+      x4[3 * i + m] = x;
+      r4[3 * i + m] = r;
+      rv[4 * m] = r.x; rv[4 * m + 1] = r.y; rv[4 * m + 2] = r.z; rv[4 * m + 3] = r.w;
     }
-    if (check) {
-      float4 l[6];
 #pragma unroll
-      for (int m = 0; m < 6; ++m) l[m] = l4[m * n4 + i];
-      const float lx[6][4] = {{l[0].x, l[0].y, l[0].z, l[0].w}, {l[1].x, l[1].y, l[1].z, l[1].w},
-                              {l[2].x, l[2].y, l[2].z, l[2].w}, {l[3].x, l[3].y, l[3].z, l[3].w},
-                              {l[4].x, l[4].y, l[4].z, l[4].w}, {l[5].x, l[5].y, l[5].z, l[5].w}};
-      const float rx[3][4] = {{rn[0].x, rn[0].y, rn[0].z, rn[0].w}, {rn[1].x, rn[1].y, rn[1].z, rn[1].w},
-                              {rn[2].x, rn[2].y, rn[2].z, rn[2].w}};
+    for (int m = 0; m < 12; ++m) rr += (double)rv[m] * rv[m];
+    if (check) {
+      float l[24];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        const float4 v = l4[6 * i + m];
+        l[4 * m] = v.x; l[4 * m + 1] = v.y; l[4 * m + 2] = v.z; l[4 * m + 3] = v.w;
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const double t0 = (double)lx[0][v] * rx[0][v];
-        const double t1 = (double)lx[1][v] * rx[0][v] + (double)lx[2][v] * rx[1][v];
-        const double t2 = (double)lx[3][v] * rx[0][v] + (double)lx[4][v] * rx[1][v] + (double)lx[5][v] * rx[2][v];
+        const float* lv = l + 6 * v;
+        const float* r = rv + 3 * v;
+        const double t0 = (double)lv[0] * r[0];
+        const double t1 = (double)lv[1] * r[0] + (double)lv[2] * r[1];
+        const double t2 = (double)lv[3] * r[0] + (double)lv[4] * r[1] + (double)lv[5] * r[2];
         rt += t0 * t0 + t1 * t1 + t2 * t2;
       }
     }
@@ -430,7 +481,7 @@ k_init_scalars(const double* __restrict__ bb_part, int nbb, PcgScalars* sc, doub
   }
 }
 
-// p = L^{-T} x in FP64 (x FP32 or FP64, SoA [3][N4]) and the per-workgroup max |p|.
+// p = L^{-T} x in FP64 (x FP32 or FP64, AoS [N4][3]) and the per-workgroup max |p|.
 template <class XT>
 __global__ void __launch_bounds__(kVecBlock)
 k_finish(int N, int N4, const float* __restrict__ Linv, const XT* __restrict__ x, double* __restrict__ pout,
@@ -438,7 +489,7 @@ k_finish(int N, int N4, const float* __restrict__ Linv, const XT* __restrict__ x
   double m = 0.0;
   for (int v = blockIdx.x * kVecBlock + threadIdx.x; v < N; v += gridDim.x * kVecBlock) {
     const float* l = Linv + 6LL * v;
-    const double x0 = x[v], x1 = x[N4 + v], x2 = x[2LL * N4 + v];
+    const double x0 = x[3LL * v], x1 = x[3LL * v + 1], x2 = x[3LL * v + 2];
     const double p0 = (double)l[0] * x0 + (double)l[1] * x1 + (double)l[3] * x2;
     const double p1 = (double)l[2] * x1 + (double)l[4] * x2;
     const double p2 = (double)l[5] * x2;
@@ -462,7 +513,6 @@ k_residual64(PcgSystem S, const float* __restrict__ bhat, const double* __restri
   // with bhat == nullptr: rd = H_hat xd and no partials
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int wave = threadIdx.x / kSlice, lane = threadIdx.x % kSlice;
-  const long long n4 = S.N4;
   const float* __restrict__ blk = static_cast<const float*>(S.blk);
   double rt = 0.0;
   for (int sl = lb * kSlicesPerGroup + wave; sl < S.nslices; sl += gridDim.x * kSlicesPerGroup) {
@@ -474,7 +524,7 @@ k_residual64(PcgSystem S, const float* __restrict__ bhat, const double* __restri
       const int c = S.scol[e];
       float b[9];
       load_block(blk, e, b);
-      const double x0 = xd[c], x1 = xd[n4 + c], x2 = xd[2 * n4 + c];
+      const double x0 = xd[3LL * c], x1 = xd[3LL * c + 1], x2 = xd[3LL * c + 2];
       a0 += (double)b[0] * x0 + (double)b[1] * x1 + (double)b[2] * x2;
       a1 += (double)b[3] * x0 + (double)b[4] * x1 + (double)b[5] * x2;
       a2 += (double)b[6] * x0 + (double)b[7] * x1 + (double)b[8] * x2;
@@ -484,27 +534,28 @@ k_residual64(PcgSystem S, const float* __restrict__ bhat, const double* __restri
       const int c = t.y;
       float b[9];
       load_block(blk, t.x, b);
-      const double x0 = xd[c], x1 = xd[n4 + c], x2 = xd[2 * n4 + c];
+      const double x0 = xd[3LL * c], x1 = xd[3LL * c + 1], x2 = xd[3LL * c + 2];
       a0 += (double)b[0] * x0 + (double)b[3] * x1 + (double)b[6] * x2;
       a1 += (double)b[1] * x0 + (double)b[4] * x1 + (double)b[7] * x2;
       a2 += (double)b[2] * x0 + (double)b[5] * x1 + (double)b[8] * x2;
     }
     const int row = sl * kSlice + lane;
+    const long long o = 3LL * row;
     if (row < S.N && !bhat) {
-      rd[row] = xd[row] + a0;
-      rd[n4 + row] = xd[n4 + row] + a1;
-      rd[2 * n4 + row] = xd[2 * n4 + row] + a2;
+      rd[o] = xd[o] + a0;
+      rd[o + 1] = xd[o + 1] + a1;
+      rd[o + 2] = xd[o + 2] + a2;
     } else if (row < S.N) {
-      const double r0 = (double)bhat[row] - (xd[row] + a0);
-      const double r1 = (double)bhat[n4 + row] - (xd[n4 + row] + a1);
-      const double r2 = (double)bhat[2 * n4 + row] - (xd[2 * n4 + row] + a2);
-      rd[row] = r0;
-      rd[n4 + row] = r1;
-      rd[2 * n4 + row] = r2;
-      const float* L = S.Lf;
-      const double t0 = (double)L[row] * r0;
-      const double t1 = (double)L[n4 + row] * r0 + (double)L[2 * n4 + row] * r1;
-      const double t2 = (double)L[3 * n4 + row] * r0 + (double)L[4 * n4 + row] * r1 + (double)L[5 * n4 + row] * r2;
+      const double r0 = (double)bhat[o] - (xd[o] + a0);
+      const double r1 = (double)bhat[o + 1] - (xd[o + 1] + a1);
+      const double r2 = (double)bhat[o + 2] - (xd[o + 2] + a2);
+      rd[o] = r0;
+      rd[o + 1] = r1;
+      rd[o + 2] = r2;
+      const float* L = S.Lf + 6LL * row;
+      const double t0 = (double)L[0] * r0;
+      const double t1 = (double)L[1] * r0 + (double)L[2] * r1;
+      const double t2 = (double)L[3] * r0 + (double)L[4] * r1 + (double)L[5] * r2;
       rt += t0 * t0 + t1 * t1 + t2 * t2;
     }
   }
