@@ -96,13 +96,14 @@ def cpu_baseline(sc, gpu_iters, frac):
 
 
 def serve_trace(server, reqs, arrivals, timeout=600.0):
-    """Submit reqs[i] at arrivals[i] seconds after the start (Poisson trace),
-    poll completions; returns per-request latency (done - submit, s), the
-    span from the first submit to the last completion, and statuses."""
-    from paper_2512_12151_amd import bfal
+    """Submit reqs[i] at arrivals[i] seconds after the start (a Poisson trace,
+    or all at 0 for a capacity run) and poll completions.  Returns per-request
+    latency (done - submit, s), the span from the first submit to the last
+    completion, statuses, and the mean setup and PCG times (ms)."""
     n = len(reqs)
     lat = np.zeros(n)
     status = np.zeros(n, dtype=int)
+    setup, pcg = np.zeros(n), np.zeros(n)
     first, last = None, 0.0
     done = 0
     k = 0
@@ -116,6 +117,7 @@ def serve_trace(server, reqs, arrivals, timeout=600.0):
             _, st, times, rs = server.result(i)
             lat[i] = times["t_done"] - times["t_submit"]
             status[i] = rs
+            setup[i], pcg[i] = st["ms_assemble"], st["ms_pcg"]
             first = times["t_submit"] if first is None else min(first, times["t_submit"])
             last = max(last, times["t_done"])
             done += 1
@@ -123,43 +125,62 @@ def serve_trace(server, reqs, arrivals, timeout=600.0):
             raise RuntimeError("serving trace did not finish")
         nxt = arrivals[k] - (time.perf_counter() - t0) if k < n else 2e-4
         time.sleep(min(max(nxt, 0.0), 2e-4))
-    return lat, last - first, status
+    return lat, last - first, status, float(setup.mean()), float(pcg.mean())
 
 
-def run_serve(n_req, seed=5):
-    """C5: requests of two stacked cubes (tets ~ LogU[2k, 300k]), Poisson
-    arrivals at 0.8 x the one-at-a-time service rate (measured first on the
-    first 32 requests), served by the continuous-batching server and by the
-    same engine one request at a time, on the same trace."""
+def run_serve(n_req, seed=5, loads=(0.8, 1.2, 2.0)):
+    """Serving (continuous batching) on a stream of two-stacked-cube requests
+    (tets ~ LogU[2k, 300k]).  The one-at-a-time service time is measured first
+    (64 requests back to back on the same engine with one slot); Poisson traces
+    at `loads` x that service rate are then served by the batching server and
+    one at a time; a capacity run submits everything at once; a forced small
+    budget (1.25 x the largest request's footprint) repeats the first trace."""
     import torch
 
     import scenes
     from paper_2512_12151_amd import bfal
     log(f"serve: generating {n_req} requests")
     reqs = [scenes.serve_request(i) for i in range(n_req)]
-    free, total = torch.cuda.mem_get_info()
+    free, _ = torch.cuda.mem_get_info()
     budget = int(0.9 * free)
-    # service time one at a time (back to back, no queueing delay counted)
-    cal = min(32, n_req)
-    sv = bfal.Server(0, hbm_budget=budget, max_active=1, iters_per_round=8)
-    lat, span, _ = serve_trace(sv, reqs[:cal], np.zeros(cal))
-    sv.close()
-    service = span / cal
-    rate = 0.8 / service
+
+    def summary(lat, span, status, su, pc):
+        return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                "mean_ms": round(float(lat.mean()) * 1e3, 3),
+                "steps_per_s": round(len(lat) / span, 2), "errors": int((status < 0).sum()),
+                "mean_setup_ms": round(su, 3), "mean_pcg_ms": round(pc, 3)}
+
+    def serve(reqs_, arrivals, max_active, budget_=budget):
+        sv = bfal.Server(0, hbm_budget=budget_, max_active=max_active, iters_per_round=8)
+        try:
+            return summary(*serve_trace(sv, reqs_, arrivals))
+        finally:
+            sv.close()
+
+    cal = min(64, n_req)
+    one = serve(reqs[:cal], np.zeros(cal), 1)
+    service = 1.0 / one["steps_per_s"]
+    out = {"requests": n_req, "one_at_a_time_service_ms": round(service * 1e3, 3), "hbm_budget_bytes": budget,
+           "capacity": {"one_at_a_time": one, "batched": serve(reqs, np.zeros(n_req), 64)}}
+    log(f"serve capacity: {out['capacity']}")
     rng = np.random.default_rng(seed)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    gaps = rng.exponential(1.0, size=n_req)
+    for load in loads:
+        rate = load / service
+        arrivals = np.cumsum(gaps / rate)
+        arrivals -= arrivals[0]
+        key = f"load_{load:g}"
+        out[key] = {"arrival_rate_per_s": round(rate, 2), "batched": serve(reqs, arrivals, 64),
+                    "one_at_a_time": serve(reqs, arrivals, 1)}
+        log(f"serve {key}: {out[key]}")
+    small = int(1.25 * max(bfal.footprint_bytes(len(r["rest"]), len(r["tets"]), len(r["pt"]) + len(r["ee"]))
+                           for r in reqs))
+    rate = loads[0] / service
+    arrivals = np.cumsum(gaps / rate)
     arrivals -= arrivals[0]
-    out = {"requests": n_req, "arrival_rate_per_s": round(rate, 2),
-           "one_at_a_time_service_ms": round(service * 1e3, 3), "hbm_budget_bytes": budget}
-    for name, max_active in (("batched", 64), ("one_at_a_time", 1)):
-        sv = bfal.Server(0, hbm_budget=budget, max_active=max_active, iters_per_round=8)
-        lat, span, status = serve_trace(sv, reqs, arrivals)
-        sv.close()
-        out[name] = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                     "mean_ms": round(float(lat.mean()) * 1e3, 3),
-                     "steps_per_s": round(n_req / span, 2), "errors": int((status < 0).sum())}
-        log(f"serve {name}: {out[name]}")
+    out["small_budget"] = {"hbm_budget_bytes": small, "load": loads[0], "batched": serve(reqs, arrivals, 64, small)}
+    log(f"serve small budget: {out['small_budget']}")
     return out
 
 

@@ -176,7 +176,7 @@ bf_status bf_footprint_bytes(int32_t n_nodes, int32_t n_tets, int32_t n_constrai
 /* A server solves independent Newton-step requests (each: a mesh, its state
  * and its active constraint set; the same operation as bf_newton_step, FP32
  * mode) with continuous batching on one device.  Two threads of the library
- * work in the background: an admission thread takes submitted requests in
+ * work in the background: admission threads take submitted requests in
  * arrival order and admits the head of the queue when its footprint
  * (bf_footprint_bytes) fits beside the admitted ones in hbm_budget and fewer
  * than max_active are admitted, then assembles it on its own stream; a batch
@@ -184,7 +184,8 @@ bf_status bf_footprint_bytes(int32_t n_nodes, int32_t n_tets, int32_t n_constrai
  * block-diagonal system with per-request scalars, iters_per_round iterations
  * between scheduling points), retires finished requests and frees their
  * budget.  Requests arriving while others are on the GPU join the batch as
- * slots and memory free up.  max_active = 1 serves one request at a time.
+ * slots and memory free up; several admission workers assemble arriving
+ * requests concurrently.  max_active = 1 serves one request at a time.
  * Threads: submit, poll, result and stats may be called from any one thread;
  * the server uses its own streams, so the calling thread's context is free. */
 typedef struct bf_server bf_server;
@@ -192,6 +193,7 @@ typedef struct {
   size_t hbm_budget;         /* device bytes the admitted requests may hold (footprint estimates), > 0 */
   int32_t max_active;        /* at most this many admitted requests, >= 1 */
   int32_t iters_per_round;   /* batched PCG iterations between scheduling points, >= 1 */
+  int32_t admit_threads;     /* admission workers (each assembles on its own stream); 0 means 4 */
 } bf_server_opts;
 typedef struct {
   double t_submit, t_admit, t_done;  /* seconds on bf_clock_now()'s clock */

@@ -59,7 +59,8 @@ class BfalError(RuntimeError):
 
 
 class bf_server_opts(C.Structure):
-    _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int32), ("iters_per_round", C.c_int32)]
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int32), ("iters_per_round", C.c_int32),
+                ("admit_threads", C.c_int32)]
 
 
 class bf_request_times(C.Structure):
@@ -273,8 +274,8 @@ class Server:
     """Continuous-batching server (bf_server_*): submit host-memory requests,
     poll for finished ids, take results.  Arguments are marshalled only."""
 
-    def __init__(self, device=0, hbm_budget=8 << 30, max_active=64, iters_per_round=8):
-        o = bf_server_opts(int(hbm_budget), int(max_active), int(iters_per_round))
+    def __init__(self, device=0, hbm_budget=8 << 30, max_active=64, iters_per_round=8, admit_threads=4):
+        o = bf_server_opts(int(hbm_budget), int(max_active), int(iters_per_round), int(admit_threads))
         self.h = C.c_void_p()
         st = lib().bf_server_create(int(device), C.byref(o), C.byref(self.h))
         if st != BF_OK:

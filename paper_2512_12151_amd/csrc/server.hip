@@ -1,12 +1,13 @@
 // Serving engine of libbfal: continuous batching of independent Newton-step
 // solves (one request = one mesh with its state and active constraint set).
 //
-// Two native threads share one device:
-//   admission  takes submitted requests in arrival order, admits the head of
-//              the queue when its device footprint fits the HBM budget and a
-//              slot is free, and runs its setup and assembly (per-mesh setup,
-//              constraint linearization, merged pattern, element and contact
-//              blocks, block-Jacobi factors, sliced storage) on its own stream;
+// Native threads share one device:
+//   admission  (several workers, one stream each) take submitted requests in
+//              arrival order, admit the head of the queue when its device
+//              footprint fits the HBM budget and a slot is free, and run its
+//              setup and assembly (per-mesh setup, constraint linearization,
+//              merged pattern, element and contact blocks, block-Jacobi
+//              factors, sliced storage) on the worker's stream;
 //   batch      runs the PCG of every admitted request together: each round is
 //              a few iterations of the batched SpMV/update kernel pair, whose
 //              grid is the concatenation of the requests' grids (a
@@ -65,7 +66,7 @@ struct Slot {
 }  // namespace
 
 struct bf_server {
-  bf_context* admit_ctx = nullptr;   // own contexts: one stream each
+  std::vector<bf_context*> admit_ctx;   // own contexts: one stream per admission worker
   bf_context* batch_ctx = nullptr;
   size_t budget = 0, used = 0;
   int max_active = 1, iters_per_round = 8;
@@ -78,7 +79,8 @@ struct bf_server {
   std::unordered_map<int64_t, Request*> done; // finished, result not yet taken
   std::vector<int64_t> done_unreported;
   bool stop = false;
-  std::thread admit_thread, batch_thread;
+  std::vector<std::thread> admit_threads;
+  std::thread batch_thread;
   // batch thread only
   std::vector<int> active;
   DevBuf sys_dev, map_spmv, map_vec, status_dev;
@@ -111,9 +113,8 @@ void finish_request(bf_server* sv, Request* r, bf_status st, const std::string& 
   sv->done_unreported.push_back(r->id);
 }
 
-// Setup and assembly of one request in slot si, on the admission stream.
-bf_status prepare(bf_server* sv, int si, Request* r) {
-  bf_context* c = sv->admit_ctx;
+// Setup and assembly of one request in slot si, on an admission worker's stream.
+bf_status prepare(bf_server* sv, bf_context* c, int si, Request* r) {
   Slot& sl = sv->slots[si];
   if (!sl.pb) {
     sl.pb = new (std::nothrow) bf_problem();
@@ -145,8 +146,9 @@ bf_status prepare(bf_server* sv, int si, Request* r) {
   return BF_OK;
 }
 
-void admission_loop(bf_server* sv) {
-  (void)hipSetDevice(sv->admit_ctx->device);
+void admission_loop(bf_server* sv, int worker) {
+  bf_context* c = sv->admit_ctx[worker];
+  (void)hipSetDevice(c->device);
   for (;;) {
     Request* r = nullptr;
     int si = -1;
@@ -176,10 +178,10 @@ void admission_loop(bf_server* sv) {
       }
     }
     r->t_admit = now_s();
-    const bf_status st = prepare(sv, si, r);
+    const bf_status st = prepare(sv, c, si, r);
     r->ms_setup = (now_s() - r->t_admit) * 1e3;
     if (st != BF_OK) {
-      const std::string msg = sv->admit_ctx->err;
+      const std::string msg = c->err;
       {
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->used -= r->footprint;
@@ -390,11 +392,18 @@ double bf_clock_now(void) { return now_s(); }
 bf_status bf_server_create(int32_t device, const bf_server_opts* o, bf_server** out) {
   if (!out || !o) return BF_ERR_INVALID_ARG;
   *out = nullptr;
-  if (o->max_active < 1 || o->iters_per_round < 1 || o->hbm_budget == 0) return BF_ERR_INVALID_ARG;
+  if (o->max_active < 1 || o->iters_per_round < 1 || o->hbm_budget == 0 || o->admit_threads < 0 ||
+      o->admit_threads > 64)
+    return BF_ERR_INVALID_ARG;
   bf_server* sv = new (std::nothrow) bf_server();
   if (!sv) return BF_ERR_OOM;
-  bf_status st = bf_context_create(device, nullptr, &sv->admit_ctx);
-  if (st == BF_OK) st = bf_context_create(device, nullptr, &sv->batch_ctx);
+  const int nadmit = o->admit_threads > 0 ? o->admit_threads : 4;
+  bf_status st = bf_context_create(device, nullptr, &sv->batch_ctx);
+  for (int i = 0; i < nadmit && st == BF_OK; ++i) {
+    bf_context* c = nullptr;
+    st = bf_context_create(device, nullptr, &c);
+    if (st == BF_OK) sv->admit_ctx.push_back(c);
+  }
   if (st != BF_OK) {
     bf_server_destroy(sv);
     return st;
@@ -404,7 +413,7 @@ bf_status bf_server_create(int32_t device, const bf_server_opts* o, bf_server** 
   sv->iters_per_round = o->iters_per_round;
   sv->slots.resize(o->max_active);
   for (int i = o->max_active - 1; i >= 0; --i) sv->free_slots.push_back(i);
-  sv->admit_thread = std::thread(admission_loop, sv);
+  for (int i = 0; i < nadmit; ++i) sv->admit_threads.emplace_back(admission_loop, sv, i);
   sv->batch_thread = std::thread(batch_loop, sv);
   *out = sv;
   return BF_OK;
@@ -511,10 +520,11 @@ void bf_server_destroy(bf_server* sv) {
     sv->stop = true;
   }
   sv->cv.notify_all();
-  if (sv->admit_thread.joinable()) sv->admit_thread.join();
+  for (std::thread& t : sv->admit_threads)
+    if (t.joinable()) t.join();
   if (sv->batch_thread.joinable()) sv->batch_thread.join();
   if (sv->batch_ctx) (void)hipStreamSynchronize(sv->batch_ctx->stream);
-  if (sv->admit_ctx) (void)hipStreamSynchronize(sv->admit_ctx->stream);
+  for (bf_context* c : sv->admit_ctx) (void)hipStreamSynchronize(c->stream);
   for (Slot& sl : sv->slots)
     if (sl.pb) bf_problem_destroy(sl.pb);
   for (Request* r : sv->pending) delete r;
@@ -527,7 +537,7 @@ void bf_server_destroy(bf_server* sv) {
   if (sv->h_sys) (void)hipHostFree(sv->h_sys);
   if (sv->h_map) (void)hipHostFree(sv->h_map);
   if (sv->h_status) (void)hipHostFree(sv->h_status);
-  bf_context_destroy(sv->admit_ctx);
+  for (bf_context* c : sv->admit_ctx) bf_context_destroy(c);
   bf_context_destroy(sv->batch_ctx);
   delete sv;
 }
