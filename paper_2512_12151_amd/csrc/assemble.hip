@@ -136,8 +136,10 @@ k_assemble_rows(int N, const int* __restrict__ row_ptr, const int* __restrict__ 
     const float M10 = -L10 * M00 * M11;
     const float M21 = -L21 * M11 * M22;
     const float M20 = -(L20 * M00 + L21 * M10) * M22;
-    float* lf = Lf + 6LL * r;
-    lf[0] = L00; lf[1] = L10; lf[2] = L11; lf[3] = L20; lf[4] = L21; lf[5] = L22;
+    // L as SoA [6][N4] for the solver's residual check
+    const long long N4 = (N + 3) & ~3;
+    Lf[r] = L00; Lf[N4 + r] = L10; Lf[2 * N4 + r] = L11; Lf[3 * N4 + r] = L20; Lf[4 * N4 + r] = L21;
+    Lf[5 * N4 + r] = L22;
     float* li = Linv + 6LL * r;
     li[0] = M00; li[1] = M10; li[2] = M11; li[3] = M20; li[4] = M21; li[5] = M22;
     // b_hat = L^{-1} b with b = -G

@@ -62,7 +62,7 @@ constexpr int kSlice = 64;         // rows per slice of the sliced block storage
 //                of the row's column c, by increasing r;
 // padded slots hold a zero block, and zeroed padding follows the last slot of
 // each array (see slot_padding).  Vectors are FP32 AoS [N4][3] (N4 = N
-// rounded up to 4; pads are zero), Lf is [N4][6].  The SpMV grid gives this
+// rounded up to 4; pads are zero), Lf is SoA [6][N4].  The SpMV grid gives this
 // system spmv_nwg workgroups of 4 slices each; the update grid vec_nwg.
 struct PcgSystem {
   int N, N4, nslices;

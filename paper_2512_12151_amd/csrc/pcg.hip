@@ -391,45 +391,61 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
   }
   const float alpha = (float)(rho / pq);
   const bool check = ((k + 1) % sc->check_every) == 0;
-  const long long ng = S.N4 / 4;   // groups of 4 nodes: 3 float4 per vector, 6 float4 of L
+  // Chunks of 4 * kVecBlock nodes: the three vectors' float4s of a chunk are
+  // contiguous, so every load and store below is one contiguous run per
+  // wavefront; the new residual is staged in LDS for the per-node |L r|^2,
+  // with L stored SoA [6][N4].
+  __shared__ float4 rs[3 * kVecBlock];
+  const long long n4 = S.N4;
+  const long long nf4 = 3 * n4 / 4;   // float4 per vector
   const float4* __restrict__ p4 = reinterpret_cast<const float4*>((k & 1) ? S.P1 : S.P0);
   const float4* __restrict__ q4 = reinterpret_cast<const float4*>(S.q);
   float4* __restrict__ x4 = reinterpret_cast<float4*>(S.x);
   float4* __restrict__ r4 = reinterpret_cast<float4*>(S.r);
   const float4* __restrict__ l4 = reinterpret_cast<const float4*>(S.Lf);
+  const int t = threadIdx.x;
   double rr = 0.0, rt = 0.0;
-  for (long long i = (long long)lb * kVecBlock + threadIdx.x; i < ng; i += (long long)S.vec_nwg * kVecBlock) {
-    float rv[12];
+  const long long nchunk = (n4 + 4 * kVecBlock - 1) / (4 * kVecBlock);
+  for (long long ch = lb; ch < nchunk; ch += S.vec_nwg) {
+    const long long fb = ch * 3 * kVecBlock;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      const float4 p = p4[3 * i + m], q = q4[3 * i + m];
-      float4 x = x4[3 * i + m], r = r4[3 * i + m];
-      x.x = __fmaf_rn(alpha, p.x, x.x); x.y = __fmaf_rn(alpha, p.y, x.y);
-      x.z = __fmaf_rn(alpha, p.z, x.z); x.w = __fmaf_rn(alpha, p.w, x.w);
-      r.x = __fmaf_rn(-alpha, q.x, r.x); r.y = __fmaf_rn(-alpha, q.y, r.y);
-      r.z = __fmaf_rn(-alpha, q.z, r.z); r.w = __fmaf_rn(-alpha, q.w, r.w);
-      x4[3 * i + m] = x;
-      r4[3 * i + m] = r;
-      rv[4 * m] = r.x; rv[4 * m + 1] = r.y; rv[4 * m + 2] = r.z; rv[4 * m + 3] = r.w;
+      const long long f = fb + m * kVecBlock + t;
+      if (f < nf4) {
+        const float4 p = p4[f], q = q4[f];
+        float4 x = x4[f], r = r4[f];
+        x.x = __fmaf_rn(alpha, p.x, x.x); x.y = __fmaf_rn(alpha, p.y, x.y);
+        x.z = __fmaf_rn(alpha, p.z, x.z); x.w = __fmaf_rn(alpha, p.w, x.w);
+        r.x = __fmaf_rn(-alpha, q.x, r.x); r.y = __fmaf_rn(-alpha, q.y, r.y);
+        r.z = __fmaf_rn(-alpha, q.z, r.z); r.w = __fmaf_rn(-alpha, q.w, r.w);
+        x4[f] = x;
+        r4[f] = r;
+        rr += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
+        rs[m * kVecBlock + t] = r;
+      }
     }
-#pragma unroll
-    for (int m = 0; m < 12; ++m) rr += (double)rv[m] * rv[m];
     if (check) {
-      float l[24];
+      __syncthreads();
+      const long long v0 = ch * 4 * kVecBlock + 4LL * t;   // this thread's 4 nodes
+      if (v0 < n4) {
+        const float4 ra = rs[3 * t], rb = rs[3 * t + 1], rc = rs[3 * t + 2];
+        const float rv[12] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w, rc.x, rc.y, rc.z, rc.w};
+        float4 l[6];
 #pragma unroll
-      for (int m = 0; m < 6; ++m) {
-        const float4 v = l4[6 * i + m];
-        l[4 * m] = v.x; l[4 * m + 1] = v.y; l[4 * m + 2] = v.z; l[4 * m + 3] = v.w;
-      }
+        for (int m = 0; m < 6; ++m) l[m] = l4[(m * n4 + v0) / 4];
+        const float lx[6][4] = {{l[0].x, l[0].y, l[0].z, l[0].w}, {l[1].x, l[1].y, l[1].z, l[1].w},
+                                {l[2].x, l[2].y, l[2].z, l[2].w}, {l[3].x, l[3].y, l[3].z, l[3].w},
+                                {l[4].x, l[4].y, l[4].z, l[4].w}, {l[5].x, l[5].y, l[5].z, l[5].w}};
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float* lv = l + 6 * v;
-        const float* r = rv + 3 * v;
-        const double t0 = (double)lv[0] * r[0];
-        const double t1 = (double)lv[1] * r[0] + (double)lv[2] * r[1];
-        const double t2 = (double)lv[3] * r[0] + (double)lv[4] * r[1] + (double)lv[5] * r[2];
-        rt += t0 * t0 + t1 * t1 + t2 * t2;
+        for (int v = 0; v < 4; ++v) {
+          const float* r = rv + 3 * v;
+          const double t0 = (double)lx[0][v] * r[0];
+          const double t1 = (double)lx[1][v] * r[0] + (double)lx[2][v] * r[1];
+          const double t2 = (double)lx[3][v] * r[0] + (double)lx[4][v] * r[1] + (double)lx[5][v] * r[2];
+          rt += t0 * t0 + t1 * t1 + t2 * t2;
+        }
       }
+      __syncthreads();
     }
   }
   const double srr = block_sum_all<kVecBlock>(rr);
@@ -552,10 +568,11 @@ k_residual64(PcgSystem S, const float* __restrict__ bhat, const double* __restri
       rd[o] = r0;
       rd[o + 1] = r1;
       rd[o + 2] = r2;
-      const float* L = S.Lf + 6LL * row;
+      const float* L = S.Lf + row;   // SoA [6][N4]
+      const long long n4 = S.N4;
       const double t0 = (double)L[0] * r0;
-      const double t1 = (double)L[1] * r0 + (double)L[2] * r1;
-      const double t2 = (double)L[3] * r0 + (double)L[4] * r1 + (double)L[5] * r2;
+      const double t1 = (double)L[n4] * r0 + (double)L[2 * n4] * r1;
+      const double t2 = (double)L[3 * n4] * r0 + (double)L[4 * n4] * r1 + (double)L[5 * n4] * r2;
       rt += t0 * t0 + t1 * t1 + t2 * t2;
     }
   }
@@ -658,7 +675,7 @@ int pcg_spmv_groups(int N) {
 }
 
 int pcg_vec_groups(int N) {
-  const int ng = ((N + 3) & ~3) / 4;
+  const int ng = ((N + 3) & ~3) / 4;   // chunks of 4 * kVecBlock nodes
   int g = div_up(ng, kVecBlock);
   if (g > kMaxVecParts) g = kMaxVecParts;
   return g < 1 ? 1 : g;
