@@ -49,6 +49,35 @@ def pcg_iteration_bytes(N, nnzb):
     return spmv_bytes(N, nnzb) + 96 * N
 
 
+COUNTER_FILE = os.path.join(ROOT, "profiles", "k_spmv_large_hbm_counters.md")
+KERNEL_SOURCES = ["pcg.hip", "assemble.hip", "common.h"]
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2512_12151_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic():
+    """HBM bytes per k_spmv launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or
+    None when the SpMV sources changed since the counters were taken."""
+    import re
+    try:
+        txt = open(COUNTER_FILE).read()
+    except OSError:
+        return None
+    m_sha = re.search(r"^kernel_sources_sha256: ([0-9a-f]+)", txt, re.M)
+    m_tr = re.search(r"^traffic_bytes_per_launch: (\d+)", txt, re.M)
+    if not (m_sha and m_tr) or m_sha.group(1) != kernel_sources_sha256():
+        return None
+    return int(m_tr.group(1))
+
+
 def cpu_baseline(sc, gpu_iters, frac):
     """The FP64 oracle on a bounded sample of the workload, one thread.
 
@@ -191,7 +220,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large", choices=["large", "medium", "tiny"])
     ap.add_argument("--tol", type=float, default=1e-5)
-    ap.add_argument("--cpu-sample", type=float, default=0.05)
+    ap.add_argument("--cpu-sample", type=float, default=0.1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-iter", type=int, default=200000,
                     help="PCG iteration cap (lower it only for counter-collection runs)")
@@ -291,7 +320,7 @@ def main():
         "nnzb": nnzb,
         "rel_residual": last["rel_residual"],
         "roofline": {"bound": "hbm", "kernel": "k_spmv", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(),
                      "bytes_per_launch": sb, "avg_ms": round(spmv_ms, 5), "launches_timed": tst["spmv_timed"]},
     }
     pb.close()

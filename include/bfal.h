@@ -111,7 +111,7 @@ typedef struct {
   int64_t nnzb;              /* stored upper 3x3 blocks, diagonal included */
   double ms_lin, ms_pattern, ms_assemble, ms_pcg;  /* device time per phase */
   int32_t spmv_timed;        /* SpMV launches timed (see bf_solve_opts.time_spmv) */
-  double ms_spmv_avg;        /* their average duration (event to event, ms) */
+  double ms_spmv_avg;        /* their average duration (ms; events stamped around each dispatch) */
   double sweep_rel_residual[16]; /* BF16 mode: |b - H x_s|_2 / |b|_2 before inner solve s (FP64;
                                     entry 0 is 1), then after the last; unused entries 0 */
 } bf_step_stats;

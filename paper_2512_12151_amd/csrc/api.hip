@@ -500,9 +500,10 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
     for (;;) {
       for (int k = 0; k < poll; ++k) {
         const bool t = launched + k < ntime;
-        if (t) HIPCHK(c, hipEventRecord(pb->tev[2 * (launched + k)], s));
-        launch_pcg_iteration(Sx, use_bf16, s);
-        if (t) HIPCHK(c, hipEventRecord(pb->tev[2 * (launched + k) + 1], s));
+        if (t)
+          launch_pcg_iteration(Sx, use_bf16, s, pb->tev[2 * (launched + k)], pb->tev[2 * (launched + k) + 1]);
+        else
+          launch_pcg_iteration(Sx, use_bf16, s);
       }
       launched += poll;
       mine += poll;

@@ -193,7 +193,9 @@ void launch_pcg_init(const PcgSystem& S, const float* bhat, const double* bb_par
 // One PCG iteration of one system: the SpMV kernel (direction p = r + beta p
 // fused in, q = H_hat p, p^T q) then the update kernel (x, r, r^T r, |L r|^2).
 // bf16 selects the BF16 block copy.
-void launch_pcg_iteration(const PcgSystem& S, bool bf16, hipStream_t s);
+// With t0 and t1 set, the SpMV dispatch is timed between them.
+void launch_pcg_iteration(const PcgSystem& S, bool bf16, hipStream_t s, hipEvent_t t0 = nullptr,
+                          hipEvent_t t1 = nullptr);
 // The same iteration for several systems in one launch pair: sys[] (device)
 // lists them, wg_sys_spmv / wg_sys_vec map each workgroup to its system.
 void launch_pcg_iteration_batched(const PcgSystem* sys, const int* wg_sys_spmv, int nwg_spmv, const int* wg_sys_vec,

@@ -38,6 +38,8 @@
 // The same kernels serve a batch of independent systems: each workgroup looks
 // up its system in a table, so a batch is a block-diagonal system whose
 // scalars (alpha, beta, convergence) are kept per system.
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace bfal {
@@ -687,11 +689,18 @@ void launch_pcg_init(const PcgSystem& S, const float* bhat, const double* bb_par
   hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kBlock), 0, s, bb_part, nbb, S.sc, tol, max_iter, check_every);
 }
 
-void launch_pcg_iteration(const PcgSystem& S, bool bf16, hipStream_t s) {
-  if (bf16)
+void launch_pcg_iteration(const PcgSystem& S, bool bf16, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  // with events: the command processor stamps them around the SpMV dispatch itself
+  if (t0 && t1) {
+    if (bf16)
+      hipExtLaunchKernelGGL(k_spmv<uint32_t>, dim3(S.spmv_nwg), dim3(kSpmvBlock), 0, s, t0, t1, 0, S);
+    else
+      hipExtLaunchKernelGGL(k_spmv<float>, dim3(S.spmv_nwg), dim3(kSpmvBlock), 0, s, t0, t1, 0, S);
+  } else if (bf16) {
     hipLaunchKernelGGL(k_spmv<uint32_t>, dim3(S.spmv_nwg), dim3(kSpmvBlock), 0, s, S);
-  else
+  } else {
     hipLaunchKernelGGL(k_spmv<float>, dim3(S.spmv_nwg), dim3(kSpmvBlock), 0, s, S);
+  }
   hipLaunchKernelGGL(k_update, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, S);
 }
 
