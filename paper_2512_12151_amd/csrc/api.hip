@@ -441,12 +441,14 @@ bf_status bf_set_constraints(bf_problem* pb, const bf_constraint_desc* cd, int32
   ALLOC(c, pb->Linv, 24LL * N4);
   ALLOC(c, pb->bhat, 12LL * N4);
   ALLOC(c, pb->bb_part, 8LL * (div_up(N, kBlock) + 1));
-  ALLOC(c, pb->xs, 12LL * N4);
+  ALLOC(c, pb->xs, 24LL * N4);   // FP64 solution
+  ALLOC(c, pb->rd, 24LL * N4);   // FP64 residual (replacement, refinement)
+  ALLOC(c, pb->rpart, 8LL * (kMaxSpmvParts + 8 + 6 * 256 + 8));
   ALLOC(c, pb->r, 12LL * N4);
   ALLOC(c, pb->p0, 12LL * N4);
   ALLOC(c, pb->p1, 12LL * N4);
   ALLOC(c, pb->q, 12LL * N4);
-  for (DevBuf* b : {&pb->Lf, &pb->Linv, &pb->bhat, &pb->xs, &pb->r, &pb->p0, &pb->p1, &pb->q})
+  for (DevBuf* b : {&pb->Lf, &pb->Linv, &pb->bhat, &pb->xs, &pb->rd, &pb->r, &pb->p0, &pb->p1, &pb->q})
     HIPCHK(c, hipMemsetAsync(b->p, 0, b->bytes, s));
   HIPCHK(c, hipStreamSynchronize(s));
   ALLOC(c, pb->part, 8LL * kPartsPerSystem);
@@ -491,7 +493,7 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
     HIPCHK(c, hipEventCreate(&e));
     pb->tev.push_back(e);
   }
-  int launched = 0, total_iters = 0, timed = 0;
+  int launched = 0, total_iters = 0, timed = 0, replacements = 0;
   bool assembly_checked = false;
   // Runs the solve set up on S to its device-side stop; the first poll also
   // checks the assembly's error flags.
@@ -516,14 +518,16 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
         if (hf) return flags_to_status(c, hf);
         assembly_checked = true;
       }
+      if (pb->host_sc->done == 4 && !pb->host_sc->brk) {   // residual replacement requested
+        launch_pcg_replace(Sx, pb->bhat.as<float>(), pb->rd.as<double>(), pb->rpart.as<double>(), s);
+        ++replacements;
+        continue;
+      }
       if (pb->host_sc->done || pb->host_sc->brk) break;
-      if (mine > o->max_iter + poll) break;   // cannot happen: the device stops at max_iter
+      if (mine > o->max_iter + poll + 64 * replacements) break;   // cannot happen: the device stops at max_iter
     }
-    // launches after the device-side stop returned early: only the first
-    // iter of this solve's timed launches did a full SpMV
-    const int first = launched - mine;
-    const int full_end = first + pb->host_sc->iter;
-    timed = std::max(timed, std::min(ntime, full_end));
+    // every timed launch so far (early exits are filtered out below)
+    timed = std::max(timed, std::min(ntime, launched));
     total_iters += pb->host_sc->iter;
     return BF_OK;
   };
@@ -533,7 +537,7 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
   bool refine_capped = false;
   if (!bf16) {
     launch_pcg_init(S, pb->bhat.as<float>(), pb->bb_part.as<double>(), div_up(N, kBlock), o->tol, o->max_iter,
-                    o->check_every, s);
+                    o->check_every, true, s);
     bf_status r0 = run_solve(S, false);
     if (r0 != BF_OK) return r0;
     launch_pcg_finish(S, pb->Linv.as<float>(), pb->pout.as<double>(), pb->viol_part.as<double>(), nviol, s);
@@ -591,7 +595,7 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
       if (pb->host_sc->iter == 0) {
         HIPCHK(c, hipMemcpyAsync(zd, rd, 8 * n3, hipMemcpyDeviceToDevice, s));   // no progress: steepest descent
       } else {
-        launch_copy_f2d((int)n3, S16.x, zd, s);
+        HIPCHK(c, hipMemcpyAsync(zd, S16.x, 8 * n3, hipMemcpyDeviceToDevice, s));
       }
       // p = z - sum_j (z.q_j / p_j.q_j) p_j over the window
       const int nwin = std::min(sweeps, kFcgWindow);
@@ -657,15 +661,21 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
     stats->ms_assemble = t23;
     stats->ms_pcg = t34;
     // only launches made before convergence did the full SpMV
-    const int nt = timed;
+    // launches that returned at entry (a system waiting for a residual
+    // replacement, or already stopped) take a small fraction of a full SpMV:
+    // the average is over launches of at least half the median duration
+    const int nt = std::min(timed, ntime);
+    std::vector<float> d(nt);
+    for (int k = 0; k < nt; ++k) (void)hipEventElapsedTime(&d[k], pb->tev[2 * k], pb->tev[2 * k + 1]);
+    std::vector<float> srt(d);
+    std::sort(srt.begin(), srt.end());
+    const float med = nt > 0 ? srt[nt / 2] : 0.f;
     double tot = 0.0;
-    for (int k = 0; k < nt; ++k) {
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, pb->tev[2 * k], pb->tev[2 * k + 1]);
-      tot += ms;
-    }
-    stats->spmv_timed = nt;
-    stats->ms_spmv_avg = nt > 0 ? tot / nt : 0.0;
+    int used = 0;
+    for (float v : d)
+      if (v >= 0.5f * med) { tot += v; ++used; }
+    stats->spmv_timed = used;
+    stats->ms_spmv_avg = used > 0 ? tot / used : 0.0;
   }
   // in BF16 mode an inner breakdown only ends that inner solve
   const int sflags = bf16 ? (h.flags & ~FLAG_BREAKDOWN) : h.flags;

@@ -36,7 +36,11 @@ struct PcgScalars {
   double stat_viol;  // max_i max(0, -c_i)
   int iter;          // completed iterations (written by workgroup 0 of the update kernel)
   int ks;            // iteration index of the last SpMV (written by its workgroup 0)
-  int done;          // 1: converged, 2: max_iter (written by workgroup 0 of the SpMV)
+  double rt_ref;     // |L r|^2 right after the last residual replacement (or |b|^2)
+  int done;          // 1: converged, 2: max_iter, 4: residual replacement requested
+                     // (written by workgroup 0 of the SpMV; cleared by the replacement)
+  int verified;      // iteration of the last residual replacement (-1: none)
+  int replace_on;    // 1: replace the residual (see pcg.hip), 0: plain recurrences
   int brk;           // 1: breakdown p^T H p <= 0 (written by workgroup 0 of the update kernel)
   int max_iter;
   int check_every;
@@ -72,7 +76,7 @@ struct PcgSystem {
   const void* blk;
   const int2* sent;
   const float* Lf;
-  float* x;
+  double* x;         // FP64 solution (AoS [N4][3])
   float* r;
   float* P0;
   float* P1;
@@ -188,8 +192,13 @@ void launch_row_diag_slots(int N, const int* row_ptr, int* diag, hipStream_t s);
 int pcg_spmv_groups(int N);
 int pcg_vec_groups(int N);
 // x = 0, r = b_hat, |b|^2 from the assembly's partials, scalars reset.
+// replace: enable residual replacement (needs the FP32 blocks in S.blk).
 void launch_pcg_init(const PcgSystem& S, const float* bhat, const double* bb_part, int nbb, double tol, int max_iter,
-                     int check_every, hipStream_t s);
+                     int check_every, bool replace, hipStream_t s);
+// Residual replacement requested by a system (done == 4): r = b_hat - H_hat x
+// in FP64 (rd scratch [3 N4], rpart scratch [kMaxSpmvParts]) rounded to FP32,
+// its partials in place of the recursive ones, done cleared.
+void launch_pcg_replace(const PcgSystem& S, const float* bhat, double* rd, double* rpart, hipStream_t s);
 // One PCG iteration of one system: the SpMV kernel (direction p = r + beta p
 // fused in, q = H_hat p, p^T q) then the update kernel (x, r, r^T r, |L r|^2).
 // bf16 selects the BF16 block copy.

@@ -24,6 +24,16 @@
 // one contiguous range of slices; the whole upper matrix of the large workload
 // (~150 MB) fits the 256 MB Infinity Cache.
 //
+// Residual replacement (reliable updating): x is kept in FP64, and when the
+// recursive residual has fallen 10x since the last replacement, or claims
+// convergence, the SpMV stops the system with done = 4 and the host replaces
+// r by b - H x formed in FP64 from the stored FP32 blocks; iteration then
+// resumes with the usual recurrences (convergence is accepted only on a
+// replaced residual).  Without it, thousands of FP32 iterations let the
+// recursive residual drift far below the true one on stiff contact systems.
+// The requests depend only on the iteration's values, so a system stops at the
+// same iterations alone and in a batch.
+//
 // Grid-wide sums: every workgroup writes one FP64 partial per quantity, and
 // every workgroup of the *next* kernel re-sums all partials in the same fixed
 // order, so every workgroup derives bit-identical scalars without any device
@@ -160,13 +170,18 @@ __device__ inline bool spmv_scalars(const PcgSystem& S, bool leader, int& k, flo
   if (k > 0) {
     const bool converged = (check && rt <= sc->tol2 * sc->bb) || rho == 0.0;
     const bool capped = k >= sc->max_iter;
+    // residual replacement: to accept convergence (unless this iteration's
+    // residual was just replaced) and whenever |L r| fell 10x since the last one
+    const bool replace = sc->replace_on && rho != 0.0 &&
+                         ((converged && sc->verified != k) || (!converged && check && rt <= 1e-2 * sc->rt_ref));
     if (leader) {
       sc->rho = rho;
       if (check) sc->rr_true = rt;
-      if (converged) sc->done = 1;
+      if (replace) sc->done = 4;
+      else if (converged) sc->done = 1;
       else if (capped) sc->done = 2;
     }
-    if (converged || capped) return false;
+    if (converged || capped || replace) return false;
     beta = (float)(rho / rho_old);
   }
   if (leader) sc->ks = k;
@@ -402,9 +417,10 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
   const long long nf4 = 3 * n4 / 4;   // float4 per vector
   const float4* __restrict__ p4 = reinterpret_cast<const float4*>((k & 1) ? S.P1 : S.P0);
   const float4* __restrict__ q4 = reinterpret_cast<const float4*>(S.q);
-  float4* __restrict__ x4 = reinterpret_cast<float4*>(S.x);
+  double2* __restrict__ x2 = reinterpret_cast<double2*>(S.x);
   float4* __restrict__ r4 = reinterpret_cast<float4*>(S.r);
   const float4* __restrict__ l4 = reinterpret_cast<const float4*>(S.Lf);
+  const double ad = alpha;   // the same alpha as the residual update
   const int t = threadIdx.x;
   double rr = 0.0, rt = 0.0;
   const long long nchunk = (n4 + 4 * kVecBlock - 1) / (4 * kVecBlock);
@@ -415,12 +431,14 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
       const long long f = fb + m * kVecBlock + t;
       if (f < nf4) {
         const float4 p = p4[f], q = q4[f];
-        float4 x = x4[f], r = r4[f];
-        x.x = __fmaf_rn(alpha, p.x, x.x); x.y = __fmaf_rn(alpha, p.y, x.y);
-        x.z = __fmaf_rn(alpha, p.z, x.z); x.w = __fmaf_rn(alpha, p.w, x.w);
+        float4 r = r4[f];
+        double2 xa = x2[2 * f], xb = x2[2 * f + 1];
+        xa.x = fma(ad, (double)p.x, xa.x); xa.y = fma(ad, (double)p.y, xa.y);
+        xb.x = fma(ad, (double)p.z, xb.x); xb.y = fma(ad, (double)p.w, xb.y);
         r.x = __fmaf_rn(-alpha, q.x, r.x); r.y = __fmaf_rn(-alpha, q.y, r.y);
         r.z = __fmaf_rn(-alpha, q.z, r.z); r.w = __fmaf_rn(-alpha, q.w, r.w);
-        x4[f] = x;
+        x2[2 * f] = xa;
+        x2[2 * f + 1] = xb;
         r4[f] = r;
         rr += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
         rs[m * kVecBlock + t] = r;
@@ -468,11 +486,11 @@ __global__ void __launch_bounds__(kVecBlock) k_update_batched(const PcgSystem* _
 }
 
 __global__ void __launch_bounds__(kVecBlock)
-k_init(int n3, const float* __restrict__ bhat, float* __restrict__ x, float* __restrict__ r, double* __restrict__ part) {
+k_init(int n3, const float* __restrict__ bhat, double* __restrict__ x, float* __restrict__ r, double* __restrict__ part) {
   double rr = 0.0;
   for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) {
     const float b = bhat[i];
-    x[i] = 0.f;
+    x[i] = 0.0;
     r[i] = b;
     rr += (double)b * b;
   }
@@ -482,9 +500,12 @@ k_init(int n3, const float* __restrict__ bhat, float* __restrict__ x, float* __r
 
 __global__ void __launch_bounds__(kBlock)
 k_init_scalars(const double* __restrict__ bb_part, int nbb, PcgScalars* sc, double tol, int max_iter,
-               int check_every) {
+               int check_every, int replace) {
   const double bb = sum_parts<kBlock>(bb_part, nbb);
   if (threadIdx.x == 0) {
+    sc->rt_ref = bb;
+    sc->verified = -1;
+    sc->replace_on = replace;
     sc->bb = bb;
     sc->rr_true = bb;
     sc->rho = 0.0;
@@ -629,12 +650,12 @@ k_copy_f2d(int n3, const float* __restrict__ x, double* __restrict__ y) {
 
 // Inner solve start: r = (float) r_outer, x = 0, partials of r^T r.
 __global__ void __launch_bounds__(kVecBlock)
-k_init_from64(int n3, const double* __restrict__ rd, float* __restrict__ x, float* __restrict__ r,
+k_init_from64(int n3, const double* __restrict__ rd, double* __restrict__ x, float* __restrict__ r,
               double* __restrict__ part) {
   double rr = 0.0;
   for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) {
     const float b = (float)rd[i];
-    x[i] = 0.f;
+    x[i] = 0.0;
     r[i] = b;
     rr += (double)b * b;
   }
@@ -642,10 +663,42 @@ k_init_from64(int n3, const double* __restrict__ rd, float* __restrict__ x, floa
   if (threadIdx.x == 0) part[kPartRR + blockIdx.x] = s;
 }
 
-// x_outer += d (FP64 accumulation of the FP32 correction).
+// Residual replacement, second half: r = (float) rd over this workgroup's
+// chunk with its r^T r partial, the |L rd|^2 partials of k_residual64 folded
+// into workgroup 0's slot, the reference and the replaced iteration recorded,
+// and the system released (done = 0).
 __global__ void __launch_bounds__(kVecBlock)
-k_axpy64(int n3, const float* __restrict__ d, double* __restrict__ xd) {
-  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) xd[i] += (double)d[i];
+k_replace_fold(PcgSystem S, const double* __restrict__ rd, const double* __restrict__ rpart, int nparts) {
+  PcgScalars* sc = S.sc;
+  const int k = sc->iter;
+  const int lb = blockIdx.x;
+  const double rt = sum_parts<kVecBlock>(rpart, nparts);
+  const long long n3 = 3LL * S.N4;
+  const long long chunk = 12LL * kVecBlock;   // 4 * kVecBlock nodes, as in the update kernel
+  double rr = 0.0;
+  for (long long c0 = (long long)lb * chunk; c0 < n3; c0 += (long long)gridDim.x * chunk)
+    for (long long i = c0 + threadIdx.x; i < c0 + chunk && i < n3; i += kVecBlock) {
+      const float r = (float)rd[i];
+      S.r[i] = r;
+      rr += (double)r * r;
+    }
+  const double srr = block_sum_all<kVecBlock>(rr);
+  if (threadIdx.x == 0) {
+    S.part[kPartRR + (k & 1) * kMaxVecParts + lb] = srr;
+    S.part[kPartRT + lb] = lb == 0 ? rt : 0.0;
+  }
+  if (lb == 0 && threadIdx.x == 0) {
+    sc->rt_ref = rt;
+    sc->rr_true = rt;
+    sc->verified = k;
+    sc->done = 0;
+  }
+}
+
+// x_outer += d (FP64).
+__global__ void __launch_bounds__(kVecBlock)
+k_axpy64(int n3, const double* __restrict__ d, double* __restrict__ xd) {
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) xd[i] += d[i];
 }
 
 __global__ void __launch_bounds__(kBlock) k_sum_to(const double* __restrict__ part, int n, double* out) {
@@ -684,9 +737,16 @@ int pcg_vec_groups(int N) {
 }
 
 void launch_pcg_init(const PcgSystem& S, const float* bhat, const double* bb_part, int nbb, double tol, int max_iter,
-                     int check_every, hipStream_t s) {
+                     int check_every, bool replace, hipStream_t s) {
   hipLaunchKernelGGL(k_init, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, bhat, S.x, S.r, S.part);
-  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kBlock), 0, s, bb_part, nbb, S.sc, tol, max_iter, check_every);
+  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kBlock), 0, s, bb_part, nbb, S.sc, tol, max_iter, check_every,
+                     replace ? 1 : 0);
+}
+
+void launch_pcg_replace(const PcgSystem& S, const float* bhat, double* rd, double* rpart, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual64, dim3(S.spmv_nwg), dim3(kSpmvBlock), 0, s, S, bhat, (const double*)S.x, rd, rpart);
+  hipLaunchKernelGGL(k_replace_fold, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, S, (const double*)rd,
+                     (const double*)rpart, S.spmv_nwg);
 }
 
 void launch_pcg_iteration(const PcgSystem& S, bool bf16, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
@@ -718,14 +778,16 @@ void launch_pcg_finish(const PcgSystem& S, const float* Linv, double* pout, cons
   const int g = pcg_vec_groups(S.N);
   // the max |p| partials reuse the p^T q slots, which the solve no longer needs
   double* part = S.part + kPartPQ;
-  hipLaunchKernelGGL(k_finish<float>, dim3(g), dim3(kVecBlock), 0, s, S.N, S.N4, Linv, (const float*)S.x, pout, part);
+  hipLaunchKernelGGL(k_finish<double>, dim3(g), dim3(kVecBlock), 0, s, S.N, S.N4, Linv, (const double*)S.x, pout,
+                     part);
   hipLaunchKernelGGL(k_finish_scalars, dim3(1), dim3(kBlock), 0, s, (const double*)part, g, viol_part, nviol, S.sc);
 }
 
 void launch_pcg_init_from64(const PcgSystem& S, const double* rd, const double* rpart, int nparts, double tol,
                             int max_iter, int check_every, hipStream_t s) {
   hipLaunchKernelGGL(k_init_from64, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, rd, S.x, S.r, S.part);
-  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kBlock), 0, s, rpart, nparts, S.sc, tol, max_iter, check_every);
+  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kBlock), 0, s, rpart, nparts, S.sc, tol, max_iter, check_every,
+                     0);
 }
 
 void launch_residual64(const PcgSystem& S, const float* bhat, const double* xd, double* rd, double* rpart,
@@ -763,7 +825,7 @@ void launch_copy_f2d(int n3, const float* x, double* y, hipStream_t s) {
 }
 
 void launch_axpy64(const PcgSystem& S, double* xd, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpy64, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, (const float*)S.x, xd);
+  hipLaunchKernelGGL(k_axpy64, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, (const double*)S.x, xd);
 }
 
 void launch_pcg_finish64(const PcgSystem& S, const float* Linv, const double* xd, double* pout,

@@ -104,7 +104,7 @@ inline PcgSystem system_of(bf_problem* pb) {
   S.blk = pb->sblk.p;
   S.sent = pb->sent.as<int2>();
   S.Lf = pb->Lf.as<float>();
-  S.x = pb->xs.as<float>();
+  S.x = pb->xs.as<double>();
   S.r = pb->r.as<float>();
   S.P0 = pb->p0.as<float>();
   S.P1 = pb->p1.as<float>();

@@ -138,7 +138,7 @@ bf_status prepare(bf_server* sv, bf_context* c, int si, Request* r) {
   if (st != BF_OK) return st;
   sl.S = system_of(pb);
   launch_pcg_init(sl.S, pb->bhat.as<float>(), pb->bb_part.as<double>(), div_up(pb->N, kBlock), r->opts.tol,
-                  r->opts.max_iter, r->opts.check_every, c->stream);
+                  r->opts.max_iter, r->opts.check_every, true, c->stream);
   int hf = 0;
   st = read_flags(pb, &hf);   // synchronizes the admission stream: the slot is complete
   if (st != BF_OK) return st;
@@ -367,7 +367,12 @@ void batch_loop(bf_server* sv) {
     std::vector<int> keep;
     for (int k = 0; k < n; ++k) {
       const int* st = sv->h_status + kStatusInts * k;
-      if (st[0] || st[1]) {
+      if (st[0] == 4 && !st[1]) {   // residual replacement requested: the system stays in the batch
+        bf_problem* pb = sv->slots[sv->active[k]].pb;
+        launch_pcg_replace(sv->slots[sv->active[k]].S, pb->bhat.as<float>(), pb->rd.as<double>(),
+                           pb->rpart.as<double>(), s);
+        keep.push_back(sv->active[k]);
+      } else if (st[0] || st[1]) {
         retire(sv, sv->active[k], st);
         changed = true;
       } else {

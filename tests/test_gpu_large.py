@@ -1,0 +1,92 @@
+"""Parity at the full size of the large workload (2.25M tets, 403,155 nodes,
+1.0M constraints), in the launch configuration bench.py times, against the
+FP64 oracle assembled at full size (about a minute of CPU).
+
+Bars: the merged BSR pattern and its maps bit-exact; the FP32 gradient and
+blocks within 1e-5 relative; the returned step's residual, measured in FP64
+with the oracle's H, within 1.5e-5 of |G| (the PCG tolerance is 1e-5 on the
+FP32-stored system); the FP64 stats exact to rounding."""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def large():
+    sc = scenes.make_scene("large")
+    print("large: oracle assembly", flush=True)
+    st = oracle.assemble(sc)
+    return sc, st
+
+
+@pytest.fixture(scope="module")
+def gpu(large):
+    from paper_2512_12151_amd import bfal
+    import torch
+    sc, _ = large
+    dev = torch.device("cuda:0")
+    t = {k: torch.from_numpy(np.ascontiguousarray(sc[k])).to(dev)
+         for k in ("tets", "rest", "E", "nu", "rho", "fixed", "x", "x_hat", "x_tilde", "pt", "ee", "lam", "gamma")}
+    torch.cuda.synchronize()
+    ctx = bfal.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+    pb = bfal.Problem(ctx, t["tets"], t["rest"], t["E"], t["nu"], t["rho"], t["fixed"])
+    pb.set_state(t["x"], t["x_hat"], t["x_tilde"], sc["dt"])
+    pb.set_constraints(t["pt"], t["ee"], t["lam"], t["gamma"], sc["kappa"], sc["delta"])
+    out = torch.empty((len(sc["rest"]), 3), dtype=torch.float64, device=dev)
+    print("large: GPU Newton step", flush=True)
+    _, stats, status = pb.newton_step(tol=1e-5, max_iter=200000, poll_every=64, check_every=1, out=out)
+    torch.cuda.synchronize()
+    p = out.cpu().numpy()
+    res = dict(p=p, stats=stats, status=status, g=pb.gradient(), pattern=pb.pattern(), blocks=pb.blocks())
+    pb.close()
+    ctx.close()
+    return res
+
+
+@pytest.mark.timeout(600)
+def test_large_pattern_bit_exact(large, gpu):
+    sc, _ = large
+    row_ptr, col, emap, cmap, diag = gpu["pattern"]
+    r_ptr, r_col, r_emap, r_cmap, r_diag = oracle.pattern(len(sc["rest"]), sc["tets"], sc["pt"], sc["ee"])
+    assert np.array_equal(row_ptr, r_ptr)
+    assert np.array_equal(col, r_col)
+    assert np.array_equal(emap, r_emap)
+    assert np.array_equal(cmap, r_cmap)
+    assert np.array_equal(diag, r_diag)
+
+
+@pytest.mark.timeout(600)
+def test_large_gradient_and_blocks(large, gpu):
+    sc, st = large
+    free = ~sc["fixed"].astype(bool)
+    g = gpu["g"]
+    eg = np.linalg.norm((g - st.G)[free]) / np.linalg.norm(st.G[free])
+    row_ptr, col, *_ = gpu["pattern"]
+    B = gpu["blocks"].astype(np.float64)
+    Bref = oracle.upper_blocks(st.H, row_ptr.astype(np.int64), col)
+    eb = np.linalg.norm(B - Bref) / np.linalg.norm(Bref)
+    print(f"large: gradient rel {eg:.2e}, blocks rel {eb:.2e}", flush=True)
+    assert eg <= 1e-5
+    assert eb <= 1e-5
+    assert np.all(g[~free] == 0.0)
+
+
+@pytest.mark.timeout(600)
+def test_large_solution_residual_and_stats(large, gpu):
+    sc, st = large
+    p, stats = gpu["p"], gpu["stats"]
+    assert gpu["status"] == 0
+    r = st.H @ p.ravel() + st.G.ravel()
+    rel = np.linalg.norm(r) / np.linalg.norm(st.G)
+    print(f"large: {stats['pcg_iters']} PCG iterations, solver residual {stats['rel_residual']:.3e}, "
+          f"FP64 residual with the oracle's H {rel:.3e}", flush=True)
+    assert stats["rel_residual"] <= 1e-5
+    assert rel <= 1.5e-5
+    assert np.all(p[sc["fixed"].astype(bool)] == 0.0)
+    viol = float(np.maximum(0.0, -st.c).max())
+    assert abs(stats["max_violation"] - viol) <= 1e-12 * max(1.0, viol)
+    assert np.isclose(stats["newton_inf_over_h"], np.abs(p).max() / sc["dt"], rtol=1e-12)
