@@ -172,6 +172,43 @@ bf_status bf_get_blocks(bf_problem* pb, float* vals);
  * pattern, blocks and solver vectors), for admission control. */
 bf_status bf_footprint_bytes(int32_t n_nodes, int32_t n_tets, int32_t n_constraints, size_t* out);
 
+/* ------------------------------------------------------------- subproblem */
+/* The rest of SolveSubproblem (Algorithm 2; Section 4.2 "Alternating Primal
+ * Solve" and "Constraint Decay") around bf_newton_step: from the x_hat of
+ * bf_set_state, repeat Newton steps p = -H^{-1} G with a line search for the
+ * first r in 1, 1/2, 1/4, ... (at most 30 halvings) with L(x_hat + r p) <
+ * L(x_hat), x_hat += r p, until a full step (r = 1) is taken, no step
+ * decreases L (r = 0) or max_newton steps were taken; then update every
+ * constraint from its slack s_i = max(0, c_i(x_hat) - lambda_i/kappa): s_i = 0
+ * gives lambda_i -= kappa c_i and gamma_i = 1, s_i > 0 gives lambda_i = 0 and
+ * gamma_i *= decay (the paper's Gamma, 0.9 in its experiments).  L is the
+ * total energy of Section 4.2 with every slack at that minimizer, evaluated in
+ * FP64; a state with an inverted tet has infinite energy. */
+typedef struct {
+  int32_t newton_iters;       /* Newton steps taken */
+  int32_t pcg_iters;          /* PCG iterations summed over the steps */
+  int32_t energy_evals;       /* energy evaluations (line searches included) */
+  double energy_initial;      /* L(x_hat^0), FP64 */
+  double energy_final;        /* L(x_hat) after the Newton loop (before the multiplier update) */
+  double last_step;           /* r of the last step: 1 on the normal exit, 0 if no step decreased L */
+  double max_violation;       /* max_i max(0, -c_i(x_hat)) at the multiplier update, FP64 */
+  int32_t active;             /* constraints with s_i = 0 at the update */
+  int32_t decayed;            /* constraints with s_i > 0 at the update */
+  double ms_total;            /* device time of the call (steps, line searches) */
+} bf_subproblem_stats;
+
+/* Runs the loop above.  The problem keeps the final x_hat as its state and the
+ * updated lambda and gamma as its constraint set (so calls chain as the outer
+ * iterations of the augmented-Lagrangian method).  Outputs (any may be NULL)
+ * in `mem`: x_hat_out [n_nodes][3], lambda_out and gamma_out [n_pt + n_ee].
+ * Returns a warning when a Newton step's PCG hit max_iter. */
+bf_status bf_solve_subproblem(bf_problem* pb, const bf_solve_opts* opts, int32_t max_newton, double decay,
+                              double* x_hat_out, double* lambda_out, double* gamma_out, int32_t mem,
+                              bf_subproblem_stats* stats);
+/* L at the problem's current x_hat (FP64); *inverted = 1 (and L = inf) if a
+ * tet is inverted.  Valid after a Newton step (it uses the linearization). */
+bf_status bf_energy(bf_problem* pb, double* energy_out, int32_t* inverted);
+
 /* ---------------------------------------------------------------- serving */
 /* A server solves independent Newton-step requests (each: a mesh, its state
  * and its active constraint set; the same operation as bf_newton_step, FP32

@@ -58,6 +58,16 @@ class BfalError(RuntimeError):
         self.status = status
 
 
+class bf_subproblem_stats(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("pcg_iters", C.c_int32), ("energy_evals", C.c_int32),
+                ("energy_initial", C.c_double), ("energy_final", C.c_double), ("last_step", C.c_double),
+                ("max_violation", C.c_double), ("active", C.c_int32), ("decayed", C.c_int32),
+                ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class bf_server_opts(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int32), ("iters_per_round", C.c_int32),
                 ("admit_threads", C.c_int32)]
@@ -85,6 +95,9 @@ _PROTOS = [
     ("bf_get_pattern", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("bf_get_blocks", C.c_int, [C.c_void_p, C.c_void_p]),
     ("bf_footprint_bytes", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    ("bf_solve_subproblem", C.c_int, [C.c_void_p, C.POINTER(bf_solve_opts), C.c_int32, C.c_double, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(bf_subproblem_stats)]),
+    ("bf_energy", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     ("bf_clock_now", C.c_double, []),
     ("bf_server_create", C.c_int, [C.c_int32, C.POINTER(bf_server_opts), C.POINTER(C.c_void_p)]),
     ("bf_server_submit", C.c_int, [C.c_void_p, C.c_int64, C.POINTER(bf_mesh_desc), C.c_void_p, C.c_void_p,
@@ -218,6 +231,24 @@ class Problem:
         s = bf_step_stats()
         st = self.ctx.check(lib().bf_newton_step(self.h, C.byref(o), _ptr(p), _mem(p), C.byref(s)))
         return p, s.as_dict(), st
+
+    def solve_subproblem(self, tol=1e-5, max_iter=20000, max_newton=50, decay=0.9, poll_every=16, check_every=1):
+        """Algorithm 2 from the current x_hat: returns (x_hat, lambda, gamma, stats dict, status)."""
+        o = bf_solve_opts(float(tol), int(max_iter), BF_PREC_FP32, 1e-6, int(poll_every), int(check_every), 0, 0)
+        xh = np.empty((self.N, 3), np.float64)
+        lam = np.empty(max(self.n_c, 1), np.float64)
+        gam = np.empty(max(self.n_c, 1), np.float64)
+        s = bf_subproblem_stats()
+        st = self.ctx.check(lib().bf_solve_subproblem(self.h, C.byref(o), int(max_newton), float(decay),
+                                                      xh.ctypes.data, lam.ctypes.data, gam.ctypes.data,
+                                                      BF_MEM_HOST, C.byref(s)))
+        return xh, lam[: self.n_c], gam[: self.n_c], s.as_dict(), st
+
+    def energy(self):
+        """(L at the current x_hat in FP64, inverted flag)."""
+        e, inv = C.c_double(), C.c_int32()
+        self.ctx.check(lib().bf_energy(self.h, C.byref(e), C.byref(inv)))
+        return float(e.value), bool(inv.value)
 
     def gradient(self):
         g = np.empty((self.N, 3), dtype=np.float64)

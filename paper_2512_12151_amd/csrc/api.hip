@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <new>
 #include <vector>
 
@@ -154,7 +155,8 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
   fill_int(reinterpret_cast<int*>(pb->viol_part.p), 0, 2, s);
   launch_contact_lin(ids, pb->n_pt, n, pb->x.as<double>(), pb->xh.as<double>(), pb->clam.as<double>(),
                      pb->cgam.as<double>(), pb->kappa, pb->delta, pb->cn.as<float>(), pb->cw.as<float>(),
-                     pb->cg.as<float>(), pb->ch.as<float>(), pb->viol_part.as<double>(), flags, s);
+                     pb->cg.as<float>(), pb->ch.as<float>(), pb->lin64.as<double>(), pb->viol_part.as<double>(), flags,
+                     s);
   HIPCHK(c, hipEventRecord(pb->ev[1], s));
   // (2) merged pattern: vertex -> constraint incidence, candidates, unique rows
   int* vcnt = pb->vcnt.as<int>();
@@ -308,7 +310,8 @@ void bf_problem_destroy(bf_problem* pb) {
                     &pb->Linv, &pb->bhat, &pb->bb_part, &pb->lcnt, &pb->lptr, &pb->lsrc, &pb->sbu, &pb->sbl,
                     &pb->sblk, &pb->sblk16, &pb->scol, &pb->sent, &pb->xs, &pb->r, &pb->p0, &pb->p1, &pb->q,
                     &pb->part, &pb->scal, &pb->pout, &pb->flags, &pb->scan_tmp, &pb->scratch_int,
-                    &pb->xd, &pb->rd, &pb->zd, &pb->fcg, &pb->rpart};
+                    &pb->xd, &pb->rd, &pb->zd, &pb->fcg, &pb->rpart, &pb->lin64, &pb->pdir, &pb->xtrial,
+                    &pb->epart};
   for (DevBuf* b : bufs) b->release();
   for (auto& e : pb->ev)
     if (e) (void)hipEventDestroy(e);
@@ -406,6 +409,7 @@ bf_status bf_set_constraints(bf_problem* pb, const bf_constraint_desc* cd, int32
   // size the per-step buffers for this constraint count
   const long long cap = (long long)pb->nnzb_e + 6LL * n;
   const long long capc = (long long)pb->nnzb_e - N + 6LL * n + 16;
+  ALLOC(c, pb->lin64, 64LL * n + 64);
   ALLOC(c, pb->cn, 12LL * n + 16);
   ALLOC(c, pb->cw, 16LL * n + 16);
   ALLOC(c, pb->cg, 4LL * n + 16);
@@ -748,6 +752,150 @@ bf_status bf_get_blocks(bf_problem* pb, float* vals) {
   HIPCHK(c, hipMemcpyAsync(vals, pb->vals.p, 36LL * pb->nnzb_last, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return BF_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ subproblem
+
+namespace {
+
+// L(xs) in FP64 (the total energy of Section 4.2 with minimizing slacks);
+// *inv is set when some tet of xs is inverted (L is then infinite).
+bf_status energy_at(bf_problem* pb, const double* xs, double* L, int* inv) {
+  bf_context* c = pb->ctx;
+  hipStream_t s = c->stream;
+  const int np = energy_parts(pb->T, pb->n_c);
+  ALLOC(c, pb->epart, 8LL * (np + 8));
+  double* part = pb->epart.as<double>();
+  int* flag = reinterpret_cast<int*>(part + np + 2);
+  fill_int(flag, 0, 2, s);
+  launch_energy(pb->tets.as<int4>(), pb->T, pb->rest.as<double>(), pb->E.as<double>(), pb->nu.as<double>(),
+                pb->rho.as<double>(), pb->dt, xs, pb->xt.as<double>(), pb->cids.as<int4>(), pb->n_c,
+                pb->lin64.as<double>(), pb->x.as<double>(), pb->clam.as<double>(), pb->cgam.as<double>(), pb->kappa,
+                pb->delta, part, flag, s);
+  launch_sum_to(part, np, part + np, s);
+  // part[np] = the sum, part[np + 2] holds the inversion flag (an int)
+  double h[3] = {0.0, 0.0, 0.0};
+  HIPCHK(c, hipMemcpyAsync(h, part + np, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  int fl = 0;
+  std::memcpy(&fl, &h[2], sizeof(int));
+  *inv = fl;
+  *L = fl ? INFINITY : h[0];
+  return BF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bf_status bf_energy(bf_problem* pb, double* energy_out, int32_t* inverted) {
+  if (!pb) return BF_ERR_INVALID_ARG;
+  bf_context* c = pb->ctx;
+  if (!energy_out) return fail(c, BF_ERR_INVALID_ARG, "energy_out is NULL");
+  if (!pb->stepped) return fail(c, BF_ERR_STATE, "no Newton step has been run (the linearization is missing)");
+  HIPCHK(c, hipSetDevice(c->device));
+  int inv = 0;
+  const bf_status st = energy_at(pb, pb->xh.as<double>(), energy_out, &inv);
+  if (inverted) *inverted = inv;
+  return st;
+}
+
+bf_status bf_solve_subproblem(bf_problem* pb, const bf_solve_opts* o, int32_t max_newton, double decay,
+                              double* x_hat_out, double* lambda_out, double* gamma_out, int32_t mem,
+                              bf_subproblem_stats* stats) {
+  if (!pb) return BF_ERR_INVALID_ARG;
+  bf_context* c = pb->ctx;
+  if (!o) return fail(c, BF_ERR_INVALID_ARG, "opts is NULL");
+  if (max_newton < 1) return fail(c, BF_ERR_INVALID_ARG, "max_newton must be >= 1");
+  if (!(decay > 0.0 && decay <= 1.0)) return fail(c, BF_ERR_INVALID_ARG, "decay must lie in (0, 1]");
+  if (mem != BF_MEM_HOST && mem != BF_MEM_DEVICE) return fail(c, BF_ERR_INVALID_ARG, "bad mem kind");
+  if (!pb->has_state) return fail(c, BF_ERR_STATE, "bf_set_state must be called first");
+  if (pb->cap_nnzb == 0) return fail(c, BF_ERR_STATE, "bf_set_constraints must be called first");
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  const int N = pb->N, n = pb->n_c;
+  const long long n3 = 3LL * N;
+  ALLOC(c, pb->pdir, 8 * n3);
+  ALLOC(c, pb->xtrial, 8 * n3);
+  hipEvent_t e0 = pb->ev[0];
+  bf_subproblem_stats out{};
+  double* xh = pb->xh.as<double>();
+  double L0 = 0.0;
+  bool have_L0 = false;
+  bf_status warn = BF_OK;
+  float total_ms = 0.f;
+  for (int it = 0; it < max_newton; ++it) {
+    bf_step_stats ns{};
+    const bf_status st = bf_newton_step(pb, o, pb->pdir.as<double>(), BF_MEM_DEVICE, &ns);
+    if (st < 0) return st;
+    if (st > 0) warn = st;
+    total_ms += (float)(ns.ms_lin + ns.ms_pattern + ns.ms_assemble + ns.ms_pcg);
+    out.pcg_iters += ns.pcg_iters;
+    ++out.newton_iters;
+    HIPCHK(c, hipEventRecord(e0, s));
+    if (!have_L0) {   // the linearization exists from the first step on
+      int inv = 0;
+      bf_status r0 = energy_at(pb, xh, &L0, &inv);
+      if (r0 != BF_OK) return r0;
+      ++out.energy_evals;
+      if (inv) return fail(c, BF_ERR_INVERTED_ELEMENT, "inverted element in the initial x_hat");
+      out.energy_initial = L0;
+      have_L0 = true;
+    }
+    // halving line search: the first r = 2^-k with L(x_hat + r p) < L(x_hat)
+    double r = 1.0, L = L0;
+    bool ok = false;
+    for (int k = 0; k <= 30; ++k, r *= 0.5) {
+      launch_state_axpy((int)n3, xh, r, pb->pdir.as<double>(), pb->xtrial.as<double>(), s);
+      int inv = 0;
+      bf_status r0 = energy_at(pb, pb->xtrial.as<double>(), &L, &inv);
+      if (r0 != BF_OK) return r0;
+      ++out.energy_evals;
+      if (!inv && L < L0) { ok = true; break; }
+    }
+    if (!ok) r = 0.0;
+    if (ok) {
+      HIPCHK(c, hipMemcpyAsync(xh, pb->xtrial.p, 8 * n3, hipMemcpyDeviceToDevice, s));
+      L0 = L;
+    }
+    HIPCHK(c, hipEventRecord(pb->ev[1], s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, pb->ev[1]);
+    total_ms += ms;
+    out.last_step = r;
+    if (r == 1.0 || r == 0.0) break;
+  }
+  out.energy_final = L0;
+  // multiplier and decay update at the final x_hat
+  const int g = div_up(n, 256);
+  ALLOC(c, pb->epart, 8LL * (2 * g + 8));
+  double* part = pb->epart.as<double>();
+  double hc[2] = {0.0, 0.0};
+  if (n > 0) {
+    launch_dual_update(pb->cids.as<int4>(), n, pb->lin64.as<double>(), pb->x.as<double>(), xh, pb->kappa, pb->delta,
+                       decay, pb->clam.as<double>(), pb->cgam.as<double>(), part, s);
+    std::vector<double> hp(2 * g);
+    HIPCHK(c, hipMemcpyAsync(hp.data(), part, 16LL * g, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int k = 0; k < g; ++k) {
+      hc[0] += hp[k];
+      hc[1] = std::max(hc[1], hp[g + k]);
+    }
+  }
+  out.active = (int32_t)hc[0];
+  out.decayed = n - out.active;
+  out.max_violation = hc[1];
+  out.ms_total = total_ms;
+  if (x_hat_out) HIPCHK(c, hipMemcpyAsync(x_hat_out, xh, 8 * n3, kind_out(mem), s));
+  if (lambda_out && n) HIPCHK(c, hipMemcpyAsync(lambda_out, pb->clam.p, 8LL * n, kind_out(mem), s));
+  if (gamma_out && n) HIPCHK(c, hipMemcpyAsync(gamma_out, pb->cgam.p, 8LL * n, kind_out(mem), s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (stats) *stats = out;
+  c->err.clear();
+  return warn;
 }
 
 }  // extern "C"

@@ -136,9 +136,10 @@ void launch_mass(const int* ecptr, const int* elist, const int* erow_ptr, const 
 // contact.hip: per-step constraint work
 void launch_check_constraints(const int4* ids, int n_c, int N, const double* lam, const double* gam,
                               int* flags, hipStream_t s);
+// lin64 receives the FP64 linearization, SoA [8][n_c]: d, n (3), w (4).
 void launch_contact_lin(const int4* ids, int n_pt, int n_c, const double* x, const double* xh,
                         const double* lam, const double* gam, double kappa, double delta,
-                        float* cn, float* cw, float* cg, float* ch, double* viol_part, int* flags,
+                        float* cn, float* cw, float* cg, float* ch, double* lin64, double* viol_part, int* flags,
                         hipStream_t s);
 void launch_vertex_incidence_count(const int4* ids, int n_c, int* cnt, hipStream_t s);
 void launch_vertex_incidence_fill(const int4* ids, int n_c, const int* ptr, int* cursor, int* inc,
@@ -151,6 +152,22 @@ void launch_candidate_fill(const int* erow_ptr, const int* ecol, const int* vptr
 void launch_merged_write(const int* cand, const int* cptr, const int* row_ptr, const int* erow_ptr,
                          const int* ecol, int N, int* col, int* eslot, hipStream_t s);
 void launch_cmap(const int4* ids, int n_c, const int* row_ptr, const int* col, int* cmap, hipStream_t s);
+
+// subproblem.hip (the rest of Algorithm 2).  The total energy L(x) in FP64
+// (per-tet Neo-Hookean from the rest shape, lumped inertia folded per tet,
+// slack-minimized AL terms from lin64) as nparts partials in part, and any
+// inverted tet raised into *inverted; xt = xa + r p; the multiplier and
+// decay update in place (counts of active constraints and the violation
+// max into per-workgroup partials).
+int energy_parts(int T, int n_c);
+void launch_energy(const int4* tets, int T, const double* rest, const double* E, const double* nu,
+                   const double* rho, double h, const double* x, const double* xt, const int4* ids, int n_c,
+                   const double* lin64, const double* xlin, const double* lam, const double* gam, double kappa,
+                   double delta, double* part, int* inverted, hipStream_t s);
+void launch_state_axpy(int n3, const double* xa, double r, const double* p, double* xt, hipStream_t s);
+void launch_dual_update(const int4* ids, int n_c, const double* lin64, const double* xlin, const double* xh,
+                        double kappa, double delta, double decay, double* lam, double* gam, double* part,
+                        hipStream_t s);
 
 // elastic.hip
 void launch_elastic(const int4* tets, int T, const double* rest, const double* xh, const float* Dminv9,

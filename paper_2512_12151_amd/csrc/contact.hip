@@ -50,7 +50,8 @@ __global__ void __launch_bounds__(kBlock)
 k_contact_lin(const int4* __restrict__ ids, int n_pt, int n_c, const double* __restrict__ x,
               const double* __restrict__ xh, const double* __restrict__ lam, const double* __restrict__ gam,
               double kappa, double delta, float* __restrict__ cn, float* __restrict__ cw,
-              float* __restrict__ cg, float* __restrict__ ch, double* __restrict__ viol_part, int* flags) {
+              float* __restrict__ cg, float* __restrict__ ch, double* __restrict__ lin64,
+              double* __restrict__ viol_part, int* flags) {
   __shared__ double red[kBlock / kWave];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double viol = 0.0;
@@ -129,6 +130,7 @@ k_contact_lin(const int4* __restrict__ ids, int n_pt, int n_c, const double* __r
       cn[i] = cn[n_c + i] = cn[2LL * n_c + i] = 0.f;
       cw[i] = cw[n_c + i] = cw[2LL * n_c + i] = cw[3LL * n_c + i] = 0.f;
       cg[i] = ch[i] = 0.f;
+      for (int m = 0; m < 8; ++m) lin64[(long long)m * n_c + i] = 0.0;
     } else {
       const d3 n = mul(diff, 1.0 / d);
       // c_i(x_hat) = d_i(x) + grad d_i(x)^T (x_hat - x) - delta
@@ -142,6 +144,10 @@ k_contact_lin(const int4* __restrict__ ids, int n_pt, int n_c, const double* __r
       cw[i] = (float)w0; cw[n_c + i] = (float)w1; cw[2LL * n_c + i] = (float)w2; cw[3LL * n_c + i] = (float)w3;
       cg[i] = (float)gfac;
       ch[i] = (float)(kappa * g);
+      // the FP64 linearization, for the energy and the multiplier update: SoA [8][n]
+      const double lv[8] = {d, n.x, n.y, n.z, w0, w1, w2, w3};
+#pragma unroll
+      for (int m = 0; m < 8; ++m) lin64[(long long)m * n_c + i] = lv[m];
     }
   }
   // block max of the violation (FP64)
@@ -339,10 +345,10 @@ void launch_check_constraints(const int4* ids, int n_c, int N, const double* lam
 
 void launch_contact_lin(const int4* ids, int n_pt, int n_c, const double* x, const double* xh, const double* lam,
                         const double* gam, double kappa, double delta, float* cn, float* cw, float* cg, float* ch,
-                        double* viol_part, int* flags, hipStream_t s) {
+                        double* lin64, double* viol_part, int* flags, hipStream_t s) {
   if (n_c > 0)
     hipLaunchKernelGGL(k_contact_lin, dim3(div_up(n_c, kBlock)), dim3(kBlock), 0, s, ids, n_pt, n_c, x, xh, lam,
-                       gam, kappa, delta, cn, cw, cg, ch, viol_part, flags);
+                       gam, kappa, delta, cn, cw, cg, ch, lin64, viol_part, flags);
 }
 
 void launch_vertex_incidence_count(const int4* ids, int n_c, int* cnt, hipStream_t s) {

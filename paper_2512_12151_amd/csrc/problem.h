@@ -41,6 +41,8 @@ struct bf_problem {
   DevBuf vals, grad, Lf, Linv, bhat, bb_part, lcnt, lptr, lsrc, sbu, sbl, sblk, sblk16, scol, sent;
   DevBuf xs, r, p0, p1, q, part, scal, pout, flags, scan_tmp, scratch_int;
   DevBuf xd, rd, zd, fcg, rpart;   // refinement: FP64 solution, residual, inner solution, directions, partials
+  DevBuf lin64;                    // FP64 linearization of the constraints, SoA [8][n]
+  DevBuf pdir, xtrial, epart;      // subproblem: Newton direction, line-search trial state, partials
   long long cap_nnzb = 0, cap_cand = 0;
   long long nslot_u = 0, nslot_l = 0;   // slots of the sliced storage of the last step
   PcgScalars* host_sc = nullptr;
