@@ -44,9 +44,9 @@ def spmv_bytes(N, nnzb):
 
 
 def pcg_iteration_bytes(N, nnzb):
-    """k_spmv + k_update (p, q, x, r and the factor L read, x and r written:
-    96 B/node)."""
-    return spmv_bytes(N, nnzb) + 96 * N
+    """k_spmv + k_update (p, q, r and the factor L read, 60 B/node; the FP64
+    x read and written, 48 B/node; r written, 12 B/node: 120 B/node)."""
+    return spmv_bytes(N, nnzb) + 120 * N
 
 
 COUNTER_FILE = os.path.join(ROOT, "profiles", "k_spmv_large_hbm_counters.md")
@@ -157,6 +157,33 @@ def serve_trace(server, reqs, arrivals, timeout=600.0):
     return lat, last - first, status, float(setup.mean()), float(pcg.mean())
 
 
+def run_subproblem(args):
+    """The rest of Algorithm 2 on the medium workload: Newton steps with the
+    FP64 halving line search until a full step (r = 1/2, 1/2, 1 here), then
+    the multiplier update.  The large workload's multipliers are drawn apart
+    from its state, so its first steps ask for metre-sized moves that the line
+    search cuts to r ~ 1/64; it takes tens of Newton steps and is not a bench
+    line.  Timed once, after a warm-up call on a fresh problem."""
+    import torch
+
+    import scenes
+    from paper_2512_12151_amd import bfal
+    sc = scenes.make_scene("medium")
+    ctx = bfal.Context(0)
+    out = {}
+    for rep in range(2):
+        pb = bfal.Problem.from_scene(ctx, sc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, _, sst, status = pb.solve_subproblem(tol=args.tol, max_iter=args.max_iter, max_newton=20)
+        ms = (time.perf_counter() - t0) * 1e3
+        pb.close()
+        out = {"workload": "medium", "ms": round(ms, 2), "status": status,
+               **{k: (round(v, 6) if isinstance(v, float) else v) for k, v in sst.items()}}
+    ctx.close()
+    return out
+
+
 def run_serve(n_req, seed=5, loads=(0.8, 1.2, 2.0)):
     """Serving (continuous batching) on a stream of two-stacked-cube requests
     (tets ~ LogU[2k, 300k]).  The one-at-a-time service time is measured first
@@ -224,6 +251,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-iter", type=int, default=200000,
                     help="PCG iteration cap (lower it only for counter-collection runs)")
+    ap.add_argument("--no-subproblem", dest="subproblem", action="store_false",
+                    help="skip the SolveSubproblem measurement (Newton loop with line search, multiplier update)")
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving trace (0 skips the serving measurement)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -323,7 +352,18 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(),
                      "bytes_per_launch": sb, "avg_ms": round(spmv_ms, 5), "launches_timed": tst["spmv_timed"]},
     }
+    if args.subproblem:
+        # FP64 energy evaluation (the line search's unit of work) on this workload
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            pb.energy()
+        t_energy = (time.perf_counter() - t0) / 5 * 1e3
     pb.close()
+    if args.subproblem:
+        line["subproblem"] = run_subproblem(args)
+        line["subproblem"]["energy_eval_ms_" + args.workload] = round(t_energy, 3)
+        log(f"subproblem: {line['subproblem']}")
     if args.serve_requests > 0:
         line["serve"] = run_serve(args.serve_requests)
     if not args.no_cpu_baseline:

@@ -178,7 +178,9 @@ bf_status bf_footprint_bytes(int32_t n_nodes, int32_t n_tets, int32_t n_constrai
  * bf_set_state, repeat Newton steps p = -H^{-1} G with a line search for the
  * first r in 1, 1/2, 1/4, ... (at most 30 halvings) with L(x_hat + r p) <
  * L(x_hat), x_hat += r p, until a full step (r = 1) is taken, no step
- * decreases L (r = 0) or max_newton steps were taken; then update every
+ * decreases L (r = 0) or max_newton steps were taken (a step whose PCG meets
+ * negative curvature uses its iterate so far, as truncated Newton does, and
+ * the call then returns BF_WARN_PCG_MAXITER); then update every
  * constraint from its slack s_i = max(0, c_i(x_hat) - lambda_i/kappa): s_i = 0
  * gives lambda_i -= kappa c_i and gamma_i = 1, s_i > 0 gives lambda_i = 0 and
  * gamma_i *= decay (the paper's Gamma, 0.9 in its experiments).  L is the
@@ -195,6 +197,7 @@ typedef struct {
   int32_t active;             /* constraints with s_i = 0 at the update */
   int32_t decayed;            /* constraints with s_i > 0 at the update */
   double ms_total;            /* device time of the call (steps, line searches) */
+  int32_t truncated;          /* steps whose PCG met p^T H p <= 0 and used its iterate so far */
 } bf_subproblem_stats;
 
 /* Runs the loop above.  The problem keeps the final x_hat as its state and the

@@ -62,7 +62,7 @@ class bf_subproblem_stats(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("pcg_iters", C.c_int32), ("energy_evals", C.c_int32),
                 ("energy_initial", C.c_double), ("energy_final", C.c_double), ("last_step", C.c_double),
                 ("max_violation", C.c_double), ("active", C.c_int32), ("decayed", C.c_int32),
-                ("ms_total", C.c_double)]
+                ("ms_total", C.c_double), ("truncated", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

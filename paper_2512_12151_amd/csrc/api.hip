@@ -683,6 +683,7 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
   }
   // in BF16 mode an inner breakdown only ends that inner solve
   const int sflags = bf16 ? (h.flags & ~FLAG_BREAKDOWN) : h.flags;
+  pb->last_breakdown = (sflags & FLAG_BREAKDOWN) && !(hflags & ~FLAG_BREAKDOWN) && !(sflags & ~FLAG_BREAKDOWN);
   if (hflags | sflags) return flags_to_status(c, hflags | sflags);
   c->err.clear();
   if ((!bf16 && h.done == 2 && !h.brk) || refine_capped) {
@@ -828,9 +829,19 @@ bf_status bf_solve_subproblem(bf_problem* pb, const bf_solve_opts* o, int32_t ma
   float total_ms = 0.f;
   for (int it = 0; it < max_newton; ++it) {
     bf_step_stats ns{};
+    pb->last_breakdown = false;
     const bf_status st = bf_newton_step(pb, o, pb->pdir.as<double>(), BF_MEM_DEVICE, &ns);
-    if (st < 0) return st;
-    if (st > 0) warn = st;
+    if (st == BF_ERR_NOT_SPD && pb->last_breakdown) {
+      // negative curvature met by the PCG: the iterate reached so far is a
+      // descent direction of the quadratic model (truncated Newton); the line
+      // search decides how far to go
+      ++out.truncated;
+      warn = BF_WARN_PCG_MAXITER;
+    } else if (st < 0) {
+      return st;
+    } else if (st > 0) {
+      warn = st;
+    }
     total_ms += (float)(ns.ms_lin + ns.ms_pattern + ns.ms_assemble + ns.ms_pcg);
     out.pcg_iters += ns.pcg_iters;
     ++out.newton_iters;

@@ -47,6 +47,7 @@ struct bf_problem {
   long long nslot_u = 0, nslot_l = 0;   // slots of the sliced storage of the last step
   PcgScalars* host_sc = nullptr;
   bool stepped = false;
+  bool last_breakdown = false;     // the last step's PCG stopped at p^T H p <= 0 (nothing else failed)
   long long nnzb_last = 0;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> tev;   // SpMV timing events (pairs), created on demand

@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import scenes
+from subproblem_checks import check_subproblem
 
 pytestmark = pytest.mark.gpu
 
@@ -90,3 +91,22 @@ def test_large_solution_residual_and_stats(large, gpu):
     viol = float(np.maximum(0.0, -st.c).max())
     assert abs(stats["max_violation"] - viol) <= 1e-12 * max(1.0, viol)
     assert np.isclose(stats["newton_inf_over_h"], np.abs(p).max() / sc["dt"], rtol=1e-12)
+
+
+@pytest.mark.timeout(600)
+def test_large_subproblem_energy_and_update(large):
+    """Four Newton steps of SolveSubproblem at full size (damped: the line
+    search cuts the first steps to r ~ 1/64 here), then the multiplier update:
+    the oracle's FP64 energies and update at the GPU's states."""
+    from paper_2512_12151_amd import bfal
+    sc, _ = large
+    ctx = bfal.Context(0)
+    pb = bfal.Problem.from_scene(ctx, sc)
+    print("large: GPU subproblem", flush=True)
+    xh, lam, gam, stats, status = pb.solve_subproblem(tol=1e-5, max_iter=200000, max_newton=4)
+    pb.close()
+    ctx.close()
+    print(f"large subproblem: status {status} {stats}", flush=True)
+    assert status in (bfal.BF_OK, bfal.BF_WARN_PCG_MAXITER)
+    assert stats["newton_iters"] == 4 and 0.0 < stats["last_step"] < 1.0
+    check_subproblem(sc, xh, lam, gam, stats)

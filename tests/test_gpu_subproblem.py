@@ -13,6 +13,7 @@ import pytest
 import oracle
 from oracle import subproblem as osp
 import scenes
+from subproblem_checks import check_subproblem
 
 pytestmark = pytest.mark.gpu
 
@@ -136,3 +137,17 @@ def test_outer_iterations_reach_feasibility_like_the_oracle(ctx, bf):
         assert abs(vg[-1] - vo[-1]) <= 2.0 * np.linalg.norm(xh - xr, axis=1).max() + 1e-15
     print(f"violation gpu {['%.2e' % v for v in vg]} oracle {['%.2e' % v for v in vo]}", flush=True)
     assert vg[-1] < 0.1 * vg[0]
+
+
+def test_medium_subproblem_in_the_bench_configuration(ctx, bf):
+    """The medium workload with the options the bench times (tol 1e-5, up to
+    20 Newton steps): the oracle's energies and update at the GPU's states
+    (its direct Newton steps would take minutes on this size; the steps
+    themselves are covered by the Newton-step parity tests)."""
+    sc = scenes.medium()
+    pb = bf.Problem.from_scene(ctx, sc)
+    xh, lam, gam, stats, status = pb.solve_subproblem(tol=1e-5, max_iter=200000, max_newton=20)
+    print(f"medium: {stats}", flush=True)
+    assert status == bf.BF_OK
+    assert stats["last_step"] == 1.0 and stats["truncated"] == 0
+    check_subproblem(sc, xh, lam, gam, stats)
