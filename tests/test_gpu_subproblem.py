@@ -4,9 +4,9 @@ and the multiplier/decay update.
 
 Bars: L within 1e-9 relative (both sides FP64); the subproblem's displacement
 x_hat - x_hat^0 within 1e-4 of the oracle's in the energy norm of H at x_hat^0
-(the GPU's Newton steps are PCG solves to 1e-7, the oracle's direct); the update bit-for-bit in its branch (gamma) and
-within 1e-9 relative (lambda) against the oracle's update at the same x_hat,
-constraints within 1e-9 of the branch point excepted."""
+(the GPU's Newton steps are PCG solves to 1e-7, the oracle's direct); the update
+against the oracle's at the same x_hat as the shared checks state it (gamma
+exact in its branch, lambda within 1e-9 relative plus kappa * 1e-11)."""
 import numpy as np
 import pytest
 
@@ -110,7 +110,8 @@ def test_subproblem_matches_oracle(ctx, bf, name):
     c = osp.constraint_values_at(sc, xh)
     margin = np.abs(c - sc["lam"] / sc["kappa"]) > 1e-9 * np.maximum(1.0, np.abs(sc["lam"] / sc["kappa"]))
     assert np.array_equal(gam[margin], gam_o[margin])
-    assert np.allclose(lam[margin], lam_o[margin], rtol=1e-9, atol=1e-9)
+    # lambda' = lambda - kappa c: kappa times the FP64 difference of c_i
+    assert np.allclose(lam[margin], lam_o[margin], rtol=1e-9, atol=1e-11 * sc["kappa"])
     assert stats["active"] == int(act_o.sum()) or not margin.all()
     assert abs(stats["max_violation"] - float(np.maximum(0.0, -c).max())) <= 1e-12
 
