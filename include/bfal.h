@@ -212,6 +212,19 @@ bf_status bf_solve_subproblem(bf_problem* pb, const bf_solve_opts* opts, int32_t
  * tet is inverted.  Valid after a Newton step (it uses the linearization). */
 bf_status bf_energy(bf_problem* pb, double* energy_out, int32_t* inverted);
 
+/* Conditioning-aware penalty (Section 5.2): *mu_out = C max_i (grad^2 E)_ii,
+ * the largest scalar diagonal of the incremental potential's Hessian -- the
+ * lumped mass plus h^2 times the SPD-projected Neo-Hookean Hessian, the
+ * matrix the Newton step assembles -- at x, the state the time step starts
+ * from (bf_set_state's first argument).  The paper uses C = 0.1.  The caller
+ * passes the result as kappa to bf_set_constraints.  Fixed nodes count: their
+ * diagonals are kept by the moving-boundary elimination (Section 5.3).
+ * Requires bf_set_state; C finite and > 0 (BF_ERR_INVALID_ARG otherwise);
+ * BF_ERR_INVERTED_ELEMENT if a tet of x is inverted.  Computed from FP32 sums
+ * of the element blocks.  Uses the step's staging buffer (no allocation after
+ * the first Newton step or call). */
+bf_status bf_mu_init(bf_problem* pb, double C, double* mu_out);
+
 /* ---------------------------------------------------------------- serving */
 /* A server solves independent Newton-step requests (each: a mesh, its state
  * and its active constraint set; the same operation as bf_newton_step, FP32

@@ -10,7 +10,8 @@ x_hat += r p -- until a full step (r = 1) is taken; then update every
 constraint's multiplier and decay factor from its slack s_i = max(0, c_i -
 lambda_i/mu): when s_i = 0, lambda_i -= mu c_i and gamma_i = 1, otherwise
 lambda_i = 0 and gamma_i *= Gamma (Section 4.2, "Constraint Decay",
-Gamma = 0.9).
+Gamma = 0.9).  Section 5.2 sets the penalty at the start of a time step to
+C max_i (grad^2 E)_ii with C = 0.1.
 
 Readings (listed in DESIGN.md):
   * L is the total energy of Section 4.2 with each slack at its minimizer
@@ -21,6 +22,9 @@ Readings (listed in DESIGN.md):
     infinite energy (Neo-Hookean is non-invertible).  After 30 halvings the
     step is r = 0 and the loop stops.
   * The Newton loop stops after max_newton steps even without a full step.
+  * The penalty estimate of Section 5.2 takes the diagonal of the Hessian the
+    solver assembles (lumped mass plus SPD-projected elasticity) at x, the
+    state the time step starts from.
 Each step uses the direct solve of core.solve_direct (the exact Newton step).
 """
 from __future__ import annotations
@@ -67,6 +71,24 @@ def dual_update(scene, xh, Gamma=0.9):
     lam_new = np.where(active, lam - mu * c, 0.0)
     gam_new = np.where(active, 1.0, Gamma * gam)
     return lam_new, gam_new, active
+
+
+def hessian_diagonal(scene, st, xs):
+    """The 3N scalar diagonal of the incremental potential's Hessian at xs:
+    the lumped mass plus the diagonal of every element's SPD-projected
+    h^2 V B^T (d2Psi/dF2)^+ B (the matrix the Newton step assembles)."""
+    diag = np.repeat(st.mass, 3).astype(np.float64)
+    _, He = core.elastic_terms(xs, st.tets, st.Dminv, st.vol, st.A, st.mu_l, st.lam_l, scene["dt"])
+    dof = (3 * st.tets[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 12)
+    np.add.at(diag, dof.ravel(), np.diagonal(He, axis1=1, axis2=2).ravel())
+    return diag
+
+
+def mu_init(scene, C=0.1, st=None):
+    """Section 5.2: the initial penalty C max_i (grad^2 E)_ii, taken at x, the
+    state the time step starts from."""
+    st = core.prepare(scene) if st is None else st
+    return C * float(hessian_diagonal(scene, st, scene["x"]).max())
 
 
 def solve_subproblem(scene, max_newton=50, Gamma=0.9):

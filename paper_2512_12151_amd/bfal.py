@@ -98,6 +98,7 @@ _PROTOS = [
     ("bf_solve_subproblem", C.c_int, [C.c_void_p, C.POINTER(bf_solve_opts), C.c_int32, C.c_double, C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(bf_subproblem_stats)]),
     ("bf_energy", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    ("bf_mu_init", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double)]),
     ("bf_clock_now", C.c_double, []),
     ("bf_server_create", C.c_int, [C.c_int32, C.POINTER(bf_server_opts), C.POINTER(C.c_void_p)]),
     ("bf_server_submit", C.c_int, [C.c_void_p, C.c_int64, C.POINTER(bf_mesh_desc), C.c_void_p, C.c_void_p,
@@ -249,6 +250,12 @@ class Problem:
         e, inv = C.c_double(), C.c_int32()
         self.ctx.check(lib().bf_energy(self.h, C.byref(e), C.byref(inv)))
         return float(e.value), bool(inv.value)
+
+    def mu_init(self, C_=0.1):
+        """C max_i (grad^2 E)_ii at the start-of-step state x (Section 5.2)."""
+        m = C.c_double()
+        self.ctx.check(lib().bf_mu_init(self.h, C_, C.byref(m)))
+        return float(m.value)
 
     def gradient(self):
         g = np.empty((self.N, 3), dtype=np.float64)

@@ -803,6 +803,39 @@ bf_status bf_energy(bf_problem* pb, double* energy_out, int32_t* inverted) {
   return st;
 }
 
+bf_status bf_mu_init(bf_problem* pb, double C, double* mu_out) {
+  if (!pb) return BF_ERR_INVALID_ARG;
+  bf_context* c = pb->ctx;
+  if (!mu_out) return fail(c, BF_ERR_INVALID_ARG, "mu_out is NULL");
+  if (!(C > 0.0) || !std::isfinite(C)) return fail(c, BF_ERR_INVALID_ARG, "C must be finite and > 0");
+  if (!pb->has_state) return fail(c, BF_ERR_STATE, "bf_set_state must be called first");
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  const int N = pb->N, T = pb->T;
+  int* flags = pb->flags.as<int>();
+  fill_int(flags, 0, 16, s);
+  // the elastic Hessian at x, the state the time step starts from, into the
+  // staging buffer (the next Newton step overwrites it)
+  launch_elastic(pb->tets.as<int4>(), T, pb->rest.as<double>(), pb->x.as<double>(), pb->Dminv9.as<float>(),
+                 pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), (float)(pb->dt * pb->dt),
+                 pb->epos.as<int>(), pb->staging.as<float>(), flags, s);
+  const int np = diag_max_parts(N);
+  ALLOC(c, pb->epart, 8LL * (np + 8));
+  launch_diag_max(N, pb->erow_ptr.as<int>(), pb->ecptr.as<int>(), pb->staging.as<float>(), pb->mass.as<float>(),
+                  pb->epart.as<double>(), s);
+  std::vector<double> hp(np);
+  HIPCHK(c, hipMemcpyAsync(hp.data(), pb->epart.p, 8LL * np, hipMemcpyDeviceToHost, s));
+  int hflags = 0;
+  bf_status r0 = read_flags(pb, &hflags);   // synchronizes the stream
+  if (r0 != BF_OK) return r0;
+  if (hflags) return flags_to_status(c, hflags);
+  double m = 0.0;
+  for (double v : hp) m = std::max(m, v);
+  *mu_out = C * m;
+  c->err.clear();
+  return BF_OK;
+}
+
 bf_status bf_solve_subproblem(bf_problem* pb, const bf_solve_opts* o, int32_t max_newton, double decay,
                               double* x_hat_out, double* lambda_out, double* gamma_out, int32_t mem,
                               bf_subproblem_stats* stats) {

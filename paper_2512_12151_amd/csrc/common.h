@@ -165,6 +165,9 @@ void launch_energy(const int4* tets, int T, const double* rest, const double* E,
                    const double* lin64, const double* xlin, const double* lam, const double* gam, double kappa,
                    double delta, double* part, int* inverted, hipStream_t s);
 void launch_state_axpy(int n3, const double* xa, double r, const double* p, double* xt, hipStream_t s);
+int diag_max_parts(int N);
+void launch_diag_max(int N, const int* erow_ptr, const int* ecptr, const float* staging, const float* mass,
+                     double* part, hipStream_t s);
 void launch_dual_update(const int4* ids, int n_c, const double* lin64, const double* xlin, const double* xh,
                         double kappa, double delta, double decay, double* lam, double* gam, double* part,
                         hipStream_t s);

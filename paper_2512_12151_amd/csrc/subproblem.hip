@@ -11,7 +11,10 @@
 //  - the trial state x_hat + r p;
 //  - the multiplier and decay update after the Newton loop: s_i = 0 gives
 //    lambda_i -= mu c_i and gamma_i = 1, s_i > 0 gives lambda_i = 0 and
-//    gamma_i *= Gamma (Section 4.2, "Constraint Decay").
+//    gamma_i *= Gamma (Section 4.2, "Constraint Decay");
+//  - the conditioning-aware penalty of Section 5.2, C max_i (grad^2 E)_ii: the
+//    largest scalar diagonal of the lumped mass plus the SPD-projected elastic
+//    Hessian (the matrix the solver assembles), at the start-of-step state.
 // Sums use per-workgroup FP64 partials summed in a fixed order.
 #include "common.h"
 
@@ -180,9 +183,50 @@ k_dual_update(const int4* __restrict__ ids, int n_c, const double* __restrict__ 
   }
 }
 
+// Largest scalar diagonal of M + h^2 (projected elastic Hessian), per
+// workgroup: the diagonal block of row r is the sum of its staging range (the
+// static pattern holds the diagonal first in each row), plus the lumped mass.
+__global__ void __launch_bounds__(kEBlock)
+k_diag_max(int N, const int* __restrict__ erow_ptr, const int* __restrict__ ecptr, const float* __restrict__ staging,
+           const float* __restrict__ mass, double* __restrict__ part) {
+  const int r = blockIdx.x * kEBlock + threadIdx.x;
+  double m = 0.0;
+  if (r < N) {
+    const int es = erow_ptr[r];
+    float d0 = 0.f, d1 = 0.f, d2 = 0.f;
+    for (int j = ecptr[es]; j < ecptr[es + 1]; ++j) {
+      const float* st = staging + 9LL * j;   // symmetric 6 (xx, xy, xz, yy, yz, zz), then the gradient
+      d0 += st[0];
+      d1 += st[3];
+      d2 += st[5];
+    }
+    const float mv = mass[r];
+    m = (double)fmaxf(fmaxf(d0 + mv, d1 + mv), d2 + mv);
+  }
+  __shared__ double red[kEBlock / kWave];
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, kWave));
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = red[0];
+    for (int w = 1; w < kEBlock / kWave; ++w) b = fmax(b, red[w]);
+    part[blockIdx.x] = b;
+  }
+}
+
 }  // namespace
 
 int energy_parts(int T, int n_c) { return div_up(T, kEBlock) + div_up(n_c, kEBlock); }
+
+int diag_max_parts(int N) { return div_up(N, kEBlock); }
+
+void launch_diag_max(int N, const int* erow_ptr, const int* ecptr, const float* staging, const float* mass,
+                     double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_max, dim3(div_up(N, kEBlock)), dim3(kEBlock), 0, s, N, erow_ptr, ecptr, staging, mass,
+                     part);
+}
 
 void launch_energy(const int4* tets, int T, const double* rest, const double* E, const double* nu,
                    const double* rho, double h, const double* x, const double* xt, const int4* ids, int n_c,

@@ -110,3 +110,22 @@ def test_large_subproblem_energy_and_update(large):
     assert status in (bfal.BF_OK, bfal.BF_WARN_PCG_MAXITER)
     assert stats["newton_iters"] == 4 and 0.0 < stats["last_step"] < 1.0
     check_subproblem(sc, xh, lam, gam, stats)
+
+
+@pytest.mark.timeout(600)
+def test_large_mu_init(large):
+    """Section 5.2's penalty estimate at the large workload's x (the stack
+    compressed 40 % in z, so the projection is active in many tets): within
+    1e-5 relative of the oracle's FP64 value."""
+    from oracle import subproblem as osp
+    from paper_2512_12151_amd import bfal
+    sc, _ = large
+    ctx = bfal.Context(0)
+    pb = bfal.Problem.from_scene(ctx, sc)
+    mu = pb.mu_init(0.1)
+    pb.close()
+    ctx.close()
+    print("large: oracle mu_init", flush=True)
+    ref = osp.mu_init(sc, 0.1)
+    print(f"large: mu_init {mu:.9e}, oracle {ref:.9e} (the workload's kappa {sc['kappa']:.0e})", flush=True)
+    assert mu == pytest.approx(ref, rel=1e-5)

@@ -152,3 +152,47 @@ def test_medium_subproblem_in_the_bench_configuration(ctx, bf):
     assert status == bf.BF_OK
     assert stats["last_step"] == 1.0 and stats["truncated"] == 0
     check_subproblem(sc, xh, lam, gam, stats)
+
+
+def _with_x(sc, x):
+    sc = dict(sc)
+    sc["x"] = x
+    sc["x_tilde"] = x
+    sc["x_hat"] = x.copy()
+    return sc
+
+
+MU_CASES = {
+    "tiny_rest": lambda: scenes.tiny(),
+    "tiny_dilated": lambda: (lambda sc: _with_x(sc, 1.05 * sc["rest"]))(scenes.tiny()),
+    # 10 % compression in z: J < 1, so the projection clamps the twist modes
+    "tiny_compressed": lambda: (lambda sc: _with_x(sc, sc["rest"] * np.array([1.0, 1.0, 0.9])))(scenes.tiny()),
+    "medium": scenes.medium,
+}
+
+
+@pytest.mark.parametrize("name", list(MU_CASES))
+def test_mu_init_matches_oracle(ctx, bf, name):
+    """Section 5.2's C max_i (grad^2 E)_ii: within 1e-5 relative (FP32 sums of
+    the element blocks against FP64)."""
+    sc = MU_CASES[name]()
+    print(f"case {name}", flush=True)
+    pb = bf.Problem.from_scene(ctx, sc)
+    mu = pb.mu_init(0.1)
+    ref = osp.mu_init(sc, 0.1)
+    print(f"{name}: mu_init {mu:.9e}, oracle {ref:.9e}", flush=True)
+    assert mu == pytest.approx(ref, rel=1e-5)
+    assert pb.mu_init(0.2) == pytest.approx(2.0 * mu, rel=1e-15)
+    # the Newton step afterwards is unaffected (it rebuilds the staged blocks at x_hat)
+    p1, _, _ = pb.newton_step(tol=1e-6)
+    pb2 = bf.Problem.from_scene(ctx, sc)
+    p2, _, _ = pb2.newton_step(tol=1e-6)
+    assert np.array_equal(p1, p2)
+
+
+def test_mu_init_errors(ctx, bf):
+    sc = scenes.tiny()
+    pb = bf.Problem.from_scene(ctx, sc)
+    for C in (0.0, -1.0, float("nan")):
+        with pytest.raises(bf.BfalError):
+            pb.mu_init(C)

@@ -103,3 +103,77 @@ def test_repeated_subproblems_drive_constraints_to_feasibility():
         sc["x_hat"], sc["lam"], sc["gamma"] = xh, lam, gam
     assert viol[0] > 0.0
     assert viol[-1] < 0.1 * viol[0]
+
+
+def _kuhn_linear_elastic_diagonal(sc):
+    """The Hessian diagonal at rest written out from the rest shape alone: at
+    F = I the Neo-Hookean second variation is that of linear elasticity,
+    mu |dF|^2 + mu dF:dF^T + lambda tr(dF)^2, and moving vertex a of a tet
+    along axis i gives dF = e_i a_a^T (a_a the rows of D_m^-1, a_0 = -sum), so
+    the entry is m_v + h^2 sum_e V_e (mu |a_a|^2 + (mu + lambda) a_{a,i}^2)."""
+    rest, tets = sc["rest"], sc["tets"]
+    N = len(rest)
+    diag = np.zeros(3 * N)
+    for k, t in enumerate(tets):
+        X = rest[t]
+        Dm = np.column_stack([X[1] - X[0], X[2] - X[0], X[3] - X[0]])
+        V = abs(np.linalg.det(Dm)) / 6.0
+        Ai = np.linalg.inv(Dm)
+        a = [-(Ai[0] + Ai[1] + Ai[2]), Ai[0], Ai[1], Ai[2]]
+        E, nu, rho = sc["E"][k], sc["nu"][k], sc["rho"][k]
+        mu = E / (2 * (1 + nu))
+        lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+        for v in range(4):
+            for i in range(3):
+                diag[3 * t[v] + i] += rho * V / 4 + sc["dt"] ** 2 * V * (mu * a[v] @ a[v] + (mu + lam) * a[v][i] ** 2)
+    return diag
+
+
+def test_hessian_diagonal_at_rest_is_the_linear_elastic_closed_form():
+    sc = scenes.tiny()
+    assert np.array_equal(sc["x"], sc["rest"])
+    st = oracle.prepare(sc)
+    d = osp.hessian_diagonal(sc, st, sc["x"])
+    ref = _kuhn_linear_elastic_diagonal(sc)
+    assert np.allclose(d, ref, rtol=1e-12, atol=0.0)
+    mu0 = osp.mu_init(sc)
+    assert mu0 == pytest.approx(0.1 * ref.max(), rel=1e-12)
+    print(f"tiny: mu_init = {mu0:.4f} (the configuration's kappa is {sc['kappa']:.0e})")
+
+
+def test_hessian_diagonal_is_the_second_derivative_of_the_energy():
+    """At a deformed state where no element's projection is active the
+    diagonal equals the central second difference of E = 1/2 |x - x_tilde|_M^2
+    + h^2 sum V Psi along each coordinate (checked at the largest entry and at
+    random ones).  Near rest any compression (J < 1) makes the twist modes
+    negative (omega ~ lambda ln J), so the state is a 5 % dilation with noise."""
+    sc = dict(scenes.tiny(lateral=(0.37, 0.21)))
+    sc["pt"] = np.zeros((0, 4), np.int32)
+    sc["ee"] = np.zeros((0, 4), np.int32)
+    sc["lam"] = np.zeros(0)
+    sc["gamma"] = np.zeros(0)
+    st = oracle.prepare(sc)
+    xs = 1.05 * sc["rest"] + 1e-3 * RNG.standard_normal(sc["rest"].shape)
+    F = oracle.core.deformation_gradient(xs, st.tets, st.Dminv)
+    ev = np.linalg.eigvalsh(oracle.core.nh_hessian9(F, st.mu_l, st.lam_l))
+    assert ev.min() > 0.0, "the projection must be inactive for this pin"
+    d = osp.hessian_diagonal(sc, st, xs)
+    eps = 1e-4
+    for j in [int(np.argmax(d))] + list(RNG.choice(3 * len(xs), 8, replace=False)):
+        v, i = divmod(j, 3)
+        f = []
+        for s in (-1, 0, 1):
+            x2 = xs.copy()
+            x2[v, i] += s * eps
+            f.append(oracle.total_energy(sc, st, x2))
+        fd = (f[0] - 2 * f[1] + f[2]) / eps ** 2
+        assert fd == pytest.approx(d[j], rel=1e-5), (j, fd, d[j])
+
+
+def test_mu_init_is_taken_at_x_not_x_hat(shifted):
+    sc = dict(shifted)
+    m0 = osp.mu_init(sc)
+    sc["x_hat"] = sc["x_hat"] + 0.01
+    assert osp.mu_init(sc) == m0
+    sc["x"] = sc["x"] * np.array([1.0, 1.0, 0.9])
+    assert osp.mu_init(sc) != m0
