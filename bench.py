@@ -32,21 +32,21 @@ def log(msg):
 
 
 def spmv_bytes(N, nnzb):
-    """Algorithmic bytes of one launch of k_spmv (symmetric SpMV with the
-    direction update fused in): each of the n_off = nnzb - N stored upper
-    off-diagonal blocks once (36 B FP32 values + 4 B column) and its entry of
-    the transpose index (8 B: block index, source row); two row pointers per
-    row (8 B); r and the previous p read once (24 B/node); the new p and q
-    written once (24 B/node).  The second read of each block (the lower half,
-    gathered through the transpose index) is not counted."""
+    """Algorithmic bytes of one launch of k_spmv (symmetric SpMV): each of the
+    n_off = nnzb - N stored upper off-diagonal blocks once (36 B FP32 values
+    + 4 B column) and its entry of the transpose index (8 B: block index,
+    source row); two row pointers per row (8 B); p and r read once (24 B/node,
+    r for r^T q); q written once (12 B/node).  The second read of each block
+    (the lower half, gathered through the transpose index) is not counted."""
     n_off = nnzb - N
-    return 48 * n_off + 8 * (N + 1) + 48 * N
+    return 48 * n_off + 8 * (N + 1) + 36 * N
 
 
 def pcg_iteration_bytes(N, nnzb):
     """k_spmv + k_update (p, q, r and the factor L read, 60 B/node; the FP64
-    x read and written, 48 B/node; r written, 12 B/node: 120 B/node)."""
-    return spmv_bytes(N, nnzb) + 120 * N
+    x read and written, 48 B/node; r and the next p written, 24 B/node:
+    132 B/node)."""
+    return spmv_bytes(N, nnzb) + 132 * N
 
 
 COUNTER_FILE = os.path.join(ROOT, "profiles", "k_spmv_large_hbm_counters.md")

@@ -53,7 +53,9 @@ constexpr int kMaxSpmvParts = 2048;   // workgroups of the SpMV per system
 constexpr int kPartRR = 0;                              // r^T r, two slots (iterations k, k+1)
 constexpr int kPartRT = 2 * kMaxVecParts;               // |L r|^2
 constexpr int kPartPQ = 3 * kMaxVecParts;               // p^T H p
-constexpr int kPartsPerSystem = 3 * kMaxVecParts + kMaxSpmvParts;
+constexpr int kPartRQ = kPartPQ + kMaxSpmvParts;        // r^T H p
+constexpr int kPartQQ = kPartRQ + kMaxSpmvParts;        // |H p|^2
+constexpr int kPartsPerSystem = 3 * kMaxVecParts + 3 * kMaxSpmvParts;
 
 constexpr int kSlice = 64;         // rows per slice of the sliced block storage (one wavefront)
 
@@ -78,8 +80,8 @@ struct PcgSystem {
   const float* Lf;
   double* x;         // FP64 solution (AoS [N4][3])
   float* r;
-  float* P0;
-  float* P1;
+  float* P0;         // p_k for even k
+  float* P1;         // p_k for odd k
   float* q;
   double* part;      // kPartsPerSystem
   PcgScalars* sc;

@@ -5,15 +5,20 @@
 // those of PCG with z = D^{-1} r on H: p = L^{-T} p_hat, r = L r_hat.
 //
 // One iteration is two kernels on one stream, with no host round trip:
-//   spmv    convergence test on r_k; beta = rho_k / rho_{k-1};
-//           p_k = r_k + beta p_{k-1} (formed on the fly wherever p is read and
-//           stored by the row owner into the other buffer of a pair);
+//   spmv    convergence test on r_k;
 //           q = H_hat p_k = p_k + sum over the stored upper blocks of the row
 //           (B_rc p_c) + sum over the upper blocks of its column (B_cr^T p_c);
-//           p^T q (FP64).
-//   update  alpha = rho_k / p^T q; x += alpha p, r -= alpha q; rho_{k+1} =
-//           r^T r (FP64); every check_every iterations also |L r|^2, the
-//           unscaled residual norm squared.
+//           p^T q, r^T q and q^T q (FP64).
+//   update  alpha = rho_k / p^T q; beta = rho~_{k+1} / rho_k with
+//           rho~_{k+1} = |r - alpha q|^2 = rho_k - 2 alpha r^T q + alpha^2 q^T q
+//           (known before r is updated, so the direction can be formed in the
+//           same pass); x += alpha p, r -= alpha q, p_{k+1} = r_{k+1} +
+//           beta p_k into the other buffer of a pair; rho_{k+1} = r^T r
+//           (FP64, for the next alpha and the convergence test); every
+//           check_every iterations also |L r|^2, the unscaled residual norm
+//           squared.
+// Every SpMV gather then reads one vector (p) instead of forming r + beta p
+// from two.
 // The upper blocks are stored once, in slices of 64 rows with one lane per row
 // (slot k of all 64 rows contiguous), and read twice per iteration: streamed
 // for the upper part, and gathered through per-row references for the lower
@@ -25,9 +30,10 @@
 // (~150 MB) fits the 256 MB Infinity Cache.
 //
 // Residual replacement (reliable updating): x is kept in FP64, and when the
-// recursive residual has fallen 10x since the last replacement, or claims
+// recursive residual has fallen 100x since the last replacement, or claims
 // convergence, the SpMV stops the system with done = 4 and the host replaces
-// r by b - H x formed in FP64 from the stored FP32 blocks; iteration then
+// r by b - H x formed in FP64 from the stored FP32 blocks and re-forms the
+// direction from it, p_k = r_k + (rho_k / rho_{k-1}) p_{k-1}; iteration then
 // resumes with the usual recurrences (convergence is accepted only on a
 // replaced residual).  Without it, thousands of FP32 iterations let the
 // recursive residual drift far below the true one on stiff contact systems.
@@ -73,6 +79,32 @@ __device__ inline double block_sum_all(double v) {
 #pragma unroll
   for (int w = 0; w < NT / kWave; ++w) s += red[w];
   return s;
+}
+
+// Three sums over a workgroup in one LDS round; the results are valid in thread 0.
+template <int NT>
+__device__ inline void block_sum3(double& a, double& b, double& c) {
+  __shared__ double red[3][NT / kWave];
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, kWave);
+    b += __shfl_xor(b, off, kWave);
+    c += __shfl_xor(c, off, kWave);
+  }
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    red[0][threadIdx.x / kWave] = a;
+    red[1][threadIdx.x / kWave] = b;
+    red[2][threadIdx.x / kWave] = c;
+  }
+  __syncthreads();
+  a = b = c = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / kWave; ++w) {
+    a += red[0][w];
+    b += red[1][w];
+    c += red[2][w];
+  }
 }
 
 template <int NT>
@@ -122,6 +154,37 @@ __device__ inline void sum_parts3(const double* __restrict__ a, int na, const do
   }
 }
 
+// Four fixed-order sums in one pass (as sum_parts3).
+template <int NT>
+__device__ inline void sum_parts4(const double* __restrict__ a, int na, const double* __restrict__ b, int nb,
+                                  const double* __restrict__ c, int nc, const double* __restrict__ d, int nd,
+                                  double& sa, double& sb, double& sc, double& sd) {
+  __shared__ double red[4][NT / kWave];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < na; k += NT) v[0] += a[k];
+  for (int k = threadIdx.x; k < nb; k += NT) v[1] += b[k];
+  for (int k = threadIdx.x; k < nc; k += NT) v[2] += c[k];
+  for (int k = threadIdx.x; k < nd; k += NT) v[3] += d[k];
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] += __shfl_xor(v[m], off, kWave);
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) red[m][threadIdx.x / kWave] = v[m];
+  __syncthreads();
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int w = 0; w < NT / kWave; ++w)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) t[m] += red[m][w];
+  sa = t[0];
+  sb = t[1];
+  sc = t[2];
+  sd = t[3];
+}
+
 // Fixed-order sum of part[0..n) by the whole workgroup (same value in every workgroup).
 template <int NT>
 __device__ inline double sum_parts(const double* __restrict__ part, int n) {
@@ -156,17 +219,15 @@ __device__ inline void load_block(const uint32_t* __restrict__ u, int j, float b
 
 // Scalars at the start of SpMV k: returns false when the system is finished
 // (converged, capped) and the workgroup must return.  Called by the whole workgroup.
-__device__ inline bool spmv_scalars(const PcgSystem& S, bool leader, int& k, float& beta) {
+__device__ inline bool spmv_scalars(const PcgSystem& S, bool leader, int& k) {
   PcgScalars* sc = S.sc;
   if (sc->brk) return false;
   k = sc->iter;
   const double* part = S.part;
   const bool check = k > 0 && (k % sc->check_every) == 0;
-  double rho, rho_old, rt;
-  sum_parts3<kSpmvBlock>(part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg,
-                         part + kPartRR + ((k + 1) & 1) * kMaxVecParts, k > 0 ? S.vec_nwg : 0,
-                         part + kPartRT, check ? S.vec_nwg : 0, rho, rho_old, rt);
-  beta = 0.f;
+  double rho, rt, unused;
+  sum_parts3<kSpmvBlock>(part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg, part + kPartRT,
+                         check ? S.vec_nwg : 0, part, 0, rho, rt, unused);
   if (k > 0) {
     const bool converged = (check && rt <= sc->tol2 * sc->bb) || rho == 0.0;
     const bool capped = k >= sc->max_iter;
@@ -182,31 +243,19 @@ __device__ inline bool spmv_scalars(const PcgSystem& S, bool leader, int& k, flo
       else if (capped) sc->done = 2;
     }
     if (converged || capped || replace) return false;
-    beta = (float)(rho / rho_old);
   }
   if (leader) sc->ks = k;
   return true;
 }
 
-// Vector entries of p_k at node c, formed on the fly: p_k = r + beta p_{k-1}
-// (the same rounding as the row owner's, so every reader sees the same p_k).
-// Vectors are AoS [N4][3]: one 12-byte load per vector and node.
+// Vector entries of p_k at node c (AoS [N4][3]: one 12-byte load per node).
 struct PView {
-  const float* __restrict__ r;
-  const float* __restrict__ o;
-  float beta;
-  bool first;
+  const float* __restrict__ p;
   __device__ inline void at(int c, float& p0, float& p1, float& p2) const {
-    const float* rc = r + 3LL * c;
-    p0 = rc[0];
-    p1 = rc[1];
-    p2 = rc[2];
-    if (!first) {
-      const float* oc = o + 3LL * c;
-      p0 = __fmaf_rn(beta, oc[0], p0);
-      p1 = __fmaf_rn(beta, oc[1], p1);
-      p2 = __fmaf_rn(beta, oc[2], p2);
-    }
+    const float* pc = p + 3LL * c;
+    p0 = pc[0];
+    p1 = pc[1];
+    p2 = pc[2];
   }
 };
 
@@ -331,16 +380,14 @@ __device__ inline void accumulate_pairs(int ubase, int wu, int lbase, int wl, co
   }
 }
 
-// q = H_hat p_k for the slices of workgroup lb (of nwg) of one system, p_k
-// formed on the fly; returns this thread's share of p^T q.
+// q = H_hat p_k for the slices of workgroup lb (of nwg) of one system; adds
+// this thread's shares of p^T q, r^T q and q^T q.
 template <class BT>
-__device__ inline double spmv_slices(const PcgSystem& S, int lb, int nwg, int k, float beta) {
+__device__ inline void spmv_slices(const PcgSystem& S, int lb, int nwg, int k, double& pq, double& rq,
+                                   double& qq) {
   const int wave = threadIdx.x / kSlice, lane = threadIdx.x % kSlice;
-  const float* pold = (k & 1) ? S.P0 : S.P1;
-  float* __restrict__ pn = (k & 1) ? S.P1 : S.P0;
-  const PView pv{S.r, pold, beta, k == 0};
+  const PView pv{(k & 1) ? S.P1 : S.P0};
   const BT* __restrict__ blk = static_cast<const BT*>(S.blk);
-  double dot = 0.0;
   for (int sl = lb * kSlicesPerGroup + wave; sl < S.nslices; sl += nwg * kSlicesPerGroup) {
     const int bu = S.sbu[sl], wu = (S.sbu[sl + 1] - bu) / kSlice;
     const int bl = S.sbl[sl], wl = (S.sbl[sl + 1] - bl) / kSlice;
@@ -355,24 +402,30 @@ __device__ inline double spmv_slices(const PcgSystem& S, int lb, int nwg, int k,
     if (row < S.N) {
       float s0, s1, s2;
       pv.at(row, s0, s1, s2);
+      const float* rr = S.r + 3LL * row;
+      const float r0 = rr[0], r1 = rr[1], r2 = rr[2];
       const float q0 = s0 + a0, q1 = s1 + a1, q2 = s2 + a2;
-      pn[3LL * row] = s0; pn[3LL * row + 1] = s1; pn[3LL * row + 2] = s2;
       S.q[3LL * row] = q0; S.q[3LL * row + 1] = q1; S.q[3LL * row + 2] = q2;
-      dot += (double)s0 * q0 + (double)s1 * q1 + (double)s2 * q2;
+      pq += (double)s0 * q0 + (double)s1 * q1 + (double)s2 * q2;
+      rq += (double)r0 * q0 + (double)r1 * q1 + (double)r2 * q2;
+      qq += (double)q0 * q0 + (double)q1 * q1 + (double)q2 * q2;
     }
   }
-  return dot;
 }
 
 template <class BT>
 __global__ void __launch_bounds__(kSpmvBlock) k_spmv(PcgSystem S) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   int k;
-  float beta;
-  if (!spmv_scalars(S, lb == 0 && threadIdx.x == 0, k, beta)) return;
-  const double dot = spmv_slices<BT>(S, lb, gridDim.x, k, beta);
-  const double s = block_sum_all<kSpmvBlock>(dot);
-  if (threadIdx.x == 0) S.part[kPartPQ + lb] = s;
+  if (!spmv_scalars(S, lb == 0 && threadIdx.x == 0, k)) return;
+  double pq = 0.0, rq = 0.0, qq = 0.0;
+  spmv_slices<BT>(S, lb, gridDim.x, k, pq, rq, qq);
+  block_sum3<kSpmvBlock>(pq, rq, qq);
+  if (threadIdx.x == 0) {
+    S.part[kPartPQ + lb] = pq;
+    S.part[kPartRQ + lb] = rq;
+    S.part[kPartQQ + lb] = qq;
+  }
 }
 
 template <class BT>
@@ -382,22 +435,27 @@ __global__ void __launch_bounds__(kSpmvBlock) k_spmv_batched(const PcgSystem* __
   const PcgSystem S = sys[wg_sys[b]];
   const int lb = b - S.spmv_wg0;
   int k;
-  float beta;
-  if (!spmv_scalars(S, lb == 0 && threadIdx.x == 0, k, beta)) return;
-  const double dot = spmv_slices<BT>(S, lb, S.spmv_nwg, k, beta);
-  const double s = block_sum_all<kSpmvBlock>(dot);
-  if (threadIdx.x == 0) S.part[kPartPQ + lb] = s;
+  if (!spmv_scalars(S, lb == 0 && threadIdx.x == 0, k)) return;
+  double pq = 0.0, rq = 0.0, qq = 0.0;
+  spmv_slices<BT>(S, lb, S.spmv_nwg, k, pq, rq, qq);
+  block_sum3<kSpmvBlock>(pq, rq, qq);
+  if (threadIdx.x == 0) {
+    S.part[kPartPQ + lb] = pq;
+    S.part[kPartRQ + lb] = rq;
+    S.part[kPartQQ + lb] = qq;
+  }
 }
 
-// alpha, then x += alpha p, r -= alpha q over the nodes of workgroup lb of nwg.
+// alpha and beta, then x += alpha p, r -= alpha q, p_{k+1} = r + beta p over
+// the nodes of workgroup lb of nwg.
 __device__ inline void update_nodes(const PcgSystem& S, int lb) {
   PcgScalars* sc = S.sc;
   if (sc->done) return;
   const int k = sc->ks;
   double* part = S.part;
-  double rho, pq, unused;
-  sum_parts3<kVecBlock>(part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg, part + kPartPQ, S.spmv_nwg, part, 0, rho,
-                        pq, unused);
+  double rho, pq, rq, qq;
+  sum_parts4<kVecBlock>(part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg, part + kPartPQ, S.spmv_nwg,
+                        part + kPartRQ, S.spmv_nwg, part + kPartQQ, S.spmv_nwg, rho, pq, rq, qq);
   const bool leader = lb == 0 && threadIdx.x == 0;
   if (!(pq > 0.0)) {
     if (leader) {
@@ -407,6 +465,11 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
     return;
   }
   const float alpha = (float)(rho / pq);
+  // |r - alpha q|^2 with the alpha the residual update applies; a negative
+  // value (rounding, once r ~ 0) restarts the direction
+  const double ad0 = alpha;
+  const double rho_next = rho - 2.0 * ad0 * rq + ad0 * ad0 * qq;
+  const float beta = rho_next > 0.0 ? (float)(rho_next / rho) : 0.f;
   const bool check = ((k + 1) % sc->check_every) == 0;
   // Chunks of 4 * kVecBlock nodes: the three vectors' float4s of a chunk are
   // contiguous, so every load and store below is one contiguous run per
@@ -416,6 +479,7 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
   const long long n4 = S.N4;
   const long long nf4 = 3 * n4 / 4;   // float4 per vector
   const float4* __restrict__ p4 = reinterpret_cast<const float4*>((k & 1) ? S.P1 : S.P0);
+  float4* __restrict__ pn4 = reinterpret_cast<float4*>((k & 1) ? S.P0 : S.P1);
   const float4* __restrict__ q4 = reinterpret_cast<const float4*>(S.q);
   double2* __restrict__ x2 = reinterpret_cast<double2*>(S.x);
   float4* __restrict__ r4 = reinterpret_cast<float4*>(S.r);
@@ -440,6 +504,8 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
         x2[2 * f] = xa;
         x2[2 * f + 1] = xb;
         r4[f] = r;
+        pn4[f] = make_float4(__fmaf_rn(beta, p.x, r.x), __fmaf_rn(beta, p.y, r.y), __fmaf_rn(beta, p.z, r.z),
+                             __fmaf_rn(beta, p.w, r.w));
         rr += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
         rs[m * kVecBlock + t] = r;
       }
@@ -486,12 +552,14 @@ __global__ void __launch_bounds__(kVecBlock) k_update_batched(const PcgSystem* _
 }
 
 __global__ void __launch_bounds__(kVecBlock)
-k_init(int n3, const float* __restrict__ bhat, double* __restrict__ x, float* __restrict__ r, double* __restrict__ part) {
+k_init(int n3, const float* __restrict__ bhat, double* __restrict__ x, float* __restrict__ r, float* __restrict__ p0,
+       double* __restrict__ part) {
   double rr = 0.0;
   for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) {
     const float b = bhat[i];
     x[i] = 0.0;
     r[i] = b;
+    p0[i] = b;
     rr += (double)b * b;
   }
   const double s = block_sum_all<kVecBlock>(rr);
@@ -651,12 +719,13 @@ k_copy_f2d(int n3, const float* __restrict__ x, double* __restrict__ y) {
 // Inner solve start: r = (float) r_outer, x = 0, partials of r^T r.
 __global__ void __launch_bounds__(kVecBlock)
 k_init_from64(int n3, const double* __restrict__ rd, double* __restrict__ x, float* __restrict__ r,
-              double* __restrict__ part) {
+              float* __restrict__ p0, double* __restrict__ part) {
   double rr = 0.0;
   for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) {
     const float b = (float)rd[i];
     x[i] = 0.0;
     r[i] = b;
+    p0[i] = b;
     rr += (double)b * b;
   }
   const double s = block_sum_all<kVecBlock>(rr);
@@ -693,6 +762,21 @@ k_replace_fold(PcgSystem S, const double* __restrict__ rd, const double* __restr
     sc->verified = k;
     sc->done = 0;
   }
+}
+
+// After a residual replacement at iteration k: p_k = r_k + (rho_k / rho_{k-1})
+// p_{k-1} from the replaced residual (p_{k-1} is still in the other buffer).
+__global__ void __launch_bounds__(kVecBlock) k_replace_dir(PcgSystem S) {
+  const int k = S.sc->iter;
+  double rho, rho_old, unused;
+  sum_parts3<kVecBlock>(S.part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg,
+                        S.part + kPartRR + ((k + 1) & 1) * kMaxVecParts, S.vec_nwg, S.part, 0, rho, rho_old, unused);
+  const float beta = rho_old > 0.0 ? (float)(rho / rho_old) : 0.f;
+  float* __restrict__ pk = (k & 1) ? S.P1 : S.P0;
+  const float* __restrict__ pold = (k & 1) ? S.P0 : S.P1;
+  const long long n3 = 3LL * S.N4;
+  for (long long i = (long long)blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += (long long)gridDim.x * kVecBlock)
+    pk[i] = __fmaf_rn(beta, pold[i], S.r[i]);
 }
 
 // x_outer += d (FP64).
@@ -738,7 +822,7 @@ int pcg_vec_groups(int N) {
 
 void launch_pcg_init(const PcgSystem& S, const float* bhat, const double* bb_part, int nbb, double tol, int max_iter,
                      int check_every, bool replace, hipStream_t s) {
-  hipLaunchKernelGGL(k_init, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, bhat, S.x, S.r, S.part);
+  hipLaunchKernelGGL(k_init, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, bhat, S.x, S.r, S.P0, S.part);
   hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kBlock), 0, s, bb_part, nbb, S.sc, tol, max_iter, check_every,
                      replace ? 1 : 0);
 }
@@ -747,6 +831,7 @@ void launch_pcg_replace(const PcgSystem& S, const float* bhat, double* rd, doubl
   hipLaunchKernelGGL(k_residual64, dim3(S.spmv_nwg), dim3(kSpmvBlock), 0, s, S, bhat, (const double*)S.x, rd, rpart);
   hipLaunchKernelGGL(k_replace_fold, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, S, (const double*)rd,
                      (const double*)rpart, S.spmv_nwg);
+  hipLaunchKernelGGL(k_replace_dir, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, S);
 }
 
 void launch_pcg_iteration(const PcgSystem& S, bool bf16, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
@@ -785,7 +870,7 @@ void launch_pcg_finish(const PcgSystem& S, const float* Linv, double* pout, cons
 
 void launch_pcg_init_from64(const PcgSystem& S, const double* rd, const double* rpart, int nparts, double tol,
                             int max_iter, int check_every, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_from64, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, rd, S.x, S.r, S.part);
+  hipLaunchKernelGGL(k_init_from64, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, rd, S.x, S.r, S.P0, S.part);
   hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kBlock), 0, s, rpart, nparts, S.sc, tol, max_iter, check_every,
                      0);
 }
