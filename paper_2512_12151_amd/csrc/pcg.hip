@@ -121,17 +121,33 @@ __device__ inline double block_max_all(double v) {
   return s;
 }
 
+// This thread's share of a partials array of n <= kMaxSpmvParts entries:
+// a[t] + a[t + NT] + ... summed in that order, with every load issued before
+// the first add (the partials come from other XCDs through the Infinity
+// Cache; a dependent chain would wait one round trip per element).
+template <int NT>
+__device__ __forceinline__ double thread_parts(const double* __restrict__ a, int n) {
+  constexpr int kPer = (kMaxSpmvParts + NT - 1) / NT;
+  double v[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int k = threadIdx.x + u * NT;
+    v[u] = k < n ? a[k] : 0.0;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) s += v[u];
+  return s;
+}
+
 // Three fixed-order sums of part arrays (lengths n0, n1, n2; n = 0 gives 0) in
-// one pass: one load per array per thread and one LDS round, so a kernel's
-// preamble waits for one memory round trip instead of three.
+// one pass: all loads issued together and one LDS round, so a kernel's
+// preamble waits for one memory round trip.
 template <int NT>
 __device__ inline void sum_parts3(const double* __restrict__ a, int na, const double* __restrict__ b, int nb,
                                   const double* __restrict__ c, int nc, double& sa, double& sb, double& sc) {
   __shared__ double red[3][NT / kWave];
-  double va = 0.0, vb = 0.0, vc = 0.0;
-  for (int k = threadIdx.x; k < na; k += NT) va += a[k];
-  for (int k = threadIdx.x; k < nb; k += NT) vb += b[k];
-  for (int k = threadIdx.x; k < nc; k += NT) vc += c[k];
+  double va = thread_parts<NT>(a, na), vb = thread_parts<NT>(b, nb), vc = thread_parts<NT>(c, nc);
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) {
     va += __shfl_xor(va, off, kWave);
@@ -160,11 +176,7 @@ __device__ inline void sum_parts4(const double* __restrict__ a, int na, const do
                                   const double* __restrict__ c, int nc, const double* __restrict__ d, int nd,
                                   double& sa, double& sb, double& sc, double& sd) {
   __shared__ double red[4][NT / kWave];
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k = threadIdx.x; k < na; k += NT) v[0] += a[k];
-  for (int k = threadIdx.x; k < nb; k += NT) v[1] += b[k];
-  for (int k = threadIdx.x; k < nc; k += NT) v[2] += c[k];
-  for (int k = threadIdx.x; k < nd; k += NT) v[3] += d[k];
+  double v[4] = {thread_parts<NT>(a, na), thread_parts<NT>(b, nb), thread_parts<NT>(c, nc), thread_parts<NT>(d, nd)};
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1)
 #pragma unroll
@@ -446,13 +458,110 @@ __global__ void __launch_bounds__(kSpmvBlock) k_spmv_batched(const PcgSystem* __
   }
 }
 
+// Operands of one chunk of 4 * kVecBlock nodes for one thread: three float4
+// of p, q, r and the matching FP64 x, and, on check iterations, the thread's
+// 4 nodes of L (SoA [6][N4]).
+struct UpdateOperands {
+  float4 p[3], q[3], r[3], l[6];
+  double2 xa[3], xb[3];
+};
+
+__device__ __forceinline__ void load_update_operands(const PcgSystem& S, const float4* __restrict__ p4, long long ch,
+                                                     bool check, UpdateOperands& o) {
+  const int t = threadIdx.x;
+  const long long n4 = S.N4, nf4 = 3 * n4 / 4;
+  const float4* __restrict__ q4 = reinterpret_cast<const float4*>(S.q);
+  const double2* __restrict__ x2 = reinterpret_cast<const double2*>(S.x);
+  const float4* __restrict__ r4 = reinterpret_cast<const float4*>(S.r);
+  const float4* __restrict__ l4 = reinterpret_cast<const float4*>(S.Lf);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const long long f = ch * 3 * kVecBlock + m * kVecBlock + t;
+    if (f < nf4) {
+      o.p[m] = p4[f];
+      o.q[m] = q4[f];
+      o.r[m] = r4[f];
+      o.xa[m] = x2[2 * f];
+      o.xb[m] = x2[2 * f + 1];
+    }
+  }
+  const long long v0 = ch * 4 * kVecBlock + 4LL * t;
+  if (check && v0 < n4)
+#pragma unroll
+    for (int m = 0; m < 6; ++m) o.l[m] = l4[(m * n4 + v0) / 4];
+}
+
+// x += alpha p, r -= alpha q, p_{k+1} = r + beta p for one chunk; adds the
+// chunk's r^T r and (on check iterations) |L r|^2 shares.  The new residual is
+// staged in LDS (rs) for the per-node |L r|^2.
+__device__ __forceinline__ void update_chunk(const PcgSystem& S, float4* __restrict__ pn4, long long ch, bool check,
+                                             float alpha, float beta, const UpdateOperands& o, float4* rs,
+                                             double& rr, double& rt) {
+  const int t = threadIdx.x;
+  const long long n4 = S.N4, nf4 = 3 * n4 / 4;
+  double2* __restrict__ x2 = reinterpret_cast<double2*>(S.x);
+  float4* __restrict__ r4 = reinterpret_cast<float4*>(S.r);
+  const double ad = alpha;   // the same alpha as the residual update
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const long long f = ch * 3 * kVecBlock + m * kVecBlock + t;
+    if (f < nf4) {
+      const float4 p = o.p[m], q = o.q[m];
+      float4 r = o.r[m];
+      double2 xa = o.xa[m], xb = o.xb[m];
+      xa.x = fma(ad, (double)p.x, xa.x); xa.y = fma(ad, (double)p.y, xa.y);
+      xb.x = fma(ad, (double)p.z, xb.x); xb.y = fma(ad, (double)p.w, xb.y);
+      r.x = __fmaf_rn(-alpha, q.x, r.x); r.y = __fmaf_rn(-alpha, q.y, r.y);
+      r.z = __fmaf_rn(-alpha, q.z, r.z); r.w = __fmaf_rn(-alpha, q.w, r.w);
+      x2[2 * f] = xa;
+      x2[2 * f + 1] = xb;
+      r4[f] = r;
+      pn4[f] = make_float4(__fmaf_rn(beta, p.x, r.x), __fmaf_rn(beta, p.y, r.y), __fmaf_rn(beta, p.z, r.z),
+                           __fmaf_rn(beta, p.w, r.w));
+      rr += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
+      rs[m * kVecBlock + t] = r;
+    }
+  }
+  if (check) {
+    __syncthreads();
+    const long long v0 = ch * 4 * kVecBlock + 4LL * t;   // this thread's 4 nodes
+    if (v0 < n4) {
+      const float4 ra = rs[3 * t], rb = rs[3 * t + 1], rc = rs[3 * t + 2];
+      const float rv[12] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w, rc.x, rc.y, rc.z, rc.w};
+      const float lx[6][4] = {{o.l[0].x, o.l[0].y, o.l[0].z, o.l[0].w}, {o.l[1].x, o.l[1].y, o.l[1].z, o.l[1].w},
+                              {o.l[2].x, o.l[2].y, o.l[2].z, o.l[2].w}, {o.l[3].x, o.l[3].y, o.l[3].z, o.l[3].w},
+                              {o.l[4].x, o.l[4].y, o.l[4].z, o.l[4].w}, {o.l[5].x, o.l[5].y, o.l[5].z, o.l[5].w}};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float* r = rv + 3 * v;
+        const double t0 = (double)lx[0][v] * r[0];
+        const double t1 = (double)lx[1][v] * r[0] + (double)lx[2][v] * r[1];
+        const double t2 = (double)lx[3][v] * r[0] + (double)lx[4][v] * r[1] + (double)lx[5][v] * r[2];
+        rt += t0 * t0 + t1 * t1 + t2 * t2;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // alpha and beta, then x += alpha p, r -= alpha q, p_{k+1} = r + beta p over
-// the nodes of workgroup lb of nwg.
+// the nodes of workgroup lb of nwg, in chunks of 4 * kVecBlock nodes whose
+// three vectors' float4s are contiguous (every load and store is one
+// contiguous run per wavefront).  The operands of the workgroup's first chunk
+// are loaded before the grid-wide sums, so their latency overlaps the
+// reduction (a workgroup usually owns one chunk).
 __device__ inline void update_nodes(const PcgSystem& S, int lb) {
   PcgScalars* sc = S.sc;
   if (sc->done) return;
   const int k = sc->ks;
+  const bool check = ((k + 1) % sc->check_every) == 0;
   double* part = S.part;
+  __shared__ float4 rs[3 * kVecBlock];
+  const float4* __restrict__ p4 = reinterpret_cast<const float4*>((k & 1) ? S.P1 : S.P0);
+  float4* __restrict__ pn4 = reinterpret_cast<float4*>((k & 1) ? S.P0 : S.P1);
+  const long long nchunk = (S.N4 + 4 * kVecBlock - 1) / (4 * kVecBlock);
+  UpdateOperands o;
+  if (lb < nchunk) load_update_operands(S, p4, lb, check, o);
   double rho, pq, rq, qq;
   sum_parts4<kVecBlock>(part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg, part + kPartPQ, S.spmv_nwg,
                         part + kPartRQ, S.spmv_nwg, part + kPartQQ, S.spmv_nwg, rho, pq, rq, qq);
@@ -467,72 +576,14 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
   const float alpha = (float)(rho / pq);
   // |r - alpha q|^2 with the alpha the residual update applies; a negative
   // value (rounding, once r ~ 0) restarts the direction
-  const double ad0 = alpha;
-  const double rho_next = rho - 2.0 * ad0 * rq + ad0 * ad0 * qq;
+  const double ad = alpha;
+  const double rho_next = rho - 2.0 * ad * rq + ad * ad * qq;
   const float beta = rho_next > 0.0 ? (float)(rho_next / rho) : 0.f;
-  const bool check = ((k + 1) % sc->check_every) == 0;
-  // Chunks of 4 * kVecBlock nodes: the three vectors' float4s of a chunk are
-  // contiguous, so every load and store below is one contiguous run per
-  // wavefront; the new residual is staged in LDS for the per-node |L r|^2,
-  // with L stored SoA [6][N4].
-  __shared__ float4 rs[3 * kVecBlock];
-  const long long n4 = S.N4;
-  const long long nf4 = 3 * n4 / 4;   // float4 per vector
-  const float4* __restrict__ p4 = reinterpret_cast<const float4*>((k & 1) ? S.P1 : S.P0);
-  float4* __restrict__ pn4 = reinterpret_cast<float4*>((k & 1) ? S.P0 : S.P1);
-  const float4* __restrict__ q4 = reinterpret_cast<const float4*>(S.q);
-  double2* __restrict__ x2 = reinterpret_cast<double2*>(S.x);
-  float4* __restrict__ r4 = reinterpret_cast<float4*>(S.r);
-  const float4* __restrict__ l4 = reinterpret_cast<const float4*>(S.Lf);
-  const double ad = alpha;   // the same alpha as the residual update
-  const int t = threadIdx.x;
   double rr = 0.0, rt = 0.0;
-  const long long nchunk = (n4 + 4 * kVecBlock - 1) / (4 * kVecBlock);
-  for (long long ch = lb; ch < nchunk; ch += S.vec_nwg) {
-    const long long fb = ch * 3 * kVecBlock;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      const long long f = fb + m * kVecBlock + t;
-      if (f < nf4) {
-        const float4 p = p4[f], q = q4[f];
-        float4 r = r4[f];
-        double2 xa = x2[2 * f], xb = x2[2 * f + 1];
-        xa.x = fma(ad, (double)p.x, xa.x); xa.y = fma(ad, (double)p.y, xa.y);
-        xb.x = fma(ad, (double)p.z, xb.x); xb.y = fma(ad, (double)p.w, xb.y);
-        r.x = __fmaf_rn(-alpha, q.x, r.x); r.y = __fmaf_rn(-alpha, q.y, r.y);
-        r.z = __fmaf_rn(-alpha, q.z, r.z); r.w = __fmaf_rn(-alpha, q.w, r.w);
-        x2[2 * f] = xa;
-        x2[2 * f + 1] = xb;
-        r4[f] = r;
-        pn4[f] = make_float4(__fmaf_rn(beta, p.x, r.x), __fmaf_rn(beta, p.y, r.y), __fmaf_rn(beta, p.z, r.z),
-                             __fmaf_rn(beta, p.w, r.w));
-        rr += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
-        rs[m * kVecBlock + t] = r;
-      }
-    }
-    if (check) {
-      __syncthreads();
-      const long long v0 = ch * 4 * kVecBlock + 4LL * t;   // this thread's 4 nodes
-      if (v0 < n4) {
-        const float4 ra = rs[3 * t], rb = rs[3 * t + 1], rc = rs[3 * t + 2];
-        const float rv[12] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w, rc.x, rc.y, rc.z, rc.w};
-        float4 l[6];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) l[m] = l4[(m * n4 + v0) / 4];
-        const float lx[6][4] = {{l[0].x, l[0].y, l[0].z, l[0].w}, {l[1].x, l[1].y, l[1].z, l[1].w},
-                                {l[2].x, l[2].y, l[2].z, l[2].w}, {l[3].x, l[3].y, l[3].z, l[3].w},
-                                {l[4].x, l[4].y, l[4].z, l[4].w}, {l[5].x, l[5].y, l[5].z, l[5].w}};
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float* r = rv + 3 * v;
-          const double t0 = (double)lx[0][v] * r[0];
-          const double t1 = (double)lx[1][v] * r[0] + (double)lx[2][v] * r[1];
-          const double t2 = (double)lx[3][v] * r[0] + (double)lx[4][v] * r[1] + (double)lx[5][v] * r[2];
-          rt += t0 * t0 + t1 * t1 + t2 * t2;
-        }
-      }
-      __syncthreads();
-    }
+  if (lb < nchunk) update_chunk(S, pn4, lb, check, alpha, beta, o, rs, rr, rt);
+  for (long long ch = lb + S.vec_nwg; ch < nchunk; ch += S.vec_nwg) {
+    load_update_operands(S, p4, ch, check, o);
+    update_chunk(S, pn4, ch, check, alpha, beta, o, rs, rr, rt);
   }
   const double srr = block_sum_all<kVecBlock>(rr);
   const double srt = block_sum_all<kVecBlock>(rt);
