@@ -243,6 +243,9 @@ bf_status bf_context_create(int32_t device, void* hip_stream, bf_context** out) 
   if (!c) return BF_ERR_OOM;
   c->device = device;
   if (hipSetDevice(device) != hipSuccess) { delete c; return BF_ERR_HIP; }
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+    c->num_cu = ncu;
   if (hip_stream) {
     c->stream = static_cast<hipStream_t>(hip_stream);
   } else {

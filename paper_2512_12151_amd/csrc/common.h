@@ -211,7 +211,7 @@ void launch_row_diag_slots(int N, const int* row_ptr, int* diag, hipStream_t s);
 
 // pcg.hip
 // Workgroup counts of one system.
-int pcg_spmv_groups(int N);
+int pcg_spmv_groups(int N, int num_cu);
 int pcg_vec_groups(int N);
 // x = 0, r = b_hat, |b|^2 from the assembly's partials, scalars reset.
 // replace: enable residual replacement (needs the FP32 blocks in S.blk).

@@ -857,9 +857,18 @@ k_finish_scalars(const double* __restrict__ part, int n, const double* __restric
 
 }  // namespace
 
-int pcg_spmv_groups(int N) {
+// At most one SpMV workgroup per compute unit: the SpMV is bound by what one
+// CU can keep in flight, so a CU holding two workgroups would take twice as
+// long as the others (measured on the large workload: 1576 workgroups, 6 or 7
+// per CU, 44.5 us; 256, one per CU with 6 or 7 slices per wave, 42.6 us; 264
+// or 320, 54 and 65 us).  Each workgroup then walks its slices in rounds, and
+// in a round the 4 * num_cu slices in flight are consecutive per XCD, so the
+// lower-half reads of a block mostly follow its upper-half read closely.
+int pcg_spmv_groups(int N, int num_cu) {
   const int nslices = div_up(N, kSlice);
   int g = div_up(nslices, kSlicesPerGroup);
+  const int cap = num_cu >= 8 ? num_cu / 8 * 8 : 8;
+  if (g > cap) g = cap;
   if (g > kMaxSpmvParts) g = kMaxSpmvParts;
   return ((g + 7) / 8) * 8;
 }

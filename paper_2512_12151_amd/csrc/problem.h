@@ -14,6 +14,7 @@ using bfal::PcgSystem;
 
 struct bf_context {
   int device = 0;
+  int num_cu = 256;   // compute units of the device (grid sizing)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
@@ -115,7 +116,7 @@ inline PcgSystem system_of(bf_problem* pb) {
   S.part = pb->part.as<double>();
   S.sc = pb->scal.as<PcgScalars>();
   S.spmv_wg0 = 0;
-  S.spmv_nwg = pcg_spmv_groups(pb->N);
+  S.spmv_nwg = pcg_spmv_groups(pb->N, pb->ctx->num_cu);
   S.vec_wg0 = 0;
   S.vec_nwg = pcg_vec_groups(pb->N);
   return S;
