@@ -225,6 +225,73 @@ bf_status bf_energy(bf_problem* pb, double* energy_out, int32_t* inverted);
  * the first Newton step or call). */
 bf_status bf_mu_init(bf_problem* pb, double C, double* mu_out);
 
+/* ------------------------------------------- collisions (Algorithms 1 and 3) */
+/* The collision queries of the time step along the straight path from x (the
+ * intersection-free state of bf_set_state) to a target x_hat: every surface
+ * primitive pair -- point-triangle (a boundary vertex against a boundary
+ * triangle of the tet mesh not containing it) and edge-edge (two boundary
+ * edges without a common endpoint) -- whose swept boxes over both states come
+ * within delta (bf_set_constraints) of each other on every axis is tested by
+ * additive CCD (Li, Kaufman and Jiang 2021) in FP64 with separation ratio
+ * sep: the pair "collides" when the conservative time at which its distance
+ * would fall below sep times the initial one is below 1 (Section 5 uses a
+ * linear BVH broad phase and ACCD narrow phase; the tree here is built per
+ * call over FP32 boxes rounded outward, and every pair it reports is tested
+ * again exactly).  A pair at distance 0 at x collides at t = 0; a pair still
+ * stepping after 10^4 ACCD steps collides at the time reached.  The surface
+ * is extracted from the tets at the first call.  x_hat: NULL for the
+ * problem's current x_hat, else [N][3] FP64 in memory kind mem.  sep in
+ * (0, 1); 0 selects 0.1.  Requires bf_set_state and bf_set_constraints. */
+typedef struct {
+  int64_t candidates_pt, candidates_ee; /* pairs passing the exact swept-box test */
+  int32_t colliding_pt, colliding_ee;   /* of those, pairs whose collision time is below 1 */
+  int32_t new_pt, new_ee;               /* colliding pairs not in the active set, near-parallel edge pairs
+                                           excluded (update only) */
+  int32_t added_pt, added_ee;           /* new pairs kept by the earliest-time filter (update only) */
+  int32_t removed;                      /* constraints dropped for gamma < 0.01 (update only) */
+  int32_t n_pt, n_ee;                   /* size of the active set after the call */
+  double alpha_ccd;                     /* smallest collision time (1 if none) */
+  double alpha_inversion;               /* smallest inversion bound over the tets (1 if none) */
+  double ms_tree, ms_query, ms_update;  /* device time: BVH builds, queries with ACCD, set rebuild */
+} bf_ccd_stats;
+
+/* UpdateActiveSet (Algorithm 3): of the colliding pairs not already in the
+ * active set (compared by vertex sets), every vertex takes the earliest
+ * collision time T_v of the new pairs it belongs to, and a new pair is kept
+ * when its time equals T_v for one of its vertices; it enters with lambda = 0,
+ * gamma = 1.  An edge pair (near-)parallel at x (|e_a x e_b|^2 < 1e-8
+ * |e_a|^2 |e_b|^2, where the distance gradient is not unique and a Newton
+ * step would reject the constraint) does not enter the set and is not
+ * counted in new_ee; it still limits bf_max_step_size.  Constraints whose
+ * gamma fell below 0.01 are removed.  The new
+ * active set, device-resident, is: the surviving PT constraints in their
+ * order, the new PT pairs (p, t0 < t1 < t2) ordered by (p, triangle), the
+ * surviving EE constraints, the new EE pairs (a0 < a1, b0 < b1, edge a before
+ * edge b) ordered by (edge a, edge b).  kappa and delta stay.  bf_energy then
+ * needs a new Newton step. */
+bf_status bf_update_active_set(bf_problem* pb, const double* x_hat, int32_t mem, double sep, bf_ccd_stats* stats);
+
+/* MaxStepSize (Algorithm 1): *alpha = min(1, the smallest collision time of
+ * the colliding pairs, the smallest inversion bound), where a tet's inversion
+ * bound is the first t in (0, 1] with det D_s(t) = sep det D_s(0) along the
+ * path (the Neo-Hookean energy is non-invertible), found by bisection between
+ * the roots of the cubic's derivative. */
+bf_status bf_max_step_size(bf_problem* pb, const double* x_hat, int32_t mem, double sep, double* alpha,
+                           bf_ccd_stats* stats);
+
+/* Introspection for the parity tests: the colliding pairs of the last
+ * collision call (bf_update_active_set or bf_max_step_size), in no particular
+ * order -- PT rows (p, t0 < t1 < t2) and EE rows (a0 < a1, b0 < b1, edge a
+ * before edge b) with their collision times, host memory, sized by the
+ * call's colliding_pt / colliding_ee; NULL skips an array. */
+bf_status bf_get_collisions(bf_problem* pb, int32_t* pt, double* pt_toc, int32_t* ee, double* ee_toc);
+
+/* The active set: counts, then the arrays (PT rows [n_pt][4], EE rows
+ * [n_ee][4], lambda and gamma [n_pt + n_ee], PT first) in memory kind mem;
+ * NULL skips an array. */
+bf_status bf_get_constraint_counts(bf_problem* pb, int32_t* n_pt, int32_t* n_ee);
+bf_status bf_get_constraints(bf_problem* pb, int32_t* pt, int32_t* ee, double* lambda, double* gamma, int32_t mem);
+
 /* ---------------------------------------------------------------- serving */
 /* A server solves independent Newton-step requests (each: a mesh, its state
  * and its active constraint set; the same operation as bf_newton_step, FP32

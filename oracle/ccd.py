@@ -35,6 +35,10 @@ ACCD narrow phase (Section 5).  Readings (listed in the design doc):
     the roots of the cubic's derivative.
   * MaxStepSize is the smallest collision time over all candidate pairs and
     the smallest inversion bound over all tets, 1 if there is none.
+  * An edge pair that is (near-)parallel at x (|e_a x e_b|^2 < 1e-8 |e_a|^2
+    |e_b|^2, the test under which the linearization rejects a constraint) does
+    not enter the active set, before the earliest-time filter; it still limits
+    the step size.
 """
 from __future__ import annotations
 
@@ -80,19 +84,33 @@ def boxes_near(lo_a, hi_a, lo_b, hi_b, delta):
     return ok
 
 
+def _near_pairs(lo_a, hi_a, lo_b, hi_b, delta, upper=False, rows=1024):
+    """All (a, b) index pairs whose boxes are near (a < b only when upper),
+    in row-major order; all pairs are tested, a block of rows at a time."""
+    ia, ib = [], []
+    for r0 in range(0, len(lo_a), rows):
+        ok = boxes_near(lo_a[r0:r0 + rows], hi_a[r0:r0 + rows], lo_b, hi_b, delta)
+        a, b = np.nonzero(ok)
+        a = a + r0
+        if upper:
+            keep = b > a
+            a, b = a[keep], b[keep]
+        ia.append(a)
+        ib.append(b)
+    return np.concatenate(ia), np.concatenate(ib)
+
+
 def candidates(x0, x1, tris, edges, verts, delta):
     """Brute-force broad phase: PT rows (v, t0, t1, t2) and EE rows
     (a0, a1, b0, b1), each in canonical order (edge a before edge b)."""
     vlo, vhi = swept_boxes(x0, x1, verts[:, None])
     tlo, thi = swept_boxes(x0, x1, tris)
-    ok = boxes_near(vlo, vhi, tlo, thi, delta)
-    vi, ti = np.nonzero(ok)
+    vi, ti = _near_pairs(vlo, vhi, tlo, thi, delta)
     pt = np.column_stack([verts[vi], tris[ti]])
     share = (pt[:, 0] == pt[:, 1]) | (pt[:, 0] == pt[:, 2]) | (pt[:, 0] == pt[:, 3])
     pt = pt[~share]
     elo, ehi = swept_boxes(x0, x1, edges)
-    ok = boxes_near(elo, ehi, elo, ehi, delta)
-    ia, ib = np.nonzero(np.triu(ok, 1))
+    ia, ib = _near_pairs(elo, ehi, elo, ehi, delta, upper=True)
     ee = np.column_stack([edges[ia], edges[ib]])
     share = ((ee[:, 0] == ee[:, 2]) | (ee[:, 0] == ee[:, 3]) | (ee[:, 1] == ee[:, 2]) | (ee[:, 1] == ee[:, 3]))
     ee = ee[~share]
@@ -194,6 +212,16 @@ def colliding_pairs(x, xh, tris, edges, verts, delta, s=S_SEP):
     return out
 
 
+def ee_parallel(x, ee, tol=1e-8):
+    """|e_a x e_b|^2 < tol |e_a|^2 |e_b|^2 at x: the edge pairs whose distance
+    gradient is not unique (the linearization rejects them)."""
+    ee = np.asarray(ee, dtype=np.int64).reshape(-1, 4)
+    ea = x[ee[:, 1]] - x[ee[:, 0]]
+    eb = x[ee[:, 3]] - x[ee[:, 2]]
+    cr = np.cross(ea, eb)
+    return np.einsum("ij,ij->i", cr, cr) < tol * np.einsum("ij,ij->i", ea, ea) * np.einsum("ij,ij->i", eb, eb)
+
+
 def earliest_filter(n_nodes, pt, T_pt, ee, T_ee):
     """Algorithm 3's filter: T_v = min over the new pairs containing v; a pair
     stays when its time equals T_v for at least one of its vertices."""
@@ -215,6 +243,11 @@ def update_active_set(n_nodes, x, xh, tris, edges, verts, pt_c, ee_c, lam, gam, 
     gam).  Returns (pt', ee', lam', gam', info): surviving current constraints
     in their order, then the new ones (PT, then EE, each in canonical order)."""
     (pt, T_pt), (ee, T_ee) = colliding_pairs(x, xh, tris, edges, verts, delta, s)
+    n_coll = (len(pt), len(ee))
+    # an edge pair (near-)parallel at x has no unique distance gradient and
+    # cannot be linearized: it does not enter the set (it still limits the step)
+    ok = ~ee_parallel(x, ee)
+    ee, T_ee = ee[ok], T_ee[ok]
     # drop pairs already in the active set
     have_pt = {tuple(r) for r in canonical("pt", pt_c)}
     have_ee = {tuple(r) for r in canonical("ee", ee_c)}
@@ -232,7 +265,7 @@ def update_active_set(n_nodes, x, xh, tris, edges, verts, pt_c, ee_c, lam, gam, 
     ee_out = np.concatenate([np.asarray(ee_c, dtype=np.int64).reshape(-1, 4)[keep_ee], add_ee])
     lam_out = np.concatenate([lam[:n_pt][keep_pt], np.zeros(len(add_pt)), lam[n_pt:][keep_ee], np.zeros(len(add_ee))])
     gam_out = np.concatenate([gam[:n_pt][keep_pt], np.ones(len(add_pt)), gam[n_pt:][keep_ee], np.ones(len(add_ee))])
-    info = dict(colliding_pt=int(new_pt.size), colliding_ee=int(new_ee.size),
+    info = dict(colliding_pt=n_coll[0], colliding_ee=n_coll[1], parallel_ee=int((~ok).sum()),
                 new_pt=int(len(pt)), new_ee=int(len(ee)), added_pt=int(len(add_pt)), added_ee=int(len(add_ee)),
                 removed=int((~keep_pt).sum() + (~keep_ee).sum()))
     return pt_out, ee_out, lam_out, gam_out, info

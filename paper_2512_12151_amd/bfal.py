@@ -68,6 +68,17 @@ class bf_subproblem_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class bf_ccd_stats(C.Structure):
+    _fields_ = [("candidates_pt", C.c_int64), ("candidates_ee", C.c_int64), ("colliding_pt", C.c_int32),
+                ("colliding_ee", C.c_int32), ("new_pt", C.c_int32), ("new_ee", C.c_int32), ("added_pt", C.c_int32),
+                ("added_ee", C.c_int32), ("removed", C.c_int32), ("n_pt", C.c_int32), ("n_ee", C.c_int32),
+                ("alpha_ccd", C.c_double), ("alpha_inversion", C.c_double), ("ms_tree", C.c_double),
+                ("ms_query", C.c_double), ("ms_update", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class bf_server_opts(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int32), ("iters_per_round", C.c_int32),
                 ("admit_threads", C.c_int32)]
@@ -99,6 +110,12 @@ _PROTOS = [
                                       C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(bf_subproblem_stats)]),
     ("bf_energy", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     ("bf_mu_init", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double)]),
+    ("bf_update_active_set", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.POINTER(bf_ccd_stats)]),
+    ("bf_max_step_size", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double),
+                                   C.POINTER(bf_ccd_stats)]),
+    ("bf_get_collisions", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("bf_get_constraint_counts", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    ("bf_get_constraints", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     ("bf_clock_now", C.c_double, []),
     ("bf_server_create", C.c_int, [C.c_int32, C.POINTER(bf_server_opts), C.POINTER(C.c_void_p)]),
     ("bf_server_submit", C.c_int, [C.c_void_p, C.c_int64, C.POINTER(bf_mesh_desc), C.c_void_p, C.c_void_p,
@@ -250,6 +267,46 @@ class Problem:
         e, inv = C.c_double(), C.c_int32()
         self.ctx.check(lib().bf_energy(self.h, C.byref(e), C.byref(inv)))
         return float(e.value), bool(inv.value)
+
+    def update_active_set(self, x_hat=None, sep=0.1):
+        """Algorithm 3 along x -> x_hat (None: the problem's x_hat); returns the stats."""
+        st = bf_ccd_stats()
+        xp = None if x_hat is None else _ptr(x_hat)
+        mem = BF_MEM_HOST if x_hat is None else _mem(x_hat)
+        self.ctx.check(lib().bf_update_active_set(self.h, xp, mem, sep, C.byref(st)))
+        return st.as_dict()
+
+    def max_step_size(self, x_hat=None, sep=0.1):
+        """MaxStepSize along x -> x_hat; returns (alpha, stats)."""
+        st = bf_ccd_stats()
+        a = C.c_double()
+        xp = None if x_hat is None else _ptr(x_hat)
+        mem = BF_MEM_HOST if x_hat is None else _mem(x_hat)
+        self.ctx.check(lib().bf_max_step_size(self.h, xp, mem, sep, C.byref(a), C.byref(st)))
+        return float(a.value), st.as_dict()
+
+    def collisions(self, stats):
+        """The colliding pairs of the last collision call: (pt rows, pt times, ee rows, ee times)."""
+        npt, nee = stats["colliding_pt"], stats["colliding_ee"]
+        pt = np.empty((npt, 4), dtype=np.int32)
+        ee = np.empty((nee, 4), dtype=np.int32)
+        tp = np.empty(npt)
+        te = np.empty(nee)
+        self.ctx.check(lib().bf_get_collisions(self.h, pt.ctypes.data, tp.ctypes.data, ee.ctypes.data,
+                                               te.ctypes.data))
+        return pt, tp, ee, te
+
+    def constraints(self):
+        """The active set: (pt [n_pt,4], ee [n_ee,4], lambda, gamma) on the host."""
+        npt, nee = C.c_int32(), C.c_int32()
+        self.ctx.check(lib().bf_get_constraint_counts(self.h, C.byref(npt), C.byref(nee)))
+        pt = np.empty((npt.value, 4), dtype=np.int32)
+        ee = np.empty((nee.value, 4), dtype=np.int32)
+        lam = np.empty(npt.value + nee.value)
+        gam = np.empty(npt.value + nee.value)
+        self.ctx.check(lib().bf_get_constraints(self.h, pt.ctypes.data, ee.ctypes.data, lam.ctypes.data,
+                                                gam.ctypes.data, BF_MEM_HOST))
+        return pt, ee, lam, gam
 
     def mu_init(self, C_=0.1):
         """C max_i (grad^2 E)_ii at the start-of-step state x (Section 5.2)."""

@@ -314,7 +314,12 @@ void bf_problem_destroy(bf_problem* pb) {
                     &pb->sblk, &pb->sblk16, &pb->scol, &pb->sent, &pb->xs, &pb->r, &pb->p0, &pb->p1, &pb->q,
                     &pb->part, &pb->scal, &pb->pout, &pb->flags, &pb->scan_tmp, &pb->scratch_int,
                     &pb->xd, &pb->rd, &pb->zd, &pb->fcg, &pb->rpart, &pb->lin64, &pb->pdir, &pb->xtrial,
-                    &pb->epart};
+                    &pb->epart, &pb->stris, &pb->sedges, &pb->sverts, &pb->xq, &pb->tbox, &pb->tkey, &pb->tkey2,
+                    &pb->tchild, &pb->tparent, &pb->tnode, &pb->tarrive, &pb->ebox, &pb->ekey, &pb->ekey2,
+                    &pb->echild, &pb->eparent, &pb->enode, &pb->earrive, &pb->bpart, &pb->qcount, &pb->qpairs[0],
+                    &pb->qpairs[1], &pb->qtoc[0], &pb->qtoc[1], &pb->pkey, &pb->pkey2, &pb->pidx, &pb->pidx2,
+                    &pb->sort_tmp, &pb->ctmp, &pb->htable, &pb->tvmin, &pb->keepn[0], &pb->keepn[1], &pb->posn[0],
+                    &pb->posn[1], &pb->keepc, &pb->posc, &pb->nids, &pb->nlam, &pb->ngam, &pb->mpart};
   for (DevBuf* b : bufs) b->release();
   for (auto& e : pb->ev)
     if (e) (void)hipEventDestroy(e);
@@ -404,11 +409,23 @@ bf_status bf_set_constraints(bf_problem* pb, const bf_constraint_desc* cd, int32
     if (hflags) return flags_to_status(c, hflags);
   }
   HIPCHK(c, hipStreamSynchronize(s));
-  pb->n_pt = cd->n_pt;
-  pb->n_ee = cd->n_ee;
-  pb->n_c = n;
   pb->kappa = cd->kappa;
   pb->delta = cd->delta;
+  return size_constraint_buffers(pb, cd->n_pt, cd->n_ee);
+}
+
+}  // extern "C"
+
+namespace bfal {
+
+bf_status size_constraint_buffers(bf_problem* pb, int n_pt, int n_ee) {
+  bf_context* c = pb->ctx;
+  hipStream_t s = c->stream;
+  const int N = pb->N;
+  const int n = n_pt + n_ee;
+  pb->n_pt = n_pt;
+  pb->n_ee = n_ee;
+  pb->n_c = n;
   // size the per-step buffers for this constraint count
   const long long cap = (long long)pb->nnzb_e + 6LL * n;
   const long long capc = (long long)pb->nnzb_e - N + 6LL * n + 16;
@@ -466,6 +483,10 @@ bf_status bf_set_constraints(bf_problem* pb, const bf_constraint_desc* cd, int32
   c->err.clear();
   return BF_OK;
 }
+
+}  // namespace bfal
+
+extern "C" {
 
 bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, int32_t mem, bf_step_stats* stats) {
   if (!pb) return BF_ERR_INVALID_ARG;

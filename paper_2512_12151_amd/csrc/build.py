@@ -9,7 +9,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
-SOURCES = ["scan.hip", "setup.hip", "contact.hip", "elastic.hip", "assemble.hip", "pcg.hip", "subproblem.hip", "api.hip", "server.hip"]
+SOURCES = ["scan.hip", "setup.hip", "contact.hip", "elastic.hip", "assemble.hip", "pcg.hip", "subproblem.hip", "ccd.hip", "activeset.hip", "api.hip",
+           "server.hip"]
 OUT = os.path.join(PKG, "libbfal.so")
 
 FLAGS = [

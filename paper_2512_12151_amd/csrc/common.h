@@ -167,6 +167,43 @@ void launch_energy(const int4* tets, int T, const double* rest, const double* E,
                    const double* lin64, const double* xlin, const double* lam, const double* gam, double kappa,
                    double delta, double* part, int* inverted, hipStream_t s);
 void launch_state_axpy(int n3, const double* xa, double r, const double* p, double* xt, hipStream_t s);
+// ccd.hip: collision queries along x -> x_hat (boxes are 24-byte FP32 min/max).
+size_t ccd_sort_tmp_bytes(int n);
+hipError_t ccd_sort_pairs(void* tmp, size_t tmp_bytes, const unsigned long long* kin, unsigned long long* kout,
+                          const int* vin, int* vout, int n, hipStream_t s);
+size_t ccd_sort_keys_tmp_bytes(int n);
+hipError_t ccd_sort_keys(void* tmp, size_t tmp_bytes, const unsigned long long* kin, unsigned long long* kout, int n,
+                         hipStream_t s);
+void launch_prim_boxes(int n, const int* ids, int k, const double* x, const double* xh, void* box, hipStream_t s);
+int ccd_bounds_parts(int n);
+void launch_morton(int n, const void* box, void* part, unsigned long long* key, hipStream_t s);
+void launch_build_tree(int n, const unsigned long long* key, const void* pbox, int2* child, int* parent, void* node,
+                       int* arrive, hipStream_t s);
+void launch_query(bool ee, int nq, const int* qids, int nt, const int* tids, const int2* child, const void* node,
+                  const unsigned long long* key, const double* x, const double* xh, double delta, double sep,
+                  int* count, int cap, int2* pairs, double* toc, hipStream_t s);
+void launch_pair_keys(int n, const int2* pairs, unsigned long long* key, int* idx, hipStream_t s);
+void launch_hash_insert(int n_c, int n_pt, const int4* ids, int* table, unsigned int mask, hipStream_t s);
+void launch_fill_u64(unsigned long long* a, unsigned long long v, int n, hipStream_t s);
+void launch_pair_rows(int n, bool ee, const int2* pairs, const int* qids, const int* tids, int4* rows, hipStream_t s);
+void launch_new_and_tv(int n, bool ee, const int* order, const int2* pairs, const double* toc, const int* qids,
+                       const int* tids, int n_pt, const int4* cids, const int* table, unsigned int mask,
+                       const double* x, int* is_new, unsigned long long* tv, hipStream_t s);
+void launch_keep_new(int n, bool ee, const int* order, const int2* pairs, const double* toc, const int* qids,
+                     const int* tids, const unsigned long long* tv, int* keep, hipStream_t s);
+void launch_keep_current(int lo, int hi, const double* gam, double gmin, int* keep, hipStream_t s);
+void launch_scatter_current(int lo, int hi, const int* keep, const int* pos, int base, const int4* ids,
+                            const double* lam, const double* gam, int4* oids, double* olam, double* ogam,
+                            hipStream_t s);
+void launch_scatter_new(int n, bool ee, const int* keep, const int* pos, int base, const int* order,
+                        const int2* pairs, const int* qids, const int* tids, int4* oids, double* olam, double* ogam,
+                        hipStream_t s);
+int ccd_min_parts(int n);
+void launch_min_toc(int n, const double* toc, double* part, hipStream_t s);
+int inversion_parts(int T);
+void launch_inversion_bound(int T, const int4* tets, const double* x, const double* xh, double sep, double* part,
+                            hipStream_t s);
+
 int diag_max_parts(int N);
 void launch_diag_max(int N, const int* erow_ptr, const int* ecptr, const float* staging, const float* mass,
                      double* part, hipStream_t s);

@@ -47,6 +47,19 @@ struct bf_problem {
   long long cap_nnzb = 0, cap_cand = 0;
   long long nslot_u = 0, nslot_l = 0;   // slots of the sliced storage of the last step
   PcgScalars* host_sc = nullptr;
+  // collision queries: the surface (built at the first call), two BVHs, the
+  // colliding pairs and the active-set rebuild
+  bool surf_ready = false;
+  int nF = 0, nE = 0, nV = 0;
+  DevBuf stris, sedges, sverts;
+  DevBuf xq;
+  DevBuf tbox, tkey, tkey2, tchild, tparent, tnode, tarrive;
+  DevBuf ebox, ekey, ekey2, echild, eparent, enode, earrive;
+  DevBuf bpart, qcount, qpairs[2], qtoc[2], pkey, pkey2, pidx, pidx2, sort_tmp, ctmp;
+  DevBuf htable, tvmin, keepn[2], posn[2], keepc, posc, nids, nlam, ngam, mpart;
+  int qcap[2] = {0, 0};
+  int qhits[2] = {0, 0};   // colliding pairs of the last collision call (-1: none yet)
+  bool collided = false;
   bool stepped = false;
   bool last_breakdown = false;     // the last step's PCG stopped at p^T H p <= 0 (nothing else failed)
   long long nnzb_last = 0;
@@ -136,5 +149,8 @@ bf_status problem_init(bf_context* c, bf_problem* pb, const bf_mesh_desc* m, int
 // copy when bf16).  Enqueued on the context's stream; after it system_of(pb)
 // describes the step's PCG system.  Assembly errors are raised into pb->flags.
 bf_status step_assemble(bf_problem* pb, bool bf16);
+// Sets the constraint counts (PT first) and sizes every per-constraint and
+// per-step buffer for them; the constraint arrays themselves are the caller's.
+bf_status size_constraint_buffers(bf_problem* pb, int n_pt, int n_ee);
 
 }  // namespace bfal

@@ -284,6 +284,41 @@ def large(seed: int = 3, nxy: int = 50, nz: int = 30, blocks: int = 5, a: float 
                    fixed, x, x_hat, x.copy(), 0.01, pt, ee, lam, 1e5, 1e-3, 1e-5)
 
 
+def ccd_target(sc: dict, recipe: str, seed: int = 11) -> np.ndarray:
+    """A target state x_hat for the collision queries along x -> x_hat.
+
+    push       the upper cube of a two-cube stack (rest z > 1) 4 mm down into
+               the lower one, every free node jittered by N(0, 0.5 mm);
+    push_deep  the same, 0.3 down (through more than one cell layer), jitter 5 mm;
+    jitter     every free node moved by N(0, 0.3 mm) (the cubes' gaps are 0.01-1 mm);
+    layers     block b of the stacked blocks (rest z in [0.601 b, 0.601 b + 0.6])
+               1 mm * b down, so each interface (gap 0.6 mm) interpenetrates by
+               0.4 mm, jitter N(0, 0.1 mm);
+    static     x_hat = x.
+    Fixed nodes stay at x."""
+    rng = _rng(seed, "ccd_" + recipe)
+    x = sc["x"]
+    rest = sc["rest"]
+    xh = x.copy()
+    if recipe == "push":
+        xh += rng.normal(0.0, 5e-4, size=x.shape)
+        xh[rest[:, 2] > 1.0, 2] -= 0.004
+    elif recipe == "push_deep":
+        xh += rng.normal(0.0, 5e-3, size=x.shape)
+        xh[rest[:, 2] > 1.0, 2] -= 0.3
+    elif recipe == "jitter":
+        xh += rng.normal(0.0, 3e-4, size=x.shape)
+    elif recipe == "layers":
+        b = np.floor(rest[:, 2] / 0.601 + 1e-9)
+        xh += rng.normal(0.0, 1e-4, size=x.shape)
+        xh[:, 2] -= 1e-3 * b
+    elif recipe != "static":
+        raise ValueError(recipe)
+    fixed = sc["fixed"].astype(bool)
+    xh[fixed] = x[fixed]
+    return xh
+
+
 def serve_request(i: int):
     """One request of the serving stream: two stacked n^3 cubes, tets ~ LogU[2k, 300k]."""
     r = _rng(1000 + i, "size")
