@@ -184,6 +184,48 @@ def run_subproblem(args):
     return out
 
 
+def run_ccd(reps=5):
+    """The collision queries of Algorithms 1 and 3 on the large workload with
+    its blocks pushed 1 mm per layer into each other (target state on the
+    device): MaxStepSize and UpdateActiveSet (from the workload's own active
+    set, restored before every call), median of reps calls after one warm-up
+    call (which also extracts the surface, once per problem)."""
+    import torch
+
+    import scenes
+    from paper_2512_12151_amd import bfal
+    sc = scenes.make_scene("large")
+    xh = torch.from_numpy(scenes.ccd_target(sc, "layers")).to("cuda:0")
+    ctx = bfal.Context(0)
+    pb = bfal.Problem.from_scene(ctx, sc)
+    pb.max_step_size(xh)
+    ms_step, ms_upd, st_step, st_upd = [], [], None, None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        alpha, st_step = pb.max_step_size(xh)
+        ms_step.append((time.perf_counter() - t0) * 1e3)
+    for _ in range(reps):
+        pb.set_constraints(sc["pt"], sc["ee"], sc["lam"], sc["gamma"], sc["kappa"], sc["delta"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st_upd = pb.update_active_set(xh)
+        ms_upd.append((time.perf_counter() - t0) * 1e3)
+    pb.close()
+    ctx.close()
+    r = lambda v: round(float(v), 3)
+    return {"workload": "large, blocks pushed 1 mm per layer (0.4 mm interpenetration per interface)",
+            "surface": {"triangles": 110000, "edges": 165000, "vertices": 55010},
+            "max_step_size_ms": r(np.median(ms_step)), "alpha": alpha,
+            "update_active_set_ms": r(np.median(ms_upd)),
+            "device_ms": {"bvh_build": r(st_step["ms_tree"]), "query_accd": r(st_step["ms_query"]),
+                          "set_rebuild": r(st_upd["ms_update"])},
+            "candidates": [st_step["candidates_pt"], st_step["candidates_ee"]],
+            "colliding": [st_step["colliding_pt"], st_step["colliding_ee"]],
+            "added": [st_upd["added_pt"], st_upd["added_ee"]], "removed": st_upd["removed"],
+            "active_after": [st_upd["n_pt"], st_upd["n_ee"]]}
+
+
 def run_serve(n_req, seed=5, loads=(0.8, 1.2, 2.0)):
     """Serving (continuous batching) on a stream of two-stacked-cube requests
     (tets ~ LogU[2k, 300k]).  The one-at-a-time service time is measured first
@@ -253,6 +295,8 @@ def main():
                     help="PCG iteration cap (lower it only for counter-collection runs)")
     ap.add_argument("--no-subproblem", dest="subproblem", action="store_false",
                     help="skip the SolveSubproblem measurement (Newton loop with line search, multiplier update)")
+    ap.add_argument("--no-ccd", dest="ccd", action="store_false",
+                    help="skip the collision-query measurement (MaxStepSize, UpdateActiveSet)")
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving trace (0 skips the serving measurement)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -364,6 +408,9 @@ def main():
         line["subproblem"] = run_subproblem(args)
         line["subproblem"]["energy_eval_ms_" + args.workload] = round(t_energy, 3)
         log(f"subproblem: {line['subproblem']}")
+    if args.ccd:
+        line["ccd"] = run_ccd()
+        log(f"ccd: {line['ccd']}")
     if args.serve_requests > 0:
         line["serve"] = run_serve(args.serve_requests)
     if not args.no_cpu_baseline:
