@@ -91,6 +91,7 @@ bf_status ensure_sort_tmp(bf_problem* pb, int n) {
 // A BVH over n primitives of k vertices (ids AoS [n][k]).
 bf_status build_tree(bf_problem* pb, int n, const int* ids, int k, const double* xh, DevBuf& box, DevBuf& key,
                      DevBuf& key2, DevBuf& child, DevBuf& parent, DevBuf& node, DevBuf& arrive) {
+  // parent holds the internal nodes' leaf ranges, arrive the sparse table of run boxes
   bf_context* c = pb->ctx;
   hipStream_t s = c->stream;
   if (n == 0) return BF_OK;
@@ -98,9 +99,9 @@ bf_status build_tree(bf_problem* pb, int n, const int* ids, int k, const double*
   ALLOC(c, key, 8LL * n);
   ALLOC(c, key2, 8LL * n);
   ALLOC(c, child, 8LL * std::max(n - 1, 1));
-  ALLOC(c, parent, 8LL * n);
+  ALLOC(c, parent, 8LL * std::max(n - 1, 1));          // internal node leaf ranges
   ALLOC(c, node, 48LL * n);
-  ALLOC(c, arrive, 4LL * n);
+  ALLOC(c, arrive, 24LL * n * ccd_table_levels(n));    // sparse table of run boxes
   ALLOC(c, pb->bpart, 24LL * ccd_bounds_parts(n));
   launch_prim_boxes(n, ids, k, pb->x.as<double>(), xh, box.p, s);
   launch_morton(n, box.p, pb->bpart.p, key.as<unsigned long long>(), s);
@@ -108,8 +109,8 @@ bf_status build_tree(bf_problem* pb, int n, const int* ids, int k, const double*
   if (st != BF_OK) return st;
   HIPCHK(c, ccd_sort_keys(pb->sort_tmp.p, pb->sort_tmp.bytes, key.as<unsigned long long>(),
                           key2.as<unsigned long long>(), n, s));
-  launch_build_tree(n, key2.as<unsigned long long>(), box.p, child.as<int2>(), parent.as<int>(), node.p,
-                    arrive.as<int>(), s);
+  launch_build_tree(n, key2.as<unsigned long long>(), box.p, child.as<int2>(), parent.as<int2>(), node.p, arrive.p,
+                    s);
   return BF_OK;
 }
 

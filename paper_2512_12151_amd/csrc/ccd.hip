@@ -255,7 +255,7 @@ __device__ inline int common_prefix(const unsigned long long* key, int n, int i,
 // found by a binary search on the common-prefix length; children are internal
 // nodes or leaves (leaf k is node n - 1 + k).
 __global__ void k_karras(int n, const unsigned long long* __restrict__ key, int2* __restrict__ child,
-                         int* __restrict__ parent) {
+                         int2* __restrict__ range) {
   const int i = blockIdx.x * kCcdBlock + threadIdx.x;
   if (i >= n - 1) return;
   const int d = common_prefix(key, n, i, i + 1) - common_prefix(key, n, i, i - 1) >= 0 ? 1 : -1;
@@ -276,38 +276,49 @@ __global__ void k_karras(int n, const unsigned long long* __restrict__ key, int2
   const int left = (min(i, j) == g) ? (n - 1 + g) : g;
   const int right = (max(i, j) == g + 1) ? (n - 1 + g + 1) : g + 1;
   child[i] = make_int2(left, right);
-  parent[left] = i;
-  parent[right] = i;
+  range[i] = make_int2(min(i, j), max(i, j));
 }
 
-// Leaf boxes in sorted order, then every leaf walks up: the second thread to
-// reach an internal node (per-node counter) writes the union of its children.
-__global__ void k_refit(int n, const unsigned long long* __restrict__ key, const Box* __restrict__ pbox,
-                        const int2* __restrict__ child, const int* __restrict__ parent, Box* __restrict__ node,
-                        int* __restrict__ arrive) {
+// Node boxes without atomics: an internal node covers the contiguous range
+// [a, b] of sorted leaves, so its box is the union of two overlapping runs of
+// 2^m leaves (2^m <= b - a + 1 < 2^(m+1)), read from a sparse table whose
+// level k holds the union of the 2^k leaves starting at each position.
+__device__ inline Box box_union(const Box& a, const Box& b) {
+  Box u;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    u.lo[q] = fminf(a.lo[q], b.lo[q]);
+    u.hi[q] = fmaxf(a.hi[q], b.hi[q]);
+  }
+  return u;
+}
+
+// Level 0 of the table and the leaf nodes: the primitive boxes in key order.
+__global__ void k_leaf_boxes(int n, const unsigned long long* __restrict__ key, const Box* __restrict__ pbox,
+                             Box* __restrict__ level0, Box* __restrict__ node) {
   const int k = blockIdx.x * kCcdBlock + threadIdx.x;
   if (k >= n) return;
-  const int prim = (int)(key[k] & 0xffffffffu);
-  int v = n - 1 + k;
-  node[v] = pbox[prim];
-  if (n == 1) return;
-  v = parent[v];
-  while (true) {
-    __threadfence();
-    const int prev = __hip_atomic_fetch_add(&arrive[v], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == 0) return;   // the sibling subtree is not done yet
-    const int2 c = child[v];
-    const Box a = node[c.x], b = node[c.y];
-    Box u;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      u.lo[q] = fminf(a.lo[q], b.lo[q]);
-      u.hi[q] = fmaxf(a.hi[q], b.hi[q]);
-    }
-    node[v] = u;
-    if (v == 0) return;
-    v = parent[v];
-  }
+  const Box b = pbox[(int)(key[k] & 0xffffffffu)];
+  level0[k] = b;
+  node[n - 1 + k] = b;
+}
+
+// Level k from level k - 1 (run length h = 2^(k-1)): entries i + 2h <= n.
+__global__ void k_sparse_level(int n, int h, const Box* __restrict__ prev, Box* __restrict__ next) {
+  const int i = blockIdx.x * kCcdBlock + threadIdx.x;
+  if (i + 2 * h > n) return;
+  next[i] = box_union(prev[i], prev[i + h]);
+}
+
+__global__ void k_node_boxes(int n, const int2* __restrict__ range, const Box* __restrict__ table,
+                             Box* __restrict__ node) {
+  const int i = blockIdx.x * kCcdBlock + threadIdx.x;
+  if (i >= n - 1) return;
+  const int2 r = range[i];
+  const int len = r.y - r.x + 1;
+  const int m = 31 - __clz(len);
+  const Box* lv = table + (long long)m * n;
+  node[i] = box_union(lv[r.x], lv[r.y - (1 << m) + 1]);
 }
 
 // ------------------------------------------------------------ queries
@@ -719,14 +730,28 @@ void launch_morton(int n, const void* box, void* part, unsigned long long* key, 
                      static_cast<const Box*>(part), np, key);
 }
 
-void launch_build_tree(int n, const unsigned long long* key, const void* pbox, int2* child, int* parent, void* node,
-                       int* arrive, hipStream_t s) {
+int ccd_table_levels(int n) {
+  int L = 1;
+  while ((2LL << (L - 1)) <= n) ++L;   // levels 0 .. L-1 with 2^(L-1) <= n
+  return L;
+}
+
+void launch_build_tree(int n, const unsigned long long* key, const void* pbox, int2* child, int2* range, void* node,
+                       void* table, hipStream_t s) {
   if (n <= 0) return;
-  if (n > 1)
-    hipLaunchKernelGGL(k_karras, dim3(div_up(n - 1, kCcdBlock)), dim3(kCcdBlock), 0, s, n, key, child, parent);
-  fill_int(arrive, 0, n, s);
-  hipLaunchKernelGGL(k_refit, dim3(div_up(n, kCcdBlock)), dim3(kCcdBlock), 0, s, n, key,
-                     static_cast<const Box*>(pbox), child, parent, static_cast<Box*>(node), arrive);
+  Box* T = static_cast<Box*>(table);
+  hipLaunchKernelGGL(k_leaf_boxes, dim3(div_up(n, kCcdBlock)), dim3(kCcdBlock), 0, s, n, key,
+                     static_cast<const Box*>(pbox), T, static_cast<Box*>(node));
+  if (n == 1) return;
+  hipLaunchKernelGGL(k_karras, dim3(div_up(n - 1, kCcdBlock)), dim3(kCcdBlock), 0, s, n, key, child, range);
+  const int L = ccd_table_levels(n);
+  for (int k = 1; k < L; ++k) {
+    const int h = 1 << (k - 1);
+    hipLaunchKernelGGL(k_sparse_level, dim3(div_up(n - 2 * h + 1, kCcdBlock)), dim3(kCcdBlock), 0, s, n, h,
+                       T + (long long)(k - 1) * n, T + (long long)k * n);
+  }
+  hipLaunchKernelGGL(k_node_boxes, dim3(div_up(n - 1, kCcdBlock)), dim3(kCcdBlock), 0, s, n, range, T,
+                     static_cast<Box*>(node));
 }
 
 void launch_query(bool ee, int nq, const int* qids, int nt, const int* tids, const int2* child, const void* node,

@@ -177,8 +177,9 @@ hipError_t ccd_sort_keys(void* tmp, size_t tmp_bytes, const unsigned long long* 
 void launch_prim_boxes(int n, const int* ids, int k, const double* x, const double* xh, void* box, hipStream_t s);
 int ccd_bounds_parts(int n);
 void launch_morton(int n, const void* box, void* part, unsigned long long* key, hipStream_t s);
-void launch_build_tree(int n, const unsigned long long* key, const void* pbox, int2* child, int* parent, void* node,
-                       int* arrive, hipStream_t s);
+int ccd_table_levels(int n);
+void launch_build_tree(int n, const unsigned long long* key, const void* pbox, int2* child, int2* range, void* node,
+                       void* table, hipStream_t s);
 void launch_query(bool ee, int nq, const int* qids, int nt, const int* tids, const int2* child, const void* node,
                   const unsigned long long* key, const double* x, const double* xh, double delta, double sep,
                   int* count, int cap, int2* pairs, double* toc, hipStream_t s);
