@@ -258,7 +258,8 @@ typedef struct {
 /* UpdateActiveSet (Algorithm 3): of the colliding pairs not already in the
  * active set (compared by vertex sets), every vertex takes the earliest
  * collision time T_v of the new pairs it belongs to, and a new pair is kept
- * when its time equals T_v for one of its vertices; it enters with lambda = 0,
+ * when its time equals T_v for one of its vertices (up to the times' FP64
+ * rounding: T_i <= T_v (1 + 1e-9)); it enters with lambda = 0,
  * gamma = 1.  An edge pair (near-)parallel at x (|e_a x e_b|^2 < 1e-8
  * |e_a|^2 |e_b|^2, where the distance gradient is not unique and a Newton
  * step would reject the constraint) does not enter the set and is not
@@ -291,6 +292,51 @@ bf_status bf_get_collisions(bf_problem* pb, int32_t* pt, double* pt_toc, int32_t
  * NULL skips an array. */
 bf_status bf_get_constraint_counts(bf_problem* pb, int32_t* n_pt, int32_t* n_ee);
 bf_status bf_get_constraints(bf_problem* pb, int32_t* pt, int32_t* ee, double* lambda, double* gamma, int32_t mem);
+
+/* ---------------------------------------------------------- time step */
+/* One time step (Algorithm 1, Section 4.1) from the problem's state: x = x^t
+ * (intersection free), x_hat = x_hat^[0] (x^t with the moving-boundary nodes
+ * at their targets, Section 5.3), x_tilde and h from bf_set_state, the active
+ * set of bf_set_constraints (or of the previous step).  Repeats
+ *   x_hat <- SolveSubproblem (bf_solve_subproblem: Newton steps with the line
+ *            search until a full step, then the multiplier / decay update),
+ *   C     <- UpdateActiveSet along x -> the subproblem's input x_hat
+ *            (bf_update_active_set),
+ *   alpha <- MaxStepSize along x -> the new x_hat (bf_max_step_size),
+ *   x     <- (1 - alpha) x + alpha x_hat,
+ *   beta  <- (1 - alpha) beta once k + 1 >= k_min,
+ * while beta > eps (Section 6: eps = 1e-3, k_min = 2).  Section 5.2: with
+ * mu_init_c > 0 the penalty starts at mu_init_c max_i (grad^2 E)_ii
+ * (bf_mu_init; the paper uses 0.1), and whenever alpha stays below 1e-4 for
+ * 50 consecutive iterations kappa doubles and delta halves.  On return the
+ * problem holds x^{t+1}, the last x_hat and the active set with its
+ * multipliers; x_out and v_out = (x^{t+1} - x^t) / h ([N][3] FP64, kind mem,
+ * nullable) receive the state.  Returns BF_WARN_PCG_MAXITER when max_outer
+ * ends the loop (or a Newton step's PCG warned), errors of the calls above
+ * otherwise. */
+typedef struct {
+  bf_solve_opts solve;  /* the Newton steps' linear solves */
+  int32_t k_min;        /* K_min >= 1 */
+  double eps;           /* termination threshold on beta, in (0, 1) */
+  int32_t max_outer;    /* cap on the iterations, >= 1 */
+  int32_t max_newton;   /* Newton steps per subproblem, >= 1 */
+  double decay;         /* Gamma of the constraint decay, in (0, 1] */
+  double sep;           /* ACCD separation ratio (0 selects 0.1) */
+  double mu_init_c;     /* > 0: start from mu_init_c max_i (grad^2 E)_ii; 0 keeps kappa */
+} bf_time_step_opts;
+
+typedef struct {
+  int32_t outer_iters, newton_iters, pcg_iters, truncated;
+  double beta;          /* final cumulative weight of x^t */
+  double alpha_min, alpha_last;
+  int32_t n_pt, n_ee;   /* active set at the end */
+  int32_t mu_doublings;
+  double kappa, delta;  /* at the end */
+  double ms_subproblem, ms_ccd, ms_total;   /* device time of the subproblems and collision calls; wall time */
+} bf_time_step_stats;
+
+bf_status bf_time_step(bf_problem* pb, const bf_time_step_opts* o, double* x_out, double* v_out, int32_t mem,
+                       bf_time_step_stats* stats);
 
 /* ---------------------------------------------------------------- serving */
 /* A server solves independent Newton-step requests (each: a mesh, its state

@@ -35,6 +35,10 @@ ACCD narrow phase (Section 5).  Readings (listed in the design doc):
     the roots of the cubic's derivative.
   * MaxStepSize is the smallest collision time over all candidate pairs and
     the smallest inversion bound over all tets, 1 if there is none.
+  * "The earliest collision time" of a vertex is taken up to the times' own
+    rounding: a pair is kept when T_i <= T_v (1 + 1e-9).  Pairs of a rigidly
+    moving structured mesh are tied in exact arithmetic, and two FP64 ACCD
+    codes place such ties 1e-16..1e-10 apart in either order.
   * An edge pair that is (near-)parallel at x (|e_a x e_b|^2 < 1e-8 |e_a|^2
     |e_b|^2, the test under which the linearization rejects a constraint) does
     not enter the active set, before the earliest-time filter; it still limits
@@ -50,6 +54,7 @@ S_SEP = 0.1          # ACCD separation ratio
 STEP_FRAC = 0.9      # ACCD step safety factor after the first step
 MAX_ACCD_ITERS = 10_000   # steps per pair; a pair still running counts as colliding at the time reached
 GAMMA_REMOVE = 0.01  # Algorithm 3: constraints with gamma below this are removed
+TIE_REL = 1e-9       # a time within this relative distance of T_v counts as T_v
 
 
 # ------------------------------------------------------------------ surface --
@@ -224,7 +229,8 @@ def ee_parallel(x, ee, tol=1e-8):
 
 def earliest_filter(n_nodes, pt, T_pt, ee, T_ee):
     """Algorithm 3's filter: T_v = min over the new pairs containing v; a pair
-    stays when its time equals T_v for at least one of its vertices."""
+    stays when its time equals T_v for at least one of its vertices, equality
+    taken up to the times' own rounding (T_i <= T_v (1 + 1e-9))."""
     Tv = np.full(n_nodes, np.inf)
     for ids, T in ((pt, T_pt), (ee, T_ee)):
         for a in range(4):
@@ -233,7 +239,7 @@ def earliest_filter(n_nodes, pt, T_pt, ee, T_ee):
     for ids, T in ((pt, T_pt), (ee, T_ee)):
         k = np.zeros(len(ids), dtype=bool)
         for a in range(4):
-            k |= Tv[ids[:, a]] == T
+            k |= T <= Tv[ids[:, a]] * (1.0 + TIE_REL)
         keep.append(k)
     return keep
 

@@ -79,6 +79,22 @@ class bf_ccd_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class bf_time_step_opts(C.Structure):
+    _fields_ = [("solve", bf_solve_opts), ("k_min", C.c_int32), ("eps", C.c_double), ("max_outer", C.c_int32),
+                ("max_newton", C.c_int32), ("decay", C.c_double), ("sep", C.c_double), ("mu_init_c", C.c_double)]
+
+
+class bf_time_step_stats(C.Structure):
+    _fields_ = [("outer_iters", C.c_int32), ("newton_iters", C.c_int32), ("pcg_iters", C.c_int32),
+                ("truncated", C.c_int32), ("beta", C.c_double), ("alpha_min", C.c_double),
+                ("alpha_last", C.c_double), ("n_pt", C.c_int32), ("n_ee", C.c_int32), ("mu_doublings", C.c_int32),
+                ("kappa", C.c_double), ("delta", C.c_double), ("ms_subproblem", C.c_double),
+                ("ms_ccd", C.c_double), ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class bf_server_opts(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int32), ("iters_per_round", C.c_int32),
                 ("admit_threads", C.c_int32)]
@@ -113,6 +129,8 @@ _PROTOS = [
     ("bf_update_active_set", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.POINTER(bf_ccd_stats)]),
     ("bf_max_step_size", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double),
                                    C.POINTER(bf_ccd_stats)]),
+    ("bf_time_step", C.c_int, [C.c_void_p, C.POINTER(bf_time_step_opts), C.c_void_p, C.c_void_p, C.c_int32,
+                               C.POINTER(bf_time_step_stats)]),
     ("bf_get_collisions", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("bf_get_constraint_counts", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     ("bf_get_constraints", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
@@ -284,6 +302,20 @@ class Problem:
         mem = BF_MEM_HOST if x_hat is None else _mem(x_hat)
         self.ctx.check(lib().bf_max_step_size(self.h, xp, mem, sep, C.byref(a), C.byref(st)))
         return float(a.value), st.as_dict()
+
+    def time_step(self, tol=1e-7, max_iter=50000, k_min=2, eps=1e-3, max_outer=200, max_newton=20, decay=0.9,
+                  sep=0.1, mu_init_c=0.0, poll_every=16):
+        """Algorithm 1 from the current state; returns (x, v, stats, status) on the host."""
+        o = bf_time_step_opts()
+        o.solve = bf_solve_opts(tol, max_iter, BF_PREC_FP32, 1e-6, poll_every, 1, 0, 0)
+        o.k_min, o.eps, o.max_outer, o.max_newton = k_min, eps, max_outer, max_newton
+        o.decay, o.sep, o.mu_init_c = decay, sep, mu_init_c
+        x = np.empty((self.N, 3))
+        v = np.empty((self.N, 3))
+        st = bf_time_step_stats()
+        status = self.ctx.check(lib().bf_time_step(self.h, C.byref(o), x.ctypes.data, v.ctypes.data, BF_MEM_HOST,
+                                                   C.byref(st)))
+        return x, v, st.as_dict(), status
 
     def collisions(self, stats):
         """The colliding pairs of the last collision call: (pt rows, pt times, ee rows, ee times)."""

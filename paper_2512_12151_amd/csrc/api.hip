@@ -319,7 +319,8 @@ void bf_problem_destroy(bf_problem* pb) {
                     &pb->echild, &pb->eparent, &pb->enode, &pb->earrive, &pb->bpart, &pb->qcount, &pb->qpairs[0],
                     &pb->qpairs[1], &pb->qtoc[0], &pb->qtoc[1], &pb->pkey, &pb->pkey2, &pb->pidx, &pb->pidx2,
                     &pb->sort_tmp, &pb->ctmp, &pb->htable, &pb->tvmin, &pb->keepn[0], &pb->keepn[1], &pb->posn[0],
-                    &pb->posn[1], &pb->keepc, &pb->posc, &pb->nids, &pb->nlam, &pb->ngam, &pb->mpart};
+                    &pb->posn[1], &pb->keepc, &pb->posc, &pb->nids, &pb->nlam, &pb->ngam, &pb->mpart,
+                    &pb->xstart, &pb->xprev, &pb->vout};
   for (DevBuf* b : bufs) b->release();
   for (auto& e : pb->ev)
     if (e) (void)hipEventDestroy(e);

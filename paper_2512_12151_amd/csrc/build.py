@@ -9,7 +9,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
-SOURCES = ["scan.hip", "setup.hip", "contact.hip", "elastic.hip", "assemble.hip", "pcg.hip", "subproblem.hip", "ccd.hip", "activeset.hip", "api.hip",
+SOURCES = ["scan.hip", "setup.hip", "contact.hip", "elastic.hip", "assemble.hip", "pcg.hip", "subproblem.hip", "ccd.hip", "activeset.hip", "timestep.hip", "api.hip",
            "server.hip"]
 OUT = os.path.join(PKG, "libbfal.so")
 

@@ -23,7 +23,8 @@
 // The active-set update then keeps, of the colliding pairs not already
 // constrained, those whose time is the earliest of one of their vertices
 // (per-vertex atomicMin over the FP64 bit patterns, which order like the
-// values for t >= 0), sorts them into a canonical order, and rebuilds the
+// values for t >= 0; "earliest" up to 1e-9 relative, the times' rounding),
+// sorts them into a canonical order, and rebuilds the
 // constraint arrays: surviving current PT constraints (gamma >= 0.01, in
 // their order), new PT pairs, surviving current EE constraints, new EE pairs.
 #include <hipcub/hipcub.hpp>
@@ -547,8 +548,10 @@ __global__ void k_keep_new(int n, bool ee, const int* __restrict__ order, const 
   if (!keep[i]) return;   // holds is_new on entry
   const int o = order[i];
   const int4 id = pair_ids(ee, pairs[o], qids, tids);
-  const unsigned long long b = (unsigned long long)__double_as_longlong(toc[o]);
-  keep[i] = (tv[id.x] == b || tv[id.y] == b || tv[id.z] == b || tv[id.w] == b) ? 1 : 0;
+  // the earliest time of a vertex, up to the times' own rounding
+  const double t = toc[o];
+  auto earliest = [&](int v) { return t <= __longlong_as_double((long long)tv[v]) * (1.0 + 1e-9); };
+  keep[i] = (earliest(id.x) || earliest(id.y) || earliest(id.z) || earliest(id.w)) ? 1 : 0;
 }
 
 __global__ void k_keep_current(int lo, int hi, const double* __restrict__ gam, double gmin, int* __restrict__ keep) {

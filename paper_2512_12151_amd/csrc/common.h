@@ -205,6 +205,8 @@ int inversion_parts(int T);
 void launch_inversion_bound(int T, const int4* tets, const double* x, const double* xh, double sep, double* part,
                             hipStream_t s);
 
+void launch_blend(int n3, double* x, const double* xh, double alpha, hipStream_t s);
+void launch_velocity(int n3, const double* x, const double* x0, double inv_h, double* v, hipStream_t s);
 int diag_max_parts(int N);
 void launch_diag_max(int N, const int* erow_ptr, const int* ecptr, const float* staging, const float* mass,
                      double* part, hipStream_t s);

@@ -57,6 +57,7 @@ struct bf_problem {
   DevBuf ebox, ekey, ekey2, echild, eparent, enode, earrive;
   DevBuf bpart, qcount, qpairs[2], qtoc[2], pkey, pkey2, pidx, pidx2, sort_tmp, ctmp;
   DevBuf htable, tvmin, keepn[2], posn[2], keepc, posc, nids, nlam, ngam, mpart;
+  DevBuf xstart, xprev, vout;   // time step: x^t, the subproblem's input x_hat, the velocity
   int qcap[2] = {0, 0};
   int qhits[2] = {0, 0};   // colliding pairs of the last collision call (-1: none yet)
   bool collided = false;

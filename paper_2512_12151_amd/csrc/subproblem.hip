@@ -216,7 +216,28 @@ k_diag_max(int N, const int* __restrict__ erow_ptr, const int* __restrict__ ecpt
   }
 }
 
+// x += alpha (x_hat - x): the next intersection-free state (Algorithm 1).
+__global__ void __launch_bounds__(kEBlock)
+k_blend(int n3, double* __restrict__ x, const double* __restrict__ xh, double alpha) {
+  const int i = blockIdx.x * kEBlock + threadIdx.x;
+  if (i < n3) x[i] = (1.0 - alpha) * x[i] + alpha * xh[i];
+}
+
+__global__ void __launch_bounds__(kEBlock)
+k_velocity(int n3, const double* __restrict__ x, const double* __restrict__ x0, double inv_h, double* __restrict__ v) {
+  const int i = blockIdx.x * kEBlock + threadIdx.x;
+  if (i < n3) v[i] = (x[i] - x0[i]) * inv_h;
+}
+
 }  // namespace
+
+void launch_blend(int n3, double* x, const double* xh, double alpha, hipStream_t s) {
+  hipLaunchKernelGGL(k_blend, dim3(div_up(n3, kEBlock)), dim3(kEBlock), 0, s, n3, x, xh, alpha);
+}
+
+void launch_velocity(int n3, const double* x, const double* x0, double inv_h, double* v, hipStream_t s) {
+  hipLaunchKernelGGL(k_velocity, dim3(div_up(n3, kEBlock)), dim3(kEBlock), 0, s, n3, x, x0, inv_h, v);
+}
 
 int energy_parts(int T, int n_c) { return div_up(T, kEBlock) + div_up(n_c, kEBlock); }
 

@@ -1,3 +1,3 @@
 """Seeded synthetic inputs (meshes, states, constraint sets); no solver arithmetic."""
-from .configs import ccd_target, digest, large, make_scene, medium, serve_request, tiny  # noqa: F401
+from .configs import bar, ccd_target, digest, falling_cubes, large, make_scene, medium, serve_request, tiny  # noqa: F401
 from .mesh import boundary_faces, face_edges, kuhn_box, kuhn_cube  # noqa: F401

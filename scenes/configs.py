@@ -284,6 +284,44 @@ def large(seed: int = 3, nxy: int = 50, nz: int = 30, blocks: int = 5, a: float 
                    fixed, x, x_hat, x.copy(), 0.01, pt, ee, lam, 1e5, 1e-3, 1e-5)
 
 
+def bar(nx: int = 8, n: int = 2, a: float = 0.1, stretch: float = 1.1, dt: float = 100.0):
+    """A bar of nx x n x n cells (spacing a) along x, E = 1e4, nu = 0, rho = 1000;
+    both end faces are moving-boundary nodes, the far one (x = nx a) moved to
+    stretch * nx a in x_hat^[0]; x = x_tilde = rest, no constraints.  With
+    nu = 0 the static solution is the homogeneous stretch (stretch X, Y, Z),
+    and with dt = 100 s the inertia term is ~1e-7 of the elastic one."""
+    rest, tets = kuhn_box(nx, n, n, a)
+    N, T = len(rest), len(tets)
+    L = nx * a
+    fixed = ((np.abs(rest[:, 0]) < 1e-12) | (np.abs(rest[:, 0] - L) < 1e-12)).astype(np.uint8)
+    x = rest.copy()
+    x_hat = x.copy()
+    far = np.abs(rest[:, 0] - L) < 1e-12
+    x_hat[far, 0] = stretch * L
+    return _finish("bar", 0, rest, tets, np.full(T, 1e4), np.zeros(T), np.full(T, 1000.0), fixed, x, x_hat,
+                   x.copy(), dt, np.zeros((0, 4)), np.zeros((0, 4)), np.zeros(0), 1e4, 1e-3, 1e-8)
+
+
+def falling_cubes(v: float = -0.5, dt: float = 0.01, n: int = 4, lateral=(0.37, 0.21), jitter: float = 0.0,
+                  seed: int = 6):
+    """The two-cube stack (1 mm gap, bottom face of the lower cube fixed) with
+    the upper cube moving down at v m/s: x_tilde = x + dt v on its nodes, so
+    one step of 5 mm would cross the gap; x_hat^[0] = x; no constraints yet.
+    jitter > 0 moves every free node of x by N(0, jitter) first, so that no two
+    contact pairs are tied in collision time."""
+    a, rest, tets, n_lo, top, bot, _ = _stack_two_cubes(n, 1e-3, lateral)
+    N, T = len(rest), len(tets)
+    fixed = np.zeros(N, dtype=np.uint8)
+    fixed[:n_lo][rest[:n_lo, 2] == 0.0] = 1
+    x = rest.copy()
+    if jitter > 0.0:
+        x += _rng(seed, "jitter").normal(0.0, jitter, size=x.shape) * (1 - fixed)[:, None]
+    xt = x.copy()
+    xt[n_lo:, 2] += dt * v
+    return _finish("falling_cubes", 0, rest, tets, np.full(T, 1e5), np.full(T, 0.4), np.full(T, 1000.0), fixed, x,
+                   x.copy(), xt, dt, np.zeros((0, 4)), np.zeros((0, 4)), np.zeros(0), 1e4, 1e-3, 1e-8)
+
+
 def ccd_target(sc: dict, recipe: str, seed: int = 11) -> np.ndarray:
     """A target state x_hat for the collision queries along x -> x_hat.
 

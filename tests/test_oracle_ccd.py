@@ -148,6 +148,16 @@ def pushed_state(sc, depth=0.004, noise=0.0005, seed=3):
     return np.where(sc["fixed"][:, None] == 1, sc["x"], xh)
 
 
+def test_earliest_filter_keeps_ties_up_to_rounding():
+    """Two pairs at one vertex whose times differ only by rounding are both
+    its earliest; a pair 1e-6 later is not."""
+    pt = np.array([[0, 1, 2, 3], [0, 4, 5, 6], [0, 7, 8, 9]])
+    T = np.array([0.5, 0.5 * (1 + 1e-12), 0.5 * (1 + 1e-6)])
+    pt[1:, 1:] = [[1, 2, 3], [1, 2, 3]]            # the later pairs share all of A's vertices
+    kpt, _ = ccd.earliest_filter(10, pt, T, np.zeros((0, 4), np.int64), np.zeros(0))
+    assert list(kpt) == [True, True, False]
+
+
 def test_update_active_set_bookkeeping():
     """Two stacked cubes, the upper one pushed into the lower: new pairs enter
     with lambda 0, gamma 1; a pair already in the set is not added again; a
