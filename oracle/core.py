@@ -117,15 +117,93 @@ def nh_dP(F, dF, mu, lam):
             + (lam * tr)[:, None, None] * FinvT)
 
 
-def nh_hessian9(F, mu, lam):
+# Stable Neo-Hookean (reading: the rest-stable form of Smith, de Goes and Kim,
+# "Analytic Eigensystems for Isotropic Distortion Energies", 2019; the paper
+# names SNH in Table 2 without printing it):
+#   Psi = mu/2 (tr F^T F - 3) - mu (J - 1) + lam/2 (J - 1)^2.
+
+def snh_energy(F, mu, lam):
+    J = np.linalg.det(F)
+    I1 = np.einsum("tij,tij->t", F, F)
+    return 0.5 * mu * (I1 - 3.0) - mu * (J - 1.0) + 0.5 * lam * (J - 1.0) ** 2
+
+
+def _cof(F):
+    """Cofactor matrix dJ/dF = J F^{-T}."""
+    J = np.linalg.det(F)
+    return J[:, None, None] * np.transpose(np.linalg.inv(F), (0, 2, 1))
+
+
+def snh_stress(F, mu, lam):
+    """P = mu F + (lam (J - 1) - mu) cof(F)."""
+    J = np.linalg.det(F)
+    return mu[:, None, None] * F + (lam * (J - 1.0) - mu)[:, None, None] * _cof(F)
+
+
+def snh_dP(F, dF, mu, lam):
+    """mu dF + lam (cof F : dF) cof F + (lam (J - 1) - mu) d(cof F)[dF], with
+    d(cof F)[dF] = J (tr(F^{-1} dF) F^{-T} - F^{-T} dF^T F^{-T})."""
+    J = np.linalg.det(F)
+    Finv = np.linalg.inv(F)
+    FinvT = np.transpose(Finv, (0, 2, 1))
+    C = J[:, None, None] * FinvT
+    dFT = np.transpose(dF, (0, 2, 1))
+    tr = np.einsum("tij,tji->t", Finv, dF)
+    dC = J[:, None, None] * (tr[:, None, None] * FinvT - FinvT @ dFT @ FinvT)
+    return (mu[:, None, None] * dF + (lam * np.einsum("tij,tij->t", C, dF))[:, None, None] * C
+            + (lam * (J - 1.0) - mu)[:, None, None] * dC)
+
+
+# Materials per tet: 0 Neo-Hookean, 1 stable Neo-Hookean.  Both energies need
+# J > 0 here (the solver keeps every tet uninverted).
+
+def _mat(mat, T):
+    return np.zeros(T, dtype=np.int64) if mat is None else np.asarray(mat, dtype=np.int64)
+
+
+def psi_energy(F, mu, lam, mat=None):
+    m = _mat(mat, len(F))
+    J = np.linalg.det(F)
+    if np.any(J <= 0):
+        raise ValueError("inverted element (J <= 0)")
+    out = np.empty(len(F))
+    for code, fn in ((0, nh_energy), (1, snh_energy)):
+        k = m == code
+        if k.any():
+            out[k] = fn(F[k], mu[k], lam[k])
+    return out
+
+
+def psi_stress(F, mu, lam, mat=None):
+    m = _mat(mat, len(F))
+    out = np.empty_like(F)
+    for code, fn in ((0, nh_stress), (1, snh_stress)):
+        k = m == code
+        if k.any():
+            out[k] = fn(F[k], mu[k], lam[k])
+    return out
+
+
+def psi_dP(F, dF, mu, lam, mat=None):
+    m = _mat(mat, len(F))
+    out = np.empty_like(F)
+    for code, fn in ((0, nh_dP), (1, snh_dP)):
+        k = m == code
+        if k.any():
+            out[k] = fn(F[k], dF[k], mu[k], lam[k])
+    return out
+
+
+def nh_hessian9(F, mu, lam, mat=None):
     """d^2 Psi / dF^2 as a 9x9 matrix over row-major vec(F) (index 3i+j <-> F_ij),
-    built column by column from the directional derivative, then symmetrized."""
+    built column by column from the directional derivative, then symmetrized
+    (per tet of its material; Neo-Hookean when mat is None)."""
     T = len(F)
     H = np.empty((T, 9, 9))
     for k in range(9):
         E = np.zeros((T, 3, 3))
         E[:, k // 3, k % 3] = 1.0
-        H[:, :, k] = nh_dP(F, E, mu, lam).reshape(T, 9)
+        H[:, :, k] = psi_dP(F, E, mu, lam, mat).reshape(T, 9)
     return 0.5 * (H + np.transpose(H, (0, 2, 1)))
 
 
@@ -149,14 +227,16 @@ def dF_map(A):
     return B
 
 
-def elastic_terms(xh, tets, Dminv, vol, A, mu, lam, h):
+def elastic_terms(xh, tets, Dminv, vol, A, mu, lam, h, mat=None):
     """Per-element gradient h^2 V P A_a^T [T,4,3] and PSD-projected Hessian
     h^2 V B^T (d2Psi/dF2)^+ B [T,12,12]."""
     F = deformation_gradient(xh, tets, Dminv)
-    P = nh_stress(F, mu, lam)
+    if np.any(np.linalg.det(F) <= 0):
+        raise ValueError("inverted element (J <= 0)")
+    P = psi_stress(F, mu, lam, mat)
     w = h * h * vol
     g = w[:, None, None] * np.einsum("tij,taj->tai", P, A)
-    H9p = psd_project(nh_hessian9(F, mu, lam))
+    H9p = psd_project(nh_hessian9(F, mu, lam, mat))
     B = dF_map(A)
     He = w[:, None, None] * (np.transpose(B, (0, 2, 1)) @ H9p @ B)
     return g, He
@@ -324,6 +404,7 @@ def prepare(scene):
     st.tets = scene["tets"].astype(np.int64)
     st.Dminv, st.vol, st.A = rest_geometry(scene["rest"], st.tets)
     st.mu_l, st.lam_l = lame(scene["E"], scene["nu"])
+    st.mat = np.asarray(scene.get("material", np.zeros(len(scene["tets"]))), dtype=np.int64)
     st.mass = lumped_mass(st.N, st.tets, st.vol, scene["rho"])
     st.fixed = scene["fixed"].astype(bool)
     return st
@@ -343,7 +424,7 @@ def assemble(scene, st=None):
     cols.append(diag)
     vals.append(np.repeat(st.mass, 3))
     # elasticity
-    ge, He = elastic_terms(xh, st.tets, st.Dminv, st.vol, st.A, st.mu_l, st.lam_l, h)
+    ge, He = elastic_terms(xh, st.tets, st.Dminv, st.vol, st.A, st.mu_l, st.lam_l, h, st.mat)
     np.add.at(G, st.tets.ravel(), ge.reshape(-1, 3))
     dof = (3 * st.tets[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 12)
     rows.append(np.repeat(dof, 12, axis=1).ravel())
@@ -391,7 +472,7 @@ def total_energy(scene, st, xh):
     h = scene["dt"]
     F = deformation_gradient(xh, st.tets, st.Dminv)
     Ei = 0.5 * np.sum(st.mass[:, None] * (xh - scene["x_tilde"]) ** 2)
-    Ee = h * h * np.sum(st.vol * nh_energy(F, st.mu_l, st.lam_l))
+    Ee = h * h * np.sum(st.vol * psi_energy(F, st.mu_l, st.lam_l, st.mat))
     ids, d, nrm, w = linearize(scene["x"], scene["pt"], scene["ee"])
     c = constraint_values(xh, scene["x"], ids, d, nrm, w, scene["delta"])
     Ec = np.sum(al_energy(c, scene["lam"], scene["gamma"], scene["kappa"]))

@@ -78,7 +78,7 @@ def hessian_diagonal(scene, st, xs):
     the lumped mass plus the diagonal of every element's SPD-projected
     h^2 V B^T (d2Psi/dF2)^+ B (the matrix the Newton step assembles)."""
     diag = np.repeat(st.mass, 3).astype(np.float64)
-    _, He = core.elastic_terms(xs, st.tets, st.Dminv, st.vol, st.A, st.mu_l, st.lam_l, scene["dt"])
+    _, He = core.elastic_terms(xs, st.tets, st.Dminv, st.vol, st.A, st.mu_l, st.lam_l, scene["dt"], st.mat)
     dof = (3 * st.tets[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 12)
     np.add.at(diag, dof.ravel(), np.diagonal(He, axis1=1, axis2=2).ravel())
     return diag

@@ -172,11 +172,13 @@ def _stack_two_cubes(n, gap, lateral=(0.0, 0.0)):
     return a, nodes, tets, len(lo), top, bot, n_surf
 
 
-def tiny(seed: int = 1, lateral=(0.0, 0.0), n: int = 4, n_pt: int = 25, n_ee: int = 40):
+def tiny(seed: int = 1, lateral=(0.0, 0.0), n: int = 4, n_pt: int = 25, n_ee: int = 40, material=None):
     """Two stacked unit cubes (4^3 cells each), upper cube 1e-3 above the lower.
 
     `lateral` shifts the upper cube sideways (in cells) so that point-triangle
-    pairs also fall in the triangle interior; the default is the plain stack."""
+    pairs also fall in the triangle interior; the default is the plain stack.
+    `material`: None (Neo-Hookean), "snh" (stable Neo-Hookean everywhere) or
+    "mixed" (the upper cube stable Neo-Hookean)."""
     a, rest, tets, n_lo, top, bot, _ = _stack_two_cubes(n, 1e-3, lateral)
     N, T = len(rest), len(tets)
     fixed = np.zeros(N, dtype=np.uint8)
@@ -186,8 +188,14 @@ def tiny(seed: int = 1, lateral=(0.0, 0.0), n: int = 4, n_pt: int = 25, n_ee: in
     x_hat = x + noise * (1 - fixed)[:, None]
     pt, ee = _pick(x, [(top, bot)], n_pt, n_ee)
     lam = _rng(seed, "lambda").uniform(0.0, 100.0, size=len(pt) + len(ee))
+    extra = None
+    if material is not None:
+        mat = np.ones(T, dtype=np.int32) if material == "snh" else np.zeros(T, dtype=np.int32)
+        if material == "mixed":
+            mat[len(tets) // 2:] = 1
+        extra = {"material": mat}
     return _finish("tiny", seed, rest, tets, np.full(T, 1e5), np.full(T, 0.4), np.full(T, 1000.0),
-                   fixed, x, x_hat, x.copy(), 0.01, pt, ee, lam, 1e4, 1e-3, 1e-8)
+                   fixed, x, x_hat, x.copy(), 0.01, pt, ee, lam, 1e4, 1e-3, 1e-8, extra)
 
 
 def medium(seed: int = 2, nx: int = 4, ny: int = 5, n: int = 10, n_pt: int = 12000, n_ee: int = 8000):

@@ -248,3 +248,77 @@ def test_inverted_element_raises():
     mu, lam = mats(1)
     with pytest.raises(ValueError):
         oracle.nh_stress(F, mu, lam)
+
+
+# ---------------------------------------------------------------- stable Neo-Hookean
+
+def _rand_F(rng, n, scale=0.3):
+    F = np.eye(3)[None] + scale * rng.standard_normal((n, 3, 3))
+    F = F[np.linalg.det(F) > 0.2]
+    return F
+
+
+def test_snh_rest_and_uniform_scaling():
+    mu, lam = np.array([3.0]), np.array([7.0])
+    I = np.eye(3)[None]
+    assert oracle.core.snh_energy(I, mu, lam)[0] == 0.0
+    assert np.abs(oracle.core.snh_stress(I, mu, lam)).max() < 1e-15
+    for s_ in (0.7, 1.0, 1.3):
+        F = s_ * I
+        ref = 1.5 * 3.0 * (s_ ** 2 - 1) - 3.0 * (s_ ** 3 - 1) + 0.5 * 7.0 * (s_ ** 3 - 1) ** 2
+        assert oracle.core.snh_energy(F, mu, lam)[0] == pytest.approx(ref, rel=1e-13, abs=1e-14)
+
+
+def test_snh_stress_and_hessian_are_derivatives():
+    rng = np.random.default_rng(21)
+    F = _rand_F(rng, 20)
+    n = len(F)
+    mu, lam = rng.uniform(1, 5, n), rng.uniform(1, 20, n)
+    P = oracle.core.snh_stress(F, mu, lam)
+    eps = 1e-6
+    for k in range(9):
+        E = np.zeros((n, 3, 3))
+        E[:, k // 3, k % 3] = 1.0
+        fd = (oracle.core.snh_energy(F + eps * E, mu, lam) - oracle.core.snh_energy(F - eps * E, mu, lam)) / (2 * eps)
+        assert np.allclose(fd, P[:, k // 3, k % 3], rtol=1e-7, atol=1e-7)
+        dP = oracle.core.snh_dP(F, E, mu, lam)
+        fdP = (oracle.core.snh_stress(F + eps * E, mu, lam) - oracle.core.snh_stress(F - eps * E, mu, lam)) / (2 * eps)
+        assert np.allclose(fdP, dP, rtol=1e-6, atol=1e-6)
+
+
+def test_snh_rotation_invariance():
+    rng = np.random.default_rng(22)
+    F = _rand_F(rng, 10)
+    n = len(F)
+    mu, lam = np.full(n, 2.0), np.full(n, 9.0)
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    R = Q * np.sign(np.linalg.det(Q))
+    RF = R[None] @ F
+    assert np.allclose(oracle.core.snh_energy(RF, mu, lam), oracle.core.snh_energy(F, mu, lam), rtol=1e-12)
+    assert np.allclose(oracle.core.snh_stress(RF, mu, lam), R[None] @ oracle.core.snh_stress(F, mu, lam), atol=1e-12)
+
+
+def test_snh_analytic_eigensystem_matches_the_numeric_hessian():
+    """The closed forms the element kernel uses, derived for Psi = m(sigma) +
+    g(J) with q = J g'(J), r = J^2 g''(J) (SNH: q = J (lam (J - 1) - mu),
+    r = lam J^2): the 3x3 Hessian in the singular values has diagonal
+    mu + r / s_i^2 and off-diagonal (r + q) / (s_i s_j); the pair modes are
+    mu + q / (s_i s_j) and mu - q / (s_i s_j).  Their nine values equal the
+    eigenvalues of the oracle's 9x9 d2Psi/dF2."""
+    rng = np.random.default_rng(23)
+    F = _rand_F(rng, 30, 0.4)
+    n = len(F)
+    mu, lam = rng.uniform(1, 5, n), rng.uniform(1, 20, n)
+    H9 = oracle.core.nh_hessian9(F, mu, lam, np.ones(n))
+    for e in range(n):
+        s_ = np.linalg.svd(F[e], compute_uv=False)
+        J = np.linalg.det(F[e])
+        q = J * (lam[e] * (J - 1) - mu[e])
+        r = lam[e] * J * J
+        Hs = np.array([[mu[e] + r / s_[i] ** 2 if i == j else (r + q) / (s_[i] * s_[j]) for j in range(3)]
+                       for i in range(3)])
+        vals = list(np.linalg.eigvalsh(Hs))
+        for i, j in ((0, 1), (0, 2), (1, 2)):
+            vals += [mu[e] + q / (s_[i] * s_[j]), mu[e] - q / (s_[i] * s_[j])]
+        num = np.linalg.eigvalsh(H9[e])
+        assert np.allclose(np.sort(vals), num, rtol=1e-9, atol=1e-9 * np.abs(num).max())
