@@ -25,7 +25,8 @@ BF_PREC_FP32, BF_PREC_BF16_REFINE = 0, 1
 
 class bf_mesh_desc(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("n_tets", C.c_int32), ("tets", C.c_void_p), ("rest", C.c_void_p),
-                ("E", C.c_void_p), ("nu", C.c_void_p), ("rho", C.c_void_p), ("fixed", C.c_void_p)]
+                ("E", C.c_void_p), ("nu", C.c_void_p), ("rho", C.c_void_p), ("fixed", C.c_void_p),
+                ("material", C.c_void_p)]
 
 
 class bf_constraint_desc(C.Structure):
@@ -219,22 +220,27 @@ def _host(a, dtype):
 class Problem:
     """One mesh on one context: state, constraints, Newton steps, introspection."""
 
-    def __init__(self, ctx: Context, tets, rest, E, nu, rho, fixed=None):
+    def __init__(self, ctx: Context, tets, rest, E, nu, rho, fixed=None, material=None):
+        """material: per-tet codes, 0 Neo-Hookean and 1 stable Neo-Hookean (None: all 0)."""
         self.ctx = ctx
         dev = not isinstance(tets, np.ndarray)
         if not dev:
             tets, rest = _host(tets, np.int32), _host(rest, np.float64)
             E, nu, rho = _host(E, np.float64), _host(nu, np.float64), _host(rho, np.float64)
             fixed = None if fixed is None else _host(fixed, np.uint8)
+            material = None if material is None else _host(material, np.int32)
+        elif any(isinstance(a, np.ndarray) for a in (rest, E, nu, rho, fixed, material)):
+            raise TypeError("device meshes take every array on the device")
         self.N, self.T = int(rest.shape[0]), int(tets.shape[0])
-        d = bf_mesh_desc(self.N, self.T, _ptr(tets), _ptr(rest), _ptr(E), _ptr(nu), _ptr(rho), _ptr(fixed))
+        d = bf_mesh_desc(self.N, self.T, _ptr(tets), _ptr(rest), _ptr(E), _ptr(nu), _ptr(rho), _ptr(fixed),
+                         _ptr(material))
         self.h = C.c_void_p()
         ctx.check(lib().bf_problem_create(ctx.h, C.byref(d), BF_MEM_DEVICE if dev else BF_MEM_HOST, C.byref(self.h)))
         self.n_c = 0
 
     @classmethod
     def from_scene(cls, ctx, sc):
-        pb = cls(ctx, sc["tets"], sc["rest"], sc["E"], sc["nu"], sc["rho"], sc["fixed"])
+        pb = cls(ctx, sc["tets"], sc["rest"], sc["E"], sc["nu"], sc["rho"], sc["fixed"], sc.get("material"))
         pb.set_state(sc["x"], sc["x_hat"], sc["x_tilde"], sc["dt"])
         pb.set_constraints(sc["pt"], sc["ee"], sc["lam"], sc["gamma"], sc["kappa"], sc["delta"])
         return pb

@@ -36,6 +36,8 @@ bf_status problem_init(bf_context* c, bf_problem* pb, const bf_mesh_desc* m, int
       if (!(m->E[e] > 0.0) || !std::isfinite(m->E[e]) || !(m->nu[e] > -1.0 && m->nu[e] < 0.5) ||
           !(m->rho[e] > 0.0) || !std::isfinite(m->rho[e]))
         return fail(c, BF_ERR_INVALID_ARG, "invalid material value");
+      if (m->material && m->material[e] != 0 && m->material[e] != 1)
+        return fail(c, BF_ERR_INVALID_ARG, "material code must be 0 (Neo-Hookean) or 1 (stable Neo-Hookean)");
     }
     if (!finite_all(m->rest, 3LL * N)) return fail(c, BF_ERR_INVALID_ARG, "non-finite rest position");
   }
@@ -64,6 +66,11 @@ bf_status problem_init(bf_context* c, bf_problem* pb, const bf_mesh_desc* m, int
   HIPCHK(c, hipMemcpyAsync(pb->E.p, m->E, 8LL * T, kind_in(mem), s));
   HIPCHK(c, hipMemcpyAsync(pb->nu.p, m->nu, 8LL * T, kind_in(mem), s));
   HIPCHK(c, hipMemcpyAsync(pb->rho.p, m->rho, 8LL * T, kind_in(mem), s));
+  pb->has_mat = m->material != nullptr;
+  if (pb->has_mat) {
+    ALLOC(c, pb->mat, 4LL * T);
+    HIPCHK(c, hipMemcpyAsync(pb->mat.p, m->material, 4LL * T, kind_in(mem), s));
+  }
   if (m->fixed) {
     HIPCHK(c, hipMemcpyAsync(pb->fixed.p, m->fixed, N, kind_in(mem), s));
   } else {
@@ -181,7 +188,7 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
   const float h2 = (float)(pb->dt * pb->dt);
   launch_elastic(pb->tets.as<int4>(), T, pb->rest.as<double>(), pb->xh.as<double>(), pb->Dminv9.as<float>(),
                  pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), h2, pb->epos.as<int>(),
-                 pb->staging.as<float>(), flags, s);
+                 pb->staging.as<float>(), pb->has_mat ? pb->mat.as<int>() : nullptr, flags, s);
   launch_assemble_rows(N, row_ptr, pb->col.as<int>(), pb->eslot.as<int>(), pb->ecptr.as<int>(), pb->staging.as<float>(),
                        vptr, pb->vinc.as<int>(), ids, n, pb->cn.as<float>(), pb->cw.as<float>(), pb->cg.as<float>(),
                        pb->ch.as<float>(), pb->mass.as<float>(), pb->xh.as<double>(), pb->xt.as<double>(),
@@ -320,7 +327,7 @@ void bf_problem_destroy(bf_problem* pb) {
                     &pb->qpairs[1], &pb->qtoc[0], &pb->qtoc[1], &pb->pkey, &pb->pkey2, &pb->pidx, &pb->pidx2,
                     &pb->sort_tmp, &pb->ctmp, &pb->htable, &pb->tvmin, &pb->keepn[0], &pb->keepn[1], &pb->posn[0],
                     &pb->posn[1], &pb->keepc, &pb->posc, &pb->nids, &pb->nlam, &pb->ngam, &pb->mpart,
-                    &pb->xstart, &pb->xprev, &pb->vout};
+                    &pb->xstart, &pb->xprev, &pb->vout, &pb->mat};
   for (DevBuf* b : bufs) b->release();
   for (auto& e : pb->ev)
     if (e) (void)hipEventDestroy(e);
@@ -799,7 +806,7 @@ bf_status energy_at(bf_problem* pb, const double* xs, double* L, int* inv) {
   launch_energy(pb->tets.as<int4>(), pb->T, pb->rest.as<double>(), pb->E.as<double>(), pb->nu.as<double>(),
                 pb->rho.as<double>(), pb->dt, xs, pb->xt.as<double>(), pb->cids.as<int4>(), pb->n_c,
                 pb->lin64.as<double>(), pb->x.as<double>(), pb->clam.as<double>(), pb->cgam.as<double>(), pb->kappa,
-                pb->delta, part, flag, s);
+                pb->delta, pb->has_mat ? pb->mat.as<int>() : nullptr, part, flag, s);
   launch_sum_to(part, np, part + np, s);
   // part[np] = the sum, part[np + 2] holds the inversion flag (an int)
   double h[3] = {0.0, 0.0, 0.0};
@@ -843,7 +850,7 @@ bf_status bf_mu_init(bf_problem* pb, double C, double* mu_out) {
   // staging buffer (the next Newton step overwrites it)
   launch_elastic(pb->tets.as<int4>(), T, pb->rest.as<double>(), pb->x.as<double>(), pb->Dminv9.as<float>(),
                  pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), (float)(pb->dt * pb->dt),
-                 pb->epos.as<int>(), pb->staging.as<float>(), flags, s);
+                 pb->epos.as<int>(), pb->staging.as<float>(), pb->has_mat ? pb->mat.as<int>() : nullptr, flags, s);
   const int np = diag_max_parts(N);
   ALLOC(c, pb->epart, 8LL * (np + 8));
   launch_diag_max(N, pb->erow_ptr.as<int>(), pb->ecptr.as<int>(), pb->staging.as<float>(), pb->mass.as<float>(),

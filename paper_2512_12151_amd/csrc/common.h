@@ -165,7 +165,7 @@ int energy_parts(int T, int n_c);
 void launch_energy(const int4* tets, int T, const double* rest, const double* E, const double* nu,
                    const double* rho, double h, const double* x, const double* xt, const int4* ids, int n_c,
                    const double* lin64, const double* xlin, const double* lam, const double* gam, double kappa,
-                   double delta, double* part, int* inverted, hipStream_t s);
+                   double delta, const int* mat, double* part, int* inverted, hipStream_t s);
 void launch_state_axpy(int n3, const double* xa, double r, const double* p, double* xt, hipStream_t s);
 // ccd.hip: collision queries along x -> x_hat (boxes are 24-byte FP32 min/max).
 size_t ccd_sort_tmp_bytes(int n);
@@ -217,7 +217,7 @@ void launch_dual_update(const int4* ids, int n_c, const double* lin64, const dou
 // elastic.hip
 void launch_elastic(const int4* tets, int T, const double* rest, const double* xh, const float* Dminv9,
                     const float* vol, const float* mu, const float* lam, float h2, const int* epos,
-                    float* staging, int* flags, hipStream_t s);
+                    float* staging, const int* mat, int* flags, hipStream_t s);
 
 // assemble.hip
 void launch_assemble_rows(int N, const int* row_ptr, const int* col, const int* eslot, const int* ecptr,

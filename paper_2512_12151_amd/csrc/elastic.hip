@@ -1,4 +1,5 @@
-// Neo-Hookean element kernel: one thread per tet.
+// Hyperelastic element kernel (Neo-Hookean or stable Neo-Hookean per tet):
+// one thread per tet.
 //
 // Per tet it forms F (from FP64 displacement differences, then FP32), the
 // stress P, the element gradient h^2 V P A_a^T, and the ten upper 3x3 blocks
@@ -16,11 +17,21 @@
 // singular-value pair.  Blocks are written to the fixed assembly order
 // (staging position of each (tet, pair)), so no atomics touch the matrix.
 //
-// Energy (reading of the paper, which names Neo-Hookean without printing it):
-//   Psi = mu/2 (tr F^T F - 3) - mu ln J + lam/2 (ln J)^2.
+// Energies (readings of the paper, which names both materials in Table 2
+// without printing them), Psi = mu/2 (tr F^T F - 3) + g(J):
+//   Neo-Hookean         g = -mu ln J + lam/2 (ln J)^2
+//   stable Neo-Hookean  g = -mu (J - 1) + lam/2 (J - 1)^2   (rest-stable form of
+//                       Smith, de Goes and Kim 2019)
 // Cancellation-free forms near rest: with G = F - I,
 //   J - 1 = tr G + ((tr G)^2 - tr(G^2))/2 + det G,  ln J = log1p(J - 1),
-//   P = F^{-T} [ mu (G + G^T + G^T G) + lam ln J I ].
+//   Neo-Hookean  P = F^{-T} [ mu (G + G^T + G^T G) + lam ln J I ],
+//   stable NH    P = mu (G + G^T - tr(G) I - cof G) + lam (J - 1) cof F
+// (the second from cof(I + G) = (1 + tr G) I - G^T + cof G).
+// With q = J g'(J) and r = J^2 g''(J) the Hessian of Psi in the singular
+// values is mu I + diag(r / S_i^2) off-diagonal (r + q) / (S_i S_j), and the
+// twist / flip eigenvalues of pair (i, j) are mu +- q / (S_i S_j):
+//   Neo-Hookean  q = lam ln J - mu,          r = mu + lam - lam ln J
+//   stable NH    q = J (lam (J - 1) - mu),  r = lam J^2.
 #include "common.h"
 
 namespace bfal {
@@ -77,6 +88,19 @@ __device__ inline float det3(const float M[3][3]) {
 // S from a Givens QR of F V (McAdams et al. 2011, "Computing the singular
 // value decomposition of 3x3 matrices with minimal branching and elementary
 // floating point operations", steps: symmetric eigenanalysis, sorting, QR).
+// Cofactor matrix of M (d det M / dM).
+__device__ inline void cof3(const float M[3][3], float C[3][3]) {
+  C[0][0] = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+  C[0][1] = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+  C[0][2] = M[1][0] * M[2][1] - M[1][1] * M[2][0];
+  C[1][0] = M[0][2] * M[2][1] - M[0][1] * M[2][2];
+  C[1][1] = M[0][0] * M[2][2] - M[0][2] * M[2][0];
+  C[1][2] = M[0][1] * M[2][0] - M[0][0] * M[2][1];
+  C[2][0] = M[0][1] * M[1][2] - M[0][2] * M[1][1];
+  C[2][1] = M[0][2] * M[1][0] - M[0][0] * M[1][2];
+  C[2][2] = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+}
+
 __device__ inline void svd3(const float F[3][3], float U[3][3], float S[3], float V[3][3]) {
   float A[3][3];
 #pragma unroll
@@ -144,7 +168,7 @@ __global__ void __launch_bounds__(kBlock)
 k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest, const double* __restrict__ xh,
           const float* __restrict__ Dminv9, const float* __restrict__ vol, const float* __restrict__ mu_,
           const float* __restrict__ lam_, float h2, const int* __restrict__ epos, float* __restrict__ staging,
-          int* flags) {
+          const int* __restrict__ mat, int* flags) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= T) return;
   const int4 t = tets[e];
@@ -192,32 +216,42 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
     return;
   }
   const float mu = mu_[e], lam = lam_[e];
-  const float lnJ = log1pf(Jm1);
-  // P = F^{-T} Sp with Sp = mu (G + G^T + G^T G) + lam lnJ I; F^{-T} = cof(F) / J
-  float Sp[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const float gtg = Gm[0][i] * Gm[0][j] + Gm[1][i] * Gm[1][j] + Gm[2][i] * Gm[2][j];
-      Sp[i][j] = mu * (Gm[i][j] + Gm[j][i] + gtg) + (i == j ? lam * lnJ : 0.f);
-    }
+  const bool snh = mat != nullptr && mat[e] == 1;
   float C[3][3];
-  C[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
-  C[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
-  C[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
-  C[1][0] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
-  C[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
-  C[1][2] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
-  C[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
-  C[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
-  C[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
-  const float iJ = 1.f / J;
-  float P[3][3];
+  cof3(F, C);
+  float P[3][3], q, r, rq;
+  if (snh) {
+    float Cg[3][3];
+    cof3(Gm, Cg);
+    const float trG = Gm[0][0] + Gm[1][1] + Gm[2][2];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) P[i][j] = (C[i][0] * Sp[0][j] + C[i][1] * Sp[1][j] + C[i][2] * Sp[2][j]) * iJ;
+      for (int j = 0; j < 3; ++j)
+        P[i][j] = mu * (Gm[i][j] + Gm[j][i] - (i == j ? trG : 0.f) - Cg[i][j]) + lam * Jm1 * C[i][j];
+    q = J * (lam * Jm1 - mu);
+    r = lam * J * J;
+    rq = r + q;
+  } else {
+    const float lnJ = log1pf(Jm1);
+    // P = F^{-T} Sp with Sp = mu (G + G^T + G^T G) + lam lnJ I; F^{-T} = cof(F) / J
+    float Sp[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const float gtg = Gm[0][i] * Gm[0][j] + Gm[1][i] * Gm[1][j] + Gm[2][i] * Gm[2][j];
+        Sp[i][j] = mu * (Gm[i][j] + Gm[j][i] + gtg) + (i == j ? lam * lnJ : 0.f);
+      }
+    const float iJ = 1.f / J;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) P[i][j] = (C[i][0] * Sp[0][j] + C[i][1] * Sp[1][j] + C[i][2] * Sp[2][j]) * iJ;
+    q = lam * lnJ - mu;
+    r = mu + lam - lam * lnJ;
+    rq = lam;
+  }
   // rows A_a (A_1..A_3 = rows of Dm^{-1}, A_0 = -their sum)
   float A[4][3];
 #pragma unroll
@@ -228,15 +262,14 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
   // SVD and the analytic eigensystem
   float U[3][3], S[3], V[3][3];
   svd3(F, U, S, V);
-  const float lnJs = lnJ;
   float Ah[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-      Ah[i][j] = (i == j) ? mu + (mu + lam - lam * lnJs) / (S[i] * S[i]) : lam / (S[i] * S[j]);
-  if (mu - lam * lnJs < 0.f) {
-    // Ah = mu I + (mu - lam lnJ) diag(1/S^2) + lam s s^T can be indefinite only here: clamp its eigenvalues
+    for (int j = 0; j < 3; ++j) Ah[i][j] = (i == j) ? mu + r / (S[i] * S[i]) : rq / (S[i] * S[j]);
+  if (q > 0.f || rq < 0.f) {
+    // Ah = mu I + diag(1/S) (-q I + (r + q) 1 1^T) diag(1/S) is PSD when -q >= 0 and r + q >= 0;
+    // otherwise it may be indefinite: clamp its eigenvalues
     float E3[3][3], Q[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -255,8 +288,8 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const float ss = S[pi[k]] * S[pj[k]];
-    const float wt = fmaxf(mu + (lam * lnJs - mu) / ss, 0.f);
-    const float wf = fmaxf(mu + (mu - lam * lnJs) / ss, 0.f);
+    const float wt = fmaxf(mu + q / ss, 0.f);
+    const float wf = fmaxf(mu - q / ss, 0.f);
     c1[k] = 0.5f * (wt + wf);
     c2[k] = 0.5f * (wf - wt);
   }
@@ -319,10 +352,10 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
 
 void launch_elastic(const int4* tets, int T, const double* rest, const double* xh, const float* Dminv9,
                     const float* vol, const float* mu, const float* lam, float h2, const int* epos, float* staging,
-                    int* flags, hipStream_t s) {
+                    const int* mat, int* flags, hipStream_t s) {
   if (T > 0)
     hipLaunchKernelGGL(k_elastic, dim3(div_up(T, kBlock)), dim3(kBlock), 0, s, tets, T, rest, xh, Dminv9, vol, mu,
-                       lam, h2, epos, staging, flags);
+                       lam, h2, epos, staging, mat, flags);
 }
 
 }  // namespace bfal

@@ -24,7 +24,8 @@ struct bf_problem {
   bf_context* ctx = nullptr;
   int N = 0, T = 0;
   // mesh (per-mesh setup)
-  DevBuf tets, rest, E, nu, rho, fixed, Dminv9, vol, mu, lam, mass;
+  DevBuf tets, rest, E, nu, rho, fixed, Dminv9, vol, mu, lam, mass, mat;
+  bool has_mat = false;   // per-tet material codes present (else all Neo-Hookean)
   int nnzb_e = 0;
   DevBuf erow_ptr, ecol, emap, ecptr, elist, epos, staging;
   // state

@@ -124,7 +124,7 @@ bf_status prepare(bf_server* sv, bf_context* c, int si, Request* r) {
   bf_problem* pb = sl.pb;
   pb->ctx = c;
   bf_mesh_desc m{r->N, r->T, r->tets.data(), r->rest.data(), r->E.data(), r->nu.data(), r->rho.data(),
-                 r->fixed.empty() ? nullptr : r->fixed.data()};
+                 r->fixed.empty() ? nullptr : r->fixed.data(), nullptr};
   bf_status st = problem_init(c, pb, &m, BF_MEM_HOST);
   if (st != BF_OK) return st;
   st = bf_set_state(pb, r->x.data(), r->xh.data(), r->xt.data(), r->dt, BF_MEM_HOST);

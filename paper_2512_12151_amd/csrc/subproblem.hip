@@ -67,7 +67,8 @@ k_energy(const int4* __restrict__ tets, int T, const double* __restrict__ rest, 
          const double* __restrict__ nu, const double* __restrict__ rho, double h2, const double* __restrict__ x,
          const double* __restrict__ xt, const int4* __restrict__ ids, int n_c, const double* __restrict__ lin64,
          const double* __restrict__ xlin, const double* __restrict__ lam, const double* __restrict__ gam,
-         double kappa, double delta, int tet_groups, double* __restrict__ part, int* inverted) {
+         double kappa, double delta, int tet_groups, const int* __restrict__ mat, double* __restrict__ part,
+         int* inverted) {
   double e = 0.0;
   if ((int)blockIdx.x < tet_groups) {
     const int k = blockIdx.x * kEBlock + threadIdx.x;
@@ -112,8 +113,13 @@ k_energy(const int4* __restrict__ tets, int T, const double* __restrict__ rest, 
         for (int i = 0; i < 3; ++i)
 #pragma unroll
           for (int j = 0; j < 3; ++j) I1 += F[i][j] * F[i][j];
-        const double lnJ = log(J);
-        const double psi = 0.5 * mu * (I1 - 3.0) - mu * lnJ + 0.5 * la * lnJ * lnJ;
+        double psi;
+        if (mat != nullptr && mat[k] == 1) {
+          psi = 0.5 * mu * (I1 - 3.0) - mu * (J - 1.0) + 0.5 * la * (J - 1.0) * (J - 1.0);
+        } else {
+          const double lnJ = log(J);
+          psi = 0.5 * mu * (I1 - 3.0) - mu * lnJ + 0.5 * la * lnJ * lnJ;
+        }
         e = h2 * vol * psi;
       }
       // inertia: the lumped mass rho V / 4 of each vertex, folded per tet
@@ -252,11 +258,11 @@ void launch_diag_max(int N, const int* erow_ptr, const int* ecptr, const float* 
 void launch_energy(const int4* tets, int T, const double* rest, const double* E, const double* nu,
                    const double* rho, double h, const double* x, const double* xt, const int4* ids, int n_c,
                    const double* lin64, const double* xlin, const double* lam, const double* gam, double kappa,
-                   double delta, double* part, int* inverted, hipStream_t s) {
+                   double delta, const int* mat, double* part, int* inverted, hipStream_t s) {
   const int tg = div_up(T, kEBlock);
   const int g = energy_parts(T, n_c);
   hipLaunchKernelGGL(k_energy, dim3(g), dim3(kEBlock), 0, s, tets, T, rest, E, nu, rho, h * h, x, xt, ids, n_c, lin64,
-                     xlin, lam, gam, kappa, delta, tg, part, inverted);
+                     xlin, lam, gam, kappa, delta, tg, mat, part, inverted);
 }
 
 void launch_state_axpy(int n3, const double* xa, double r, const double* p, double* xt, hipStream_t s) {
