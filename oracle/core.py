@@ -154,8 +154,65 @@ def snh_dP(F, dF, mu, lam):
             + (lam * (J - 1.0) - mu)[:, None, None] * dC)
 
 
-# Materials per tet: 0 Neo-Hookean, 1 stable Neo-Hookean.  Both energies need
-# J > 0 here (the solver keeps every tet uninverted).
+# Corotated linear elasticity (reading: Table 2's "corotated linear (COR)"; the
+# classic form built on the polar decomposition F = R S, R a rotation and S
+# symmetric): Psi = mu ||F - R||^2 + lam/2 (tr S - 3)^2, i.e. linear elasticity
+# in the corotated frame, in terms of S - I.
+
+def polar(F):
+    """F = R S with det R = +1 (from a library SVD: R = U V^T with the sign of
+    the smallest singular direction flipped when det F < 0)."""
+    U, s, Vt = np.linalg.svd(F)
+    d = np.sign(np.linalg.det(U @ Vt))
+    U = U.copy()
+    U[:, :, 2] *= d[:, None]
+    R = U @ Vt
+    S = np.transpose(R, (0, 2, 1)) @ F
+    return R, 0.5 * (S + np.transpose(S, (0, 2, 1)))
+
+
+def cor_energy(F, mu, lam):
+    R, S = polar(F)
+    trS = np.einsum("tii->t", S)
+    return mu * np.einsum("tij,tij->t", F - R, F - R) + 0.5 * lam * (trS - 3.0) ** 2
+
+
+def cor_stress(F, mu, lam):
+    """P = 2 mu (F - R) + lam (tr S - 3) R: the rotation's variation drops out,
+    since (F - R) : dR = (S - I) : R^T dR and R^T dR is skew."""
+    R, S = polar(F)
+    trS = np.einsum("tii->t", S)
+    return 2.0 * mu[:, None, None] * (F - R) + (lam * (trS - 3.0))[:, None, None] * R
+
+
+def _polar_rotation_differential(R, S, dF):
+    """dR = R [w]x with (tr S I - S) w = axial(R^T dF - dF^T R): from
+    R^T dF = (R^T dR) S + dS with R^T dR skew and dS symmetric, the skew part
+    gives W S + S W = R^T dF - dF^T R, and W S + S W = [(tr S I - S) w]x."""
+    A = np.transpose(R, (0, 2, 1)) @ dF
+    A = A - np.transpose(A, (0, 2, 1))
+    a = np.stack([A[:, 2, 1], A[:, 0, 2], A[:, 1, 0]], axis=1)
+    M = np.einsum("tii->t", S)[:, None, None] * np.eye(3)[None] - S
+    w = np.linalg.solve(M, a[:, :, None])[:, :, 0]
+    W = np.zeros_like(R)
+    W[:, 0, 1], W[:, 0, 2], W[:, 1, 2] = -w[:, 2], w[:, 1], -w[:, 0]
+    W[:, 1, 0], W[:, 2, 0], W[:, 2, 1] = w[:, 2], -w[:, 1], w[:, 0]
+    return R @ W
+
+
+def cor_dP(F, dF, mu, lam):
+    """2 mu (dF - dR) + lam (R : dF) R + lam (tr S - 3) dR, using
+    d tr S = R : dF."""
+    R, S = polar(F)
+    trS = np.einsum("tii->t", S)
+    dR = _polar_rotation_differential(R, S, dF)
+    RdF = np.einsum("tij,tij->t", R, dF)
+    return (2.0 * mu[:, None, None] * (dF - dR) + (lam * RdF)[:, None, None] * R
+            + (lam * (trS - 3.0))[:, None, None] * dR)
+
+
+# Materials per tet: 0 Neo-Hookean, 1 stable Neo-Hookean, 2 corotated linear.
+# Every energy needs J > 0 here (the solver keeps every tet uninverted).
 
 def _mat(mat, T):
     return np.zeros(T, dtype=np.int64) if mat is None else np.asarray(mat, dtype=np.int64)
@@ -167,7 +224,7 @@ def psi_energy(F, mu, lam, mat=None):
     if np.any(J <= 0):
         raise ValueError("inverted element (J <= 0)")
     out = np.empty(len(F))
-    for code, fn in ((0, nh_energy), (1, snh_energy)):
+    for code, fn in ((0, nh_energy), (1, snh_energy), (2, cor_energy)):
         k = m == code
         if k.any():
             out[k] = fn(F[k], mu[k], lam[k])
@@ -177,7 +234,7 @@ def psi_energy(F, mu, lam, mat=None):
 def psi_stress(F, mu, lam, mat=None):
     m = _mat(mat, len(F))
     out = np.empty_like(F)
-    for code, fn in ((0, nh_stress), (1, snh_stress)):
+    for code, fn in ((0, nh_stress), (1, snh_stress), (2, cor_stress)):
         k = m == code
         if k.any():
             out[k] = fn(F[k], mu[k], lam[k])
@@ -187,7 +244,7 @@ def psi_stress(F, mu, lam, mat=None):
 def psi_dP(F, dF, mu, lam, mat=None):
     m = _mat(mat, len(F))
     out = np.empty_like(F)
-    for code, fn in ((0, nh_dP), (1, snh_dP)):
+    for code, fn in ((0, nh_dP), (1, snh_dP), (2, cor_dP)):
         k = m == code
         if k.any():
             out[k] = fn(F[k], dF[k], mu[k], lam[k])

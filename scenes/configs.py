@@ -177,8 +177,9 @@ def tiny(seed: int = 1, lateral=(0.0, 0.0), n: int = 4, n_pt: int = 25, n_ee: in
 
     `lateral` shifts the upper cube sideways (in cells) so that point-triangle
     pairs also fall in the triangle interior; the default is the plain stack.
-    `material`: None (Neo-Hookean), "snh" (stable Neo-Hookean everywhere) or
-    "mixed" (the upper cube stable Neo-Hookean)."""
+    `material`: None (Neo-Hookean), "snh" / "cor" (stable Neo-Hookean /
+    corotated linear everywhere), "mixed" / "mixed_cor" (the upper cube stable
+    Neo-Hookean / corotated linear) or "all3" (tets cycling through codes 0, 1, 2)."""
     a, rest, tets, n_lo, top, bot, _ = _stack_two_cubes(n, 1e-3, lateral)
     N, T = len(rest), len(tets)
     fixed = np.zeros(N, dtype=np.uint8)
@@ -190,9 +191,13 @@ def tiny(seed: int = 1, lateral=(0.0, 0.0), n: int = 4, n_pt: int = 25, n_ee: in
     lam = _rng(seed, "lambda").uniform(0.0, 100.0, size=len(pt) + len(ee))
     extra = None
     if material is not None:
-        mat = np.ones(T, dtype=np.int32) if material == "snh" else np.zeros(T, dtype=np.int32)
-        if material == "mixed":
-            mat[len(tets) // 2:] = 1
+        codes = {"snh": (1, 1), "cor": (2, 2), "mixed": (0, 1), "mixed_cor": (0, 2)}
+        if material == "all3":
+            mat = (np.arange(T) % 3).astype(np.int32)
+        else:
+            lo, up = codes[material]
+            mat = np.full(T, lo, dtype=np.int32)
+            mat[len(tets) // 2:] = up
         extra = {"material": mat}
     return _finish("tiny", seed, rest, tets, np.full(T, 1e5), np.full(T, 0.4), np.full(T, 1000.0),
                    fixed, x, x_hat, x.copy(), 0.01, pt, ee, lam, 1e4, 1e-3, 1e-8, extra)

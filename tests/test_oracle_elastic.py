@@ -322,3 +322,100 @@ def test_snh_analytic_eigensystem_matches_the_numeric_hessian():
             vals += [mu[e] + q / (s_[i] * s_[j]), mu[e] - q / (s_[i] * s_[j])]
         num = np.linalg.eigvalsh(H9[e])
         assert np.allclose(np.sort(vals), num, rtol=1e-9, atol=1e-9 * np.abs(num).max())
+
+
+def _rotations(rng, n):
+    Q, _ = np.linalg.qr(rng.standard_normal((n, 3, 3)))
+    return Q * np.sign(np.linalg.det(Q))[:, None, None]
+
+
+def test_cor_closed_form_from_a_known_polar_pair():
+    """F built as R S from a rotation R and an SPD S fixes the polar factors, so
+    Psi = mu ||S - I||^2 + lam/2 tr(S - I)^2 and P = 2 mu R (S - I) + lam tr(S - I) R
+    exactly (||F - R|| = ||R (S - I)|| = ||S - I||)."""
+    rng = np.random.default_rng(31)
+    n = 25
+    R = _rotations(rng, n)
+    B = rng.standard_normal((n, 3, 3)) * 0.25
+    S = np.eye(3)[None] + 0.5 * (B + np.transpose(B, (0, 2, 1)))
+    S = S[np.all(np.linalg.eigvalsh(S) > 0.2, axis=1)]
+    R = R[:len(S)]
+    n = len(S)
+    F = R @ S
+    mu, lam = rng.uniform(1, 5, n), rng.uniform(1, 20, n)
+    D = S - np.eye(3)[None]
+    tr = np.einsum("tii->t", D)
+    psi = mu * np.einsum("tij,tij->t", D, D) + 0.5 * lam * tr ** 2
+    P = 2.0 * mu[:, None, None] * (R @ D) + (lam * tr)[:, None, None] * R
+    assert np.allclose(oracle.core.cor_energy(F, mu, lam), psi, rtol=1e-12, atol=1e-14)
+    assert np.allclose(oracle.core.cor_stress(F, mu, lam), P, rtol=1e-12, atol=1e-13)
+    I = np.eye(3)[None]
+    assert oracle.core.cor_energy(I, mu[:1], lam[:1])[0] == 0.0
+    assert np.abs(oracle.core.cor_stress(I, mu[:1], lam[:1])).max() < 1e-15
+
+
+def test_cor_stress_and_hessian_are_derivatives():
+    rng = np.random.default_rng(32)
+    F = _rand_F(rng, 20)
+    n = len(F)
+    mu, lam = rng.uniform(1, 5, n), rng.uniform(1, 20, n)
+    P = oracle.core.cor_stress(F, mu, lam)
+    eps = 1e-6
+    for k in range(9):
+        E = np.zeros((n, 3, 3))
+        E[:, k // 3, k % 3] = 1.0
+        fd = (oracle.core.cor_energy(F + eps * E, mu, lam) - oracle.core.cor_energy(F - eps * E, mu, lam)) / (2 * eps)
+        assert np.allclose(fd, P[:, k // 3, k % 3], rtol=1e-7, atol=1e-7)
+        dP = oracle.core.cor_dP(F, E, mu, lam)
+        fdP = (oracle.core.cor_stress(F + eps * E, mu, lam) - oracle.core.cor_stress(F - eps * E, mu, lam)) / (2 * eps)
+        assert np.allclose(fdP, dP, rtol=1e-6, atol=1e-6)
+
+
+def test_cor_rotation_invariance():
+    rng = np.random.default_rng(33)
+    F = _rand_F(rng, 10)
+    n = len(F)
+    mu, lam = np.full(n, 2.0), np.full(n, 9.0)
+    R = _rotations(rng, 1)[0]
+    RF = R[None] @ F
+    assert np.allclose(oracle.core.cor_energy(RF, mu, lam), oracle.core.cor_energy(F, mu, lam), rtol=1e-12)
+    assert np.allclose(oracle.core.cor_stress(RF, mu, lam), R[None] @ oracle.core.cor_stress(F, mu, lam), atol=1e-12)
+
+
+def test_cor_analytic_eigensystem_matches_the_numeric_hessian():
+    """The closed forms the element kernel uses for Psi = mu sum (s_i - 1)^2 +
+    lam/2 (sum s_i - 3)^2: the 3x3 Hessian in the singular values is
+    2 mu I + lam 1 1^T; with Psi_i = 2 mu (s_i - 1) + lam (sum s - 3) the pair
+    modes are (Psi_i + Psi_j) / (s_i + s_j) and (Psi_i - Psi_j) / (s_i - s_j) = 2 mu.
+    Their nine values equal the eigenvalues of the oracle's 9x9 d2Psi/dF2."""
+    rng = np.random.default_rng(34)
+    F = _rand_F(rng, 30, 0.4)
+    n = len(F)
+    mu, lam = rng.uniform(1, 5, n), rng.uniform(1, 20, n)
+    H9 = oracle.core.nh_hessian9(F, mu, lam, np.full(n, 2))
+    for e in range(n):
+        s_ = np.linalg.svd(F[e], compute_uv=False)
+        t = s_.sum() - 3.0
+        dpsi = 2.0 * mu[e] * (s_ - 1.0) + lam[e] * t
+        vals = list(np.linalg.eigvalsh(2.0 * mu[e] * np.eye(3) + lam[e] * np.ones((3, 3))))
+        for i, j in ((0, 1), (0, 2), (1, 2)):
+            vals += [(dpsi[i] + dpsi[j]) / (s_[i] + s_[j]), 2.0 * mu[e]]
+        num = np.linalg.eigvalsh(H9[e])
+        assert np.allclose(np.sort(vals), num, rtol=1e-9, atol=1e-9 * np.abs(num).max())
+
+
+def test_material_dispatch_per_tet():
+    """psi_* pick each tet's own material (codes 0, 1, 2) in one call."""
+    rng = np.random.default_rng(35)
+    F = _rand_F(rng, 12)
+    n = len(F)
+    mu, lam = rng.uniform(1, 5, n), rng.uniform(1, 20, n)
+    mat = np.arange(n) % 3
+    E = oracle.core.psi_energy(F, mu, lam, mat)
+    P = oracle.core.psi_stress(F, mu, lam, mat)
+    for code, fe, fs in ((0, oracle.core.nh_energy, oracle.core.nh_stress),
+                         (1, oracle.core.snh_energy, oracle.core.snh_stress),
+                         (2, oracle.core.cor_energy, oracle.core.cor_stress)):
+        k = mat == code
+        assert np.array_equal(E[k], fe(F[k], mu[k], lam[k]))
+        assert np.array_equal(P[k], fs(F[k], mu[k], lam[k]))
