@@ -72,12 +72,13 @@ typedef struct {
   const double* nu;      /* [n_tets] Poisson ratio in (-1, 0.5) */
   const double* rho;     /* [n_tets] density (kg/m^3), > 0 */
   const uint8_t* fixed;  /* [n_nodes] 1 = Dirichlet node (Section 5.3); may be NULL */
-  const int32_t* material; /* [n_tets] 0 Neo-Hookean, 1 stable Neo-Hookean (Table 2); NULL: all 0.
-                              Neo-Hookean: mu/2 (I_C - 3) - mu ln J + lam/2 (ln J)^2; stable Neo-Hookean (the
-                              rest-stable form of Smith, de Goes and Kim 2019): mu/2 (I_C - 3) - mu (J - 1)
-                              + lam/2 (J - 1)^2.  Every tet must stay uninverted (J > 0).  Host arrays are
-                              validated; on device arrays a value other than 1 reads as 0.  Serving accepts
-                              Neo-Hookean meshes only (material NULL). */
+  const int32_t* material; /* [n_tets] 0 Neo-Hookean, 1 stable Neo-Hookean, 2 corotated linear (Table 2);
+                              NULL: all 0.  Neo-Hookean: mu/2 (I_C - 3) - mu ln J + lam/2 (ln J)^2; stable
+                              Neo-Hookean (the rest-stable form of Smith, de Goes and Kim 2019): mu/2 (I_C - 3)
+                              - mu (J - 1) + lam/2 (J - 1)^2; corotated linear (F = R S the polar
+                              decomposition): mu |F - R|^2 + lam/2 (tr S - 3)^2.  Every tet must stay
+                              uninverted (J > 0).  Host arrays are validated; on device arrays a value other
+                              than 1 or 2 reads as 0.  Serving accepts Neo-Hookean meshes only (NULL). */
 } bf_mesh_desc;
 
 /* Active constraint set C = {(i, lambda_i, gamma_i)} (Algorithm 2 input). */

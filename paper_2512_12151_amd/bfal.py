@@ -221,7 +221,7 @@ class Problem:
     """One mesh on one context: state, constraints, Newton steps, introspection."""
 
     def __init__(self, ctx: Context, tets, rest, E, nu, rho, fixed=None, material=None):
-        """material: per-tet codes, 0 Neo-Hookean and 1 stable Neo-Hookean (None: all 0)."""
+        """material: per-tet codes, 0 Neo-Hookean, 1 stable Neo-Hookean, 2 corotated linear (None: all 0)."""
         self.ctx = ctx
         dev = not isinstance(tets, np.ndarray)
         if not dev:

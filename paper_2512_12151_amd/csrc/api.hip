@@ -36,8 +36,9 @@ bf_status problem_init(bf_context* c, bf_problem* pb, const bf_mesh_desc* m, int
       if (!(m->E[e] > 0.0) || !std::isfinite(m->E[e]) || !(m->nu[e] > -1.0 && m->nu[e] < 0.5) ||
           !(m->rho[e] > 0.0) || !std::isfinite(m->rho[e]))
         return fail(c, BF_ERR_INVALID_ARG, "invalid material value");
-      if (m->material && m->material[e] != 0 && m->material[e] != 1)
-        return fail(c, BF_ERR_INVALID_ARG, "material code must be 0 (Neo-Hookean) or 1 (stable Neo-Hookean)");
+      if (m->material && (m->material[e] < 0 || m->material[e] > 2))
+        return fail(c, BF_ERR_INVALID_ARG,
+                    "material code must be 0 (Neo-Hookean), 1 (stable Neo-Hookean) or 2 (corotated linear)");
     }
     if (!finite_all(m->rest, 3LL * N)) return fail(c, BF_ERR_INVALID_ARG, "non-finite rest position");
   }

@@ -1,5 +1,5 @@
-// Hyperelastic element kernel (Neo-Hookean or stable Neo-Hookean per tet):
-// one thread per tet.
+// Hyperelastic element kernel (Neo-Hookean, stable Neo-Hookean or corotated
+// linear per tet): one thread per tet.
 //
 // Per tet it forms F (from FP64 displacement differences, then FP32), the
 // stress P, the element gradient h^2 V P A_a^T, and the ten upper 3x3 blocks
@@ -17,8 +17,8 @@
 // singular-value pair.  Blocks are written to the fixed assembly order
 // (staging position of each (tet, pair)), so no atomics touch the matrix.
 //
-// Energies (readings of the paper, which names both materials in Table 2
-// without printing them), Psi = mu/2 (tr F^T F - 3) + g(J):
+// Energies (readings of the paper, which names its materials in Table 2
+// without printing them); the first two are Psi = mu/2 (tr F^T F - 3) + g(J):
 //   Neo-Hookean         g = -mu ln J + lam/2 (ln J)^2
 //   stable Neo-Hookean  g = -mu (J - 1) + lam/2 (J - 1)^2   (rest-stable form of
 //                       Smith, de Goes and Kim 2019)
@@ -32,6 +32,10 @@
 // twist / flip eigenvalues of pair (i, j) are mu +- q / (S_i S_j):
 //   Neo-Hookean  q = lam ln J - mu,          r = mu + lam - lam ln J
 //   stable NH    q = J (lam (J - 1) - mu),  r = lam J^2.
+// Corotated linear (Table 2's COR, F = R S the polar decomposition):
+//   Psi = mu ||F - R||^2 + lam/2 (tr S - 3)^2 = mu sum (S_k - 1)^2 + lam/2 (sum S_k - 3)^2,
+// whose Hessian in the singular values is 2 mu I + lam 1 1^T and whose twist /
+// flip eigenvalues are (Psi_i + Psi_j) / (S_i + S_j) and 2 mu.
 #include "common.h"
 
 namespace bfal {
@@ -216,42 +220,7 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
     return;
   }
   const float mu = mu_[e], lam = lam_[e];
-  const bool snh = mat != nullptr && mat[e] == 1;
-  float C[3][3];
-  cof3(F, C);
-  float P[3][3], q, r, rq;
-  if (snh) {
-    float Cg[3][3];
-    cof3(Gm, Cg);
-    const float trG = Gm[0][0] + Gm[1][1] + Gm[2][2];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-        P[i][j] = mu * (Gm[i][j] + Gm[j][i] - (i == j ? trG : 0.f) - Cg[i][j]) + lam * Jm1 * C[i][j];
-    q = J * (lam * Jm1 - mu);
-    r = lam * J * J;
-    rq = r + q;
-  } else {
-    const float lnJ = log1pf(Jm1);
-    // P = F^{-T} Sp with Sp = mu (G + G^T + G^T G) + lam lnJ I; F^{-T} = cof(F) / J
-    float Sp[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const float gtg = Gm[0][i] * Gm[0][j] + Gm[1][i] * Gm[1][j] + Gm[2][i] * Gm[2][j];
-        Sp[i][j] = mu * (Gm[i][j] + Gm[j][i] + gtg) + (i == j ? lam * lnJ : 0.f);
-      }
-    const float iJ = 1.f / J;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) P[i][j] = (C[i][0] * Sp[0][j] + C[i][1] * Sp[1][j] + C[i][2] * Sp[2][j]) * iJ;
-    q = lam * lnJ - mu;
-    r = mu + lam - lam * lnJ;
-    rq = lam;
-  }
+  const int code = mat != nullptr ? mat[e] : 0;
   // rows A_a (A_1..A_3 = rows of Dm^{-1}, A_0 = -their sum)
   float A[4][3];
 #pragma unroll
@@ -259,17 +228,102 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
     A[1][j] = Dm[0][j]; A[2][j] = Dm[1][j]; A[3][j] = Dm[2][j];
     A[0][j] = -(Dm[0][j] + Dm[1][j] + Dm[2][j]);
   }
-  // SVD and the analytic eigensystem
+  // SVD, then per material the stress, the 3x3 Hessian in the singular values
+  // (Ah) and the twist / flip eigenvalues of the pairs (0,1), (0,2), (1,2)
   float U[3][3], S[3], V[3][3];
   svd3(F, U, S, V);
-  float Ah[3][3];
+  const int pi[3] = {0, 0, 1}, pj[3] = {1, 2, 2};
+  float P[3][3], Ah[3][3], wt[3], wf[3];
+  bool clamp;
+  if (code == 2) {
+    // corotated linear: Psi = mu sum (S_k - 1)^2 + lam/2 (sum S_k - 3)^2.  S_k - 1 without
+    // cancellation: e_k = S_k^2 - 1 is the Rayleigh quotient of F^T F - I = G + G^T + G^T G
+    // along V_k, and S_k - 1 = e_k / (1 + sqrt(1 + e_k)).
+    float d[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) {
+      float ek = 0.f;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) Ah[i][j] = (i == j) ? mu + r / (S[i] * S[i]) : rq / (S[i] * S[j]);
-  if (q > 0.f || rq < 0.f) {
-    // Ah = mu I + diag(1/S) (-q I + (r + q) 1 1^T) diag(1/S) is PSD when -q >= 0 and r + q >= 0;
-    // otherwise it may be indefinite: clamp its eigenvalues
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const float gtg = Gm[0][i] * Gm[0][j] + Gm[1][i] * Gm[1][j] + Gm[2][i] * Gm[2][j];
+          ek += V[i][k] * (Gm[i][j] + Gm[j][i] + gtg) * V[j][k];
+        }
+      d[k] = ek / (1.f + sqrtf(fmaxf(1.f + ek, 0.f)));
+    }
+    const float tr = d[0] + d[1] + d[2];
+    float dpsi[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dpsi[k] = 2.f * mu * d[k] + lam * tr;
+    // P = U diag(dPsi/dS) V^T = 2 mu (F - R) + lam tr(S - I) R
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        P[i][j] = U[i][0] * dpsi[0] * V[j][0] + U[i][1] * dpsi[1] * V[j][1] + U[i][2] * dpsi[2] * V[j][2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Ah[i][j] = (i == j ? 2.f * mu : 0.f) + lam;
+    clamp = lam < 0.f;   // 2 mu I + lam 1 1^T is PSD for lam >= 0
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int i = pi[k], j = pj[k];
+      wt[k] = (dpsi[i] + dpsi[j]) / (2.f + d[i] + d[j]);
+      wf[k] = 2.f * mu;   // (dPsi_i - dPsi_j) / (S_i - S_j)
+    }
+  } else {
+    float C[3][3];
+    cof3(F, C);
+    float q, r, rq;
+    if (code == 1) {
+      float Cg[3][3];
+      cof3(Gm, Cg);
+      const float trG = Gm[0][0] + Gm[1][1] + Gm[2][2];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          P[i][j] = mu * (Gm[i][j] + Gm[j][i] - (i == j ? trG : 0.f) - Cg[i][j]) + lam * Jm1 * C[i][j];
+      q = J * (lam * Jm1 - mu);
+      r = lam * J * J;
+      rq = r + q;
+    } else {
+      const float lnJ = log1pf(Jm1);
+      // P = F^{-T} Sp with Sp = mu (G + G^T + G^T G) + lam lnJ I; F^{-T} = cof(F) / J
+      float Sp[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const float gtg = Gm[0][i] * Gm[0][j] + Gm[1][i] * Gm[1][j] + Gm[2][i] * Gm[2][j];
+          Sp[i][j] = mu * (Gm[i][j] + Gm[j][i] + gtg) + (i == j ? lam * lnJ : 0.f);
+        }
+      const float iJ = 1.f / J;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) P[i][j] = (C[i][0] * Sp[0][j] + C[i][1] * Sp[1][j] + C[i][2] * Sp[2][j]) * iJ;
+      q = lam * lnJ - mu;
+      r = mu + lam - lam * lnJ;
+      rq = lam;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Ah[i][j] = (i == j) ? mu + r / (S[i] * S[i]) : rq / (S[i] * S[j]);
+    // Ah = mu I + diag(1/S) (-q I + (r + q) 1 1^T) diag(1/S) is PSD when -q >= 0 and r + q >= 0
+    clamp = q > 0.f || rq < 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float ss = S[pi[k]] * S[pj[k]];
+      wt[k] = mu + q / ss;
+      wf[k] = mu - q / ss;
+    }
+  }
+  if (clamp) {
+    // Ah may be indefinite: clamp its eigenvalues
     float E3[3][3], Q[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -282,16 +336,12 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
 #pragma unroll
       for (int j = 0; j < 3; ++j) Ah[i][j] = l0 * Q[i][0] * Q[j][0] + l1 * Q[i][1] * Q[j][1] + l2 * Q[i][2] * Q[j][2];
   }
-  // twist / flip eigenvalues per singular-value pair (0,1), (0,2), (1,2)
   float c1[3], c2[3];
-  const int pi[3] = {0, 0, 1}, pj[3] = {1, 2, 2};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const float ss = S[pi[k]] * S[pj[k]];
-    const float wt = fmaxf(mu + q / ss, 0.f);
-    const float wf = fmaxf(mu - q / ss, 0.f);
-    c1[k] = 0.5f * (wt + wf);
-    c2[k] = 0.5f * (wf - wt);
+    const float t = fmaxf(wt[k], 0.f), f = fmaxf(wf[k], 0.f);
+    c1[k] = 0.5f * (t + f);
+    c2[k] = 0.5f * (f - t);
   }
   float AV[4][3];
 #pragma unroll

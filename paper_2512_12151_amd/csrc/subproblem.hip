@@ -60,6 +60,47 @@ __device__ inline double constraint_value(const int4 t, int i, int n_c, const do
   return c;
 }
 
+// Sum over k of S_k - 1 and of (S_k - 1)^2 for the singular values S_k of
+// F = I + G (all positive, J > 0), without cancellation near rest: the
+// eigenvalues e_k of F^T F - I = G + G^T + G^T G by cyclic Jacobi, then
+// S_k - 1 = e_k / (1 + sqrt(1 + e_k)).
+__device__ void stretch_sums(const double G[3][3], double& sum1, double& sum2) {
+  double A[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      A[i][j] = G[i][j] + G[j][i] + G[0][i] * G[0][j] + G[1][i] * G[1][j] + G[2][i] * G[2][j];
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (off <= 1e-34 * dia || off == 0.0) break;
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0;
+      const int q = pq == 0 ? 1 : 2;
+      const double apq = A[p][q];
+      if (apq == 0.0) continue;
+      const double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+      const double t = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+      const int r = 3 - p - q;
+      const double arp = A[r][p], arq = A[r][q];
+      A[p][p] -= t * apq;
+      A[q][q] += t * apq;
+      A[p][q] = A[q][p] = 0.0;
+      A[r][p] = A[p][r] = c * arp - s * arq;
+      A[r][q] = A[q][r] = s * arp + c * arq;
+    }
+  }
+  sum1 = sum2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double d = A[k][k] / (1.0 + sqrt(fmax(1.0 + A[k][k], 0.0)));
+    sum1 += d;
+    sum2 += d * d;
+  }
+}
+
 // One partial per workgroup: tets in the first ceil(T / kEBlock) workgroups,
 // constraints in the rest.
 __global__ void __launch_bounds__(kEBlock)
@@ -114,7 +155,17 @@ k_energy(const int4* __restrict__ tets, int T, const double* __restrict__ rest, 
 #pragma unroll
           for (int j = 0; j < 3; ++j) I1 += F[i][j] * F[i][j];
         double psi;
-        if (mat != nullptr && mat[k] == 1) {
+        const int code = mat != nullptr ? mat[k] : 0;
+        if (code == 2) {
+          // corotated linear: mu sum (S_i - 1)^2 + lam/2 (sum S_i - 3)^2
+          double G[3][3], s1, s2;
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) G[i][j] = F[i][j] - (i == j ? 1.0 : 0.0);
+          stretch_sums(G, s1, s2);
+          psi = mu * s2 + 0.5 * la * s1 * s1;
+        } else if (code == 1) {
           psi = 0.5 * mu * (I1 - 3.0) - mu * (J - 1.0) + 0.5 * la * (J - 1.0) * (J - 1.0);
         } else {
           const double lnJ = log(J);

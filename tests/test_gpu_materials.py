@@ -1,12 +1,14 @@
-"""Per-tet materials (Table 2: Neo-Hookean and stable Neo-Hookean) on the GPU
-against the FP64 oracle, through the C-ABI.
+"""Per-tet materials (Table 2: Neo-Hookean, stable Neo-Hookean, corotated
+linear) on the GPU against the FP64 oracle, through the C-ABI.
 
-States: the shifted tiny stack, all stable Neo-Hookean or mixed (upper cube
-stable Neo-Hookean), at the generator's 1 % noise and under three large
-deformations that reach every branch of the element kernel's projection:
-the lower cube stretched 1.8x in z (J up to 1.89: q = J (lam (J-1) - mu) > 0,
-the 3x3 scaling Hessian is clamped), compressed to 0.6x (J down to 0.57:
-r + q = J (lam (2J - 1) - mu) < 0, clamped as well) and sheared by 0.5.
+States: the shifted tiny stack, all stable Neo-Hookean, all corotated, mixed
+with Neo-Hookean (upper cube the other material) or all three cycling per tet,
+at the generator's 1 % noise and under three large deformations that reach
+every branch of the element kernel's projection: the lower cube stretched 1.8x
+in z (J up to 1.89; stable Neo-Hookean: q = J (lam (J-1) - mu) > 0, the 3x3
+scaling Hessian is clamped), compressed to 0.6x (J down to 0.57: r + q =
+J (lam (2J - 1) - mu) < 0, clamped as well; corotated: the twist modes
+(Psi_i + Psi_j) / (S_i + S_j) turn negative and are clamped) and sheared by 0.5.
 
 Bars, as for Neo-Hookean: the FP32 gradient and the assembled blocks within
 1e-5 relative, the FP64 energy within 1e-9 relative, the Newton direction
@@ -51,7 +53,7 @@ def deformed(material, kind):
     return sc
 
 
-CASES = [(m, k) for m in ("snh", "mixed") for k in ("noise", "stretch", "compress", "shear")]
+CASES = [(m, k) for m in ("snh", "mixed", "cor", "mixed_cor", "all3") for k in ("noise", "stretch", "compress", "shear")]
 
 
 def rel(a, b):
@@ -82,7 +84,8 @@ def test_gradient_blocks_energy(ctx, bf, material, kind):
     assert ep <= 1e-4
 
 
-@pytest.mark.parametrize("material,kind", [("snh", "stretch"), ("mixed", "stretch"), ("snh", "compress")])
+@pytest.mark.parametrize("material,kind", [("snh", "stretch"), ("mixed", "stretch"), ("snh", "compress"),
+                                           ("cor", "compress"), ("mixed_cor", "stretch"), ("all3", "stretch")])
 def test_subproblem(ctx, bf, material, kind):
     print(f"case {material}/{kind}", flush=True)
     sc = deformed(material, kind)
@@ -112,9 +115,10 @@ def test_neo_hookean_code_matches_no_material_array(ctx, bf):
     assert a.energy() == b.energy()
 
 
-def test_mu_init_snh(ctx, bf):
-    """Section 5.2's mu_init on a stable Neo-Hookean mesh (at x, the start state)."""
-    sc = deformed("mixed", "stretch")
+@pytest.mark.parametrize("material", ["mixed", "all3"])
+def test_mu_init_materials(ctx, bf, material):
+    """Section 5.2's mu_init on meshes of several materials (at x, the start state)."""
+    sc = deformed(material, "stretch")
     sc["x"] = sc["x_hat"].copy()
     pb = bf.Problem.from_scene(ctx, sc)
     m = pb.mu_init(0.1)
@@ -126,7 +130,7 @@ def test_mu_init_snh(ctx, bf):
 def test_invalid_material_code_rejected(ctx, bf):
     sc = dict(scenes.tiny(material="snh"))
     sc["material"] = sc["material"].copy()
-    sc["material"][3] = 2
+    sc["material"][3] = 3
     with pytest.raises(bf.BfalError) as e:
         bf.Problem.from_scene(ctx, sc)
     assert e.value.status == -1   # BF_ERR_INVALID_ARG
