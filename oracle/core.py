@@ -499,6 +499,10 @@ def assemble(scene, st=None):
     rows.append(np.repeat(cdof, 12, axis=1).ravel())
     cols.append(np.tile(cdof, (1, 12)).ravel())
     vals.append(Hc.ravel())
+    # semi-implicit friction of the previous step's contacts (Appendix A)
+    if scene.get("friction") is not None:
+        from . import friction
+        friction.add_to(scene["friction"], xh, G, rows, cols, vals)
     H = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(3 * N, 3 * N)).tocsr()
     H.sum_duplicates()
@@ -525,7 +529,8 @@ def apply_dbc(G, H, fixed):
 
 def total_energy(scene, st, xh):
     """L(x_hat) = 1/2 |x_hat - x_tilde|_M^2 + h^2 sum V Psi + sum AL terms
-    (Section 4.2, total energy).  Used only to check G by finite differences."""
+    (Section 4.2, total energy), plus the friction terms when the scene holds a
+    friction set (Appendix A).  Used only to check G by finite differences."""
     h = scene["dt"]
     F = deformation_gradient(xh, st.tets, st.Dminv)
     Ei = 0.5 * np.sum(st.mass[:, None] * (xh - scene["x_tilde"]) ** 2)
@@ -533,7 +538,11 @@ def total_energy(scene, st, xh):
     ids, d, nrm, w = linearize(scene["x"], scene["pt"], scene["ee"])
     c = constraint_values(xh, scene["x"], ids, d, nrm, w, scene["delta"])
     Ec = np.sum(al_energy(c, scene["lam"], scene["gamma"], scene["kappa"]))
-    return Ei + Ee + Ec
+    Ef = 0.0
+    if scene.get("friction") is not None:
+        from . import friction
+        Ef = friction.energy(scene["friction"], xh)
+    return Ei + Ee + Ec + Ef
 
 
 # ---------------------------------------------------------------- pattern ---

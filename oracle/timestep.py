@@ -20,17 +20,20 @@ Readings (listed in DESIGN.md):
     is the remainder of that path, where the pairs that blocked it are; it
     sees the multipliers and decay factors the subproblem just updated.
   * A cap max_outer on the iterations (the paper has none).
+  * With mu_f > 0 the friction set of Appendix A is captured once, at x^t from
+    the incoming constraints and multipliers, and held for the whole step.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from . import ccd
+from . import friction
 from . import subproblem as sp
 
 
 def time_step(scene, K_min=2, eps=1e-3, max_outer=200, Gamma=0.9, max_newton=20, mu_init_C=None,
-              sep=ccd.S_SEP):
+              sep=ccd.S_SEP, mu_f=0.0, eps_v=1e-3):
     """Algorithm 1 from scene["x"] (= x^t) and scene["x_hat"] (= x_hat^[0]).
     Returns (x, v, constraints (pt, ee, lam, gam), info)."""
     sc = dict(scene)
@@ -42,6 +45,7 @@ def time_step(scene, K_min=2, eps=1e-3, max_outer=200, Gamma=0.9, max_newton=20,
     lam = np.asarray(sc["lam"], dtype=np.float64).copy()
     gam = np.asarray(sc["gamma"], dtype=np.float64).copy()
     kappa, delta = float(sc["kappa"]), float(sc["delta"])
+    sc["friction"] = friction.capture(sc, mu_f, eps_v) if mu_f > 0 else None
     if mu_init_C is not None:
         kappa = sp.mu_init(sc, mu_init_C)
     tris, edges, verts = ccd.surface(sc["tets"])
