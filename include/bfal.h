@@ -152,6 +152,20 @@ bf_status bf_set_state(bf_problem* pb, const double* x, const double* x_hat, con
  * device memory is validated by a kernel before any use. */
 bf_status bf_set_constraints(bf_problem* pb, const bf_constraint_desc* cons, int32_t mem);
 
+/* Semi-implicit friction (Appendix A; IPC's smoothed friction).  Captures the
+ * friction set from the current constraints, multipliers, kappa and delta at
+ * the current x (= x^t, the start of a time step): per contact its closest-point
+ * weights w and normal n at x^t and coef = mu_f max(0, lambda - kappa (d(x^t) -
+ * delta)), which is h^2 mu_f F^t with the previous step's normal force F^t.
+ * Until the next call every Newton step, energy and subproblem adds, per
+ * contact, coef f_0(|u|) with u the tangential part of sum_a w_a (x_hat_a -
+ * x^t_a) and f_0 IPC's C^2 mollified norm with threshold eps_v h (h from
+ * bf_set_state).  Later bf_set_constraints / bf_update_active_set calls leave
+ * the friction set as captured.  mu_f = 0 clears it.  Requires bf_set_state;
+ * mu_f >= 0 finite and, when mu_f > 0, eps_v > 0 finite (BF_ERR_INVALID_ARG
+ * otherwise).  Allocates the per-contact buffers on the device. */
+bf_status bf_set_friction(bf_problem* pb, double mu_f, double eps_v);
+
 /* One Newton step: constraint linearization at x, merged BSR pattern,
  * assembly of G and the SPD-projected H, block-Jacobi PCG for p = -H^{-1} G,
  * and the FP64 stats.  p_out is [n_nodes][3] doubles in `mem`.  stats may be
@@ -221,7 +235,7 @@ bf_status bf_energy(bf_problem* pb, double* energy_out, int32_t* inverted);
 
 /* Conditioning-aware penalty (Section 5.2): *mu_out = C max_i (grad^2 E)_ii,
  * the largest scalar diagonal of the incremental potential's Hessian -- the
- * lumped mass plus h^2 times the SPD-projected Neo-Hookean Hessian, the
+ * lumped mass plus h^2 times the SPD-projected elastic Hessian, the
  * matrix the Newton step assembles -- at x, the state the time step starts
  * from (bf_set_state's first argument).  The paper uses C = 0.1.  The caller
  * passes the result as kappa to bf_set_constraints.  Fixed nodes count: their
@@ -315,7 +329,11 @@ bf_status bf_get_constraints(bf_problem* pb, int32_t* pt, int32_t* ee, double* l
  * while beta > eps (Section 6: eps = 1e-3, k_min = 2).  Section 5.2: with
  * mu_init_c > 0 the penalty starts at mu_init_c max_i (grad^2 E)_ii
  * (bf_mu_init; the paper uses 0.1), and whenever alpha stays below 1e-4 for
- * 50 consecutive iterations kappa doubles and delta halves.  On return the
+ * 50 consecutive iterations kappa doubles and delta halves.  Friction
+ * (Appendix A): the step first calls bf_set_friction(mu_f, eps_v), so the
+ * friction set comes from the incoming active set and multipliers at x^t and
+ * holds for the whole step; mu_f = 0 steps without friction (and clears a
+ * set captured earlier).  The paper uses k_min = 6 with friction.  On return the
  * problem holds x^{t+1}, the last x_hat and the active set with its
  * multipliers; x_out and v_out = (x^{t+1} - x^t) / h ([N][3] FP64, kind mem,
  * nullable) receive the state.  Returns BF_WARN_PCG_MAXITER when max_outer
@@ -330,6 +348,8 @@ typedef struct {
   double decay;         /* Gamma of the constraint decay, in (0, 1] */
   double sep;           /* ACCD separation ratio (0 selects 0.1) */
   double mu_init_c;     /* > 0: start from mu_init_c max_i (grad^2 E)_ii; 0 keeps kappa */
+  double mu_f;          /* friction coefficient (0: no friction) */
+  double eps_v;         /* friction smoothing: f_0 is |u| beyond eps_v h (used when mu_f > 0) */
 } bf_time_step_opts;
 
 typedef struct {

@@ -82,7 +82,8 @@ class bf_ccd_stats(C.Structure):
 
 class bf_time_step_opts(C.Structure):
     _fields_ = [("solve", bf_solve_opts), ("k_min", C.c_int32), ("eps", C.c_double), ("max_outer", C.c_int32),
-                ("max_newton", C.c_int32), ("decay", C.c_double), ("sep", C.c_double), ("mu_init_c", C.c_double)]
+                ("max_newton", C.c_int32), ("decay", C.c_double), ("sep", C.c_double), ("mu_init_c", C.c_double),
+                ("mu_f", C.c_double), ("eps_v", C.c_double)]
 
 
 class bf_time_step_stats(C.Structure):
@@ -127,6 +128,7 @@ _PROTOS = [
                                       C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(bf_subproblem_stats)]),
     ("bf_energy", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     ("bf_mu_init", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double)]),
+    ("bf_set_friction", C.c_int, [C.c_void_p, C.c_double, C.c_double]),
     ("bf_update_active_set", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.POINTER(bf_ccd_stats)]),
     ("bf_max_step_size", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double),
                                    C.POINTER(bf_ccd_stats)]),
@@ -310,12 +312,13 @@ class Problem:
         return float(a.value), st.as_dict()
 
     def time_step(self, tol=1e-7, max_iter=50000, k_min=2, eps=1e-3, max_outer=200, max_newton=20, decay=0.9,
-                  sep=0.1, mu_init_c=0.0, poll_every=16):
+                  sep=0.1, mu_init_c=0.0, poll_every=16, mu_f=0.0, eps_v=1e-3):
         """Algorithm 1 from the current state; returns (x, v, stats, status) on the host."""
         o = bf_time_step_opts()
         o.solve = bf_solve_opts(tol, max_iter, BF_PREC_FP32, 1e-6, poll_every, 1, 0, 0)
         o.k_min, o.eps, o.max_outer, o.max_newton = k_min, eps, max_outer, max_newton
         o.decay, o.sep, o.mu_init_c = decay, sep, mu_init_c
+        o.mu_f, o.eps_v = mu_f, eps_v
         x = np.empty((self.N, 3))
         v = np.empty((self.N, 3))
         st = bf_time_step_stats()
@@ -345,6 +348,10 @@ class Problem:
         self.ctx.check(lib().bf_get_constraints(self.h, pt.ctypes.data, ee.ctypes.data, lam.ctypes.data,
                                                 gam.ctypes.data, BF_MEM_HOST))
         return pt, ee, lam, gam
+
+    def set_friction(self, mu_f, eps_v=1e-3):
+        """Appendix A: capture the friction set from the current constraints at x (mu_f = 0 clears it)."""
+        self.ctx.check(lib().bf_set_friction(self.h, float(mu_f), float(eps_v)))
 
     def mu_init(self, C_=0.1):
         """C max_i (grad^2 E)_ii at the start-of-step state x (Section 5.2)."""

@@ -153,10 +153,18 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
   bf_context* c = pb->ctx;
   HIPCHK(c, hipSetDevice(c->device));
   hipStream_t s = c->stream;
-  const int N = pb->N, T = pb->T, n = pb->n_c;
+  const int N = pb->N, T = pb->T, n = pb->n_c, nf = pb->n_f;
   int* flags = pb->flags.as<int>();
   int* tmp = pb->scan_tmp.as<int>();
   const int4* ids = pb->cids.as<int4>();
+  // the pattern's stencils: the constraints, then the friction contacts
+  const int4* pids = ids;
+  const int npat = n + nf;
+  if (nf > 0) {
+    if (n) HIPCHK(c, hipMemcpyAsync(pb->pids.p, pb->cids.p, 16LL * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(pb->pids.as<char>() + 16LL * n, pb->fids.p, 16LL * nf, hipMemcpyDeviceToDevice, s));
+    pids = pb->pids.as<int4>();
+  }
   fill_int(flags, 0, 16, s);
   HIPCHK(c, hipEventRecord(pb->ev[0], s));
   // (1) constraint linearization at x and AL factors at x_hat
@@ -170,29 +178,31 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
   int* vcnt = pb->vcnt.as<int>();
   int* vptr = pb->vptr.as<int>();
   fill_int(vcnt, 0, N, s);
-  launch_vertex_incidence_count(ids, n, vcnt, s);
+  launch_vertex_incidence_count(pids, npat, vcnt, s);
   scan_exclusive(vcnt, vptr, N, vptr + N, tmp, s);
   fill_int(vcnt, 0, N, s);
-  launch_vertex_incidence_fill(ids, n, vptr, vcnt, pb->vinc.as<int>(), s);
+  launch_vertex_incidence_fill(pids, npat, vptr, vcnt, pb->vinc.as<int>(), s);
   sort_segments(pb->vinc.as<int>(), vptr, N, s);
   int* cptr = pb->cptr.as<int>();
-  launch_candidate_count(pb->erow_ptr.as<int>(), vptr, pb->vinc.as<int>(), ids, N, pb->ccount.as<int>(), s);
+  launch_candidate_count(pb->erow_ptr.as<int>(), vptr, pb->vinc.as<int>(), pids, N, pb->ccount.as<int>(), s);
   scan_exclusive(pb->ccount.as<int>(), cptr, N, cptr + N, tmp, s);
-  launch_candidate_fill(pb->erow_ptr.as<int>(), pb->ecol.as<int>(), vptr, pb->vinc.as<int>(), ids, N, cptr,
+  launch_candidate_fill(pb->erow_ptr.as<int>(), pb->ecol.as<int>(), vptr, pb->vinc.as<int>(), pids, N, cptr,
                         pb->cand.as<int>(), pb->ucount.as<int>(), s);
   int* row_ptr = pb->row_ptr.as<int>();
   scan_exclusive(pb->ucount.as<int>(), row_ptr, N, row_ptr + N, tmp, s);
   launch_merged_write(pb->cand.as<int>(), cptr, row_ptr, pb->erow_ptr.as<int>(), pb->ecol.as<int>(), N,
                       pb->col.as<int>(), pb->eslot.as<int>(), s);
   HIPCHK(c, hipEventRecord(pb->ev[2], s));
-  // (3) assembly
+  // (3) assembly (friction terms at x_hat first)
+  launch_friction_terms(pb->fids.as<int4>(), nf, pb->xh.as<double>(), pb->fx0.as<double>(), pb->f64.as<double>(),
+                        pb->fric_e, pb->fgk.as<float>(), s);
   const float h2 = (float)(pb->dt * pb->dt);
   launch_elastic(pb->tets.as<int4>(), T, pb->rest.as<double>(), pb->xh.as<double>(), pb->Dminv9.as<float>(),
                  pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), h2, pb->epos.as<int>(),
                  pb->staging.as<float>(), pb->has_mat ? pb->mat.as<int>() : nullptr, flags, s);
   launch_assemble_rows(N, row_ptr, pb->col.as<int>(), pb->eslot.as<int>(), pb->ecptr.as<int>(), pb->staging.as<float>(),
-                       vptr, pb->vinc.as<int>(), ids, n, pb->cn.as<float>(), pb->cw.as<float>(), pb->cg.as<float>(),
-                       pb->ch.as<float>(), pb->mass.as<float>(), pb->xh.as<double>(), pb->xt.as<double>(),
+                       vptr, pb->vinc.as<int>(), pids, n, pb->cn.as<float>(), pb->cw.as<float>(), pb->cg.as<float>(),
+                       pb->ch.as<float>(), nf, pb->fgk.as<float>(), pb->mass.as<float>(), pb->xh.as<double>(), pb->xt.as<double>(),
                        pb->fixed.as<uint8_t>(), pb->vals.as<float>(), pb->grad.as<float>(), pb->Lf.as<float>(),
                        pb->Linv.as<float>(), pb->bhat.as<float>(), pb->bb_part.as<double>(), flags, s);
   // sliced storage of the scaled matrix: per column the source rows of its
@@ -328,7 +338,8 @@ void bf_problem_destroy(bf_problem* pb) {
                     &pb->qpairs[1], &pb->qtoc[0], &pb->qtoc[1], &pb->pkey, &pb->pkey2, &pb->pidx, &pb->pidx2,
                     &pb->sort_tmp, &pb->ctmp, &pb->htable, &pb->tvmin, &pb->keepn[0], &pb->keepn[1], &pb->posn[0],
                     &pb->posn[1], &pb->keepc, &pb->posc, &pb->nids, &pb->nlam, &pb->ngam, &pb->mpart,
-                    &pb->xstart, &pb->xprev, &pb->vout, &pb->mat};
+                    &pb->xstart, &pb->xprev, &pb->vout, &pb->mat, &pb->fids, &pb->f64, &pb->fx0, &pb->fgk,
+                    &pb->pids};
   for (DevBuf* b : bufs) b->release();
   for (auto& e : pb->ev)
     if (e) (void)hipEventDestroy(e);
@@ -423,6 +434,32 @@ bf_status bf_set_constraints(bf_problem* pb, const bf_constraint_desc* cd, int32
   return size_constraint_buffers(pb, cd->n_pt, cd->n_ee);
 }
 
+bf_status bf_set_friction(bf_problem* pb, double mu_f, double eps_v) {
+  if (!pb) return BF_ERR_INVALID_ARG;
+  bf_context* c = pb->ctx;
+  if (!(mu_f >= 0.0) || !std::isfinite(mu_f)) return fail(c, BF_ERR_INVALID_ARG, "mu_f must be finite and >= 0");
+  if (mu_f > 0.0 && (!(eps_v > 0.0) || !std::isfinite(eps_v)))
+    return fail(c, BF_ERR_INVALID_ARG, "eps_v must be positive and finite");
+  if (!pb->has_state) return fail(c, BF_ERR_STATE, "bf_set_friction needs the state (bf_set_state) first");
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  const int nf = mu_f > 0.0 ? pb->n_c : 0;
+  if (nf > 0) {
+    ALLOC(c, pb->fids, 16LL * nf);
+    ALLOC(c, pb->f64, 64LL * nf);
+    ALLOC(c, pb->fgk, 52LL * nf);
+    ALLOC(c, pb->fx0, 24LL * pb->N);
+    HIPCHK(c, hipMemcpyAsync(pb->fids.p, pb->cids.p, 16LL * nf, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(pb->fx0.p, pb->x.p, 24LL * pb->N, hipMemcpyDeviceToDevice, s));
+    launch_friction_capture(pb->fids.as<int4>(), pb->n_pt, nf, pb->x.as<double>(), pb->clam.as<double>(), pb->kappa,
+                            pb->delta, mu_f, pb->f64.as<double>(), s);
+    HIPCHK(c, hipGetLastError());
+  }
+  pb->n_f = nf;
+  pb->fric_e = eps_v * pb->dt;
+  return size_constraint_buffers(pb, pb->n_pt, pb->n_ee);
+}
+
 }  // extern "C"
 
 namespace bfal {
@@ -435,9 +472,11 @@ bf_status size_constraint_buffers(bf_problem* pb, int n_pt, int n_ee) {
   pb->n_pt = n_pt;
   pb->n_ee = n_ee;
   pb->n_c = n;
-  // size the per-step buffers for this constraint count
-  const long long cap = (long long)pb->nnzb_e + 6LL * n;
-  const long long capc = (long long)pb->nnzb_e - N + 6LL * n + 16;
+  // size the per-step buffers for this constraint count (the pattern also
+  // holds the stencils of the friction contacts)
+  const long long np = (long long)n + pb->n_f;
+  const long long cap = (long long)pb->nnzb_e + 6LL * np;
+  const long long capc = (long long)pb->nnzb_e - N + 6LL * np + 16;
   ALLOC(c, pb->lin64, 64LL * n + 64);
   ALLOC(c, pb->cn, 12LL * n + 16);
   ALLOC(c, pb->cw, 16LL * n + 16);
@@ -446,7 +485,8 @@ bf_status size_constraint_buffers(bf_problem* pb, int n_pt, int n_ee) {
   ALLOC(c, pb->viol_part, 8LL * (div_up(n, kBlock) + 1));
   ALLOC(c, pb->vcnt, 4LL * (N + 1));
   ALLOC(c, pb->vptr, 4LL * (N + 1));
-  ALLOC(c, pb->vinc, 16LL * n + 16);
+  ALLOC(c, pb->vinc, 16LL * np + 16);
+  if (pb->n_f > 0) ALLOC(c, pb->pids, 16LL * np + 16);
   ALLOC(c, pb->ccount, 4LL * (N + 1));
   ALLOC(c, pb->cptr, 4LL * (N + 1));
   ALLOC(c, pb->cand, 4LL * capc);
@@ -486,7 +526,7 @@ bf_status size_constraint_buffers(bf_problem* pb, int n_pt, int n_ee) {
   HIPCHK(c, hipStreamSynchronize(s));
   ALLOC(c, pb->part, 8LL * kPartsPerSystem);
   ALLOC(c, pb->pout, 24LL * N);
-  ALLOC(c, pb->scan_tmp, 4LL * scan_tmp_ints((long long)10 * pb->T + N + 6LL * n + 16));
+  ALLOC(c, pb->scan_tmp, 4LL * scan_tmp_ints((long long)10 * pb->T + N + 6LL * np + 16));
   pb->cap_nnzb = cap;
   pb->cap_cand = capc;
   c->err.clear();
@@ -799,7 +839,13 @@ namespace {
 bf_status energy_at(bf_problem* pb, const double* xs, double* L, int* inv) {
   bf_context* c = pb->ctx;
   hipStream_t s = c->stream;
-  const int np = energy_parts(pb->T, pb->n_c);
+  const int np = energy_parts(pb->T, pb->n_c, pb->n_f);
+  FrictionView fr;
+  fr.n_f = pb->n_f;
+  fr.ids = pb->fids.as<int4>();
+  fr.f64 = pb->f64.as<double>();
+  fr.x0 = pb->fx0.as<double>();
+  fr.e = pb->fric_e;
   ALLOC(c, pb->epart, 8LL * (np + 8));
   double* part = pb->epart.as<double>();
   int* flag = reinterpret_cast<int*>(part + np + 2);
@@ -807,7 +853,7 @@ bf_status energy_at(bf_problem* pb, const double* xs, double* L, int* inv) {
   launch_energy(pb->tets.as<int4>(), pb->T, pb->rest.as<double>(), pb->E.as<double>(), pb->nu.as<double>(),
                 pb->rho.as<double>(), pb->dt, xs, pb->xt.as<double>(), pb->cids.as<int4>(), pb->n_c,
                 pb->lin64.as<double>(), pb->x.as<double>(), pb->clam.as<double>(), pb->cgam.as<double>(), pb->kappa,
-                pb->delta, pb->has_mat ? pb->mat.as<int>() : nullptr, part, flag, s);
+                pb->delta, pb->has_mat ? pb->mat.as<int>() : nullptr, fr, part, flag, s);
   launch_sum_to(part, np, part + np, s);
   // part[np] = the sum, part[np + 2] holds the inversion flag (an int)
   double h[3] = {0.0, 0.0, 0.0};

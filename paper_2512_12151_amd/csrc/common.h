@@ -161,11 +161,20 @@ void launch_cmap(const int4* ids, int n_c, const int* row_ptr, const int* col, i
 // inverted tet raised into *inverted; xt = xa + r p; the multiplier and
 // decay update in place (counts of active constraints and the violation
 // max into per-workgroup partials).
-int energy_parts(int T, int n_c);
+// The friction set of a step (Appendix A): contacts, the FP64 capture SoA
+// [8][n_f] (normal, weights, coefficient), x^t and e = eps_v h.
+struct FrictionView {
+  int n_f = 0;
+  const int4* ids = nullptr;
+  const double* f64 = nullptr;
+  const double* x0 = nullptr;
+  double e = 0.0;
+};
+int energy_parts(int T, int n_c, int n_f);
 void launch_energy(const int4* tets, int T, const double* rest, const double* E, const double* nu,
                    const double* rho, double h, const double* x, const double* xt, const int4* ids, int n_c,
                    const double* lin64, const double* xlin, const double* lam, const double* gam, double kappa,
-                   double delta, const int* mat, double* part, int* inverted, hipStream_t s);
+                   double delta, const int* mat, FrictionView fr, double* part, int* inverted, hipStream_t s);
 void launch_state_axpy(int n3, const double* xa, double r, const double* p, double* xt, hipStream_t s);
 // ccd.hip: collision queries along x -> x_hat (boxes are 24-byte FP32 min/max).
 size_t ccd_sort_tmp_bytes(int n);
@@ -214,6 +223,13 @@ void launch_dual_update(const int4* ids, int n_c, const double* lin64, const dou
                         double kappa, double delta, double decay, double* lam, double* gam, double* part,
                         hipStream_t s);
 
+// contact.hip: semi-implicit friction (capture at x^t into FP64 SoA [8][n_f];
+// per-step terms at x_hat into FP32 SoA [13][n_f])
+void launch_friction_capture(const int4* ids, int n_pt, int n_f, const double* x, const double* lam, double kappa,
+                             double delta, double mu_f, double* f64, hipStream_t s);
+void launch_friction_terms(const int4* ids, int n_f, const double* xh, const double* x0, const double* f64, double e,
+                           float* fgk, hipStream_t s);
+
 // elastic.hip
 void launch_elastic(const int4* tets, int T, const double* rest, const double* xh, const float* Dminv9,
                     const float* vol, const float* mu, const float* lam, float h2, const int* epos,
@@ -222,8 +238,8 @@ void launch_elastic(const int4* tets, int T, const double* rest, const double* x
 // assemble.hip
 void launch_assemble_rows(int N, const int* row_ptr, const int* col, const int* eslot, const int* ecptr,
                           const float* staging, const int* vptr, const int* vinc, const int4* ids, int n_c,
-                          const float* cn, const float* cw, const float* cg, const float* ch,
-                          const float* mass, const double* xh, const double* xt, const uint8_t* fixed,
+                          const float* cn, const float* cw, const float* cg, const float* ch, int n_f,
+                          const float* fgk, const float* mass, const double* xh, const double* xt, const uint8_t* fixed,
                           float* vals, float* grad, float* Lf, float* Linv, float* bhat, double* bb_part,
                           int* flags, hipStream_t s);
 // Sliced storage of the scaled matrix: lower_count / lower_fill /

@@ -33,6 +33,82 @@ __device__ inline double seg_param(d3 p, d3 u, d3 e) { return clamp01(dot(sub(p,
 
 __device__ inline int vtx(const int4& t, int a) { return a == 0 ? t.x : a == 1 ? t.y : a == 2 ? t.z : t.w; }
 
+// Closest points of a PT pair (point X0, triangle X1 X2 X3: interior projection
+// if inside, else the best edge point) or an EE pair (segments X0 X1 and
+// X2 X3) at x: diff = (point of the first primitive) - (point of the second)
+// = sum_a w_a X_a.  Returns true for a degenerate pair (sliver triangle,
+// near-parallel edges) whose gradient is not unique.
+__device__ inline bool closest_pair(const int4 t, bool is_pt, const double* __restrict__ x, d3& diff, double w[4]) {
+  const d3 X0 = ld3(x, t.x), X1 = ld3(x, t.y), X2 = ld3(x, t.z), X3 = ld3(x, t.w);
+  double w0, w1, w2, w3;
+  bool degenerate = false;
+  if (is_pt) {
+    // point X0 against triangle (X1, X2, X3): interior projection if inside, else best edge point
+    const d3 e1 = sub(X2, X1), e2 = sub(X3, X1), r = sub(X0, X1);
+    const double a11 = dot(e1, e1), a12 = dot(e1, e2), a22 = dot(e2, e2);
+    const double r1 = dot(e1, r), r2 = dot(e2, r);
+    const double det = a11 * a22 - a12 * a12;
+    degenerate = !(det > 1e-12 * a11 * a22);
+    double best = INFINITY, b0 = 1.0, b1 = 0.0, b2 = 0.0;
+    if (!degenerate) {
+      const double u = (a22 * r1 - a12 * r2) / det, v = (a11 * r2 - a12 * r1) / det;
+      if (u >= 0.0 && v >= 0.0 && u + v <= 1.0) {
+        const d3 q = add(X1, add(mul(e1, u), mul(e2, v)));
+        const d3 dd = sub(X0, q);
+        best = sqrt(dot(dd, dd));
+        b0 = 1.0 - u - v; b1 = u; b2 = v;
+      }
+    }
+    const d3 T[3] = {X1, X2, X3};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int ia = k, ib = (k + 1) % 3;
+      const double s = seg_param(X0, T[ia], sub(T[ib], T[ia]));
+      const d3 q = add(T[ia], mul(sub(T[ib], T[ia]), s));
+      const d3 dd = sub(X0, q);
+      const double dist = sqrt(dot(dd, dd));
+      if (dist < best) {
+        best = dist;
+        double bb[3] = {0.0, 0.0, 0.0};
+        bb[ia] = 1.0 - s; bb[ib] = s;
+        b0 = bb[0]; b1 = bb[1]; b2 = bb[2];
+      }
+    }
+    const d3 q = add(add(mul(X1, b0), mul(X2, b1)), mul(X3, b2));
+    diff = sub(X0, q);
+    w0 = 1.0; w1 = -b0; w2 = -b1; w3 = -b2;
+  } else {
+    // segments X0 + s (X1 - X0) and X2 + t (X3 - X2)
+    const d3 ea = sub(X1, X0), eb = sub(X3, X2), r = sub(X0, X2);
+    const double aa = dot(ea, ea), bb = dot(eb, eb), ab = dot(ea, eb);
+    const double ar = dot(ea, r), br = dot(eb, r);
+    const d3 cr = cross(ea, eb);
+    degenerate = dot(cr, cr) < 1e-8 * aa * bb;   // (near-)parallel pair: gradient not unique
+    const double det = aa * bb - ab * ab;
+    double best = INFINITY, sb = 0.0, tb = 0.0;
+    if (!degenerate && det > 0.0) {
+      const double s = (-ar * bb + ab * br) / det, tt = (aa * br - ab * ar) / det;
+      if (s >= 0.0 && s <= 1.0 && tt >= 0.0 && tt <= 1.0) {
+        const d3 dd = sub(add(X0, mul(ea, s)), add(X2, mul(eb, tt)));
+        best = sqrt(dot(dd, dd));
+        sb = s; tb = tt;
+      }
+    }
+    const double cs[4] = {0.0, 1.0, seg_param(X2, X0, ea), seg_param(X3, X0, ea)};
+    const double ct[4] = {seg_param(X0, X2, eb), seg_param(X1, X2, eb), 0.0, 1.0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const d3 dd = sub(add(X0, mul(ea, cs[k])), add(X2, mul(eb, ct[k])));
+      const double dist = sqrt(dot(dd, dd));
+      if (dist < best) { best = dist; sb = cs[k]; tb = ct[k]; }
+    }
+    diff = sub(add(X0, mul(ea, sb)), add(X2, mul(eb, tb)));
+    w0 = 1.0 - sb; w1 = sb; w2 = -(1.0 - tb); w3 = -tb;
+  }
+  w[0] = w0; w[1] = w1; w[2] = w2; w[3] = w3;
+  return degenerate;
+}
+
 __global__ void k_check_constraints(const int4* __restrict__ ids, int n_c, int N, const double* __restrict__ lam,
                                     const double* __restrict__ gam, int* flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -58,72 +134,10 @@ k_contact_lin(const int4* __restrict__ ids, int n_pt, int n_c, const double* __r
   if (i < n_c) {
     const int4 t = ids[i];
     const d3 X0 = ld3(x, t.x), X1 = ld3(x, t.y), X2 = ld3(x, t.z), X3 = ld3(x, t.w);
-    double w0, w1, w2, w3;
+    double wv[4];
     d3 diff;
-    bool degenerate = false;
-    if (i < n_pt) {
-      // point X0 against triangle (X1, X2, X3): interior projection if inside, else best edge point
-      const d3 e1 = sub(X2, X1), e2 = sub(X3, X1), r = sub(X0, X1);
-      const double a11 = dot(e1, e1), a12 = dot(e1, e2), a22 = dot(e2, e2);
-      const double r1 = dot(e1, r), r2 = dot(e2, r);
-      const double det = a11 * a22 - a12 * a12;
-      degenerate = !(det > 1e-12 * a11 * a22);
-      double best = INFINITY, b0 = 1.0, b1 = 0.0, b2 = 0.0;
-      if (!degenerate) {
-        const double u = (a22 * r1 - a12 * r2) / det, v = (a11 * r2 - a12 * r1) / det;
-        if (u >= 0.0 && v >= 0.0 && u + v <= 1.0) {
-          const d3 q = add(X1, add(mul(e1, u), mul(e2, v)));
-          const d3 dd = sub(X0, q);
-          best = sqrt(dot(dd, dd));
-          b0 = 1.0 - u - v; b1 = u; b2 = v;
-        }
-      }
-      const d3 T[3] = {X1, X2, X3};
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int ia = k, ib = (k + 1) % 3;
-        const double s = seg_param(X0, T[ia], sub(T[ib], T[ia]));
-        const d3 q = add(T[ia], mul(sub(T[ib], T[ia]), s));
-        const d3 dd = sub(X0, q);
-        const double dist = sqrt(dot(dd, dd));
-        if (dist < best) {
-          best = dist;
-          double bb[3] = {0.0, 0.0, 0.0};
-          bb[ia] = 1.0 - s; bb[ib] = s;
-          b0 = bb[0]; b1 = bb[1]; b2 = bb[2];
-        }
-      }
-      const d3 q = add(add(mul(X1, b0), mul(X2, b1)), mul(X3, b2));
-      diff = sub(X0, q);
-      w0 = 1.0; w1 = -b0; w2 = -b1; w3 = -b2;
-    } else {
-      // segments X0 + s (X1 - X0) and X2 + t (X3 - X2)
-      const d3 ea = sub(X1, X0), eb = sub(X3, X2), r = sub(X0, X2);
-      const double aa = dot(ea, ea), bb = dot(eb, eb), ab = dot(ea, eb);
-      const double ar = dot(ea, r), br = dot(eb, r);
-      const d3 cr = cross(ea, eb);
-      degenerate = dot(cr, cr) < 1e-8 * aa * bb;   // (near-)parallel pair: gradient not unique
-      const double det = aa * bb - ab * ab;
-      double best = INFINITY, sb = 0.0, tb = 0.0;
-      if (!degenerate && det > 0.0) {
-        const double s = (-ar * bb + ab * br) / det, tt = (aa * br - ab * ar) / det;
-        if (s >= 0.0 && s <= 1.0 && tt >= 0.0 && tt <= 1.0) {
-          const d3 dd = sub(add(X0, mul(ea, s)), add(X2, mul(eb, tt)));
-          best = sqrt(dot(dd, dd));
-          sb = s; tb = tt;
-        }
-      }
-      const double cs[4] = {0.0, 1.0, seg_param(X2, X0, ea), seg_param(X3, X0, ea)};
-      const double ct[4] = {seg_param(X0, X2, eb), seg_param(X1, X2, eb), 0.0, 1.0};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const d3 dd = sub(add(X0, mul(ea, cs[k])), add(X2, mul(eb, ct[k])));
-        const double dist = sqrt(dot(dd, dd));
-        if (dist < best) { best = dist; sb = cs[k]; tb = ct[k]; }
-      }
-      diff = sub(add(X0, mul(ea, sb)), add(X2, mul(eb, tb)));
-      w0 = 1.0 - sb; w1 = sb; w2 = -(1.0 - tb); w3 = -tb;
-    }
+    const bool degenerate = closest_pair(t, i < n_pt, x, diff, wv);
+    const double w0 = wv[0], w1 = wv[1], w2 = wv[2], w3 = wv[3];
     const double d = sqrt(dot(diff, diff));
     if (degenerate || !(d > 0.0)) {
       atomicOr(flags, FLAG_DEGENERATE);
@@ -334,6 +348,80 @@ __global__ void k_cmap(const int4* __restrict__ ids, int n_c, const int* __restr
   cmap[i] = find_slot(row_ptr, col, min(va, vb), max(va, vb));
 }
 
+// Friction capture (Appendix A, semi-implicit): per contact of the previous
+// step, at x^t, the closest-point weights w, the normal n and the coefficient
+// coef = mu_f max(0, lambda - kappa (d - delta)) = h^2 mu_f F^t.  FP64 SoA
+// [8][n_f]: n (3), w (4), coef.  A degenerate pair contributes nothing.
+__global__ void __launch_bounds__(kBlock)
+k_friction_capture(const int4* __restrict__ ids, int n_pt, int n_f, const double* __restrict__ x,
+                   const double* __restrict__ lam, double kappa, double delta, double mu_f,
+                   double* __restrict__ f64) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_f) return;
+  double w[4];
+  d3 diff;
+  const bool degenerate = closest_pair(ids[i], i < n_pt, x, diff, w);
+  const double d = sqrt(dot(diff, diff));
+  double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (!degenerate && d > 0.0) {
+    const d3 n = mul(diff, 1.0 / d);
+    v[0] = n.x; v[1] = n.y; v[2] = n.z;
+    v[3] = w[0]; v[4] = w[1]; v[5] = w[2]; v[6] = w[3];
+    v[7] = mu_f * fmax(0.0, lam[i] - kappa * (d - delta));
+  }
+#pragma unroll
+  for (int m = 0; m < 8; ++m) f64[(long long)m * n_f + i] = v[m];
+}
+
+// Friction terms at x_hat (IPC's smoothed f_0 of the tangential relative
+// displacement, e = eps_v h): with v = sum_a w_a (x_hat_a - x^t_a), u = P v
+// (P = I - n n^T), y = |u|, t = u / y,
+//   gradient in v:  coef f_1(y)/y u
+//   Hessian in v:   coef (f_1(y)/y P + (f_1'(y) - f_1(y)/y) t t^T),
+// f_1(y)/y = 1/y and f_1' = 0 for y >= e, 2/e - y/e^2 and 2/e - 2y/e^2 below.
+// Its eigenvalues coef f_1/y (tangent, across t), coef f_1' (along t) and 0
+// (normal) are never negative, so the SPD projection leaves it unchanged.
+// Computed in FP64, stored FP32 SoA [13][n_f]: gradient (3), Hessian (6:
+// xx xy xz yy yz zz), weights (4).
+__global__ void __launch_bounds__(kBlock)
+k_friction_terms(const int4* __restrict__ ids, int n_f, const double* __restrict__ xh,
+                 const double* __restrict__ x0, const double* __restrict__ f64, double e,
+                 float* __restrict__ fgk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_f) return;
+  const int4 t4 = ids[i];
+  const int vv[4] = {t4.x, t4.y, t4.z, t4.w};
+  double fv[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) fv[m] = f64[(long long)m * n_f + i];
+  d3 v = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < 4; ++a) v = add(v, mul(sub(ld3(xh, vv[a]), ld3(x0, vv[a])), fv[3 + a]));
+  const d3 n = {fv[0], fv[1], fv[2]};
+  const d3 u = sub(v, mul(n, dot(n, v)));
+  const double y = sqrt(dot(u, u));
+  const double coef = fv[7];
+  const double f1y = y >= e ? 1.0 / y : 2.0 / e - y / (e * e);
+  const double f1p = y >= e ? 0.0 : 2.0 / e - 2.0 * y / (e * e);
+  const d3 tt = y > 0.0 ? mul(u, 1.0 / y) : d3{0.0, 0.0, 0.0};
+  const double g[3] = {coef * f1y * u.x, coef * f1y * u.y, coef * f1y * u.z};
+  const double nn[3] = {n.x, n.y, n.z}, tv[3] = {tt.x, tt.y, tt.z};
+  const int ri[6] = {0, 0, 0, 1, 1, 2}, ci[6] = {0, 1, 2, 1, 2, 2};
+  float out[13];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) out[k] = (float)g[k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int r = ri[k], c = ci[k];
+    const double P = (r == c ? 1.0 : 0.0) - nn[r] * nn[c];
+    out[3 + k] = (float)(coef * (f1y * P + (f1p - f1y) * tv[r] * tv[c]));
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) out[9 + a] = (float)fv[3 + a];
+#pragma unroll
+  for (int m = 0; m < 13; ++m) fgk[(long long)m * n_f + i] = out[m];
+}
+
 }  // namespace
 
 void launch_check_constraints(const int4* ids, int n_c, int N, const double* lam, const double* gam, int* flags,
@@ -381,6 +469,20 @@ void launch_merged_write(const int* cand, const int* cptr, const int* row_ptr, c
 void launch_cmap(const int4* ids, int n_c, const int* row_ptr, const int* col, int* cmap, hipStream_t s) {
   if (n_c > 0)
     hipLaunchKernelGGL(k_cmap, dim3(div_up(10LL * n_c, kBlock)), dim3(kBlock), 0, s, ids, n_c, row_ptr, col, cmap);
+}
+
+void launch_friction_capture(const int4* ids, int n_pt, int n_f, const double* x, const double* lam, double kappa,
+                             double delta, double mu_f, double* f64, hipStream_t s) {
+  if (n_f > 0)
+    hipLaunchKernelGGL(k_friction_capture, dim3(div_up(n_f, kBlock)), dim3(kBlock), 0, s, ids, n_pt, n_f, x, lam,
+                       kappa, delta, mu_f, f64);
+}
+
+void launch_friction_terms(const int4* ids, int n_f, const double* xh, const double* x0, const double* f64, double e,
+                           float* fgk, hipStream_t s) {
+  if (n_f > 0)
+    hipLaunchKernelGGL(k_friction_terms, dim3(div_up(n_f, kBlock)), dim3(kBlock), 0, s, ids, n_f, xh, x0, f64, e,
+                       fgk);
 }
 
 }  // namespace bfal

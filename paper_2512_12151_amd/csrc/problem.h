@@ -36,6 +36,11 @@ struct bf_problem {
   int n_pt = 0, n_ee = 0, n_c = 0;
   DevBuf cids, clam, cgam;
   double kappa = 1.0, delta = 0.0;
+  // semi-implicit friction (Appendix A): the contacts captured at x^t, held for
+  // the step; pids = constraints then friction contacts (the pattern's stencils)
+  int n_f = 0;
+  double fric_e = 0.0;             // eps_v h
+  DevBuf fids, f64, fx0, fgk, pids;
   // per-step buffers
   DevBuf cn, cw, cg, ch, viol_part;
   DevBuf vcnt, vptr, vinc;

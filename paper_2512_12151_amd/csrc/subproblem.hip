@@ -102,14 +102,14 @@ __device__ void stretch_sums(const double G[3][3], double& sum1, double& sum2) {
 }
 
 // One partial per workgroup: tets in the first ceil(T / kEBlock) workgroups,
-// constraints in the rest.
+// constraints in the next ceil(n_c / kEBlock), friction contacts in the rest.
 __global__ void __launch_bounds__(kEBlock)
 k_energy(const int4* __restrict__ tets, int T, const double* __restrict__ rest, const double* __restrict__ E,
          const double* __restrict__ nu, const double* __restrict__ rho, double h2, const double* __restrict__ x,
          const double* __restrict__ xt, const int4* __restrict__ ids, int n_c, const double* __restrict__ lin64,
          const double* __restrict__ xlin, const double* __restrict__ lam, const double* __restrict__ gam,
-         double kappa, double delta, int tet_groups, const int* __restrict__ mat, double* __restrict__ part,
-         int* inverted) {
+         double kappa, double delta, int tet_groups, int con_groups, const int* __restrict__ mat, FrictionView fr,
+         double* __restrict__ part, int* inverted) {
   double e = 0.0;
   if ((int)blockIdx.x < tet_groups) {
     const int k = blockIdx.x * kEBlock + threadIdx.x;
@@ -183,6 +183,27 @@ k_energy(const int4* __restrict__ tets, int T, const double* __restrict__ rest, 
           in += dd * dd;
         }
       e += 0.5 * (rho[k] * vol / 4.0) * in;
+    }
+  } else if ((int)blockIdx.x >= tet_groups + con_groups) {
+    // friction (Appendix A): coef f_0(|u|) with IPC's smoothed norm, e = eps_v h
+    const int i = (blockIdx.x - tet_groups - con_groups) * kEBlock + threadIdx.x;
+    if (i < fr.n_f) {
+      const int4 t = fr.ids[i];
+      const int vv[4] = {t.x, t.y, t.z, t.w};
+      const long long nf = fr.n_f;
+      double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const double wa = fr.f64[(3 + a) * nf + i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[k] += wa * (x[3LL * vv[a] + k] - fr.x0[3LL * vv[a] + k]);
+      }
+      const double n0 = fr.f64[i], n1 = fr.f64[nf + i], n2 = fr.f64[2 * nf + i];
+      const double vn = n0 * v[0] + n1 * v[1] + n2 * v[2];
+      const double u0 = v[0] - vn * n0, u1 = v[1] - vn * n1, u2 = v[2] - vn * n2;
+      const double y = sqrt(u0 * u0 + u1 * u1 + u2 * u2), ee = fr.e;
+      const double f0 = y >= ee ? y : -y * y * y / (3.0 * ee * ee) + y * y / ee + ee / 3.0;
+      e = fr.f64[7 * nf + i] * f0;
     }
   } else {
     const int i = (blockIdx.x - tet_groups) * kEBlock + threadIdx.x;
@@ -296,7 +317,7 @@ void launch_velocity(int n3, const double* x, const double* x0, double inv_h, do
   hipLaunchKernelGGL(k_velocity, dim3(div_up(n3, kEBlock)), dim3(kEBlock), 0, s, n3, x, x0, inv_h, v);
 }
 
-int energy_parts(int T, int n_c) { return div_up(T, kEBlock) + div_up(n_c, kEBlock); }
+int energy_parts(int T, int n_c, int n_f) { return div_up(T, kEBlock) + div_up(n_c, kEBlock) + div_up(n_f, kEBlock); }
 
 int diag_max_parts(int N) { return div_up(N, kEBlock); }
 
@@ -309,11 +330,11 @@ void launch_diag_max(int N, const int* erow_ptr, const int* ecptr, const float* 
 void launch_energy(const int4* tets, int T, const double* rest, const double* E, const double* nu,
                    const double* rho, double h, const double* x, const double* xt, const int4* ids, int n_c,
                    const double* lin64, const double* xlin, const double* lam, const double* gam, double kappa,
-                   double delta, const int* mat, double* part, int* inverted, hipStream_t s) {
-  const int tg = div_up(T, kEBlock);
-  const int g = energy_parts(T, n_c);
+                   double delta, const int* mat, FrictionView fr, double* part, int* inverted, hipStream_t s) {
+  const int tg = div_up(T, kEBlock), cg = div_up(n_c, kEBlock);
+  const int g = energy_parts(T, n_c, fr.n_f);
   hipLaunchKernelGGL(k_energy, dim3(g), dim3(kEBlock), 0, s, tets, T, rest, E, nu, rho, h * h, x, xt, ids, n_c, lin64,
-                     xlin, lam, gam, kappa, delta, tg, mat, part, inverted);
+                     xlin, lam, gam, kappa, delta, tg, cg, mat, fr, part, inverted);
 }
 
 void launch_state_axpy(int n3, const double* xa, double r, const double* p, double* xt, hipStream_t s) {

@@ -35,6 +35,11 @@ bf_status bf_time_step(bf_problem* pb, const bf_time_step_opts* o, double* x_out
   HIPCHK(c, hipMemcpyAsync(pb->xstart.p, pb->x.p, 8 * n3, hipMemcpyDeviceToDevice, s));
   bf_time_step_stats out{};
   bf_status warn = BF_OK;
+  {
+    // the friction set of this step, from the incoming contacts at x^t (Appendix A)
+    bf_status st = bf_set_friction(pb, o->mu_f, o->eps_v);
+    if (st != BF_OK) return st;
+  }
   if (o->mu_init_c > 0.0) {
     double mu = 0.0;
     bf_status st = bf_mu_init(pb, o->mu_init_c, &mu);
