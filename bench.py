@@ -106,7 +106,7 @@ def cpu_baseline(sc, gpu_iters, frac):
         full = oracle.prepare(sc)
         m = len(sub["tets"])
         full.tets, full.Dminv, full.vol, full.A = full.tets[:m], full.Dminv[:m], full.vol[:m], full.A[:m]
-        full.mu_l, full.lam_l = full.mu_l[:m], full.lam_l[:m]
+        full.mu_l, full.lam_l, full.mat = full.mu_l[:m], full.lam_l[:m], full.mat[:m]
         t0 = time.perf_counter()
         st = oracle.assemble(sub, full)
         t_asm = time.perf_counter() - t0
