@@ -226,6 +226,82 @@ def run_ccd(reps=5):
             "active_after": [st_upd["n_pt"], st_upd["n_ee"]]}
 
 
+def run_variants(ctx, t, sc, opts, base):
+    """The other materials and friction (Table 2, Appendix A) on the large
+    workload: one Newton step each (after a warm-up step) with every tet stable
+    Neo-Hookean or corotated linear, and with Neo-Hookean plus the friction set
+    captured from the workload's 1M contacts (eps_v = 1e-3 as in Table 2;
+    mu_f = 1e-5 because the workload's multipliers, up to 1e4, are drawn far
+    above what a step on its 1e-2 kg nodes produces: mu_f keeps the sticking
+    stiffness 2 mu_f lambda / (eps_v h) below kappa, which the FP32 blocks can
+    hold).  The assembly phase holds the element kernel of the material and
+    the friction terms; the PCG solves a different matrix in each, so its
+    iteration count is reported beside the time."""
+    import torch
+
+    from paper_2512_12151_amd import bfal
+    T = len(sc["tets"])
+    out = {}
+    keys = ("ms_lin", "ms_pattern", "ms_assemble", "ms_pcg")
+
+    def step(pb):
+        res = torch.empty((len(sc["rest"]), 3), dtype=torch.float64, device="cuda:0")
+        pb.newton_step(out=res, **opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st, status = pb.newton_step(out=res, **opts)
+        ms = (time.perf_counter() - t0) * 1e3
+        return {"ms_step": round(ms, 3), "status": status, "pcg_iters": st["pcg_iters"],
+                **{k: round(st[k], 3) for k in keys}}
+
+    for name, code in (("snh", 1), ("cor", 2)):
+        mat = torch.full((T,), code, dtype=torch.int32, device="cuda:0")
+        pb = bfal.Problem(ctx, t["tets"], t["rest"], t["E"], t["nu"], t["rho"], t["fixed"], material=mat)
+        pb.set_state(t["x"], t["x_hat"], t["x_tilde"], sc["dt"])
+        pb.set_constraints(t["pt"], t["ee"], t["lam"], t["gamma"], sc["kappa"], sc["delta"])
+        out[name] = step(pb)
+        pb.close()
+        log(f"material {name}: {out[name]}")
+    base.set_friction(1e-5, 1e-3)
+    out["nh_friction"] = step(base)
+    base.set_friction(0.0)
+    log(f"friction: {out['nh_friction']}")
+    return out
+
+
+def run_time_step(reps=3):
+    """Algorithm 1 with friction: two stacked 8^3-cell cubes (12,288 tets), the
+    upper one thrown down at 0.5 m/s and sideways at 0.2 m/s onto the lower one;
+    the first step lands it (contacts appear), the second, timed, carries the
+    active set and multipliers and captures the friction set from them
+    (mu_f = 0.5, eps_v = 1e-3, K_min = 6 as the paper uses with friction).
+    Median of reps runs of the second step on fresh problems."""
+    import scenes
+    from paper_2512_12151_amd import bfal
+    sc = dict(scenes.falling_cubes(n=8, jitter=1e-5))
+    N, h = len(sc["x"]), sc["dt"]
+    sc["x_tilde"] = sc["x_tilde"].copy()
+    sc["x_tilde"][N // 2:, 0] += h * 0.2
+    ctx = bfal.Context(0)
+    kw = dict(tol=1e-5, mu_f=0.5, eps_v=1e-3, k_min=6)
+    ms, last = [], None
+    for _ in range(reps):
+        pb = bfal.Problem.from_scene(ctx, sc)
+        x1, v1, st1, _ = pb.time_step(**kw)
+        pb.set_state(x1, x1.copy(), x1 + h * v1, h)
+        t0 = time.perf_counter()
+        _, _, last, status = pb.time_step(**kw)
+        ms.append((time.perf_counter() - t0) * 1e3)
+        pb.close()
+    ctx.close()
+    r = lambda v: round(float(v), 3)
+    return {"workload": "two 8^3-cell cubes (12288 tets), thrown at (0.2, 0, -0.5) m/s, the step after landing",
+            "ms_step": r(np.median(ms)), "status": status, "outer_iters": last["outer_iters"],
+            "newton_iters": last["newton_iters"], "pcg_iters": last["pcg_iters"],
+            "ms_subproblem": r(last["ms_subproblem"]), "ms_ccd": r(last["ms_ccd"]),
+            "active_after": [last["n_pt"], last["n_ee"]]}
+
+
 def run_serve(n_req, seed=5, loads=(0.8, 1.2, 2.0)):
     """Serving (continuous batching) on a stream of two-stacked-cube requests
     (tets ~ LogU[2k, 300k]).  The one-at-a-time service time is measured first
@@ -295,6 +371,8 @@ def main():
                     help="PCG iteration cap (lower it only for counter-collection runs)")
     ap.add_argument("--no-subproblem", dest="subproblem", action="store_false",
                     help="skip the SolveSubproblem measurement (Newton loop with line search, multiplier update)")
+    ap.add_argument("--no-variants", dest="variants", action="store_false",
+                    help="skip the material / friction step variants and the time-step leg")
     ap.add_argument("--no-ccd", dest="ccd", action="store_false",
                     help="skip the collision-query measurement (MaxStepSize, UpdateActiveSet)")
     ap.add_argument("--serve-requests", type=int, default=512,
@@ -403,11 +481,16 @@ def main():
         for _ in range(5):
             pb.energy()
         t_energy = (time.perf_counter() - t0) / 5 * 1e3
+    if args.variants:
+        line["variants"] = run_variants(ctx, t, sc, opts, pb)
     pb.close()
     if args.subproblem:
         line["subproblem"] = run_subproblem(args)
         line["subproblem"]["energy_eval_ms_" + args.workload] = round(t_energy, 3)
         log(f"subproblem: {line['subproblem']}")
+    if args.variants:
+        line["time_step"] = run_time_step()
+        log(f"time step: {line['time_step']}")
     if args.ccd:
         line["ccd"] = run_ccd()
         log(f"ccd: {line['ccd']}")

@@ -157,14 +157,8 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
   int* flags = pb->flags.as<int>();
   int* tmp = pb->scan_tmp.as<int>();
   const int4* ids = pb->cids.as<int4>();
-  // the pattern's stencils: the constraints, then the friction contacts
-  const int4* pids = ids;
-  const int npat = n + nf;
-  if (nf > 0) {
-    if (n) HIPCHK(c, hipMemcpyAsync(pb->pids.p, pb->cids.p, 16LL * n, hipMemcpyDeviceToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(pb->pids.as<char>() + 16LL * n, pb->fids.p, 16LL * nf, hipMemcpyDeviceToDevice, s));
-    pids = pb->pids.as<int4>();
-  }
+  const int4* pids = ids;   // the pattern's stencils
+  int npat = n;
   fill_int(flags, 0, 16, s);
   HIPCHK(c, hipEventRecord(pb->ev[0], s));
   // (1) constraint linearization at x and AL factors at x_hat
@@ -174,7 +168,27 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
                      pb->cg.as<float>(), pb->ch.as<float>(), pb->lin64.as<double>(), pb->viol_part.as<double>(), flags,
                      s);
   HIPCHK(c, hipEventRecord(pb->ev[1], s));
-  // (2) merged pattern: vertex -> constraint incidence, candidates, unique rows
+  // (2) merged pattern: vertex -> constraint incidence, candidates, unique rows.
+  // Its stencils: the constraints, then the friction contacts that match no
+  // constraint (a matched contact adds its terms at its constraint's incidences)
+  if (nf > 0) {
+    const unsigned cap = friction_table_capacity(n);
+    int* cfr = pb->cfr.as<int>();
+    int* extra = pb->fextra.as<int>();
+    int* pos = pb->fpos.as<int>();
+    fill_int(pb->ftab.as<int>(), -1, cap, s);
+    fill_int(cfr, -1, n + 1, s);
+    launch_stencil_insert(ids, n, pb->ftab.as<int>(), cap - 1, s);
+    launch_friction_match(pb->fids.as<int4>(), nf, ids, pb->ftab.as<int>(), cap - 1, cfr, extra, s);
+    scan_exclusive(extra, pos, nf, pos + nf, tmp, s);
+    int n_extra = 0;
+    HIPCHK(c, hipMemcpyAsync(&n_extra, pos + nf, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (n) HIPCHK(c, hipMemcpyAsync(pb->pids.p, pb->cids.p, 16LL * n, hipMemcpyDeviceToDevice, s));
+    launch_friction_extra(pb->fids.as<int4>(), nf, extra, pos, n, pb->pids.as<int4>(), pb->fext.as<int>(), s);
+    HIPCHK(c, hipStreamSynchronize(s));
+    pids = pb->pids.as<int4>();
+    npat = n + n_extra;
+  }
   int* vcnt = pb->vcnt.as<int>();
   int* vptr = pb->vptr.as<int>();
   fill_int(vcnt, 0, N, s);
@@ -202,7 +216,8 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
                  pb->staging.as<float>(), pb->has_mat ? pb->mat.as<int>() : nullptr, flags, s);
   launch_assemble_rows(N, row_ptr, pb->col.as<int>(), pb->eslot.as<int>(), pb->ecptr.as<int>(), pb->staging.as<float>(),
                        vptr, pb->vinc.as<int>(), pids, n, pb->cn.as<float>(), pb->cw.as<float>(), pb->cg.as<float>(),
-                       pb->ch.as<float>(), nf, pb->fgk.as<float>(), pb->mass.as<float>(), pb->xh.as<double>(), pb->xt.as<double>(),
+                       pb->ch.as<float>(), nf, pb->fgk.as<float>(), pb->cfr.as<int>(), pb->fext.as<int>(),
+                       pb->mass.as<float>(), pb->xh.as<double>(), pb->xt.as<double>(),
                        pb->fixed.as<uint8_t>(), pb->vals.as<float>(), pb->grad.as<float>(), pb->Lf.as<float>(),
                        pb->Linv.as<float>(), pb->bhat.as<float>(), pb->bb_part.as<double>(), flags, s);
   // sliced storage of the scaled matrix: per column the source rows of its
@@ -339,7 +354,7 @@ void bf_problem_destroy(bf_problem* pb) {
                     &pb->sort_tmp, &pb->ctmp, &pb->htable, &pb->tvmin, &pb->keepn[0], &pb->keepn[1], &pb->posn[0],
                     &pb->posn[1], &pb->keepc, &pb->posc, &pb->nids, &pb->nlam, &pb->ngam, &pb->mpart,
                     &pb->xstart, &pb->xprev, &pb->vout, &pb->mat, &pb->fids, &pb->f64, &pb->fx0, &pb->fgk,
-                    &pb->pids};
+                    &pb->pids, &pb->ftab, &pb->cfr, &pb->fextra, &pb->fpos, &pb->fext};
   for (DevBuf* b : bufs) b->release();
   for (auto& e : pb->ev)
     if (e) (void)hipEventDestroy(e);
@@ -486,7 +501,14 @@ bf_status size_constraint_buffers(bf_problem* pb, int n_pt, int n_ee) {
   ALLOC(c, pb->vcnt, 4LL * (N + 1));
   ALLOC(c, pb->vptr, 4LL * (N + 1));
   ALLOC(c, pb->vinc, 16LL * np + 16);
-  if (pb->n_f > 0) ALLOC(c, pb->pids, 16LL * np + 16);
+  if (pb->n_f > 0) {
+    ALLOC(c, pb->pids, 16LL * np + 16);
+    ALLOC(c, pb->ftab, 4LL * friction_table_capacity(n));
+    ALLOC(c, pb->cfr, 4LL * (n + 1));
+    ALLOC(c, pb->fextra, 4LL * (pb->n_f + 1));
+    ALLOC(c, pb->fpos, 4LL * (pb->n_f + 1));
+    ALLOC(c, pb->fext, 4LL * (pb->n_f + 1));
+  }
   ALLOC(c, pb->ccount, 4LL * (N + 1));
   ALLOC(c, pb->cptr, 4LL * (N + 1));
   ALLOC(c, pb->cand, 4LL * capc);

@@ -6,10 +6,11 @@
 //   - AL contact terms of the contact loop of Algorithm 2, for every incident
 //     constraint in increasing id: G_a += gfac w_a n and block(a, b) +=
 //     hfac w_a w_b n n^T (hfac = kappa gamma, kept also for inactive pairs);
-//   - friction terms of the previous step's contacts (Appendix A), listed
-//     after the constraints (ids n_c .. n_c + n_f - 1): G_a += w_a g and
-//     block(a, b) += w_a w_b K with the contact's gradient g and 3x3 Hessian K
-//     in the relative displacement;
+//   - friction terms of the previous step's contacts (Appendix A): G_a +=
+//     w_a g and block(a, b) += w_a w_b K with the contact's gradient g and 3x3
+//     Hessian K in the relative displacement, at the incidences of the
+//     constraint with the same stencil (cfr) or, for a contact without one,
+//     at its own stencil listed after the constraints (fext);
 //   - moving-boundary elimination (Section 5.3): G_v = 0 and every entry in
 //     the rows and columns of a fixed node zeroed except its scalar diagonals.
 // Then the block-Jacobi preconditioner (the paper's 3x3 block-Jacobi PCG) is
@@ -35,12 +36,41 @@ __device__ inline int find_slot(const int* __restrict__ col, int lo, int hi, int
   return lo;
 }
 
+// Friction contact fi at vertex slot a of its stencil t, into row r's
+// diagonal d, gradient g and upper blocks.
+__device__ inline void add_friction(int fi, int a, const int4& t, int r, int o, int n, int n_f,
+                                    const float* __restrict__ fgk, const int* __restrict__ col, float* vals,
+                                    float d[6], float g[3]) {
+  float K[6], w[4];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) K[k] = fgk[(3LL + k) * n_f + fi];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = fgk[(9LL + k) * n_f + fi];
+  const float wa = w[a];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g[k] += wa * fgk[(long long)k * n_f + fi];
+  const float saa = wa * wa;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) d[k] += saa * K[k];
+  for (int b = 0; b < 4; ++b) {
+    const int vb = vtx(t, b);
+    if (b == a || vb < r) continue;
+    const int s = find_slot(col, o + 1, o + n - 1, vb);
+    const float sab = wa * w[b];
+    float* v = vals + 9LL * s;
+    v[0] += sab * K[0]; v[1] += sab * K[1]; v[2] += sab * K[2];
+    v[3] += sab * K[1]; v[4] += sab * K[3]; v[5] += sab * K[4];
+    v[6] += sab * K[2]; v[7] += sab * K[4]; v[8] += sab * K[5];
+  }
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_assemble_rows(int N, const int* __restrict__ row_ptr, const int* __restrict__ col, const int* __restrict__ eslot,
                 const int* __restrict__ ecptr, const float* __restrict__ staging, const int* __restrict__ vptr,
                 const int* __restrict__ vinc, const int4* __restrict__ ids, int n_c, const float* __restrict__ cn,
                 const float* __restrict__ cw, const float* __restrict__ cg, const float* __restrict__ ch, int n_f,
-                const float* __restrict__ fgk, const float* __restrict__ mass, const double* __restrict__ xh, const double* __restrict__ xt,
+                const float* __restrict__ fgk, const int* __restrict__ cfr, const int* __restrict__ fext,
+                const float* __restrict__ mass, const double* __restrict__ xh, const double* __restrict__ xt,
                 const uint8_t* __restrict__ fixed, float* __restrict__ vals, float* __restrict__ grad,
                 float* __restrict__ Lf, float* __restrict__ Linv, float* __restrict__ bhat,
                 double* __restrict__ bb_part, int* flags) {
@@ -86,29 +116,12 @@ k_assemble_rows(int N, const int* __restrict__ row_ptr, const int* __restrict__ 
       const int ci = vinc[j] >> 2, a = vinc[j] & 3;
       const int4 t = ids[ci];
       if (ci >= n_c) {
-        const int fi = ci - n_c;
-        float K[6], w[4];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) K[k] = fgk[(3LL + k) * n_f + fi];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) w[k] = fgk[(9LL + k) * n_f + fi];
-        const float wa = w[a];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) g[k] += wa * fgk[(long long)k * n_f + fi];
-        const float saa = wa * wa;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) d[k] += saa * K[k];
-        for (int b = 0; b < 4; ++b) {
-          const int vb = vtx(t, b);
-          if (b == a || vb < r) continue;
-          const int s = find_slot(col, o + 1, o + n - 1, vb);
-          const float sab = wa * w[b];
-          float* v = vals + 9LL * s;
-          v[0] += sab * K[0]; v[1] += sab * K[1]; v[2] += sab * K[2];
-          v[3] += sab * K[1]; v[4] += sab * K[3]; v[5] += sab * K[4];
-          v[6] += sab * K[2]; v[7] += sab * K[4]; v[8] += sab * K[5];
-        }
+        add_friction(fext[ci - n_c], a, t, r, o, n, n_f, fgk, col, vals, d, g);
         continue;
+      }
+      if (n_f > 0) {
+        const int fi = cfr[ci];
+        if (fi >= 0) add_friction(fi, a, t, r, o, n, n_f, fgk, col, vals, d, g);
       }
       const float n0 = cn[ci], n1 = cn[n_c + ci], n2 = cn[2LL * n_c + ci];
       const float w[4] = {cw[ci], cw[n_c + ci], cw[2LL * n_c + ci], cw[3LL * n_c + ci]};
@@ -334,12 +347,12 @@ __global__ void k_row_diag_slots(int N, const int* __restrict__ row_ptr, int* di
 void launch_assemble_rows(int N, const int* row_ptr, const int* col, const int* eslot, const int* ecptr,
                           const float* staging, const int* vptr, const int* vinc, const int4* ids, int n_c,
                           const float* cn, const float* cw, const float* cg, const float* ch, int n_f,
-                          const float* fgk, const float* mass, const double* xh, const double* xt,
-                          const uint8_t* fixed, float* vals, float* grad, float* Lf, float* Linv, float* bhat,
-                          double* bb_part, int* flags, hipStream_t s) {
+                          const float* fgk, const int* cfr, const int* fext, const float* mass, const double* xh,
+                          const double* xt, const uint8_t* fixed, float* vals, float* grad, float* Lf, float* Linv,
+                          float* bhat, double* bb_part, int* flags, hipStream_t s) {
   hipLaunchKernelGGL(k_assemble_rows, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, eslot, ecptr,
-                     staging, vptr, vinc, ids, n_c, cn, cw, cg, ch, n_f, fgk, mass, xh, xt, fixed, vals, grad, Lf,
-                     Linv, bhat, bb_part, flags);
+                     staging, vptr, vinc, ids, n_c, cn, cw, cg, ch, n_f, fgk, cfr, fext, mass, xh, xt, fixed, vals,
+                     grad, Lf, Linv, bhat, bb_part, flags);
 }
 
 void launch_lower_count(int N, const int* row_ptr, const int* col, int* lcnt, hipStream_t s) {

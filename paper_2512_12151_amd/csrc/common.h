@@ -229,6 +229,15 @@ void launch_friction_capture(const int4* ids, int n_pt, int n_f, const double* x
                              double delta, double mu_f, double* f64, hipStream_t s);
 void launch_friction_terms(const int4* ids, int n_f, const double* xh, const double* x0, const double* f64, double e,
                            float* fgk, hipStream_t s);
+// Friction contact -> constraint with the same stencil: table insert of the
+// constraint rows (tab filled with -1 first, mask = capacity - 1), match
+// (cfr[ci] = fi, cfr filled with -1 first; extra[fi] = 1 when unmatched), and
+// the unmatched contacts' stencils at pids[n_c + pos[fi]] with fext[pos[fi]] = fi.
+void launch_stencil_insert(const int4* ids, int n_c, int* tab, unsigned mask, hipStream_t s);
+void launch_friction_match(const int4* fids, int n_f, const int4* ids, const int* tab, unsigned mask, int* cfr,
+                           int* extra, hipStream_t s);
+void launch_friction_extra(const int4* fids, int n_f, const int* extra, const int* pos, int n_c, int4* pids,
+                           int* fext, hipStream_t s);
 
 // elastic.hip
 void launch_elastic(const int4* tets, int T, const double* rest, const double* xh, const float* Dminv9,
@@ -239,9 +248,9 @@ void launch_elastic(const int4* tets, int T, const double* rest, const double* x
 void launch_assemble_rows(int N, const int* row_ptr, const int* col, const int* eslot, const int* ecptr,
                           const float* staging, const int* vptr, const int* vinc, const int4* ids, int n_c,
                           const float* cn, const float* cw, const float* cg, const float* ch, int n_f,
-                          const float* fgk, const float* mass, const double* xh, const double* xt, const uint8_t* fixed,
-                          float* vals, float* grad, float* Lf, float* Linv, float* bhat, double* bb_part,
-                          int* flags, hipStream_t s);
+                          const float* fgk, const int* cfr, const int* fext, const float* mass, const double* xh,
+                          const double* xt, const uint8_t* fixed, float* vals, float* grad, float* Lf, float* Linv,
+                          float* bhat, double* bb_part, int* flags, hipStream_t s);
 // Sliced storage of the scaled matrix: lower_count / lower_fill /
 // sort_segments give, per column, the source rows of its upper blocks;
 // slice_widths gives the slot counts per slice (64 x the widest row), whose

@@ -348,6 +348,56 @@ __global__ void k_cmap(const int4* __restrict__ ids, int n_c, const int* __restr
   cmap[i] = find_slot(row_ptr, col, min(va, vb), max(va, vb));
 }
 
+// Matching the friction contacts to the constraints with the same stencil
+// (the capture copies the constraint rows, and the active-set rebuild keeps
+// surviving rows as they are): an open-addressing table of the constraint
+// rows (capacity a power of two >= 2 n_c, so a probe always meets an empty
+// slot), then per friction contact its constraint (cfr[ci] = fi) or a flag
+// that it needs stencils of its own.  With unique rows (the active set's) the
+// matching, and so the assembly order, is deterministic.
+__device__ inline unsigned stencil_hash(const int4 t) {
+  unsigned h = (unsigned)t.x * 0x9E3779B1u;
+  h = (h ^ (h >> 15)) + (unsigned)t.y * 0x85EBCA77u;
+  h = (h ^ (h >> 13)) + (unsigned)t.z * 0xC2B2AE3Du;
+  h = (h ^ (h >> 16)) + (unsigned)t.w * 0x27D4EB2Fu;
+  return h ^ (h >> 15);
+}
+
+__device__ inline bool same4(const int4 a, const int4 b) { return a.x == b.x && a.y == b.y && a.z == b.z && a.w == b.w; }
+
+__global__ void k_stencil_insert(const int4* __restrict__ ids, int n_c, int* tab, unsigned mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_c) return;
+  unsigned h = stencil_hash(ids[i]) & mask;
+  while (atomicCAS(&tab[h], -1, i) != -1) h = (h + 1) & mask;
+}
+
+__global__ void k_friction_match(const int4* __restrict__ fids, int n_f, const int4* __restrict__ ids,
+                                 const int* __restrict__ tab, unsigned mask, int* cfr, int* __restrict__ extra) {
+  const int fi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (fi >= n_f) return;
+  const int4 t = fids[fi];
+  unsigned h = stencil_hash(t) & mask;
+  int found = -1;
+  for (int s = tab[h]; s != -1; h = (h + 1) & mask, s = tab[h]) {
+    if (same4(ids[s], t)) { found = s; break; }
+  }
+  // a second contact with the same stencil (repeated rows) keeps stencils of its own
+  const bool matched = found >= 0 && atomicCAS(&cfr[found], -1, fi) == -1;
+  extra[fi] = matched ? 0 : 1;
+}
+
+// The unmatched friction contacts, in order, after the constraints in the
+// pattern's stencil list (pids[n_c + pos]) and their contact ids (fext[pos]).
+__global__ void k_friction_extra(const int4* __restrict__ fids, int n_f, const int* __restrict__ extra,
+                                 const int* __restrict__ pos, int n_c, int4* __restrict__ pids,
+                                 int* __restrict__ fext) {
+  const int fi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (fi >= n_f || !extra[fi]) return;
+  pids[n_c + pos[fi]] = fids[fi];
+  fext[pos[fi]] = fi;
+}
+
 // Friction capture (Appendix A, semi-implicit): per contact of the previous
 // step, at x^t, the closest-point weights w, the normal n and the coefficient
 // coef = mu_f max(0, lambda - kappa (d - delta)) = h^2 mu_f F^t.  FP64 SoA
@@ -476,6 +526,25 @@ void launch_friction_capture(const int4* ids, int n_pt, int n_f, const double* x
   if (n_f > 0)
     hipLaunchKernelGGL(k_friction_capture, dim3(div_up(n_f, kBlock)), dim3(kBlock), 0, s, ids, n_pt, n_f, x, lam,
                        kappa, delta, mu_f, f64);
+}
+
+void launch_stencil_insert(const int4* ids, int n_c, int* tab, unsigned mask, hipStream_t s) {
+  if (n_c > 0)
+    hipLaunchKernelGGL(k_stencil_insert, dim3(div_up(n_c, kBlock)), dim3(kBlock), 0, s, ids, n_c, tab, mask);
+}
+
+void launch_friction_match(const int4* fids, int n_f, const int4* ids, const int* tab, unsigned mask, int* cfr,
+                           int* extra, hipStream_t s) {
+  if (n_f > 0)
+    hipLaunchKernelGGL(k_friction_match, dim3(div_up(n_f, kBlock)), dim3(kBlock), 0, s, fids, n_f, ids, tab, mask,
+                       cfr, extra);
+}
+
+void launch_friction_extra(const int4* fids, int n_f, const int* extra, const int* pos, int n_c, int4* pids,
+                           int* fext, hipStream_t s) {
+  if (n_f > 0)
+    hipLaunchKernelGGL(k_friction_extra, dim3(div_up(n_f, kBlock)), dim3(kBlock), 0, s, fids, n_f, extra, pos, n_c,
+                       pids, fext);
 }
 
 void launch_friction_terms(const int4* ids, int n_f, const double* xh, const double* x0, const double* f64, double e,

@@ -41,6 +41,7 @@ struct bf_problem {
   int n_f = 0;
   double fric_e = 0.0;             // eps_v h
   DevBuf fids, f64, fx0, fgk, pids;
+  DevBuf ftab, cfr, fextra, fpos, fext;   // per step: friction contact <-> constraint with the same stencil
   // per-step buffers
   DevBuf cn, cw, cg, ch, viol_part;
   DevBuf vcnt, vptr, vinc;
@@ -156,6 +157,13 @@ bf_status problem_init(bf_context* c, bf_problem* pb, const bf_mesh_desc* m, int
 // copy when bf16).  Enqueued on the context's stream; after it system_of(pb)
 // describes the step's PCG system.  Assembly errors are raised into pb->flags.
 bf_status step_assemble(bf_problem* pb, bool bf16);
+// Slots of the table matching friction contacts to constraints: a power of two
+// at least twice the constraint count (at least 2), so probes always end.
+inline unsigned friction_table_capacity(int n_c) {
+  unsigned cap = 2;
+  while (cap < 2u * (unsigned)n_c) cap <<= 1;
+  return cap;
+}
 // Sets the constraint counts (PT first) and sizes every per-constraint and
 // per-step buffer for them; the constraint arrays themselves are the caller's.
 bf_status size_constraint_buffers(bf_problem* pb, int n_pt, int n_ee);
