@@ -10,11 +10,16 @@
  *   p = -H^{-1} G                     (block-Jacobi preconditioned CG)
  *
  * with E the incremental potential 1/2|x - x_tilde|_M^2 + h^2 U(x) of Section 3
- * (lumped mass M, Neo-Hookean U on linear tetrahedra), the linearized
+ * (lumped mass M; U on linear tetrahedra of Neo-Hookean, stable Neo-Hookean or
+ * corotated linear material per tet (Table 2), plus, after bf_set_friction,
+ * the semi-implicit friction potential of Appendix A), the linearized
  * constraints c_i(x_hat) = d_i(x) + grad d_i(x)^T (x_hat - x) - delta of
  * Section 4.2, slacks s_i = max(0, c_i - lambda_i/kappa), the per-element
  * SPD projection of Section 5.1 (eigenvalues of d2Psi/dF2 clamped at zero),
- * and moving-boundary (Dirichlet) nodes eliminated as in Section 5.3.  The
+ * and moving-boundary (Dirichlet) nodes eliminated as in Section 5.3.  Around
+ * the step the library also runs the rest of SolveSubproblem (Algorithm 2),
+ * the collision queries of UpdateActiveSet and MaxStepSize (Algorithms 3, 1)
+ * and whole time steps (Algorithm 1), and serves batches of steps.  The
  * paper calls the penalty mu; this ABI calls it kappa to keep mu for the Lame
  * parameter.  d_i is the unsigned distance of a point-triangle (PT) or
  * edge-edge (EE) pair (Section 3).
