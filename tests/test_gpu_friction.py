@@ -192,3 +192,33 @@ def test_set_friction_errors(ctx, bf):
         with pytest.raises(bf.BfalError) as e:
             pb.set_friction(mu, ev)
         assert e.value.status == -1   # BF_ERR_INVALID_ARG
+
+
+def test_friction_without_constraints_and_determinism(ctx, bf):
+    """Every constraint removed after the capture: all friction contacts keep
+    stencils of their own (the constraint table is empty).  With the matched
+    set, two steps are bitwise equal (the matching keeps the assembly order)."""
+    sc, scf = sliding(5)
+    pb = bf.Problem.from_scene(ctx, sc)
+    pb.set_friction(MU_F, EPS_V)
+    p1, s1, _ = pb.newton_step(tol=1e-7)
+    g1, b1 = pb.gradient(), pb.blocks()
+    p2, s2, _ = pb.newton_step(tol=1e-7)
+    assert np.array_equal(p1, p2) and np.array_equal(g1, pb.gradient()) and np.array_equal(b1, pb.blocks())
+    assert s1["pcg_iters"] == s2["pcg_iters"]
+    empty = np.zeros((0, 4), dtype=np.int32)
+    pb.set_constraints(empty, empty, np.zeros(0), np.zeros(0), sc["kappa"], sc["delta"])
+    p, _, status = pb.newton_step(tol=1e-7, max_iter=50000)
+    assert status == bf.BF_OK
+    sub = dict(scf, pt=empty, ee=empty, lam=np.zeros(0), gamma=np.zeros(0))
+    st = oracle.assemble(sub)
+    row_ptr, col, *_ = pb.pattern()
+    r_ptr, r_col, *_ = oracle.pattern(len(sc["rest"]), sc["tets"], sc["pt"], sc["ee"])
+    assert np.array_equal(row_ptr, r_ptr) and np.array_equal(col, r_col)
+    free = ~sc["fixed"].astype(bool)
+    assert rel(pb.gradient()[free], st.G[free]) <= 1e-5
+    assert rel(pb.blocks().astype(np.float64), oracle.upper_blocks(st.H, row_ptr.astype(np.int64), col)) <= 1e-5
+    L, _ = pb.energy()
+    Lref = oracle.total_energy(sub, oracle.prepare(sub), sub["x_hat"])
+    assert abs(L - Lref) <= 1e-9 * abs(Lref)
+    assert oracle.energy_norm_rel(st.H, p, oracle.solve_reference(st.H, st.G)) <= 1e-4
