@@ -166,9 +166,10 @@ bf_status bf_set_constraints(bf_problem* pb, const bf_constraint_desc* cons, int
  * contact, coef f_0(|u|) with u the tangential part of sum_a w_a (x_hat_a -
  * x^t_a) and f_0 IPC's C^2 mollified norm with threshold eps_v h (h from
  * bf_set_state).  Later bf_set_constraints / bf_update_active_set calls leave
- * the friction set as captured.  mu_f = 0 clears it.  Requires bf_set_state;
- * mu_f >= 0 finite and, when mu_f > 0, eps_v > 0 finite (BF_ERR_INVALID_ARG
- * otherwise).  Allocates the per-contact buffers on the device. */
+ * the friction set as captured.  mu_f = 0 clears it.  Requires bf_set_state
+ * and bf_set_constraints (BF_ERR_STATE otherwise); mu_f >= 0 finite and, when
+ * mu_f > 0, eps_v > 0 finite (BF_ERR_INVALID_ARG otherwise).  Allocates the
+ * per-contact buffers on the device. */
 bf_status bf_set_friction(bf_problem* pb, double mu_f, double eps_v);
 
 /* One Newton step: constraint linearization at x, merged BSR pattern,

@@ -456,9 +456,14 @@ bf_status bf_set_friction(bf_problem* pb, double mu_f, double eps_v) {
   if (mu_f > 0.0 && (!(eps_v > 0.0) || !std::isfinite(eps_v)))
     return fail(c, BF_ERR_INVALID_ARG, "eps_v must be positive and finite");
   if (!pb->has_state) return fail(c, BF_ERR_STATE, "bf_set_friction needs the state (bf_set_state) first");
+  if (pb->cap_nnzb == 0) return fail(c, BF_ERR_STATE, "bf_set_friction needs the constraints (bf_set_constraints) first");
+  const int nf = mu_f > 0.0 ? pb->n_c : 0;
+  if (nf == 0 && pb->n_f == 0) {   // no friction before or after: nothing to change
+    c->err.clear();
+    return BF_OK;
+  }
   HIPCHK(c, hipSetDevice(c->device));
   hipStream_t s = c->stream;
-  const int nf = mu_f > 0.0 ? pb->n_c : 0;
   if (nf > 0) {
     ALLOC(c, pb->fids, 16LL * nf);
     ALLOC(c, pb->f64, 64LL * nf);
