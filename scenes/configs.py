@@ -335,6 +335,23 @@ def falling_cubes(v: float = -0.5, dt: float = 0.01, n: int = 4, lateral=(0.37, 
                    x.copy(), xt, dt, np.zeros((0, 4)), np.zeros((0, 4)), np.zeros(0), 1e4, 1e-3, 1e-8)
 
 
+def slope(n: int = 4, E: float = 1e7, incline: float = float(np.arctan(0.5)), dt: float = 0.01):
+    """The two-cube stack with the lower cube fixed (the ground) and the upper
+    one resting 1 mm above it, under gravity tilted by `incline` (the same as
+    an inclined ground: g = 9.8 (sin, 0, -cos)), stiff enough (E = 1e7) to
+    slide as a body.  x_tilde is left to the caller, who adds h v + h^2 g per
+    step; scene["gravity"] holds g."""
+    sc = dict(falling_cubes(v=0.0, dt=dt, n=n))
+    N, T = len(sc["x"]), len(sc["tets"])
+    fixed = sc["fixed"].copy()
+    fixed[: N // 2] = 1
+    sc["fixed"] = fixed
+    sc["E"] = np.full(T, E)
+    sc["gravity"] = 9.8 * np.array([np.sin(incline), 0.0, -np.cos(incline)])
+    sc["name"] = "slope"
+    return sc
+
+
 def ccd_target(sc: dict, recipe: str, seed: int = 11) -> np.ndarray:
     """A target state x_hat for the collision queries along x -> x_hat.
 

@@ -222,3 +222,38 @@ def test_friction_without_constraints_and_determinism(ctx, bf):
     Lref = oracle.total_energy(sub, oracle.prepare(sub), sub["x_hat"])
     assert abs(L - Lref) <= 1e-9 * abs(Lref)
     assert oracle.energy_norm_rel(st.H, p, oracle.solve_reference(st.H, st.G)) <= 1e-4
+
+
+@pytest.mark.parametrize("mu_f", [0.0, 0.3, 0.6])
+def test_block_on_slope(ctx, bf, mu_f):
+    """Section 6's cubes on a slope (incline arctan 0.5, gravity tilted instead
+    of the ground), through the GPU's time steps with friction (K_min = 6,
+    mu_init at the first step, eps_v = 1e-3): below tan(theta) = 0.5 the block
+    slides at the analytic g (sin - mu_f cos) once the contact force has settled
+    at the weight (from the sixth step), within 1 % without friction and 3 %
+    with it; above it (mu_f = 0.6) the block stops: after 20 steps it moves at
+    under 1 cm/s, against 0.26 m/s at mu_f = 0.3 after 12."""
+    sc = scenes.slope()
+    N, h, g = len(sc["x"]), sc["dt"], sc["gravity"]
+    up = np.arange(N) >= N // 2
+    pb = bf.Problem.from_scene(ctx, sc)
+    x, v = sc["x"].copy(), np.zeros_like(sc["x"])
+    steps = 20 if mu_f > 0.5 else 12
+    vs = []
+    for step in range(steps):
+        xt = x + h * v
+        xt[up] += h * h * g
+        pb.set_state(x, x.copy(), xt, h)
+        x, v, st, status = pb.time_step(tol=1e-7, k_min=6, mu_f=mu_f, eps_v=1e-3,
+                                        mu_init_c=0.1 if step == 0 else 0.0)
+        assert status == bf.BF_OK
+        vs.append(v[up, 0].mean())
+    th = np.arctan(0.5)
+    print(f"slope mu_f {mu_f}: v {np.round(vs, 4)}", flush=True)
+    if mu_f < 0.5:
+        a = (vs[-1] - vs[5]) / (h * (len(vs) - 6))
+        a_th = 9.8 * (np.sin(th) - mu_f * np.cos(th))
+        print(f"slope mu_f {mu_f}: acceleration {a:.4f}, analytic {a_th:.4f}", flush=True)
+        assert a == pytest.approx(a_th, rel=0.01 if mu_f == 0.0 else 0.03)
+    else:
+        assert abs(vs[-1]) < 0.01 and max(vs) < 0.1
