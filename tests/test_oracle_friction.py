@@ -209,3 +209,29 @@ def test_block_on_slope_slides_at_the_analytic_acceleration():
     th = np.arctan(0.5)
     a = (vs[-1] - vs[5]) / (h * (len(vs) - 6))
     assert a == pytest.approx(9.8 * (np.sin(th) - 0.3 * np.cos(th)), rel=0.03)
+
+
+def test_momentum_conservation_with_friction():
+    """Section 6's momentum conservation in the oracle's time steps: two free
+    cubes, the upper thrown onto the lower, friction on.  Every force is
+    internal (constraint and friction weights sum to zero, energies are
+    translation invariant), and the oracle's Newton steps solve exactly, so
+    the total momentum stays at its initial value to rounding, while friction
+    drags the lower cube sideways."""
+    from oracle import timestep
+    sc0 = dict(scenes.falling_cubes(jitter=1e-5))
+    N, h = len(sc0["x"]), sc0["dt"]
+    up = np.arange(N) >= N // 2
+    sc0["fixed"] = np.zeros(N, dtype=np.uint8)
+    m = oracle.prepare(sc0).mass
+    x, v = sc0["x"].copy(), np.zeros_like(sc0["x"])
+    v[up] = [0.2, 0.0, -0.5]
+    P0 = (m[:, None] * v).sum(0)
+    pt = ee = np.zeros((0, 4), dtype=np.int64)
+    lam = gam = np.zeros(0)
+    for _ in range(3):
+        sc = dict(sc0, x=x, x_hat=x.copy(), x_tilde=x + h * v, pt=pt, ee=ee, lam=lam, gamma=gam)
+        x, v, (pt, ee, lam, gam), _ = timestep.time_step(sc, K_min=6, mu_f=0.5, eps_v=1e-3)
+    P = (m[:, None] * v).sum(0)
+    assert np.abs(P - P0).max() <= 1e-12 * np.abs(P0).max()
+    assert v[~up].mean(0)[0] > 0.005
