@@ -39,7 +39,7 @@ def gpu(large):
     pb.set_constraints(t["pt"], t["ee"], t["lam"], t["gamma"], sc["kappa"], sc["delta"])
     out = torch.empty((len(sc["rest"]), 3), dtype=torch.float64, device=dev)
     print("large: GPU Newton step", flush=True)
-    _, stats, status = pb.newton_step(tol=1e-5, max_iter=200000, poll_every=64, check_every=1, out=out)
+    _, stats, status = pb.newton_step(tol=1e-5, max_iter=200000, poll_every=64, check_every=4, out=out)
     torch.cuda.synchronize()
     p = out.cpu().numpy()
     res = dict(p=p, stats=stats, status=status, g=pb.gradient(), pattern=pb.pattern(), blocks=pb.blocks())
