@@ -103,3 +103,33 @@ def test_three_steps_stay_intersection_free(ctx, bf):
         print(f"step {step}: {st}, min gap {gaps[-1]:.3e}", flush=True)
         assert status == bf.BF_OK and gaps[-1] > 0.0
     assert gaps[-1] < 1e-3
+
+
+def test_near_rigid_cube_matches_oracle(ctx, bf):
+    """Section 6's near-rigid bodies: the jittered thrown cube with E = 1 GPa
+    (1e4 times the default material), moving sideways at 0.2 m/s, friction on
+    (mu_f = 0.5), the
+    penalty from mu_init: the same outer iterations and active set as the
+    oracle, the state within 1e-3 of the displacement (the bars of the thrown
+    cube), the landing stops the cube almost rigidly, and the end state is
+    intersection free."""
+    sc = dict(scenes.falling_cubes(jitter=1e-5))
+    sc["E"] = np.full(len(sc["tets"]), 1e9)
+    N, h = len(sc["x"]), sc["dt"]
+    up = np.arange(N) >= N // 2
+    sc["x_tilde"] = sc["x_tilde"].copy()
+    sc["x_tilde"][up, 0] += h * 0.2
+    xo, vo, (pto, eeo, lamo, gamo), info = timestep.time_step(sc, K_min=6, mu_f=0.5, eps_v=1e-3, mu_init_C=0.1)
+    pb = bf.Problem.from_scene(ctx, sc)
+    x, v, st, status = pb.time_step(tol=1e-8, max_iter=100000, k_min=6, mu_f=0.5, eps_v=1e-3, mu_init_c=0.1)
+    print(f"near-rigid: gpu {st}, oracle outer {info['outer']} alphas {info['alphas']}", flush=True)
+    assert status == bf.BF_OK
+    assert st["outer_iters"] == info["outer"]
+    disp = np.abs(xo - sc["x"]).max()
+    err = np.abs(x - xo).max()
+    print(f"near-rigid: max |x - x_oracle| {err:.3e} of displacement {disp:.3e}; upper v {v[up].mean(0)}", flush=True)
+    assert err <= 1e-3 * disp
+    pt, ee, lam, gam = pb.constraints()
+    assert np.array_equal(pt, pto) and np.array_equal(ee, eeo)
+    assert abs(v[up, 2].mean()) < 0.02 and v[up].std(0).max() < 0.01
+    assert _cross_body_min_distance(sc, x) > 0.0
