@@ -68,6 +68,7 @@ bf_status problem_init(bf_context* c, bf_problem* pb, const bf_mesh_desc* m, int
   HIPCHK(c, hipMemcpyAsync(pb->nu.p, m->nu, 8LL * T, kind_in(mem), s));
   HIPCHK(c, hipMemcpyAsync(pb->rho.p, m->rho, 8LL * T, kind_in(mem), s));
   pb->has_mat = m->material != nullptr;
+  pb->n_f = 0;   // a reused problem object starts without a friction set
   if (pb->has_mat) {
     ALLOC(c, pb->mat, 4LL * T);
     HIPCHK(c, hipMemcpyAsync(pb->mat.p, m->material, 4LL * T, kind_in(mem), s));
