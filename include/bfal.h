@@ -59,7 +59,8 @@ typedef enum {
   BF_ERR_INVERTED_ELEMENT = -4,     /* det F(x_hat) <= 0 in some tet (Neo-Hookean is non-invertible) */
   BF_ERR_DEGENERATE_CONSTRAINT = -5,/* d_i(x) <= 0, repeated vertex, or (near-)parallel EE pair */
   BF_ERR_NOT_SPD = -6,              /* a diagonal block is not SPD, or PCG breakdown p^T H p <= 0 */
-  BF_ERR_STATE = -7                 /* call order: state or constraints missing */
+  BF_ERR_BUDGET = -7,               /* serving: a request's footprint exceeds the server's HBM budget */
+  BF_ERR_STATE = -8                 /* call order: state or constraints missing */
 } bf_status;
 
 enum { BF_MEM_HOST = 0, BF_MEM_DEVICE = 1 };
@@ -412,7 +413,8 @@ bf_status bf_server_submit(bf_server* srv, int64_t req_id, const bf_mesh_desc* m
 bf_status bf_server_poll(bf_server* srv, int64_t* done_ids, int32_t cap, int32_t* n_done);
 /* Takes a finished request's result: p_out [n_nodes][3] host doubles, stats,
  * times and its status (a bf_status: BF_OK, a warning or an error such as
- * BF_ERR_OOM when its footprint exceeds the budget).  Any output may be NULL.
+ * BF_ERR_BUDGET when its footprint exceeds the whole budget).  Any output may
+ * be NULL.
  * BF_ERR_STATE if the id is not finished. */
 bf_status bf_server_result(bf_server* srv, int64_t req_id, double* p_out, bf_step_stats* stats,
                            bf_request_times* times, int32_t* req_status);

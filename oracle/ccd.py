@@ -284,11 +284,13 @@ def _det3(A):
 
 
 def inversion_bound(rest_tets_x0, x1_tets, s=S_SEP):
-    """Per tet the first t in (0, 1] with det D_s(t) = s det D_s(0), or 1.
+    """Per tet the first t in (0, 1] where det D_s(t) / det D_s(0) falls to s, or 1.
     rest_tets_x0, x1_tets: [T, 4, 3] vertex positions at t = 0 and t = 1.
-    det D_s(t) is a cubic in t; between consecutive roots of its derivative it
-    is monotone, so the first sign change of f(t) = det D_s(t) - s det D_s(0)
-    is bracketed and bisected (60 halvings, the lower end returned)."""
+    The tets need not be positively oriented: the ratio is the same for either
+    vertex order.  det D_s(t) is a cubic in t; between consecutive roots of its
+    derivative it is monotone, so the first sign change of
+    f(t) = sign(det D_s(0)) det D_s(t) - s |det D_s(0)| is bracketed and
+    bisected (60 halvings, the lower end returned)."""
     D0 = (rest_tets_x0[:, 1:] - rest_tets_x0[:, :1]).transpose(0, 2, 1)
     D1 = (x1_tets[:, 1:] - x1_tets[:, :1]).transpose(0, 2, 1)
     dD = D1 - D0
@@ -300,9 +302,11 @@ def inversion_bound(rest_tets_x0, x1_tets, s=S_SEP):
     coef = np.linalg.solve(V, vals.T).T           # [T, 4]
     out = np.ones(len(D0))
 
+    sg = np.where(j0 < 0.0, -1.0, 1.0)
+
     def f(i, t):
         c = coef[i]
-        return ((c[0] * t + c[1]) * t + c[2]) * t + c[3] - s * j0[i]
+        return sg[i] * (((c[0] * t + c[1]) * t + c[2]) * t + c[3]) - s * abs(j0[i])
 
     for i in range(len(D0)):
         a, b, c = 3 * coef[i, 0], 2 * coef[i, 1], coef[i, 2]

@@ -626,9 +626,13 @@ def solve_reference(H, G, direct_max_dof=30000):
     return p
 
 
-def block_jacobi_pcg(H, G, tol, max_iter=20000):
+def block_jacobi_pcg(H, G, tol, max_iter=20000, record=None):
     """FP64 PCG on H p = -G with the 3x3 block-Jacobi preconditioner, x0 = 0,
-    stopping at |r|_2 <= tol |b|_2 (the paper's CG relative tolerance)."""
+    stopping at |r|_2 <= tol |b|_2 (the paper's CG relative tolerance).
+
+    `record`, a dict keyed by looser tolerances, receives (iterate, iterations)
+    the first time the residual meets each of them: the solve at that
+    tolerance, since the iterates do not depend on where the loop stops."""
     b = -G.reshape(-1)
     n = H.shape[0]
     N = n // 3
@@ -652,7 +656,13 @@ def block_jacobi_pcg(H, G, tol, max_iter=20000):
     p = z.copy()
     rz = r @ z
     it = 0
-    while np.linalg.norm(r) > tol * bn and it < max_iter:
+    pending = sorted(record, reverse=True) if record is not None else []
+    while True:
+        rn = np.linalg.norm(r)
+        while pending and rn <= pending[0] * bn:
+            record[pending.pop(0)] = (x.reshape(-1, 3).copy(), it)
+        if not (rn > tol * bn and it < max_iter):
+            break
         q = Hc @ p
         alpha = rz / (p @ q)
         x += alpha * p

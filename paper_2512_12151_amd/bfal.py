@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libbfal.so")
 BF_OK = 0
 BF_WARN_PCG_MAXITER = 1
 STATUS = {0: "OK", 1: "WARN_PCG_MAXITER", -1: "ERR_INVALID_ARG", -2: "ERR_OOM", -3: "ERR_HIP",
-          -4: "ERR_INVERTED_ELEMENT", -5: "ERR_DEGENERATE_CONSTRAINT", -6: "ERR_NOT_SPD", -7: "ERR_STATE"}
+          -4: "ERR_INVERTED_ELEMENT", -5: "ERR_DEGENERATE_CONSTRAINT", -6: "ERR_NOT_SPD", -7: "ERR_BUDGET",
+          -8: "ERR_STATE"}
 BF_MEM_HOST, BF_MEM_DEVICE = 0, 1
 BF_PREC_FP32, BF_PREC_BF16_REFINE = 0, 1
 

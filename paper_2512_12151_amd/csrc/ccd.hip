@@ -615,10 +615,12 @@ __device__ inline double det3(d3 a, d3 b, d3 c) {   // det of the matrix with co
   return a.x * (b.y * c.z - b.z * c.y) - b.x * (a.y * c.z - a.z * c.y) + c.x * (a.y * b.z - a.z * b.y);
 }
 
-// Per tet the first t in (0, 1] with det D_s(t) = s det D_s(0) (1 if none):
-// the cubic's coefficients by interpolation at t = 0, 1/3, 2/3, 1, its
+// Per tet the first t in (0, 1] where det D_s(t) / det D_s(0) falls to s (1 if
+// none), for either orientation of the tet: the cubic's coefficients by
+// interpolation at t = 0, 1/3, 2/3, 1, taken times the sign of det D_s(0); its
 // derivative's roots split [0, 1] into monotone pieces, the first piece whose
-// end falls to the level is bisected (60 halvings, the lower end kept).
+// end falls to the level s |det D_s(0)| is bisected (60 halvings, the lower end
+// kept).
 __global__ void k_inversion_bound(int T, const int4* __restrict__ tets, const double* __restrict__ x,
                                   const double* __restrict__ xh, double s, double* __restrict__ part) {
   __shared__ double red[kCcdBlock];
@@ -638,11 +640,12 @@ __global__ void k_inversion_bound(int T, const int4* __restrict__ tets, const do
     const double d2a = (d1b - d1a) / (2 * h), d2b = (d1c - d1b) / (2 * h);
     const double d3v = (d2b - d2a) / (3 * h);
     // p(t) = f0 + d1a t + d2a t (t - h) + d3v t (t - h)(t - 2h)
-    const double c3 = d3v;
-    const double c2 = d2a - 3 * h * d3v;
-    const double c1 = d1a - h * d2a + 2 * h * h * d3v;
-    const double c0v = f0;
-    const double level = s * f0;
+    const double sg = f0 < 0.0 ? -1.0 : 1.0;
+    const double c3 = sg * d3v;
+    const double c2 = sg * (d2a - 3 * h * d3v);
+    const double c1 = sg * (d1a - h * d2a + 2 * h * h * d3v);
+    const double c0v = sg * f0;
+    const double level = s * c0v;
     auto F = [&](double tt) { return ((c3 * tt + c2) * tt + c1) * tt + c0v - level; };
     double knots[4];
     int nk = 0;

@@ -353,8 +353,12 @@ __global__ void k_cmap(const int4* __restrict__ ids, int n_c, const int* __restr
 // surviving rows as they are): an open-addressing table of the constraint
 // rows (capacity a power of two >= 2 n_c, so a probe always meets an empty
 // slot), then per friction contact its constraint (cfr[ci] = fi) or a flag
-// that it needs stencils of its own.  With unique rows (the active set's) the
-// matching, and so the assembly order, is deterministic.
+// that it needs stencils of its own.  Repeated rows are matched by index, not
+// by the order in which threads arrive: a contact takes the lowest-numbered
+// constraint with its stencil (linear probing keeps every key of one home slot
+// in the run that starts there, so the whole run is searched), and of several
+// contacts with one stencil the lowest-numbered one is matched.  The matching,
+// and so the assembly order, is deterministic.
 __device__ inline unsigned stencil_hash(const int4 t) {
   unsigned h = (unsigned)t.x * 0x9E3779B1u;
   h = (h ^ (h >> 15)) + (unsigned)t.y * 0x85EBCA77u;
@@ -379,12 +383,19 @@ __global__ void k_friction_match(const int4* __restrict__ fids, int n_f, const i
   const int4 t = fids[fi];
   unsigned h = stencil_hash(t) & mask;
   int found = -1;
-  for (int s = tab[h]; s != -1; h = (h + 1) & mask, s = tab[h]) {
-    if (same4(ids[s], t)) { found = s; break; }
-  }
-  // a second contact with the same stencil (repeated rows) keeps stencils of its own
-  const bool matched = found >= 0 && atomicCAS(&cfr[found], -1, fi) == -1;
-  extra[fi] = matched ? 0 : 1;
+  for (int s = tab[h]; s != -1; h = (h + 1) & mask, s = tab[h])
+    if (same4(ids[s], t) && (found < 0 || s < found)) found = s;
+  // cfr starts at -1 (the largest unsigned value): it ends at the lowest contact
+  if (found >= 0) atomicMin(reinterpret_cast<unsigned*>(cfr) + found, (unsigned)fi);
+  extra[fi] = found;
+}
+
+// A contact keeps stencils of its own unless it is the one its constraint took.
+__global__ void k_friction_flag(int n_f, const int* __restrict__ cfr, int* __restrict__ extra) {
+  const int fi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (fi >= n_f) return;
+  const int found = extra[fi];
+  extra[fi] = (found >= 0 && cfr[found] == fi) ? 0 : 1;
 }
 
 // The unmatched friction contacts, in order, after the constraints in the
@@ -535,9 +546,11 @@ void launch_stencil_insert(const int4* ids, int n_c, int* tab, unsigned mask, hi
 
 void launch_friction_match(const int4* fids, int n_f, const int4* ids, const int* tab, unsigned mask, int* cfr,
                            int* extra, hipStream_t s) {
-  if (n_f > 0)
+  if (n_f > 0) {
     hipLaunchKernelGGL(k_friction_match, dim3(div_up(n_f, kBlock)), dim3(kBlock), 0, s, fids, n_f, ids, tab, mask,
                        cfr, extra);
+    hipLaunchKernelGGL(k_friction_flag, dim3(div_up(n_f, kBlock)), dim3(kBlock), 0, s, n_f, (const int*)cfr, extra);
+  }
 }
 
 void launch_friction_extra(const int4* fids, int n_f, const int* extra, const int* pos, int n_c, int4* pids,

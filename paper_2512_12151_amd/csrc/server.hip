@@ -161,7 +161,7 @@ void admission_loop(bf_server* sv, int worker) {
           if (h->footprint > sv->budget) {   // can never fit: reject without blocking the queue
             sv->pending.pop_front();
             lk.unlock();
-            finish_request(sv, h, BF_ERR_OOM, "request footprint exceeds the server's HBM budget");
+            finish_request(sv, h, BF_ERR_BUDGET, "request footprint exceeds the server's HBM budget");
             lk.lock();
             continue;
           }

@@ -222,3 +222,34 @@ def test_large_collisions_sampled(ctx, bf):
     # inversion bound on sampled tets
     tt = sc["tets"][rng.choice(len(sc["tets"]), 2000, replace=False)].astype(np.int64)
     assert st["alpha_inversion"] <= ccd.inversion_bound(x[tt], xh[tt]).min() * (1 + 1e-12)
+
+
+def test_inversion_bound_either_orientation(ctx, bf):
+    """MaxStepSize's inversion bound (Algorithm 1) on a mesh whose tets are
+    half negatively oriented (two vertices of every other tet swapped; the
+    element terms do not depend on the order): a static target is never
+    limited, and an interior node pushed 1.2 cell widths gives the oracle's
+    bound and the bound of the same mesh in positive order."""
+    sc = scenes.tiny(lateral=(0.37, 0.21))
+    flipped = dict(sc)
+    t = sc["tets"].copy()
+    t[::2, 1], t[::2, 2] = sc["tets"][::2, 2], sc["tets"][::2, 1]
+    flipped["tets"] = np.ascontiguousarray(t)
+    interior = 2 + 5 * 2 + 25 * 2          # node (2, 2, 2) of the lower 4^3 cube
+    assert not sc["fixed"][interior]
+    xh = sc["x"].copy()
+    xh[interior] += [0.0, 0.0, 0.3]
+    alphas = {}
+    for name, s in (("positive", sc), ("flipped", flipped)):
+        print(f"inversion bound: {name}", flush=True)
+        pb = bf.Problem.from_scene(ctx, s)
+        a_static, _ = pb.max_step_size(sc["x"].copy())
+        assert a_static == 1.0
+        alphas[name], _ = pb.max_step_size(xh)
+        pb.close()
+    tris, edges, verts = ccd.surface(flipped["tets"])
+    ref = ccd.max_step_size(sc["x"], xh, flipped["tets"], tris, edges, verts, sc["delta"])
+    print(f"inversion bound: gpu {alphas}, oracle {ref}", flush=True)
+    assert 0.0 < ref < 1.0
+    for a in alphas.values():
+        assert a == pytest.approx(ref, rel=1e-8)

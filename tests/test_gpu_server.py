@@ -99,10 +99,10 @@ def test_budget_admission_and_rejection(bf, alone):
         assert np.array_equal(got[i][0], alone[i][0])
     assert sv.stats()["used_bytes"] == 0
     sv.close()
-    # a request larger than the whole budget is rejected with ERR_OOM
+    # a request larger than the whole budget is rejected with ERR_BUDGET
     small = min(sizes.values())
     sv = bf.Server(0, hbm_budget=small, max_active=4, iters_per_round=4)
     big = max(sizes, key=sizes.get)
     got = run_server(bf, sv, [big])
-    assert got[big][3] == -2   # BF_ERR_OOM
+    assert got[big][3] == -7   # BF_ERR_BUDGET
     sv.close()

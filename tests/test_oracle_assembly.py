@@ -174,3 +174,129 @@ def test_reference_solve_pcg_branch_matches_direct():
     p_d = oracle.solve_direct(st.H, st.G, method="splu")
     p_r = oracle.solve_reference(st.H, st.G, direct_max_dof=0)
     assert oracle.energy_norm_rel(st.H, p_r, p_d) <= 1e-9
+
+
+# --------------------------------------------------------------------------
+# Pins of the contact terms' Hessian weight and of the offset in c_i
+# (Section 4.2: the linearized constraint c_i(x_hat) = d_i(x) + grad d_i(x)^T
+# (x_hat - x) - delta, and the Newton step's Hessian term mu gamma_i grad d_i
+# grad d_i^T, kept for every constraint).
+
+def _two_tets(pt, ee, lam, gamma, kappa=1e4, delta=1e-3, x_hat=None):
+    """Tet A with its vertex 0 at p = (0.2, 0.3, 0.05) above the triangle
+    (0,0,0), (1,0,0), (0,1,0) of tet B in the plane z = 0 (both positively
+    oriented), no fixed nodes."""
+    p = np.array([0.2, 0.3, 0.05])
+    rest = np.array([p, p + [1, 0, 0], p + [0, 1, 0], p + [0, 0, 1],
+                     [0, 0, 0], [0, 1, 0], [1, 0, 0], [0, 0, -1]], dtype=np.float64)
+    tets = np.array([[0, 1, 2, 3], [4, 5, 6, 7]], dtype=np.int32)
+    n_c = len(pt) + len(ee)
+    return dict(name="two_tets", seed=0, rest=rest, tets=tets, E=np.full(2, 1e5), nu=np.full(2, 0.4),
+                rho=np.full(2, 1000.0), fixed=np.zeros(8, np.uint8), x=rest.copy(),
+                x_hat=rest.copy() if x_hat is None else x_hat, x_tilde=rest.copy(), dt=0.01,
+                pt=np.asarray(pt, np.int32).reshape(-1, 4), ee=np.asarray(ee, np.int32).reshape(-1, 4),
+                lam=np.full(n_c, float(lam)), gamma=np.full(n_c, float(gamma)), kappa=kappa, delta=delta, tol=1e-8)
+
+
+def _contact_part(sc):
+    """(G, H) of the constraints alone: the scene assembled with and without them."""
+    with_c = oracle.assemble(sc)
+    bare = dict(sc, pt=np.zeros((0, 4), np.int32), ee=np.zeros((0, 4), np.int32), lam=np.zeros(0),
+                gamma=np.zeros(0))
+    without = oracle.assemble(bare)
+    return with_c, with_c.G - without.G, (with_c.H - without.H).toarray()
+
+
+# Hand cases.  PT (p, t0, t1, t2) = (0, 4, 6, 5): the closest point of the
+# triangle (0,0,0), (1,0,0), (0,1,0) to p = (0.2, 0.3, 0.05) is (0.2, 0.3, 0),
+# barycentric (0.5, 0.2, 0.3), so d = 0.05, n = (0, 0, 1), w = (1, -0.5, -0.2, -0.3).
+# EE (a0, a1, b0, b1) = (0, 2, 6, 5): edge a runs from p along +y, edge b from
+# (1,0,0) to (0,1,0); the closest points are s = 0.5 on a, t = 0.8 on b, so
+# d = 0.05, n = (0, 0, 1), w = (1 - s, s, -(1 - t), -t) = (0.5, 0.5, -0.2, -0.8).
+HAND = {"pt": ((0, 4, 6, 5), (1.0, -0.5, -0.2, -0.3)),
+        "ee": ((0, 2, 6, 5), (0.5, 0.5, -0.2, -0.8))}
+
+
+@pytest.mark.parametrize("kind", ["pt", "ee"])
+def test_contact_blocks_and_gradient_on_hand_case(kind):
+    ids, w = HAND[kind]
+    w = np.array(w)
+    n = np.array([0.0, 0.0, 1.0])
+    kappa, gamma, lam = 1e4, 0.6, 1000.0
+    rows = [ids]
+    sc = _two_tets(rows if kind == "pt" else [], rows if kind == "ee" else [], lam, gamma, kappa)
+    st, Gc, Hc = _contact_part(sc)
+    assert np.isclose(st.d[0], 0.05, rtol=1e-14) and np.allclose(st.nrm[0], n, atol=1e-14)
+    assert np.allclose(st.w[0], w, atol=1e-14)
+    # c at x_hat = x is d - delta; g = gamma min(kappa c - lambda, 0) = 0.6 (490 - 1000)
+    assert np.isclose(st.c[0], 0.05 - 1e-3, rtol=1e-13)
+    gval = gamma * (kappa * (0.05 - 1e-3) - lam)
+    assert np.isclose(gval, -306.0)
+    for a, v in enumerate(ids):
+        assert np.allclose(Gc[v], gval * w[a] * n, rtol=1e-12, atol=1e-9)
+    for a, va in enumerate(ids):
+        for b, vb in enumerate(ids):
+            blk = Hc[3 * va:3 * va + 3, 3 * vb:3 * vb + 3]
+            assert np.allclose(blk, kappa * gamma * w[a] * w[b] * np.outer(n, n), rtol=1e-12, atol=1e-6)
+    others = np.setdiff1d(np.arange(8), ids)
+    assert np.all(Gc[others] == 0.0)
+    dofs = (3 * others[:, None] + np.arange(3)).ravel()
+    assert np.abs(Hc[dofs]).max() <= 1e-6 and np.abs(Hc[:, dofs]).max() <= 1e-6
+
+
+@pytest.mark.parametrize("kind", ["pt", "ee"])
+def test_constraint_value_offset_and_linearization(kind):
+    """c(x_hat) = d - delta + sum_a w_a n . (x_hat_a - x_a), by hand: p moves
+    down 0.02 and the constraint's third vertex moves (0.1, 0, 0.01)."""
+    ids, w = HAND[kind]
+    delta = 2.5e-3
+    rows = [ids]
+    xh = _two_tets([], [], 0.0, 1.0)["rest"].copy()
+    xh[ids[0]] += [0.0, 0.0, -0.02]
+    xh[ids[2]] += [0.1, 0.0, 0.01]
+    sc = _two_tets(rows if kind == "pt" else [], rows if kind == "ee" else [], 0.0, 1.0, delta=delta, x_hat=xh)
+    st = oracle.assemble(sc)
+    want = 0.05 - delta + w[0] * (-0.02) + w[2] * 0.01
+    assert np.isclose(st.c[0], want, rtol=1e-13)
+    sc0 = _two_tets(rows if kind == "pt" else [], rows if kind == "ee" else [], 0.0, 1.0, delta=delta)
+    assert np.isclose(oracle.assemble(sc0).c[0], 0.05 - delta, rtol=1e-14)
+
+
+def test_hessian_is_jacobian_of_gradient_where_nothing_is_projected():
+    """All constraints in the branch mu c < lambda (so G's contact part is
+    gamma (mu c - lambda) grad d, linear in x_hat) and every tet's 9x9
+    Hessian positive definite (so the projection changes nothing): then H is
+    exactly the Jacobian of G, and (G(x+eps v) - G(x-eps v)) / 2 eps = H v.
+    gamma varies per constraint (not 1), so a dropped or misplaced weight in
+    the Hessian fails here even where G is right."""
+    sc = free(scenes.tiny(lateral=(0.37, 0.21)))
+    rng = np.random.default_rng(17)
+    # each cube dilated 5 % about its own centre (twist modes stay positive), small noise
+    xh = sc["rest"].copy()
+    half = len(xh) // 2
+    for sl in (slice(0, half), slice(half, None)):
+        cen = xh[sl].mean(axis=0)
+        xh[sl] = cen + 1.05 * (xh[sl] - cen)
+    xh += rng.normal(0.0, 1e-3, size=xh.shape)
+    sc["x_hat"] = xh
+    n_c = len(sc["lam"])
+    sc["lam"] = np.full(n_c, 2000.0)
+    sc["gamma"] = rng.uniform(0.3, 1.7, size=n_c)
+    st = oracle.assemble(sc)
+    assert np.all(sc["kappa"] * st.c < sc["lam"] - 100.0)           # active branch, with margin
+    F = oracle.deformation_gradient(xh, st.tets, st.Dminv)
+    ev = np.linalg.eigvalsh(oracle.nh_hessian9(F, st.mu_l, st.lam_l))
+    assert ev.min() > 1e-3 * ev.max()                               # nothing to project
+    H = st.H.tocsr()
+    eps = 1e-6
+    for _ in range(3):
+        v = rng.normal(size=xh.shape)
+        Gp = oracle.assemble(dict(sc, x_hat=xh + eps * v)).G
+        Gm = oracle.assemble(dict(sc, x_hat=xh - eps * v)).G
+        fd = ((Gp - Gm) / (2 * eps)).ravel()
+        Hv = H @ v.ravel()
+        assert np.linalg.norm(fd - Hv) <= 1e-6 * np.linalg.norm(Hv)
+        # the contact part alone is resolved too (it is a large share of H v here)
+        bare = dict(sc, pt=sc["pt"][:0], ee=sc["ee"][:0], lam=sc["lam"][:0], gamma=sc["gamma"][:0])
+        Hc_v = Hv - oracle.assemble(bare).H @ v.ravel()
+        assert np.linalg.norm(Hc_v) > 1e-3 * np.linalg.norm(Hv)

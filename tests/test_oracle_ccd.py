@@ -217,3 +217,27 @@ def test_max_step_size_is_the_smallest_bound():
     xa = x + a * (xh - x)
     pt, ee = ccd.candidates(x, xh, tris, edges, verts, sc["delta"])
     assert ccd._dist("pt", xa[pt]).min() > 0 and ccd._dist("ee", xa[ee]).min() > 0
+
+
+def test_inversion_bound_does_not_depend_on_vertex_order():
+    """A negatively oriented tet (two vertices swapped) gets the bound of the
+    same tet in positive order: the closed forms above, and a static tet is
+    never limited (before the fix, a negative det D_s(0) gave 0 here)."""
+    rest = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    flip = [0, 2, 1, 3]
+    X1 = rest.copy()
+    X1[3, 2] = -1.0
+    t = ccd.inversion_bound(rest[flip][None], X1[flip][None])
+    assert t[0] == pytest.approx((1 - S) / 2, abs=1e-12)
+    c = rest.mean(axis=0)
+    t = ccd.inversion_bound(rest[flip][None], (2 * c - rest)[flip][None])
+    assert t[0] == pytest.approx((1 - S ** (1 / 3)) / 2, abs=1e-12)
+    assert ccd.inversion_bound(rest[flip][None], rest[flip][None])[0] == 1.0
+    assert ccd.inversion_bound(rest[flip][None], 1.5 * rest[flip][None])[0] == 1.0
+    # random motions: every tet's bound equals its flipped twin's
+    rng = np.random.default_rng(8)
+    X0 = rest[None] + rng.normal(0.0, 0.05, size=(50, 4, 3))
+    X1 = X0 + rng.normal(0.0, 0.6, size=(50, 4, 3))
+    a = ccd.inversion_bound(X0, X1)
+    b = ccd.inversion_bound(X0[:, flip], X1[:, flip])
+    assert np.allclose(a, b, atol=1e-12) and (a < 1.0).sum() >= 10
