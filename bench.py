@@ -32,21 +32,54 @@ def log(msg):
 
 
 def spmv_bytes(N, nnzb):
-    """Algorithmic bytes of one launch of k_spmv (symmetric SpMV): each of the
-    n_off = nnzb - N stored upper off-diagonal blocks once (36 B FP32 values
-    + 4 B column) and its entry of the transpose index (8 B: block index,
-    source row); two row pointers per row (8 B); p and r read once (24 B/node,
-    r for r^T q); q written once (12 B/node).  The second read of each block
-    (the lower half, gathered through the transpose index) is not counted."""
+    """Algorithmic bytes of one launch of the symmetric SpMV (the roofline's
+    unit of work): every stored upper block once, 36 B of FP32 values and a
+    4 B column index; a row pointer per row (4(N + 1) B); the vector read and
+    the product written (24 B/node).  nnzb counts the stored upper blocks with
+    the diagonal."""
+    return 40 * nnzb + 4 * (N + 1) + 24 * N
+
+
+def spmv_design_bytes(N, nnzb):
+    """What this design's SpMV must move at least: the n_off = nnzb - N
+    off-diagonal upper blocks once (36 B values + 4 B column; the diagonal
+    blocks of the scaled matrix are identities and are not stored), one 8 B
+    lower reference per block, two slice offsets per row, p and r read (r for
+    r^T q) and q written (36 B/node).  The lower half's second read of each
+    block is not counted (the same data)."""
     n_off = nnzb - N
     return 48 * n_off + 8 * (N + 1) + 36 * N
 
 
 def pcg_iteration_bytes(N, nnzb, check_every=1):
-    """k_spmv + k_update (p, q and r read, 36 B/node; the FP64 x read and
-    written, 48 B/node; r and the next p written, 24 B/node: 108 B/node, and
-    the factor L, 24 B/node, on the iterations that test |L r|)."""
-    return spmv_bytes(N, nnzb) + (108 + 24.0 / check_every) * N
+    """The SpMV's design bytes + the update kernel (p, q and r read, 36 B/node;
+    the FP64 x read and written, 48 B/node; r and the next p written,
+    24 B/node: 108 B/node, and the factor L, 24 B/node, on the iterations that
+    test |L r|)."""
+    return spmv_design_bytes(N, nnzb) + (108 + 24.0 / check_every) * N
+
+
+def copy_ceiling():
+    """Device-to-device copy of 512 MiB (read + write bytes per second), the
+    bandwidth a plain stream reaches on this device."""
+    import torch
+    n = 128 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_read": 4 * n, "bytes_written": 4 * n, "ms": round(ms, 4),
+            "gbs_read_plus_write": round(8 * n / (ms * 1e-3) / 1e9, 1)}
 
 
 COUNTER_FILE = os.path.join(ROOT, "profiles", "k_spmv_large_hbm_counters.md")
@@ -155,6 +188,62 @@ def serve_trace(server, reqs, arrivals, timeout=600.0):
         nxt = arrivals[k] - (time.perf_counter() - t0) if k < n else 2e-4
         time.sleep(min(max(nxt, 0.0), 2e-4))
     return lat, last - first, status, float(setup.mean()), float(pcg.mean())
+
+
+def run_abi_end_to_end(ctx, sc, opts):
+    """The same Newton step through the C-ABI with host buffers: a problem
+    created from host arrays (per-mesh setup, timed separately), then
+    bf_set_state and bf_set_constraints from host memory, bf_newton_step into
+    a host array; wall time of the three calls (PCIe copies included).  Median
+    of three after one warm-up call."""
+    from paper_2512_12151_amd import bfal
+    t0 = time.perf_counter()
+    pb = bfal.Problem(ctx, sc["tets"], sc["rest"], sc["E"], sc["nu"], sc["rho"], sc["fixed"])
+    ms_create = (time.perf_counter() - t0) * 1e3
+    ms = []
+    for rep in range(4):
+        t0 = time.perf_counter()
+        pb.set_state(sc["x"], sc["x_hat"], sc["x_tilde"], sc["dt"])
+        pb.set_constraints(sc["pt"], sc["ee"], sc["lam"], sc["gamma"], sc["kappa"], sc["delta"])
+        _, st, _ = pb.newton_step(**opts)
+        if rep:
+            ms.append((time.perf_counter() - t0) * 1e3)
+    pb.close()
+    return {"ms_problem_create": round(ms_create, 2), "ms_state_constraints_step": round(float(np.median(ms)), 2),
+            "pcg_iters": st["pcg_iters"],
+            "note": "host buffers in and out: x, x_hat, x_tilde, the constraint rows, lambda, gamma copied in, "
+                    "p copied out; not the metric (the metric's inputs are already in HBM)"}
+
+
+def run_bf16(args):
+    """The precision variant on the medium workload (120k tets): BF16 copies of
+    the scaled blocks inside the FP32/FP64 refinement to a 1e-6 relative
+    residual (inner tolerance 0.3), beside plain FP32 PCG to the same 1e-6.
+    Per sweep: the FP64 relative residual of the FP32-stored system."""
+    import torch
+
+    import scenes
+    from paper_2512_12151_amd import bfal
+    sc = scenes.make_scene("medium")
+    ctx = bfal.Context(0)
+    pb = bfal.Problem.from_scene(ctx, sc)
+    out = {}
+    for name, kw in (("bf16_refine", dict(tol=0.3, refine_tol=1e-6, precision=bfal.BF_PREC_BF16_REFINE)),
+                     ("fp32", dict(tol=1e-6))):
+        pb.newton_step(max_iter=50000, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st, status = pb.newton_step(max_iter=50000, **kw)
+        ms = (time.perf_counter() - t0) * 1e3
+        out[name] = {"ms_step": round(ms, 3), "status": status, "pcg_iters": st["pcg_iters"],
+                     "sweeps": st["refine_sweeps"], "rel_residual": st["rel_residual"],
+                     "ms_pcg": round(st["ms_pcg"], 3)}
+        if name == "bf16_refine":
+            out[name]["sweep_rel_residual"] = [float("%.3e" % v) for v in st["sweep_rel_residual"]]
+    pb.close()
+    ctx.close()
+    out["workload"] = "medium: 120000 tets, 26620 nodes, 12000 PT + 8000 EE, kappa 1e4, refinement to 1e-6"
+    return out
 
 
 def run_subproblem(args):
@@ -377,6 +466,8 @@ def main():
                     help="skip the material / friction step variants and the time-step leg")
     ap.add_argument("--no-ccd", dest="ccd", action="store_false",
                     help="skip the collision-query measurement (MaxStepSize, UpdateActiveSet)")
+    ap.add_argument("--no-bf16", dest="bf16", action="store_false",
+                    help="skip the BF16-blocks-with-refinement leg on the medium workload")
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving trace (0 skips the serving measurement)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -395,21 +486,7 @@ def main():
     from paper_2512_12151_amd import bfal
 
     if args.copy_probe:
-        n = 128 * 1024 * 1024   # floats: 512 MiB per buffer
-        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 20
-        e0.record()
-        for _ in range(reps):
-            b.copy_(a)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "ms": ms,
-                          "gbs_read_plus_write": 8 * n / (ms * 1e-3) / 1e9}), flush=True)
+        print(json.dumps(copy_ceiling()), flush=True)
         return
 
     log(f"generating workload {args.workload}")
@@ -431,17 +508,24 @@ def main():
     for w in range(args.warmup):
         _, st, status = pb.newton_step(out=out, **opts)
         log(f"warmup {w}: status {status}, {st['pcg_iters']} PCG iterations, rel residual {st['rel_residual']:.2e}")
+    # every step bracketed by events on the library's stream (torch's current
+    # stream, handed to the context); the wall clock spans all of them
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = []
     last = None
     for k in range(args.steps):
+        ev[k][0].record(stream)
         _, last, status = pb.newton_step(out=out, **opts)
+        ev[k][1].record(stream)
         iters.append(last["pcg_iters"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_step = elapsed / args.steps * 1e3
-    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step, iterations {iters}")
+    ms_events = [a.elapsed_time(b) for a, b in ev]
+    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step, event median {np.median(ms_events):.2f}, "
+        f"iterations {iters}")
     # dominant kernel: time the SpMV launches of one more step with HIP events on the library's stream
     _, tst, _ = pb.newton_step(out=out, time_spmv=256, **opts)
     nnzb = int(last["nnzb"])
@@ -450,6 +534,7 @@ def main():
     achieved = sb / (spmv_ms * 1e-3) / 1e9
     it_mean = float(np.mean(iters))
     pcg_gbs = pcg_iteration_bytes(N, nnzb, args.check_every) * last["pcg_iters"] / (last["ms_pcg"] * 1e-3) / 1e9
+    cc = copy_ceiling()
     line = {
         "metric": "Newton-step assemble+PCG ms @1e-5 rel residual",
         "value": round(ms_step, 3),
@@ -467,16 +552,27 @@ def main():
                                f"{len(sc['ee'])} EE constraints, kappa {sc['kappa']:g}, PCG tol {args.tol:g} "
                                f"(|L r| tested every {args.check_every} iterations)",
                    "parallelism": "single GPU"},
+        "ms_step_events": {"median": round(float(np.median(ms_events)), 3), "min": round(min(ms_events), 3),
+                           "max": round(max(ms_events), 3)},
         "pcg_iters": it_mean,
         "pcg_iters_per_s": round(last["pcg_iters"] / (last["ms_pcg"] * 1e-3), 1),
         "phase_ms": {k: round(last[k], 3) for k in ("ms_lin", "ms_pattern", "ms_assemble", "ms_pcg")},
-        "pcg_hbm_gbs": round(pcg_gbs, 1),
+        "pcg_design_gbs": round(pcg_gbs, 1),
         "nnzb": nnzb,
         "rel_residual": last["rel_residual"],
         "roofline": {"bound": "hbm", "kernel": "k_spmv", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(),
-                     "bytes_per_launch": sb, "avg_ms": round(spmv_ms, 5), "launches_timed": tst["spmv_timed"]},
+                     "traffic_scope": "bytes past L2 (rocprofv3 FETCH_SIZE and WRITE_SIZE per launch, scaled by a "
+                                      "plain copy's readings); Infinity Cache hits are included",
+                     "bytes_per_launch": sb, "bytes_formula": "40 nnzb + 4 (N + 1) + 24 N",
+                     "design_bytes_per_launch": spmv_design_bytes(N, nnzb),
+                     "design_frac": round(spmv_design_bytes(N, nnzb) / (spmv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "avg_ms": round(spmv_ms, 5), "launches_timed": tst["spmv_timed"],
+                     "copy_ceiling_gbs": cc["gbs_read_plus_write"],
+                     "frac_of_copy_ceiling": round(achieved / cc["gbs_read_plus_write"], 4)},
     }
+    line["abi_end_to_end"] = run_abi_end_to_end(ctx, sc, opts)
+    log(f"abi end to end: {line['abi_end_to_end']}")
     if args.subproblem:
         # FP64 energy evaluation (the line search's unit of work) on this workload
         torch.cuda.synchronize()
@@ -487,6 +583,9 @@ def main():
     if args.variants:
         line["variants"] = run_variants(ctx, t, sc, opts, pb)
     pb.close()
+    if args.bf16:
+        line["bf16_refine"] = run_bf16(args)
+        log(f"bf16: {line['bf16_refine']}")
     if args.subproblem:
         line["subproblem"] = run_subproblem(args)
         line["subproblem"]["energy_eval_ms_" + args.workload] = round(t_energy, 3)

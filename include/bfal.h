@@ -84,7 +84,7 @@ typedef struct {
                               - mu (J - 1) + lam/2 (J - 1)^2; corotated linear (F = R S the polar
                               decomposition): mu |F - R|^2 + lam/2 (tr S - 3)^2.  Every tet must stay
                               uninverted (J > 0).  Host arrays are validated; on device arrays a value other
-                              than 1 or 2 reads as 0.  Serving accepts Neo-Hookean meshes only (NULL). */
+                              than 1 or 2 reads as 0. */
 } bf_mesh_desc;
 
 /* Active constraint set C = {(i, lambda_i, gamma_i)} (Algorithm 2 input). */
@@ -393,7 +393,8 @@ typedef struct {
   size_t hbm_budget;         /* device bytes the admitted requests may hold (footprint estimates), > 0 */
   int32_t max_active;        /* at most this many admitted requests, >= 1 */
   int32_t iters_per_round;   /* batched PCG iterations between scheduling points, >= 1 */
-  int32_t admit_threads;     /* admission workers (each assembles on its own stream); 0 means 4 */
+  int32_t admit_threads;     /* admission workers (each assembles on its own stream); 0 means 3, which with
+                                the batch stream keeps to the 4 hardware queues a process gets */
 } bf_server_opts;
 typedef struct {
   double t_submit, t_admit, t_done;  /* seconds on bf_clock_now()'s clock */
@@ -403,9 +404,13 @@ typedef struct {
 double bf_clock_now(void);
 bf_status bf_server_create(int32_t device, const bf_server_opts* opts, bf_server** out);
 /* Copies the request (host memory only) and queues it; returns at once.
- * req_id must not be queued or finished-but-untaken already.  opts->precision
- * must be BF_PREC_FP32.  Invalid meshes or constraints are reported through
- * the request's status (bf_server_result), not here. */
+ * req_id must not be queued or finished-but-untaken already.  The arrays are
+ * checked here as the single-problem calls check them (bf_check_mesh,
+ * bf_check_state, bf_check_constraints, bf_check_solve_opts of bfal_host.h),
+ * and a failing check is returned at once; opts->precision must be
+ * BF_PREC_FP32.  Errors found on the device (an inverted element, a degenerate
+ * constraint) and BF_ERR_BUDGET are reported through the request's status
+ * (bf_server_result). */
 bf_status bf_server_submit(bf_server* srv, int64_t req_id, const bf_mesh_desc* mesh, const double* x,
                            const double* x_hat, const double* x_tilde, double dt,
                            const bf_constraint_desc* cons, const bf_solve_opts* opts);

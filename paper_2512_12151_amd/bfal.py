@@ -103,6 +103,10 @@ class bf_server_opts(C.Structure):
                 ("admit_threads", C.c_int32)]
 
 
+class bf_stall_rule(C.Structure):
+    _fields_ = [("alpha_min", C.c_double), ("window", C.c_int32), ("count", C.c_int32)]
+
+
 class bf_request_times(C.Structure):
     _fields_ = [("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
 
@@ -149,6 +153,21 @@ _PROTOS = [
     ("bf_server_stats", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_size_t)]),
     ("bf_server_destroy", None, [C.c_void_p]),
+    # host rules (include/bfal_host.h): no device needed
+    ("bf_check_mesh", C.c_int, [C.POINTER(bf_mesh_desc), C.c_char_p, C.c_int32]),
+    ("bf_check_state", C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_char_p, C.c_int32]),
+    ("bf_check_constraints", C.c_int, [C.c_int32, C.POINTER(bf_constraint_desc), C.c_char_p, C.c_int32]),
+    ("bf_check_solve_opts", C.c_int, [C.POINTER(bf_solve_opts), C.c_char_p, C.c_int32]),
+    ("bf_stall_step", C.c_int32, [C.POINTER(bf_stall_rule), C.c_double, C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double)]),
+    ("bf_admission_create", C.c_int, [C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
+    ("bf_admission_destroy", None, [C.c_void_p]),
+    ("bf_admission_push", C.c_int, [C.c_void_p, C.c_int64, C.c_uint64]),
+    ("bf_admission_next", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    ("bf_admission_release", C.c_int, [C.c_void_p, C.c_int32, C.c_uint64]),
+    ("bf_admission_used", C.c_uint64, [C.c_void_p]),
+    ("bf_admission_waiting", C.c_int32, [C.c_void_p]),
+    ("bf_admission_active", C.c_int32, [C.c_void_p]),
 ]
 
 EXPORTED = [p[0] for p in _PROTOS]
@@ -406,6 +425,107 @@ def footprint_bytes(n_nodes, n_tets, n_constraints):
     return int(out.value)
 
 
+# ------------------------------------------------ host rules (bfal_host.h)
+
+def _checked(fn, *args):
+    msg = C.create_string_buffer(256)
+    st = fn(*args, msg, len(msg))
+    return int(st), msg.value.decode()
+
+
+def check_mesh(tets, rest, E, nu, rho, fixed=None, material=None):
+    """bf_check_mesh on host arrays: (status, message)."""
+    tets, rest = _host(tets, np.int32).reshape(-1, 4), _host(rest, np.float64).reshape(-1, 3)
+    E, nu, rho = _host(E, np.float64), _host(nu, np.float64), _host(rho, np.float64)
+    fixed = None if fixed is None else _host(fixed, np.uint8)
+    material = None if material is None else _host(material, np.int32)
+    d = bf_mesh_desc(len(rest), len(tets), _ptr(tets), _ptr(rest), _ptr(E), _ptr(nu), _ptr(rho), _ptr(fixed),
+                     _ptr(material))
+    return _checked(lib().bf_check_mesh, C.byref(d))
+
+
+def check_state(n_nodes, x, x_hat, x_tilde, dt):
+    """bf_check_state on host arrays: (status, message)."""
+    x, xh, xt = (None if a is None else _host(a, np.float64) for a in (x, x_hat, x_tilde))
+    return _checked(lib().bf_check_state, int(n_nodes), _ptr(x), _ptr(xh), _ptr(xt), float(dt))
+
+
+def check_constraints(n_nodes, pt, ee, lam, gamma, kappa, delta):
+    """bf_check_constraints on host arrays: (status, message)."""
+    pt, ee = _host(pt, np.int32).reshape(-1, 4), _host(ee, np.int32).reshape(-1, 4)
+    lam = _host(lam, np.float64)
+    gamma = None if gamma is None else _host(gamma, np.float64)
+    d = bf_constraint_desc(len(pt), len(ee), _ptr(pt) if len(pt) else None, _ptr(ee) if len(ee) else None,
+                           _ptr(lam) if len(lam) else None, _ptr(gamma) if gamma is not None and len(gamma) else None,
+                           float(kappa), float(delta))
+    return _checked(lib().bf_check_constraints, int(n_nodes), C.byref(d))
+
+
+def check_solve_opts(tol=1e-5, max_iter=20000, precision=BF_PREC_FP32, refine_tol=1e-6):
+    """bf_check_solve_opts: (status, message)."""
+    o = bf_solve_opts(float(tol), int(max_iter), int(precision), float(refine_tol), 16, 1, 0, 0)
+    return _checked(lib().bf_check_solve_opts, C.byref(o))
+
+
+class StallRule:
+    """Section 5.2's stall rule (bf_stall_step)."""
+
+    def __init__(self, alpha_min=1e-4, window=50):
+        self.r = bf_stall_rule(float(alpha_min), int(window), 0)
+
+    def step(self, alpha, kappa, delta):
+        """Returns (fired, kappa, delta) after one outer iteration's alpha."""
+        k, d = C.c_double(kappa), C.c_double(delta)
+        fired = lib().bf_stall_step(C.byref(self.r), float(alpha), C.byref(k), C.byref(d))
+        if fired < 0:
+            raise BfalError(-1, "bf_stall_step: bad argument")
+        return bool(fired), k.value, d.value
+
+
+class Admission:
+    """The serving engine's admission policy (bf_admission_*)."""
+
+    def __init__(self, hbm_budget, slots):
+        self.h = C.c_void_p()
+        st = lib().bf_admission_create(int(hbm_budget), int(slots), C.byref(self.h))
+        if st != BF_OK:
+            raise BfalError(st, "bf_admission_create failed")
+
+    def push(self, req_id, footprint):
+        st = lib().bf_admission_push(self.h, int(req_id), int(footprint))
+        if st != BF_OK:
+            raise BfalError(st, "bf_admission_push failed")
+
+    def next(self):
+        """(+1, id, slot) admitted, (-1, id, -1) rejected as never fitting, (0, None, None) wait."""
+        i, s = C.c_int64(), C.c_int32()
+        d = lib().bf_admission_next(self.h, C.byref(i), C.byref(s))
+        return (int(d), int(i.value), int(s.value)) if d else (0, None, None)
+
+    def release(self, slot, footprint):
+        return int(lib().bf_admission_release(self.h, int(slot), int(footprint)))
+
+    def used(self):
+        return int(lib().bf_admission_used(self.h))
+
+    def waiting(self):
+        return int(lib().bf_admission_waiting(self.h))
+
+    def active(self):
+        return int(lib().bf_admission_active(self.h))
+
+    def close(self):
+        if self.h:
+            lib().bf_admission_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def clock_now():
     """The library's monotonic clock (seconds), the one request times use."""
     return float(lib().bf_clock_now())
@@ -415,7 +535,7 @@ class Server:
     """Continuous-batching server (bf_server_*): submit host-memory requests,
     poll for finished ids, take results.  Arguments are marshalled only."""
 
-    def __init__(self, device=0, hbm_budget=8 << 30, max_active=64, iters_per_round=8, admit_threads=4):
+    def __init__(self, device=0, hbm_budget=8 << 30, max_active=64, iters_per_round=8, admit_threads=0):
         o = bf_server_opts(int(hbm_budget), int(max_active), int(iters_per_round), int(admit_threads))
         self.h = C.c_void_p()
         st = lib().bf_server_create(int(device), C.byref(o), C.byref(self.h))
@@ -432,7 +552,9 @@ class Server:
         pt, ee = _host(sc["pt"], np.int32).reshape(-1, 4), _host(sc["ee"], np.int32).reshape(-1, 4)
         lam = _host(sc["lam"], np.float64)
         gamma = None if sc.get("gamma") is None else _host(sc["gamma"], np.float64)
-        m = bf_mesh_desc(len(rest), len(tets), _ptr(tets), _ptr(rest), _ptr(E), _ptr(nu), _ptr(rho), _ptr(fixed))
+        material = None if sc.get("material") is None else _host(sc["material"], np.int32)
+        m = bf_mesh_desc(len(rest), len(tets), _ptr(tets), _ptr(rest), _ptr(E), _ptr(nu), _ptr(rho), _ptr(fixed),
+                         _ptr(material))
         d = bf_constraint_desc(len(pt), len(ee), _ptr(pt) if len(pt) else None, _ptr(ee) if len(ee) else None,
                                _ptr(lam) if len(lam) else None,
                                _ptr(gamma) if gamma is not None and len(gamma) else None,

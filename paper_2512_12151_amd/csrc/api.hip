@@ -19,29 +19,25 @@ using namespace bfal;
 namespace bfal {
 
 bf_status problem_init(bf_context* c, bf_problem* pb, const bf_mesh_desc* m, int32_t mem) {
-  if (!m || !m->tets || !m->rest || !m->E || !m->nu || !m->rho)
-    return fail(c, BF_ERR_INVALID_ARG, "mesh descriptor or one of its arrays is NULL");
-  if (m->n_nodes <= 0 || m->n_tets <= 0) return fail(c, BF_ERR_INVALID_ARG, "n_nodes and n_tets must be positive");
-  if ((long long)m->n_tets * 10 >= (1LL << 31) || (long long)m->n_nodes * 3 >= (1LL << 31))
-    return fail(c, BF_ERR_INVALID_ARG, "mesh too large for 32-bit slot indices");
   if (mem != BF_MEM_HOST && mem != BF_MEM_DEVICE) return fail(c, BF_ERR_INVALID_ARG, "mem must be BF_MEM_HOST or BF_MEM_DEVICE");
-  const int N = m->n_nodes, T = m->n_tets;
-  if (mem == BF_MEM_HOST) {
-    for (long long e = 0; e < T; ++e) {
-      const int32_t* t = m->tets + 4 * e;
-      for (int a = 0; a < 4; ++a)
-        if (t[a] < 0 || t[a] >= N) return fail(c, BF_ERR_INVALID_ARG, "tet vertex index out of range");
-      if (t[0] == t[1] || t[0] == t[2] || t[0] == t[3] || t[1] == t[2] || t[1] == t[3] || t[2] == t[3])
-        return fail(c, BF_ERR_INVALID_ARG, "tet with a repeated vertex");
-      if (!(m->E[e] > 0.0) || !std::isfinite(m->E[e]) || !(m->nu[e] > -1.0 && m->nu[e] < 0.5) ||
-          !(m->rho[e] > 0.0) || !std::isfinite(m->rho[e]))
-        return fail(c, BF_ERR_INVALID_ARG, "invalid material value");
-      if (m->material && (m->material[e] < 0 || m->material[e] > 2))
-        return fail(c, BF_ERR_INVALID_ARG,
-                    "material code must be 0 (Neo-Hookean), 1 (stable Neo-Hookean) or 2 (corotated linear)");
+  {
+    char msg[160];
+    bf_status st = BF_OK;
+    if (mem == BF_MEM_HOST) {
+      st = bf_check_mesh(m, msg, sizeof msg);
+    } else if (!m || !m->tets || !m->rest || !m->E || !m->nu || !m->rho) {
+      st = BF_ERR_INVALID_ARG;
+      std::snprintf(msg, sizeof msg, "mesh descriptor or one of its arrays is NULL");
+    } else if (m->n_nodes <= 0 || m->n_tets <= 0) {
+      st = BF_ERR_INVALID_ARG;
+      std::snprintf(msg, sizeof msg, "n_nodes and n_tets must be positive");
+    } else if ((long long)m->n_tets * 10 >= (1LL << 31) || (long long)m->n_nodes * 3 >= (1LL << 31)) {
+      st = BF_ERR_INVALID_ARG;
+      std::snprintf(msg, sizeof msg, "mesh too large for 32-bit slot indices");
     }
-    if (!finite_all(m->rest, 3LL * N)) return fail(c, BF_ERR_INVALID_ARG, "non-finite rest position");
+    if (st != BF_OK) return fail(c, st, msg);
   }
+  const int N = m->n_nodes, T = m->n_tets;
   HIPCHK(c, hipSetDevice(c->device));
   pb->ctx = c;
   pb->N = N;
@@ -88,7 +84,7 @@ bf_status problem_init(bf_context* c, bf_problem* pb, const bf_mesh_desc* m, int
   bf_status r0 = read_flags(pb, &hflags);
   if (r0 != BF_OK) return r0;
   if (hflags) return flags_to_status(c, hflags);
-  launch_rest_geometry(tets, pb->rest.as<double>(), pb->E.as<double>(), pb->nu.as<double>(), T,
+  launch_rest_geometry(tets, pb->rest.as<double>(), pb->E.as<double>(), pb->nu.as<double>(), pb->rho.as<double>(), T,
                        pb->Dminv9.as<float>(), pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), flags, s);
   // static elastic pattern: pair keys bucketed by row, sorted and unique per row
   const long long npairs = 6LL * T;
@@ -368,12 +364,22 @@ bf_status bf_set_state(bf_problem* pb, const double* x, const double* x_hat, con
                        int32_t mem) {
   if (!pb) return BF_ERR_INVALID_ARG;
   bf_context* c = pb->ctx;
-  if (!x || !x_hat || !x_tilde) return fail(c, BF_ERR_INVALID_ARG, "state array is NULL");
-  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, BF_ERR_INVALID_ARG, "dt must be positive and finite");
   if (mem != BF_MEM_HOST && mem != BF_MEM_DEVICE) return fail(c, BF_ERR_INVALID_ARG, "bad mem kind");
+  {
+    char msg[160];
+    bf_status st = BF_OK;
+    if (mem == BF_MEM_HOST) {
+      st = bf_check_state(pb->N, x, x_hat, x_tilde, dt, msg, sizeof msg);
+    } else if (!x || !x_hat || !x_tilde) {
+      st = BF_ERR_INVALID_ARG;
+      std::snprintf(msg, sizeof msg, "state array is NULL");
+    } else if (!(dt > 0.0) || !std::isfinite(dt)) {
+      st = BF_ERR_INVALID_ARG;
+      std::snprintf(msg, sizeof msg, "dt must be positive and finite");
+    }
+    if (st != BF_OK) return fail(c, st, msg);
+  }
   const long long n3 = 3LL * pb->N;
-  if (mem == BF_MEM_HOST && (!finite_all(x, n3) || !finite_all(x_hat, n3) || !finite_all(x_tilde, n3)))
-    return fail(c, BF_ERR_INVALID_ARG, "non-finite state value");
   ALLOC(c, pb->x, 8 * n3);
   ALLOC(c, pb->xh, 8 * n3);
   ALLOC(c, pb->xt, 8 * n3);
@@ -390,35 +396,32 @@ bf_status bf_set_state(bf_problem* pb, const double* x, const double* x_hat, con
 bf_status bf_set_constraints(bf_problem* pb, const bf_constraint_desc* cd, int32_t mem) {
   if (!pb) return BF_ERR_INVALID_ARG;
   bf_context* c = pb->ctx;
-  if (!cd) return fail(c, BF_ERR_INVALID_ARG, "constraint descriptor is NULL");
-  if (cd->n_pt < 0 || cd->n_ee < 0) return fail(c, BF_ERR_INVALID_ARG, "negative constraint count");
-  const long long nc = (long long)cd->n_pt + cd->n_ee;
-  if (nc * 10 >= (1LL << 31)) return fail(c, BF_ERR_INVALID_ARG, "too many constraints");
-  if ((cd->n_pt && !cd->pt) || (cd->n_ee && !cd->ee) || (nc && !cd->lambda))
-    return fail(c, BF_ERR_INVALID_ARG, "constraint array is NULL");
-  if (!(cd->kappa > 0.0) || !std::isfinite(cd->kappa)) return fail(c, BF_ERR_INVALID_ARG, "kappa must be positive");
-  if (!(cd->delta >= 0.0) || !std::isfinite(cd->delta)) return fail(c, BF_ERR_INVALID_ARG, "delta must be >= 0");
   if (mem != BF_MEM_HOST && mem != BF_MEM_DEVICE) return fail(c, BF_ERR_INVALID_ARG, "bad mem kind");
   const int N = pb->N;
-  if (mem == BF_MEM_HOST) {
-    for (int part = 0; part < 2; ++part) {
-      const int32_t* a = part ? cd->ee : cd->pt;
-      const long long n = part ? cd->n_ee : cd->n_pt;
-      for (long long i = 0; i < n; ++i) {
-        const int32_t* t = a + 4 * i;
-        for (int k = 0; k < 4; ++k)
-          if (t[k] < 0 || t[k] >= N) return fail(c, BF_ERR_INVALID_ARG, "constraint vertex index out of range");
-        if (t[0] == t[1] || t[0] == t[2] || t[0] == t[3] || t[1] == t[2] || t[1] == t[3] || t[2] == t[3])
-          return fail(c, BF_ERR_DEGENERATE_CONSTRAINT, "constraint with a repeated vertex");
-      }
+  {
+    // a device descriptor: its scalars and pointers here, its contents in k_check_constraints below
+    char msg[160];
+    bf_status st = BF_OK;
+    if (mem == BF_MEM_HOST) {
+      st = bf_check_constraints(N, cd, msg, sizeof msg);
+    } else if (cd) {
+      const long long n_all = (long long)cd->n_pt + cd->n_ee;
+      const bf_constraint_desc scalars{0, 0, nullptr, nullptr, nullptr, nullptr, cd->kappa, cd->delta};
+      st = BF_ERR_INVALID_ARG;
+      if (cd->n_pt < 0 || cd->n_ee < 0)
+        std::snprintf(msg, sizeof msg, "negative constraint count");
+      else if (n_all * 10 >= (1LL << 31))
+        std::snprintf(msg, sizeof msg, "too many constraints");
+      else if ((cd->n_pt && !cd->pt) || (cd->n_ee && !cd->ee) || (n_all && !cd->lambda))
+        std::snprintf(msg, sizeof msg, "constraint array is NULL");
+      else
+        st = bf_check_constraints(N, &scalars, msg, sizeof msg);
+    } else {
+      st = bf_check_constraints(N, cd, msg, sizeof msg);
     }
-    for (long long i = 0; i < nc; ++i) {
-      if (!(cd->lambda[i] >= 0.0) || !std::isfinite(cd->lambda[i]))
-        return fail(c, BF_ERR_INVALID_ARG, "lambda must be finite and >= 0");
-      if (cd->gamma && !(cd->gamma[i] > 0.0 && cd->gamma[i] <= 1.0))
-        return fail(c, BF_ERR_INVALID_ARG, "gamma must lie in (0, 1]");
-    }
+    if (st != BF_OK) return fail(c, st, msg);
   }
+  const long long nc = (long long)cd->n_pt + cd->n_ee;
   hipStream_t s = c->stream;
   const int n = (int)nc;
   ALLOC(c, pb->cids, 16LL * n + 16);
@@ -571,11 +574,11 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
   if (!o || !p_out) return fail(c, BF_ERR_INVALID_ARG, "opts or p_out is NULL");
   if (!pb->has_state) return fail(c, BF_ERR_STATE, "bf_set_state must be called before bf_newton_step");
   if (pb->cap_nnzb == 0) return fail(c, BF_ERR_STATE, "bf_set_constraints must be called before bf_newton_step");
-  if (!(o->tol > 0.0) || o->max_iter < 0) return fail(c, BF_ERR_INVALID_ARG, "tol must be > 0 and max_iter >= 0");
-  if (o->precision != BF_PREC_FP32 && o->precision != BF_PREC_BF16_REFINE)
-    return fail(c, BF_ERR_INVALID_ARG, "unsupported precision mode");
-  if (o->precision == BF_PREC_BF16_REFINE && !(o->refine_tol > 0.0))
-    return fail(c, BF_ERR_INVALID_ARG, "refine_tol must be > 0");
+  {
+    char msg[160];
+    const bf_status st = bf_check_solve_opts(o, msg, sizeof msg);
+    if (st != BF_OK) return fail(c, st, msg);
+  }
   const bool bf16 = o->precision == BF_PREC_BF16_REFINE;
   if (mem != BF_MEM_HOST && mem != BF_MEM_DEVICE) return fail(c, BF_ERR_INVALID_ARG, "bad mem kind");
   HIPCHK(c, hipSetDevice(c->device));

@@ -11,6 +11,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 SOURCES = ["scan.hip", "setup.hip", "contact.hip", "elastic.hip", "assemble.hip", "pcg.hip", "subproblem.hip", "ccd.hip", "activeset.hip", "timestep.hip", "api.hip",
            "server.hip"]
+# host rules (include/bfal_host.h): no HIP, built with the host compiler
+HOST_SOURCES = ["host_rules.cpp"]
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra"]
 OUT = os.path.join(PKG, "libbfal.so")
 
 FLAGS = [
@@ -38,11 +41,23 @@ def _compile(src: str, build_dir: str) -> str:
     return obj
 
 
+def _compile_host(src: str, build_dir: str) -> str:
+    """Plain host C++ (no HIP) with the host compiler."""
+    obj = os.path.join(build_dir, src.replace(".cpp", ".o"))
+    cmd = [os.environ.get("CXX", "g++"), *HOST_FLAGS, "-c", os.path.join(HERE, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"host compile failed for {src}:\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
 def build(verbose: bool = False) -> str:
     build_dir = os.path.join(PKG, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, build_dir), SOURCES))
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES) + len(HOST_SOURCES))) as ex:
+        futs = [ex.submit(_compile, s, build_dir) for s in SOURCES]
+        futs += [ex.submit(_compile_host, s, build_dir) for s in HOST_SOURCES]
+        objs = [f.result() for f in futs]
     tmp = OUT + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

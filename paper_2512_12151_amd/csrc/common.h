@@ -9,6 +9,7 @@
 #include <string>
 
 #include "../../include/bfal.h"
+#include "../../include/bfal_host.h"
 
 namespace bfal {
 
@@ -121,7 +122,7 @@ void fill_int(int* a, int v, long long n, hipStream_t s);
 // setup.hip: per-mesh work
 void launch_check_tets(const int4* tets, int T, int N, int* flags, hipStream_t s);
 void launch_rest_geometry(const int4* tets, const double* rest, const double* E, const double* nu,
-                          int T, float* Dminv9, float* vol, float* mu, float* lam, int* flags,
+                          const double* rho, int T, float* Dminv9, float* vol, float* mu, float* lam, int* flags,
                           hipStream_t s);
 void launch_elastic_pair_count(const int4* tets, int T, int* cnt, hipStream_t s);
 void launch_elastic_pair_fill(const int4* tets, int T, const int* ptr, int* cursor, int* keys,
@@ -264,10 +265,7 @@ void launch_slice_widths(int N, int nslices, const int* row_ptr, const int* lptr
 // The SpMV visits upper and lower slots in pairs, kPairs per step, and reads
 // up to (max width + kPairs) * kSlice slots past the end of a slice's range;
 // the slot arrays carry that much zeroed padding after their last slot.
-#ifndef BFAL_SPMV_PAIRS
-#define BFAL_SPMV_PAIRS 2
-#endif
-constexpr int kPairs = BFAL_SPMV_PAIRS;
+constexpr int kPairs = 2;
 inline long long slot_padding(int wmax_other) { return (long long)(wmax_other + kPairs + 1) * kSlice; }
 void launch_sell_fill(int N, int nslices, const int* row_ptr, const int* col, const float* vals, const float* Linv,
                       const int* lptr, const int* lsrc, const int* sbu, const int* sbl, float* blk, uint32_t* blk16,

@@ -271,79 +271,6 @@ struct PView {
   }
 };
 
-#ifndef BFAL_SPMV_PAIRED
-#define BFAL_SPMV_PAIRED 1
-#endif
-
-// Accumulates the w slots of one row starting at base (stride kSlice):
-// upper slots (B p_c, columns from scol) or lower slots (B^T p_r, block and
-// source row from sent), 4 slots per step with all their loads issued before
-// any is used.  The sum runs in slot order.
-template <bool kLower, class BT>
-__device__ inline void accumulate_slots(int base, int w, const int* __restrict__ scol,
-                                        const int2* __restrict__ sent, const BT* __restrict__ blk, const PView& pv,
-                                        float& a0, float& a1, float& a2) {
-  constexpr int U = 4;
-  int kk = 0;
-  for (; kk + U <= w; kk += U) {
-    int bi[U], c[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = base + (kk + u) * kSlice;
-      if (kLower) {
-        const int2 t = sent[e];
-        bi[u] = t.x;
-        c[u] = t.y;
-      } else {
-        bi[u] = e;
-        c[u] = scol[e];
-      }
-    }
-    float b[U][9], p[U][3];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      load_block(blk, bi[u], b[u]);
-      pv.at(c[u], p[u][0], p[u][1], p[u][2]);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (kLower) {
-        a0 += b[u][0] * p[u][0] + b[u][3] * p[u][1] + b[u][6] * p[u][2];
-        a1 += b[u][1] * p[u][0] + b[u][4] * p[u][1] + b[u][7] * p[u][2];
-        a2 += b[u][2] * p[u][0] + b[u][5] * p[u][1] + b[u][8] * p[u][2];
-      } else {
-        a0 += b[u][0] * p[u][0] + b[u][1] * p[u][1] + b[u][2] * p[u][2];
-        a1 += b[u][3] * p[u][0] + b[u][4] * p[u][1] + b[u][5] * p[u][2];
-        a2 += b[u][6] * p[u][0] + b[u][7] * p[u][1] + b[u][8] * p[u][2];
-      }
-    }
-  }
-  for (; kk < w; ++kk) {
-    const int e = base + kk * kSlice;
-    int bi, c;
-    if (kLower) {
-      const int2 t = sent[e];
-      bi = t.x;
-      c = t.y;
-    } else {
-      bi = e;
-      c = scol[e];
-    }
-    float b[9], p0, p1, p2;
-    load_block(blk, bi, b);
-    pv.at(c, p0, p1, p2);
-    if (kLower) {
-      a0 += b[0] * p0 + b[3] * p1 + b[6] * p2;
-      a1 += b[1] * p0 + b[4] * p1 + b[7] * p2;
-      a2 += b[2] * p0 + b[5] * p1 + b[8] * p2;
-    } else {
-      a0 += b[0] * p0 + b[1] * p1 + b[2] * p2;
-      a1 += b[3] * p0 + b[4] * p1 + b[5] * p2;
-      a2 += b[6] * p0 + b[7] * p1 + b[8] * p2;
-    }
-  }
-}
-
 // Accumulates one row's slots as pairs (upper slot k: B p_c with the column
 // from scol; lower slot k: B^T p_r with block and source row from sent),
 // kPairs pairs per step with all their loads issued before any is used.  A
@@ -404,12 +331,7 @@ __device__ inline void spmv_slices(const PcgSystem& S, int lb, int nwg, int k, d
     const int bu = S.sbu[sl], wu = (S.sbu[sl + 1] - bu) / kSlice;
     const int bl = S.sbl[sl], wl = (S.sbl[sl + 1] - bl) / kSlice;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-#if BFAL_SPMV_PAIRED
     accumulate_pairs<BT>(bu + lane, wu, bl + lane, wl, S.scol, S.sent, blk, pv, a0, a1, a2);
-#else
-    accumulate_slots<false, BT>(bu + lane, wu, S.scol, S.sent, blk, pv, a0, a1, a2);
-    accumulate_slots<true, BT>(bl + lane, wl, S.scol, S.sent, blk, pv, a0, a1, a2);
-#endif
     const int row = sl * kSlice + lane;
     if (row < S.N) {
       float s0, s1, s2;

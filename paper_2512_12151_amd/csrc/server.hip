@@ -43,7 +43,7 @@ double now_s() {
 struct Request {
   int64_t id = 0;
   int32_t N = 0, T = 0, n_pt = 0, n_ee = 0;
-  std::vector<int32_t> tets, pt, ee;
+  std::vector<int32_t> tets, pt, ee, material;
   std::vector<double> rest, E, nu, rho, x, xh, xt, lam, gam;
   std::vector<uint8_t> fixed;
   double dt = 0.0, kappa = 0.0, delta = 0.0;
@@ -68,13 +68,12 @@ struct Slot {
 struct bf_server {
   std::vector<bf_context*> admit_ctx;   // own contexts: one stream per admission worker
   bf_context* batch_ctx = nullptr;
-  size_t budget = 0, used = 0;
+  bf_admission* adm = nullptr;              // arrival-order admission by footprint and slot (bfal_host.h)
   int max_active = 1, iters_per_round = 8;
   std::mutex mu;
   std::condition_variable cv;
-  std::deque<Request*> pending;               // submitted, not admitted (arrival order)
+  std::deque<Request*> pending;               // submitted, not admitted (the admission queue's order)
   std::deque<int> ready;                      // slots assembled by the admission thread
-  std::vector<int> free_slots;
   std::vector<Slot> slots;
   std::unordered_map<int64_t, Request*> done; // finished, result not yet taken
   std::vector<int64_t> done_unreported;
@@ -124,7 +123,7 @@ bf_status prepare(bf_server* sv, bf_context* c, int si, Request* r) {
   bf_problem* pb = sl.pb;
   pb->ctx = c;
   bf_mesh_desc m{r->N, r->T, r->tets.data(), r->rest.data(), r->E.data(), r->nu.data(), r->rho.data(),
-                 r->fixed.empty() ? nullptr : r->fixed.data(), nullptr};
+                 r->fixed.empty() ? nullptr : r->fixed.data(), r->material.empty() ? nullptr : r->material.data()};
   bf_status st = problem_init(c, pb, &m, BF_MEM_HOST);
   if (st != BF_OK) return st;
   st = bf_set_state(pb, r->x.data(), r->xh.data(), r->xt.data(), r->dt, BF_MEM_HOST);
@@ -156,23 +155,22 @@ void admission_loop(bf_server* sv, int worker) {
       std::unique_lock<std::mutex> lk(sv->mu);
       for (;;) {
         if (sv->stop) return;
-        if (!sv->pending.empty()) {
+        int64_t id = 0;
+        int32_t slot = -1;
+        const int32_t d = bf_admission_next(sv->adm, &id, &slot);
+        if (d == -1) {   // can never fit: rejected without blocking the queue
           Request* h = sv->pending.front();
-          if (h->footprint > sv->budget) {   // can never fit: reject without blocking the queue
-            sv->pending.pop_front();
-            lk.unlock();
-            finish_request(sv, h, BF_ERR_BUDGET, "request footprint exceeds the server's HBM budget");
-            lk.lock();
-            continue;
-          }
-          if (!sv->free_slots.empty() && sv->used + h->footprint <= sv->budget) {
-            r = h;
-            sv->pending.pop_front();
-            si = sv->free_slots.back();
-            sv->free_slots.pop_back();
-            sv->used += r->footprint;
-            break;
-          }
+          sv->pending.pop_front();
+          lk.unlock();
+          finish_request(sv, h, BF_ERR_BUDGET, "request footprint exceeds the server's HBM budget");
+          lk.lock();
+          continue;
+        }
+        if (d == 1) {
+          r = sv->pending.front();
+          sv->pending.pop_front();
+          si = slot;
+          break;
         }
         sv->cv.wait(lk);
       }
@@ -184,8 +182,7 @@ void admission_loop(bf_server* sv, int worker) {
       const std::string msg = c->err;
       {
         std::lock_guard<std::mutex> lk(sv->mu);
-        sv->used -= r->footprint;
-        sv->free_slots.push_back(si);
+        (void)bf_admission_release(sv->adm, si, r->footprint);
         sv->slots[si].req = nullptr;
       }
       finish_request(sv, r, st, msg);
@@ -293,9 +290,8 @@ void retire(bf_server* sv, int si, const int* stat) {
   pb->stepped = true;
   {
     std::lock_guard<std::mutex> lk(sv->mu);
-    sv->used -= r->footprint;
+    (void)bf_admission_release(sv->adm, si, r->footprint);
     sl.req = nullptr;
-    sv->free_slots.push_back(si);
   }
   r->stats.ms_pcg = (now_s() - r->t_admit) * 1e3 - r->ms_setup;
   finish_request(sv, r, st, msg);
@@ -326,9 +322,8 @@ void batch_loop(bf_server* sv) {
           Request* r = sv->slots[si].req;
           {
             std::lock_guard<std::mutex> lk(sv->mu);
-            sv->used -= r->footprint;
+            (void)bf_admission_release(sv->adm, si, r->footprint);
             sv->slots[si].req = nullptr;
-            sv->free_slots.push_back(si);
           }
           finish_request(sv, r, BF_ERR_HIP, c->err);
         }
@@ -354,9 +349,8 @@ void batch_loop(bf_server* sv) {
         Request* r = sv->slots[si].req;
         {
           std::lock_guard<std::mutex> lk(sv->mu);
-          sv->used -= r->footprint;
+          (void)bf_admission_release(sv->adm, si, r->footprint);
           sv->slots[si].req = nullptr;
-          sv->free_slots.push_back(si);
         }
         finish_request(sv, r, BF_ERR_HIP, c->err);
       }
@@ -402,7 +396,9 @@ bf_status bf_server_create(int32_t device, const bf_server_opts* o, bf_server** 
     return BF_ERR_INVALID_ARG;
   bf_server* sv = new (std::nothrow) bf_server();
   if (!sv) return BF_ERR_OOM;
-  const int nadmit = o->admit_threads > 0 ? o->admit_threads : 4;
+  // three admission streams and the batch stream: within the four hardware
+  // queues a process gets by default, so the batch never shares one
+  const int nadmit = o->admit_threads > 0 ? o->admit_threads : 3;
   bf_status st = bf_context_create(device, nullptr, &sv->batch_ctx);
   for (int i = 0; i < nadmit && st == BF_OK; ++i) {
     bf_context* c = nullptr;
@@ -413,11 +409,14 @@ bf_status bf_server_create(int32_t device, const bf_server_opts* o, bf_server** 
     bf_server_destroy(sv);
     return st;
   }
-  sv->budget = o->hbm_budget;
+  st = bf_admission_create(o->hbm_budget, o->max_active, &sv->adm);
+  if (st != BF_OK) {
+    bf_server_destroy(sv);
+    return st;
+  }
   sv->max_active = o->max_active;
   sv->iters_per_round = o->iters_per_round;
   sv->slots.resize(o->max_active);
-  for (int i = o->max_active - 1; i >= 0; --i) sv->free_slots.push_back(i);
   for (int i = 0; i < nadmit; ++i) sv->admit_threads.emplace_back(admission_loop, sv, i);
   sv->batch_thread = std::thread(batch_loop, sv);
   *out = sv;
@@ -427,11 +426,15 @@ bf_status bf_server_create(int32_t device, const bf_server_opts* o, bf_server** 
 bf_status bf_server_submit(bf_server* sv, int64_t req_id, const bf_mesh_desc* m, const double* x,
                            const double* x_hat, const double* x_tilde, double dt, const bf_constraint_desc* cd,
                            const bf_solve_opts* opts) {
-  if (!sv || !m || !cd || !opts || !x || !x_hat || !x_tilde) return BF_ERR_INVALID_ARG;
-  if (m->n_nodes <= 0 || m->n_tets <= 0 || !m->tets || !m->rest || !m->E || !m->nu || !m->rho) return BF_ERR_INVALID_ARG;
-  if (cd->n_pt < 0 || cd->n_ee < 0 || (cd->n_pt + cd->n_ee > 0 && !cd->lambda)) return BF_ERR_INVALID_ARG;
-  if ((cd->n_pt && !cd->pt) || (cd->n_ee && !cd->ee)) return BF_ERR_INVALID_ARG;
-  if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->precision != BF_PREC_FP32) return BF_ERR_INVALID_ARG;
+  if (!sv || !m || !cd || !opts) return BF_ERR_INVALID_ARG;
+  // the request's host arrays, checked here as bf_problem_create, bf_set_state,
+  // bf_set_constraints and bf_newton_step check them (the FP32 mode only)
+  bf_status chk = bf_check_mesh(m, nullptr, 0);
+  if (chk == BF_OK) chk = bf_check_state(m->n_nodes, x, x_hat, x_tilde, dt, nullptr, 0);
+  if (chk == BF_OK) chk = bf_check_constraints(m->n_nodes, cd, nullptr, 0);
+  if (chk == BF_OK) chk = bf_check_solve_opts(opts, nullptr, 0);
+  if (chk != BF_OK) return chk;
+  if (opts->precision != BF_PREC_FP32) return BF_ERR_INVALID_ARG;
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->done.count(req_id)) return BF_ERR_INVALID_ARG;
@@ -453,6 +456,7 @@ bf_status bf_server_submit(bf_server* sv, int64_t req_id, const bf_mesh_desc* m,
   copy_in(r->nu, m->nu, T);
   copy_in(r->rho, m->rho, T);
   copy_in(r->fixed, m->fixed, N);
+  copy_in(r->material, m->material, T);
   copy_in(r->x, x, 3 * N);
   copy_in(r->xh, x_hat, 3 * N);
   copy_in(r->xt, x_tilde, 3 * N);
@@ -470,6 +474,11 @@ bf_status bf_server_submit(bf_server* sv, int64_t req_id, const bf_mesh_desc* m,
   }
   {
     std::lock_guard<std::mutex> lk(sv->mu);
+    const bf_status st = bf_admission_push(sv->adm, req_id, r->footprint);
+    if (st != BF_OK) {
+      delete r;
+      return st;
+    }
     sv->pending.push_back(r);
   }
   sv->cv.notify_all();
@@ -512,9 +521,9 @@ bf_status bf_server_result(bf_server* sv, int64_t req_id, double* p_out, bf_step
 bf_status bf_server_stats(bf_server* sv, int32_t* n_pending, int32_t* n_active, size_t* used_bytes) {
   if (!sv) return BF_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lk(sv->mu);
-  if (n_pending) *n_pending = (int32_t)sv->pending.size();
-  if (n_active) *n_active = (int32_t)(sv->max_active - sv->free_slots.size());
-  if (used_bytes) *used_bytes = sv->used;
+  if (n_pending) *n_pending = bf_admission_waiting(sv->adm);
+  if (n_active) *n_active = bf_admission_active(sv->adm);
+  if (used_bytes) *used_bytes = (size_t)bf_admission_used(sv->adm);
   return BF_OK;
 }
 
@@ -533,6 +542,7 @@ void bf_server_destroy(bf_server* sv) {
   for (Slot& sl : sv->slots)
     if (sl.pb) bf_problem_destroy(sl.pb);
   for (Request* r : sv->pending) delete r;
+  bf_admission_destroy(sv->adm);
   for (auto& kv : sv->done) delete kv.second;
   for (auto& sl : sv->slots) delete sl.req;
   sv->sys_dev.release();

@@ -25,7 +25,8 @@ __global__ void k_check_tets(const int4* __restrict__ tets, int T, int N, int* f
 }
 
 __global__ void k_rest_geometry(const int4* __restrict__ tets, const double* __restrict__ rest,
-                                const double* __restrict__ E, const double* __restrict__ nu, int T,
+                                const double* __restrict__ E, const double* __restrict__ nu,
+                                const double* __restrict__ rho, int T,
                                 float* __restrict__ Dminv9, float* __restrict__ vol,
                                 float* __restrict__ mu, float* __restrict__ lam, int* flags) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -45,8 +46,9 @@ __global__ void k_rest_geometry(const int4* __restrict__ tets, const double* __r
   double scale = 0.0;
   for (int i = 0; i < 3; ++i)
     for (int k = 0; k < 3; ++k) scale = fmax(scale, fabs(D[i][k]));
-  const double En = E[e], nn = nu[e];
-  if (!(fabs(det) > 1e-12 * scale * scale * scale) || !(En > 0.0) || !(nn > -1.0 && nn < 0.5)) {
+  const double En = E[e], nn = nu[e], rh = rho[e];
+  if (!(fabs(det) > 1e-12 * scale * scale * scale) || !(En > 0.0 && En < INFINITY) || !(nn > -1.0 && nn < 0.5) ||
+      !(rh > 0.0 && rh < INFINITY)) {
     atomicOr(flags, FLAG_BAD_VALUE);
     return;
   }
@@ -180,10 +182,11 @@ void launch_check_tets(const int4* tets, int T, int N, int* flags, hipStream_t s
   if (T > 0) hipLaunchKernelGGL(k_check_tets, dim3(div_up(T, kBlock)), dim3(kBlock), 0, s, tets, T, N, flags);
 }
 
-void launch_rest_geometry(const int4* tets, const double* rest, const double* E, const double* nu, int T,
-                          float* Dminv9, float* vol, float* mu, float* lam, int* flags, hipStream_t s) {
+void launch_rest_geometry(const int4* tets, const double* rest, const double* E, const double* nu,
+                          const double* rho, int T, float* Dminv9, float* vol, float* mu, float* lam, int* flags,
+                          hipStream_t s) {
   if (T > 0)
-    hipLaunchKernelGGL(k_rest_geometry, dim3(div_up(T, kBlock)), dim3(kBlock), 0, s, tets, rest, E, nu, T,
+    hipLaunchKernelGGL(k_rest_geometry, dim3(div_up(T, kBlock)), dim3(kBlock), 0, s, tets, rest, E, nu, rho, T,
                        Dminv9, vol, mu, lam, flags);
 }
 

@@ -47,7 +47,8 @@ bf_status bf_time_step(bf_problem* pb, const bf_time_step_opts* o, double* x_out
     pb->kappa = mu;
   }
   double beta = 1.0;
-  int k = 0, stall = 0;
+  int k = 0;
+  bf_stall_rule stall{1e-4, 50, 0};   // Section 5.2
   out.alpha_min = 1.0;
   while (beta > o->eps && k < o->max_outer) {
     HIPCHK(c, hipMemcpyAsync(pb->xprev.p, pb->xh.p, 8 * n3, hipMemcpyDeviceToDevice, s));
@@ -74,13 +75,7 @@ bf_status bf_time_step(bf_problem* pb, const bf_time_step_opts* o, double* x_out
     out.alpha_last = alpha;
     // Section 5.2: double the penalty and halve the offset when the step
     // stays below 1e-4 for 50 consecutive iterations
-    stall = alpha < 1e-4 ? stall + 1 : 0;
-    if (stall >= 50) {
-      pb->kappa *= 2.0;
-      pb->delta *= 0.5;
-      stall = 0;
-      ++out.mu_doublings;
-    }
+    if (bf_stall_step(&stall, alpha, &pb->kappa, &pb->delta) == 1) ++out.mu_doublings;
     ++k;
   }
   HIPCHK(c, hipStreamSynchronize(s));

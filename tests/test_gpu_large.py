@@ -3,15 +3,26 @@
 FP64 oracle assembled at full size (about a minute of CPU).
 
 Bars: the merged BSR pattern and its maps bit-exact; the FP32 gradient and
-blocks within 1e-5 relative; the returned step's residual, measured in FP64
-with the oracle's H, within 1.5e-5 of |G| (the PCG tolerance is 1e-5 on the
-FP32-stored system); the FP64 stats exact to rounding."""
+blocks within 1e-5 relative, globally and per node / per block against the
+summed magnitude of their terms (term_scales.py), also with the constraint set
+emptied (the elastic and inertia terms alone); the returned step within the
+FP64 solver's own error at the same tolerance, in the energy norm of the
+oracle's H against the oracle's reference solution (tests/golden/
+large_p_ref.npy: FP64 block-Jacobi PCG to 1e-12); its residual, measured in
+FP64 with the oracle's H, within 1.5e-5 of |G| (the PCG tolerance is 1e-5 on
+the FP32-stored system); the FP64 stats exact to rounding."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 import scenes
+import term_scales
 from subproblem_checks import check_subproblem
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 pytestmark = pytest.mark.gpu
 
@@ -74,6 +85,60 @@ def test_large_gradient_and_blocks(large, gpu):
     assert eg <= 1e-5
     assert eb <= 1e-5
     assert np.all(g[~free] == 0.0)
+    gs, bs = term_scales.scales(sc, st, row_ptr.astype(np.int64), col)
+    rg, rb, ig, ib = term_scales.elementwise(g, st.G, B, Bref, gs, bs)
+    print(f"large: element-wise gradient {rg:.2e} (node {ig}), blocks {rb:.2e} (slot {ib})", flush=True)
+    assert rg <= 1e-5
+    assert rb <= 1e-5
+
+
+@pytest.mark.timeout(900)
+def test_large_no_constraints_gradient_and_blocks():
+    """The large mesh with its constraint set emptied: the elastic and inertia
+    terms alone at full size, globally and element-wise within 1e-5."""
+    from paper_2512_12151_amd import bfal
+    sc = dict(scenes.make_scene("large"))
+    z = np.zeros((0, 4), np.int32)
+    sc.update(pt=z, ee=z, lam=np.zeros(0), gamma=np.zeros(0))
+    ctx = bfal.Context(0)
+    pb = bfal.Problem.from_scene(ctx, sc)
+    print("large, no constraints: GPU assembly", flush=True)
+    pb.newton_step(tol=1e-5, max_iter=0)
+    g, (row_ptr, col, *_), B = pb.gradient(), pb.pattern(), pb.blocks().astype(np.float64)
+    pb.close()
+    ctx.close()
+    print("large, no constraints: oracle assembly", flush=True)
+    st = oracle.assemble(sc)
+    free = ~sc["fixed"].astype(bool)
+    eg = np.linalg.norm((g - st.G)[free]) / np.linalg.norm(st.G[free])
+    Bref = oracle.upper_blocks(st.H, row_ptr.astype(np.int64), col)
+    eb = np.linalg.norm(B - Bref) / np.linalg.norm(Bref)
+    gs, bs = term_scales.scales(sc, st, row_ptr.astype(np.int64), col)
+    rg, rb, _, _ = term_scales.elementwise(g, st.G, B, Bref, gs, bs)
+    print(f"large, no constraints: gradient rel {eg:.2e}, blocks rel {eb:.2e}; element-wise {rg:.2e}, {rb:.2e}",
+          flush=True)
+    assert eg <= 1e-5 and eb <= 1e-5
+    assert rg <= 1e-5 and rb <= 1e-5
+    assert np.all(g[~free] == 0.0)
+
+
+@pytest.mark.timeout(600)
+def test_large_solution_energy_norm(large, gpu):
+    """The step against the oracle's reference solution p* in the energy norm
+    of the oracle's FP64 H.  The bar is the FP64 oracle PCG's own error at the
+    same tolerance (x0 = 0, |r| <= 1e-5 |b|; recorded with p* by the script
+    that wrote it), doubled, plus 1e-5; both iteration counts are printed."""
+    sc, st = large
+    with open(os.path.join(GOLDEN, "large_p_ref.json")) as f:
+        meta = json.load(f)
+    assert meta["digest"] == scenes.digest(sc)
+    p_ref = np.load(os.path.join(GOLDEN, "large_p_ref.npy")).astype(np.float64)
+    err = oracle.energy_norm_rel(st.H, gpu["p"], p_ref)
+    ref64 = meta["fp64_pcg_at_step_tol"]
+    print(f"large: energy-norm error {err:.3e} after {gpu['stats']['pcg_iters']} FP32 PCG iterations | FP64 "
+          f"oracle PCG at tol {ref64['tol']:g}: {ref64['energy_norm_error']:.3e} after {ref64['iterations']} "
+          f"iterations | p* storage {meta['float32_storage_energy_norm_error']:.1e}", flush=True)
+    assert err <= 2.0 * ref64["energy_norm_error"] + 1e-5
 
 
 @pytest.mark.timeout(600)

@@ -1,8 +1,11 @@
 """GPU parity through the C-ABI against the FP64 CPU oracle.
 
 Bars: the BSR pattern and its maps bit-exact; the FP32 gradient within 1e-5
-relative (2-norm over free DoFs); assembled blocks within 1e-5 relative
-(Frobenius over all blocks); the PCG solution within 1e-4 relative in the
+relative (2-norm over free DoFs) and, per node, within 1e-5 of the summed
+magnitude of the terms that node collects; assembled blocks within 1e-5
+relative (Frobenius over all blocks) and, per block, within 1e-5 of the summed
+magnitude of its terms (see term_scales.py), Dirichlet entries exactly zero;
+the PCG solution within 1e-4 relative in the
 energy norm of the oracle's FP64 H against the FP64 direct/reference solve
 when the tolerance allows it, and otherwise no worse than the FP64 oracle PCG
 at the same tolerance (whose own error is reported beside it)."""
@@ -11,6 +14,7 @@ import pytest
 
 import oracle
 import scenes
+import term_scales
 
 pytestmark = pytest.mark.gpu
 
@@ -26,6 +30,13 @@ def ctx(bf):
     return bf.Context(0)
 
 
+def _no_constraints_of(sc):
+    z = np.zeros((0, 4), np.int32)
+    out = dict(sc)
+    out.update(pt=z, ee=z, lam=np.zeros(0), gamma=np.zeros(0))
+    return out
+
+
 CASES = {
     "tiny": lambda: scenes.tiny(),
     "tiny_shifted": lambda: scenes.tiny(lateral=(0.37, 0.21)),
@@ -38,7 +49,10 @@ _cache = {}
 
 def ref(name):
     if name not in _cache:
-        sc = CASES[name]() if name in CASES else scenes.medium()
+        if name == "medium_no_constraints":
+            sc = _no_constraints_of(scenes.medium())
+        else:
+            sc = CASES[name]() if name in CASES else scenes.medium()
         st = oracle.assemble(sc)
         _cache[name] = (sc, st)
     return _cache[name]
@@ -63,12 +77,14 @@ def test_pattern_and_maps_bit_exact(ctx, bf, name):
     assert np.array_equal(diag, r_diag)
 
 
-@pytest.mark.parametrize("name", list(CASES) + ["medium"])
+@pytest.mark.parametrize("name", list(CASES) + ["medium", "medium_no_constraints"])
 def test_gradient_and_blocks(ctx, bf, name):
+    """Global and element-wise bars.  The empty constraint set holds the
+    elastic and inertia terms alone to them at the medium size."""
     sc, st = ref(name)
     print(f"case {name}", flush=True)
     pb = bf.Problem.from_scene(ctx, sc)
-    pb.newton_step(tol=1e-5)
+    pb.newton_step(tol=1e-5, max_iter=0 if name == "medium_no_constraints" else 20000)
     g = pb.gradient()
     free = ~sc["fixed"].astype(bool)
     assert rel(g[free], st.G[free]) <= 1e-5
@@ -77,6 +93,11 @@ def test_gradient_and_blocks(ctx, bf, name):
     B = pb.blocks().astype(np.float64)
     Bref = oracle.upper_blocks(st.H, row_ptr.astype(np.int64), col)
     assert rel(B, Bref) <= 1e-5
+    gs, bs = term_scales.scales(sc, st, row_ptr.astype(np.int64), col)
+    rg, rb, ig, ib = term_scales.elementwise(g, st.G, B, Bref, gs, bs)
+    print(f"{name}: element-wise gradient {rg:.2e} (node {ig}), blocks {rb:.2e} (slot {ib})", flush=True)
+    assert rg <= 1e-5
+    assert rb <= 1e-5
 
 
 @pytest.mark.parametrize("name,tol,bar", [("tiny", 1e-7, 1e-4), ("tiny_shifted", 1e-7, 1e-4),
@@ -271,3 +292,38 @@ def test_all_nodes_fixed(ctx, bf):
     p, stats, status = pb.newton_step(tol=1e-8)
     assert status == bf.BF_OK
     assert np.all(p == 0.0) and np.all(pb.gradient() == 0.0)
+
+
+# ------------------------------------------------------------- failure paths
+
+def test_pcg_max_iter_warning(ctx, bf):
+    """A cap below what the tolerance needs: the step reports
+    BF_WARN_PCG_MAXITER (a warning, the iterate is still written), stops at
+    exactly the cap, and the iterate is the PCG's: finite, zero on fixed
+    nodes, and a descent direction (p^T G < 0, as every CG iterate from 0 is)."""
+    sc, st = ref("tiny_shifted")
+    pb = bf.Problem.from_scene(ctx, sc)
+    p, stats, status = pb.newton_step(tol=1e-8, max_iter=5, poll_every=4, check_every=1)
+    assert status == bf.BF_WARN_PCG_MAXITER
+    assert stats["pcg_iters"] == 5
+    assert np.all(np.isfinite(p)) and np.all(p[sc["fixed"].astype(bool)] == 0.0)
+    assert float(np.sum(p * st.G)) < 0.0
+    assert stats["rel_residual"] > 1e-8
+    # the same call with enough iterations converges: the warning was the cap's
+    _, stats2, status2 = pb.newton_step(tol=1e-8, max_iter=20000)
+    assert status2 == bf.BF_OK and stats2["pcg_iters"] > 5
+
+
+def test_device_descriptor_bad_density(ctx, bf):
+    """A device-resident mesh is checked in the setup kernel: a non-positive
+    density (a negative lumped mass would make H indefinite) is rejected with
+    BF_ERR_INVALID_ARG instead of reaching the solver."""
+    import torch
+    sc = ref("tiny")[0]
+    dev = torch.device("cuda:0")
+    t = {k: torch.from_numpy(np.ascontiguousarray(sc[k])).to(dev) for k in ("tets", "rest", "E", "nu", "rho", "fixed")}
+    t["rho"][17] = -1000.0
+    torch.cuda.synchronize()
+    with pytest.raises(bf.BfalError) as e:
+        bf.Problem(ctx, t["tets"], t["rest"], t["E"], t["nu"], t["rho"], t["fixed"])
+    assert e.value.status == -1
