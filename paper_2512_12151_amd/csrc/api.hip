@@ -52,7 +52,7 @@ bf_status problem_init(bf_context* c, bf_problem* pb, const bf_mesh_desc* m, int
   ALLOC(c, pb->nu, 8LL * T);
   ALLOC(c, pb->rho, 8LL * T);
   ALLOC(c, pb->fixed, N);
-  ALLOC(c, pb->Dminv9, 36LL * T);
+  ALLOC(c, pb->Dminv9, 72LL * T);   // FP64 [9][T]
   ALLOC(c, pb->vol, 4LL * T);
   ALLOC(c, pb->mu, 4LL * T);
   ALLOC(c, pb->lam, 4LL * T);
@@ -85,7 +85,7 @@ bf_status problem_init(bf_context* c, bf_problem* pb, const bf_mesh_desc* m, int
   if (r0 != BF_OK) return r0;
   if (hflags) return flags_to_status(c, hflags);
   launch_rest_geometry(tets, pb->rest.as<double>(), pb->E.as<double>(), pb->nu.as<double>(), pb->rho.as<double>(), T,
-                       pb->Dminv9.as<float>(), pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), flags, s);
+                       pb->Dminv9.as<double>(), pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), flags, s);
   // static elastic pattern: pair keys bucketed by row, sorted and unique per row
   const long long npairs = 6LL * T;
   const long long nslots_tmp = (long long)N + 1;
@@ -208,7 +208,7 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
   launch_friction_terms(pb->fids.as<int4>(), nf, pb->xh.as<double>(), pb->fx0.as<double>(), pb->f64.as<double>(),
                         pb->fric_e, pb->fgk.as<float>(), s);
   const float h2 = (float)(pb->dt * pb->dt);
-  launch_elastic(pb->tets.as<int4>(), T, pb->rest.as<double>(), pb->xh.as<double>(), pb->Dminv9.as<float>(),
+  launch_elastic(pb->tets.as<int4>(), T, pb->rest.as<double>(), pb->xh.as<double>(), pb->Dminv9.as<double>(),
                  pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), h2, pb->epos.as<int>(),
                  pb->staging.as<float>(), pb->has_mat ? pb->mat.as<int>() : nullptr, flags, s);
   launch_assemble_rows(N, row_ptr, pb->col.as<int>(), pb->eslot.as<int>(), pb->ecptr.as<int>(), pb->staging.as<float>(),
@@ -303,13 +303,13 @@ bf_status bf_footprint_bytes(int32_t n_nodes, int32_t n_tets, int32_t n_constrai
   const size_t nnzb_e = N + 6 * T;                 // upper bound on the static pattern
   const size_t cap = nnzb_e + 6 * C;
   size_t b = 0;
-  b += T * (16 + 3 * 8 + 36 + 12 + 40 * 3 + 360);  // tets, E/nu/rho, Dm^-1, vol/mu/lam, emap/epos/elist, staging
+  b += T * (16 + 3 * 8 + 72 + 12 + 40 * 3 + 360);  // tets, E/nu/rho, Dm^-1 (FP64), vol/mu/lam, emap/epos/elist, staging
   b += nnzb_e * (4 + 4) + N * (4 * 3 + 24 + 4 + 1);
   b += N * 24 * 3;                                 // x, x_hat, x_tilde
   b += C * (16 + 16 + 12 + 16 + 8);                // ids, lambda/gamma, n, w, factors
   b += N * 4 * 8 + C * 16 + cap * 4 * 2;           // incidence, candidates, pattern
   b += cap * (36 + 36 + 4 + 4 + 8 + 4);            // blocks, scaled blocks, ucol, eslot, transpose index, lsrc
-  b += N * (12 * 6 + 24 * 2 + 24);                 // grad, bhat, x, r, p, q, L, L^-1, p out
+  b += N * (12 * 6 + 24 * 2 + 24);                 // grad, bhat, r, p (2), q, x, L, L^-1, p out
   b += 1 << 20;                                    // partials, scalars, scan scratch
   *out = b;
   return BF_OK;
@@ -926,7 +926,7 @@ bf_status bf_mu_init(bf_problem* pb, double C, double* mu_out) {
   fill_int(flags, 0, 16, s);
   // the elastic Hessian at x, the state the time step starts from, into the
   // staging buffer (the next Newton step overwrites it)
-  launch_elastic(pb->tets.as<int4>(), T, pb->rest.as<double>(), pb->x.as<double>(), pb->Dminv9.as<float>(),
+  launch_elastic(pb->tets.as<int4>(), T, pb->rest.as<double>(), pb->x.as<double>(), pb->Dminv9.as<double>(),
                  pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), (float)(pb->dt * pb->dt),
                  pb->epos.as<int>(), pb->staging.as<float>(), pb->has_mat ? pb->mat.as<int>() : nullptr, flags, s);
   const int np = diag_max_parts(N);

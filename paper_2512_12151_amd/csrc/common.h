@@ -122,7 +122,7 @@ void fill_int(int* a, int v, long long n, hipStream_t s);
 // setup.hip: per-mesh work
 void launch_check_tets(const int4* tets, int T, int N, int* flags, hipStream_t s);
 void launch_rest_geometry(const int4* tets, const double* rest, const double* E, const double* nu,
-                          const double* rho, int T, float* Dminv9, float* vol, float* mu, float* lam, int* flags,
+                          const double* rho, int T, double* Dminv9, float* vol, float* mu, float* lam, int* flags,
                           hipStream_t s);
 void launch_elastic_pair_count(const int4* tets, int T, int* cnt, hipStream_t s);
 void launch_elastic_pair_fill(const int4* tets, int T, const int* ptr, int* cursor, int* keys,
@@ -241,7 +241,7 @@ void launch_friction_extra(const int4* fids, int n_f, const int* extra, const in
                            int* fext, hipStream_t s);
 
 // elastic.hip
-void launch_elastic(const int4* tets, int T, const double* rest, const double* xh, const float* Dminv9,
+void launch_elastic(const int4* tets, int T, const double* rest, const double* xh, const double* Dminv9,
                     const float* vol, const float* mu, const float* lam, float h2, const int* epos,
                     float* staging, const int* mat, int* flags, hipStream_t s);
 

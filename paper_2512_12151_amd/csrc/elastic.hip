@@ -1,10 +1,11 @@
 // Hyperelastic element kernel (Neo-Hookean, stable Neo-Hookean or corotated
 // linear per tet): one thread per tet.
 //
-// Per tet it forms F (from FP64 displacement differences, then FP32), the
-// stress P, the element gradient h^2 V P A_a^T, and the ten upper 3x3 blocks
-// of the SPD-projected element Hessian by the vertex-block identity of
-// Section 5.1:
+// Per tet it forms G = F - I and the stress P in FP64 (from the FP64
+// displacement differences and the FP64 rows of D_m^{-1}), the element
+// gradient h^2 V P A_a^T (rounded to FP32 at the end), and, in FP32, the ten
+// upper 3x3 blocks of the SPD-projected element Hessian by the vertex-block
+// identity of Section 5.1:
 //
 //   H_ab = h^2 V  U [ sum_k omega_k^+ D_k (A_a V)^T (A_b V) D_k^T ] U^T
 //
@@ -22,11 +23,15 @@
 //   Neo-Hookean         g = -mu ln J + lam/2 (ln J)^2
 //   stable Neo-Hookean  g = -mu (J - 1) + lam/2 (J - 1)^2   (rest-stable form of
 //                       Smith, de Goes and Kim 2019)
-// Cancellation-free forms near rest: with G = F - I,
+// The stress is formed in FP64 because the strain can be far smaller than G:
+// a tet turned by a rotation R has G ~ R - I of order one while F^T F - I is
+// of the order of its strain, and in FP32 that difference keeps only
+// eps / strain of relative accuracy (1e-4 at a 1e-3 strain).  With G = F - I,
 //   J - 1 = tr G + ((tr G)^2 - tr(G^2))/2 + det G,  ln J = log1p(J - 1),
 //   Neo-Hookean  P = F^{-T} [ mu (G + G^T + G^T G) + lam ln J I ],
 //   stable NH    P = mu (G + G^T - tr(G) I - cof G) + lam (J - 1) cof F
-// (the second from cof(I + G) = (1 + tr G) I - G^T + cof G).
+// (the second from cof(I + G) = (1 + tr G) I - G^T + cof G); these forms
+// are free of cancellation near rest as well.
 // With q = J g'(J) and r = J^2 g''(J) the Hessian of Psi in the singular
 // values is mu I + diag(r / S_i^2) off-diagonal (r + q) / (S_i S_j), and the
 // twist / flip eigenvalues of pair (i, j) are mu +- q / (S_i S_j):
@@ -82,18 +87,12 @@ __device__ inline void jacobi3(float A[3][3], float V[3][3]) {
   }
 }
 
-__device__ inline float det3(const float M[3][3]) {
+__device__ inline double det3d(const double M[3][3]) {
   return M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
          M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
 }
 
-// Rotation-preserving SVD F = U diag(S) V^T with det U = det V = +1 (S[2]
-// carries the sign of det F).  V from the Jacobi eigenvectors of F^T F, U and
-// S from a Givens QR of F V (McAdams et al. 2011, "Computing the singular
-// value decomposition of 3x3 matrices with minimal branching and elementary
-// floating point operations", steps: symmetric eigenanalysis, sorting, QR).
-// Cofactor matrix of M (d det M / dM).
-__device__ inline void cof3(const float M[3][3], float C[3][3]) {
+__device__ inline void cof3d(const double M[3][3], double C[3][3]) {
   C[0][0] = M[1][1] * M[2][2] - M[1][2] * M[2][1];
   C[0][1] = M[1][2] * M[2][0] - M[1][0] * M[2][2];
   C[0][2] = M[1][0] * M[2][1] - M[1][1] * M[2][0];
@@ -105,6 +104,16 @@ __device__ inline void cof3(const float M[3][3], float C[3][3]) {
   C[2][2] = M[0][0] * M[1][1] - M[0][1] * M[1][0];
 }
 
+__device__ inline float det3(const float M[3][3]) {
+  return M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+         M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+}
+
+// Rotation-preserving SVD F = U diag(S) V^T with det U = det V = +1 (S[2]
+// carries the sign of det F).  V from the Jacobi eigenvectors of F^T F, U and
+// S from a Givens QR of F V (McAdams et al. 2011, "Computing the singular
+// value decomposition of 3x3 matrices with minimal branching and elementary
+// floating point operations", steps: symmetric eigenanalysis, sorting, QR).
 __device__ inline void svd3(const float F[3][3], float U[3][3], float S[3], float V[3][3]) {
   float A[3][3];
 #pragma unroll
@@ -170,47 +179,57 @@ __device__ inline void svd3(const float F[3][3], float U[3][3], float S[3], floa
 
 __global__ void __launch_bounds__(kBlock)
 k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest, const double* __restrict__ xh,
-          const float* __restrict__ Dminv9, const float* __restrict__ vol, const float* __restrict__ mu_,
+          const double* __restrict__ Dminv9, const float* __restrict__ vol, const float* __restrict__ mu_,
           const float* __restrict__ lam_, float h2, const int* __restrict__ epos, float* __restrict__ staging,
           const int* __restrict__ mat, int* flags) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= T) return;
   const int4 t = tets[e];
   const int v[4] = {t.x, t.y, t.z, t.w};
-  // displacement differences in FP64, then FP32
+  // G = F - I in FP64 from the displacement differences and the FP64 rows of D_m^{-1}
   double u0[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) u0[i] = xh[3LL * v[0] + i] - rest[3LL * v[0] + i];
-  float Du[3][3];  // column k = u_{k+1} - u_0
+  double Du[3][3];  // column k = u_{k+1} - u_0
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-      Du[i][k] = (float)((xh[3LL * v[k + 1] + i] - rest[3LL * v[k + 1] + i]) - u0[i]);
-  float Dm[3][3];
+    for (int i = 0; i < 3; ++i) Du[i][k] = (xh[3LL * v[k + 1] + i] - rest[3LL * v[k + 1] + i]) - u0[i];
+  double Dm[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) Dm[i][j] = Dminv9[(long long)(3 * i + j) * T + e];
-  float Gm[3][3], F[3][3];
+  double Gd[3][3], Fd[3][3];
+  float F[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      Gm[i][j] = Du[i][0] * Dm[0][j] + Du[i][1] * Dm[1][j] + Du[i][2] * Dm[2][j];
-      F[i][j] = Gm[i][j] + (i == j ? 1.f : 0.f);
+      Gd[i][j] = Du[i][0] * Dm[0][j] + Du[i][1] * Dm[1][j] + Du[i][2] * Dm[2][j];
+      Fd[i][j] = Gd[i][j] + (i == j ? 1.0 : 0.0);
+      F[i][j] = (float)Fd[i][j];
     }
-  const float trG = Gm[0][0] + Gm[1][1] + Gm[2][2];
-  float trG2 = 0.f;
+  // C - I = G + G^T + G^T G (the strain, FP64)
+  double CmI[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) trG2 += Gm[i][j] * Gm[j][i];
-  const float Jm1 = trG + 0.5f * (trG * trG - trG2) + det3(Gm);
-  const float J = 1.f + Jm1;
+    for (int j = 0; j < 3; ++j)
+      CmI[i][j] = Gd[i][j] + Gd[j][i] + Gd[0][i] * Gd[0][j] + Gd[1][i] * Gd[1][j] + Gd[2][i] * Gd[2][j];
+  const double trGd = Gd[0][0] + Gd[1][1] + Gd[2][2];
+  double trG2d = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) trG2d += Gd[i][j] * Gd[j][i];
+  const double Jm1d = trGd + 0.5 * (trGd * trGd - trG2d) + det3d(Gd);
+  const double Jd = 1.0 + Jm1d;
+  const float Jm1 = (float)Jm1d;
+  const float J = (float)Jd;
   const float w = h2 * vol[e];
   const long long pbase = 10LL * e;
-  if (!(J > 0.f)) {
+  if (!(Jd > 0.0) || !(J > 0.f)) {
     atomicOr(flags, FLAG_INVERTED);
     for (int k = 0; k < 10; ++k) {
       float* o = staging + 9LL * epos[pbase + k];
@@ -220,48 +239,56 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
     return;
   }
   const float mu = mu_[e], lam = lam_[e];
+  const double mud = mu, lamd = lam;
   const int code = mat != nullptr ? mat[e] : 0;
-  // rows A_a (A_1..A_3 = rows of Dm^{-1}, A_0 = -their sum)
+  // rows A_a (A_1..A_3 = rows of Dm^{-1}, A_0 = -their sum): FP64 for the
+  // gradient, FP32 for the Hessian blocks
+  double Ad[4][3];
   float A[4][3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    A[1][j] = Dm[0][j]; A[2][j] = Dm[1][j]; A[3][j] = Dm[2][j];
-    A[0][j] = -(Dm[0][j] + Dm[1][j] + Dm[2][j]);
+    Ad[1][j] = Dm[0][j]; Ad[2][j] = Dm[1][j]; Ad[3][j] = Dm[2][j];
+    Ad[0][j] = -(Dm[0][j] + Dm[1][j] + Dm[2][j]);
   }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) A[a][j] = (float)Ad[a][j];
   // SVD, then per material the stress, the 3x3 Hessian in the singular values
   // (Ah) and the twist / flip eigenvalues of the pairs (0,1), (0,2), (1,2)
   float U[3][3], S[3], V[3][3];
   svd3(F, U, S, V);
   const int pi[3] = {0, 0, 1}, pj[3] = {1, 2, 2};
-  float P[3][3], Ah[3][3], wt[3], wf[3];
+  double Pd[3][3];
+  float Ah[3][3], wt[3], wf[3];
   bool clamp;
   if (code == 2) {
     // corotated linear: Psi = mu sum (S_k - 1)^2 + lam/2 (sum S_k - 3)^2.  S_k - 1 without
-    // cancellation: e_k = S_k^2 - 1 is the Rayleigh quotient of F^T F - I = G + G^T + G^T G
-    // along V_k, and S_k - 1 = e_k / (1 + sqrt(1 + e_k)).
+    // cancellation: e_k = S_k^2 - 1 is the Rayleigh quotient of F^T F - I (FP64) along V_k
+    // (stationary in V_k, so the FP32 singular vectors suffice), and S_k - 1 = e_k / (1 + sqrt(1 + e_k)).
+    double dd[3];
     float d[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      float ek = 0.f;
+      double ek = 0.0;
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const float gtg = Gm[0][i] * Gm[0][j] + Gm[1][i] * Gm[1][j] + Gm[2][i] * Gm[2][j];
-          ek += V[i][k] * (Gm[i][j] + Gm[j][i] + gtg) * V[j][k];
-        }
-      d[k] = ek / (1.f + sqrtf(fmaxf(1.f + ek, 0.f)));
+        for (int j = 0; j < 3; ++j) ek += (double)V[i][k] * CmI[i][j] * (double)V[j][k];
+      dd[k] = ek / (1.0 + sqrt(fmax(1.0 + ek, 0.0)));
+      d[k] = (float)dd[k];
     }
-    const float tr = d[0] + d[1] + d[2];
-    float dpsi[3];
+    const double tr = dd[0] + dd[1] + dd[2];
+    double dpsi[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) dpsi[k] = 2.f * mu * d[k] + lam * tr;
+    for (int k = 0; k < 3; ++k) dpsi[k] = 2.0 * mud * dd[k] + lamd * tr;
     // P = U diag(dPsi/dS) V^T = 2 mu (F - R) + lam tr(S - I) R
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j)
-        P[i][j] = U[i][0] * dpsi[0] * V[j][0] + U[i][1] * dpsi[1] * V[j][1] + U[i][2] * dpsi[2] * V[j][2];
+        Pd[i][j] = (double)U[i][0] * dpsi[0] * V[j][0] + (double)U[i][1] * dpsi[1] * V[j][1] +
+                   (double)U[i][2] * dpsi[2] * V[j][2];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -270,41 +297,38 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int i = pi[k], j = pj[k];
-      wt[k] = (dpsi[i] + dpsi[j]) / (2.f + d[i] + d[j]);
+      wt[k] = (float)((dpsi[i] + dpsi[j]) / (2.0 + dd[i] + dd[j]));
       wf[k] = 2.f * mu;   // (dPsi_i - dPsi_j) / (S_i - S_j)
     }
   } else {
-    float C[3][3];
-    cof3(F, C);
+    double C[3][3];
+    cof3d(Fd, C);
     float q, r, rq;
     if (code == 1) {
-      float Cg[3][3];
-      cof3(Gm, Cg);
-      const float trG = Gm[0][0] + Gm[1][1] + Gm[2][2];
+      double Cg[3][3];
+      cof3d(Gd, Cg);
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-          P[i][j] = mu * (Gm[i][j] + Gm[j][i] - (i == j ? trG : 0.f) - Cg[i][j]) + lam * Jm1 * C[i][j];
+          Pd[i][j] = mud * (Gd[i][j] + Gd[j][i] - (i == j ? trGd : 0.0) - Cg[i][j]) + lamd * Jm1d * C[i][j];
       q = J * (lam * Jm1 - mu);
       r = lam * J * J;
       rq = r + q;
     } else {
-      const float lnJ = log1pf(Jm1);
-      // P = F^{-T} Sp with Sp = mu (G + G^T + G^T G) + lam lnJ I; F^{-T} = cof(F) / J
-      float Sp[3][3];
+      const double lnJd = log1p(Jm1d);
+      const float lnJ = (float)lnJd;
+      // P = F^{-T} Sp with Sp = mu (C - I) + lam lnJ I; F^{-T} = cof(F) / J
+      double Sp[3][3];
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const float gtg = Gm[0][i] * Gm[0][j] + Gm[1][i] * Gm[1][j] + Gm[2][i] * Gm[2][j];
-          Sp[i][j] = mu * (Gm[i][j] + Gm[j][i] + gtg) + (i == j ? lam * lnJ : 0.f);
-        }
-      const float iJ = 1.f / J;
+        for (int j = 0; j < 3; ++j) Sp[i][j] = mud * CmI[i][j] + (i == j ? lamd * lnJd : 0.0);
+      const double iJ = 1.0 / Jd;
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) P[i][j] = (C[i][0] * Sp[0][j] + C[i][1] * Sp[1][j] + C[i][2] * Sp[2][j]) * iJ;
+        for (int j = 0; j < 3; ++j) Pd[i][j] = (C[i][0] * Sp[0][j] + C[i][1] * Sp[1][j] + C[i][2] * Sp[2][j]) * iJ;
       q = lam * lnJ - mu;
       r = mu + lam - lam * lnJ;
       rq = lam;
@@ -383,7 +407,8 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
       o[4] = 0.5f * (Hb[1][2] + Hb[2][1]);
       o[5] = Hb[2][2];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) o[6 + i] = w * (P[i][0] * A[a][0] + P[i][1] * A[a][1] + P[i][2] * A[a][2]);
+      for (int i = 0; i < 3; ++i)
+        o[6 + i] = (float)((double)w * (Pd[i][0] * Ad[a][0] + Pd[i][1] * Ad[a][1] + Pd[i][2] * Ad[a][2]));
     } else if (v[a] < v[b]) {
 #pragma unroll
       for (int i = 0; i < 3; ++i)
@@ -400,7 +425,7 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
 
 }  // namespace
 
-void launch_elastic(const int4* tets, int T, const double* rest, const double* xh, const float* Dminv9,
+void launch_elastic(const int4* tets, int T, const double* rest, const double* xh, const double* Dminv9,
                     const float* vol, const float* mu, const float* lam, float h2, const int* epos, float* staging,
                     const int* mat, int* flags, hipStream_t s) {
   if (T > 0)

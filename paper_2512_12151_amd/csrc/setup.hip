@@ -27,7 +27,7 @@ __global__ void k_check_tets(const int4* __restrict__ tets, int T, int N, int* f
 __global__ void k_rest_geometry(const int4* __restrict__ tets, const double* __restrict__ rest,
                                 const double* __restrict__ E, const double* __restrict__ nu,
                                 const double* __restrict__ rho, int T,
-                                float* __restrict__ Dminv9, float* __restrict__ vol,
+                                double* __restrict__ Dminv9, float* __restrict__ vol,
                                 float* __restrict__ mu, float* __restrict__ lam, int* flags) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= T) return;
@@ -64,7 +64,7 @@ __global__ void k_rest_geometry(const int4* __restrict__ tets, const double* __r
   inv[1][2] = (D[0][2] * D[1][0] - D[0][0] * D[1][2]) * id;
   inv[2][2] = (D[0][0] * D[1][1] - D[0][1] * D[1][0]) * id;
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) Dminv9[(long long)(3 * i + j) * T + e] = (float)inv[i][j];
+    for (int j = 0; j < 3; ++j) Dminv9[(long long)(3 * i + j) * T + e] = inv[i][j];
   vol[e] = (float)(fabs(det) / 6.0);
   mu[e] = (float)(En / (2.0 * (1.0 + nn)));
   lam[e] = (float)(En * nn / ((1.0 + nn) * (1.0 - 2.0 * nn)));
@@ -183,7 +183,7 @@ void launch_check_tets(const int4* tets, int T, int N, int* flags, hipStream_t s
 }
 
 void launch_rest_geometry(const int4* tets, const double* rest, const double* E, const double* nu,
-                          const double* rho, int T, float* Dminv9, float* vol, float* mu, float* lam, int* flags,
+                          const double* rho, int T, double* Dminv9, float* vol, float* mu, float* lam, int* flags,
                           hipStream_t s) {
   if (T > 0)
     hipLaunchKernelGGL(k_rest_geometry, dim3(div_up(T, kBlock)), dim3(kBlock), 0, s, tets, rest, E, nu, rho, T,

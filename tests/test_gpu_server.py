@@ -87,6 +87,102 @@ def test_results_against_oracle(bf, alone):
         assert err <= 2.0 * err64 + 1e-5
 
 
+def decile_ids(n_trace=512):
+    """One request per size decile of the serving trace: the request at the
+    middle of each tenth of the trace sorted by cube size (the size rule of
+    the serving recipe, read from its seeded generator)."""
+    from scenes import configs
+    ns = []
+    for i in range(n_trace):
+        T = np.exp(configs._rng(1000 + i, "size").uniform(np.log(2e3), np.log(3e5)))
+        ns.append(int(np.clip(np.rint(np.cbrt(T / 12.0)), 6, 29)))
+    order = np.argsort(np.array(ns), kind="stable")
+    return [int(order[int((k + 0.5) / 10 * n_trace)]) for k in range(10)]
+
+
+@pytest.mark.timeout(900)
+def test_every_size_decile_against_oracle(bf):
+    """One request per size decile (cubes of 6^3 to 27^3 cells, 2.6k to 236k
+    tets) through the batching server in one mix, each held to the FP64
+    oracle in the energy norm: no worse than twice the oracle's own FP64 PCG
+    at the same tolerance, plus 1e-5."""
+    ids = decile_ids()
+    sv = bf.Server(0, hbm_budget=16 << 30, max_active=64, iters_per_round=8)
+    got = run_server(bf, sv, ids, timeout=300.0)
+    sv.close()
+    for i in ids:
+        sc = scene(i)
+        p, st_gpu, _, status = got[i]
+        assert status == bf.BF_OK
+        st = oracle.assemble(sc)
+        p_ref = oracle.solve_reference(st.H, st.G)
+        p64, it64 = oracle.block_jacobi_pcg(st.H, st.G, 1e-5)
+        err = oracle.energy_norm_rel(st.H, p, p_ref)
+        err64 = oracle.energy_norm_rel(st.H, p64, p_ref)
+        print(f"decile request {i}: {len(sc['tets'])} tets, {len(sc['pt']) + len(sc['ee'])} constraints, "
+              f"iterations {st_gpu['pcg_iters']} (fp64 {it64}), err {err:.3e} (fp64 pcg {err64:.3e})", flush=True)
+        assert err <= 2.0 * err64 + 1e-5
+
+
+def test_materials_in_the_mix(bf):
+    """Requests with per-tet material codes (stable Neo-Hookean, corotated
+    linear, mixed) are served like Neo-Hookean ones: bitwise the lone step."""
+    ids = [3, 7, 11]
+    mats = {}
+    for k, i in enumerate(ids):
+        sc = dict(scene(i))
+        T = len(sc["tets"])
+        mats[i] = [np.full(T, 1, np.int32), np.full(T, 2, np.int32), np.arange(T, dtype=np.int32) % 3][k]
+        sc["material"] = mats[i]
+        _scenes[("mat", i)] = sc
+    ctx = bf.Context(0)
+    lone = {}
+    for i in ids:
+        pb = bf.Problem.from_scene(ctx, _scenes[("mat", i)])
+        lone[i] = pb.newton_step(tol=1e-5, max_iter=20000)[0]
+        pb.close()
+    ctx.close()
+    sv = bf.Server(0, hbm_budget=4 << 30, max_active=8, iters_per_round=8)
+    for i in ids:
+        sv.submit(i, _scenes[("mat", i)], tol=1e-5, max_iter=20000)
+    got = {}
+    t0 = time.time()
+    while len(got) < len(ids):
+        for i in sv.poll():
+            got[i] = sv.result(i)
+        assert time.time() - t0 < 120.0
+        time.sleep(0.002)
+    sv.close()
+    for i in ids:
+        assert got[i][3] == bf.BF_OK
+        assert np.array_equal(got[i][0], lone[i])
+
+
+def test_submit_validates_like_the_single_problem_calls(bf):
+    """bf_server_submit applies the host checks at once (bf_check_*): an
+    out-of-range constraint index, a non-positive step and a repeated vertex
+    come back from the submit call itself."""
+    sv = bf.Server(0, hbm_budget=1 << 30, max_active=2)
+    sc = dict(scene(3))
+    bad = dict(sc)
+    pt = sc["pt"].copy()
+    pt[0, 2] = len(sc["rest"]) + 5
+    bad["pt"] = pt
+    with pytest.raises(bf.BfalError) as e:
+        sv.submit(1, bad)
+    assert e.value.status == -1
+    with pytest.raises(bf.BfalError) as e:
+        sv.submit(2, dict(sc, dt=0.0))
+    assert e.value.status == -1
+    pt = sc["pt"].copy()
+    pt[1, 1] = pt[1, 0]
+    with pytest.raises(bf.BfalError) as e:
+        sv.submit(3, dict(sc, pt=pt))
+    assert e.value.status == -5
+    assert sv.stats()["pending"] == 0
+    sv.close()
+
+
 def test_budget_admission_and_rejection(bf, alone):
     sizes = {i: bf.footprint_bytes(len(scene(i)["rest"]), len(scene(i)["tets"]),
                                    len(scene(i)["pt"]) + len(scene(i)["ee"])) for i in IDS}
