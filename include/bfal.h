@@ -239,6 +239,16 @@ bf_status bf_solve_subproblem(bf_problem* pb, const bf_solve_opts* opts, int32_t
 /* L at the problem's current x_hat (FP64); *inverted = 1 (and L = inf) if a
  * tet is inverted.  Valid after a Newton step (it uses the linearization). */
 bf_status bf_energy(bf_problem* pb, double* energy_out, int32_t* inverted);
+/* bf_energy for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and result, with the per-workgroup partials, their sum and the
+ * inversion flag in a static device array of the library (1 MiB per GPU, held
+ * until the process ends) instead of a buffer of the problem; nothing is
+ * allocated.  A problem needing more than that (8 bytes per 256 tets,
+ * constraints and friction contacts, plus 64) gets BF_ERR_INVALID_ARG.  All
+ * calls on one GPU share the array: calls that overlap on one GPU (several
+ * threads or streams) race and must be serialized by the caller. */
+bf_status bf_energy_noalloc(bf_problem* pb, double* energy_out, int32_t* inverted);
 
 /* Conditioning-aware penalty (Section 5.2): *mu_out = C max_i (grad^2 E)_ii,
  * the largest scalar diagonal of the incremental potential's Hessian -- the

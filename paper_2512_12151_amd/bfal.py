@@ -132,6 +132,7 @@ _PROTOS = [
     ("bf_solve_subproblem", C.c_int, [C.c_void_p, C.POINTER(bf_solve_opts), C.c_int32, C.c_double, C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(bf_subproblem_stats)]),
     ("bf_energy", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    ("bf_energy_noalloc", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     ("bf_mu_init", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double)]),
     ("bf_set_friction", C.c_int, [C.c_void_p, C.c_double, C.c_double]),
     ("bf_update_active_set", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.POINTER(bf_ccd_stats)]),
@@ -312,6 +313,12 @@ class Problem:
         """(L at the current x_hat in FP64, inverted flag)."""
         e, inv = C.c_double(), C.c_int32()
         self.ctx.check(lib().bf_energy(self.h, C.byref(e), C.byref(inv)))
+        return float(e.value), bool(inv.value)
+
+    def energy_noalloc(self):
+        """bf_energy_noalloc: (L at the current x_hat, inverted flag) with no device allocation."""
+        e, inv = C.c_double(), C.c_int32()
+        self.ctx.check(lib().bf_energy_noalloc(self.h, C.byref(e), C.byref(inv)))
         return float(e.value), bool(inv.value)
 
     def update_active_set(self, x_hat=None, sep=0.1):

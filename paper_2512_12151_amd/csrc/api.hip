@@ -9,12 +9,45 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "problem.h"
 
 using namespace bfal;
+
+namespace {
+
+// Scratch of bf_energy_noalloc: the energy's per-workgroup partials, their
+// sum and the inversion flag, in a file-scope device array (each GPU holds its
+// own copy).  Host code never passes the array's name to a kernel: its device
+// address is looked up once per device when a context is created and kept in
+// g_scratch (the name is only a host-side stand-in).
+constexpr size_t kScratchBytes = size_t(1) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// With `device` current: the device address of `scratch` on it (looked up on
+// the first call per device).
+hipError_t scratch_lookup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_scratch[device] = ptr;
+  return e;
+}
+
+void* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_scratch[device] : nullptr;
+}
+
+}  // namespace
 
 namespace bfal {
 
@@ -273,6 +306,7 @@ bf_status bf_context_create(int32_t device, void* hip_stream, bf_context** out) 
   if (!c) return BF_ERR_OOM;
   c->device = device;
   if (hipSetDevice(device) != hipSuccess) { delete c; return BF_ERR_HIP; }
+  if (scratch_lookup(device) != hipSuccess) { delete c; return BF_ERR_HIP; }
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
     c->num_cu = ncu;
@@ -867,7 +901,8 @@ namespace {
 
 // L(xs) in FP64 (the total energy of Section 4.2 with minimizing slacks);
 // *inv is set when some tet of xs is inverted (L is then infinite).
-bf_status energy_at(bf_problem* pb, const double* xs, double* L, int* inv) {
+bf_status energy_at(bf_problem* pb, const double* xs, double* L, int* inv, double* ext = nullptr,
+                    size_t ext_bytes = 0) {
   bf_context* c = pb->ctx;
   hipStream_t s = c->stream;
   const int np = energy_parts(pb->T, pb->n_c, pb->n_f);
@@ -877,8 +912,16 @@ bf_status energy_at(bf_problem* pb, const double* xs, double* L, int* inv) {
   fr.f64 = pb->f64.as<double>();
   fr.x0 = pb->fx0.as<double>();
   fr.e = pb->fric_e;
-  ALLOC(c, pb->epart, 8LL * (np + 8));
-  double* part = pb->epart.as<double>();
+  double* part = ext;
+  if (ext) {   // caller's storage: np partials, the sum and the flag
+    if (8ULL * (np + 8) > ext_bytes)
+      return fail(c, BF_ERR_INVALID_ARG, "problem too large for the no-allocation scratch: the energy needs " +
+                                             std::to_string(8ULL * (np + 8)) + " bytes, the scratch holds " +
+                                             std::to_string(ext_bytes));
+  } else {
+    ALLOC(c, pb->epart, 8LL * (np + 8));
+    part = pb->epart.as<double>();
+  }
   int* flag = reinterpret_cast<int*>(part + np + 2);
   fill_int(flag, 0, 2, s);
   launch_energy(pb->tets.as<int4>(), pb->T, pb->rest.as<double>(), pb->E.as<double>(), pb->nu.as<double>(),
@@ -909,6 +952,20 @@ bf_status bf_energy(bf_problem* pb, double* energy_out, int32_t* inverted) {
   HIPCHK(c, hipSetDevice(c->device));
   int inv = 0;
   const bf_status st = energy_at(pb, pb->xh.as<double>(), energy_out, &inv);
+  if (inverted) *inverted = inv;
+  return st;
+}
+
+bf_status bf_energy_noalloc(bf_problem* pb, double* energy_out, int32_t* inverted) {
+  if (!pb) return BF_ERR_INVALID_ARG;
+  bf_context* c = pb->ctx;
+  if (!energy_out) return fail(c, BF_ERR_INVALID_ARG, "energy_out is NULL");
+  if (!pb->stepped) return fail(c, BF_ERR_STATE, "no Newton step has been run (the linearization is missing)");
+  HIPCHK(c, hipSetDevice(c->device));
+  void* ptr = scratch_of(c->device);
+  if (!ptr) return fail(c, BF_ERR_HIP, "the scratch of this device was not set up");
+  int inv = 0;
+  const bf_status st = energy_at(pb, pb->xh.as<double>(), energy_out, &inv, static_cast<double*>(ptr), kScratchBytes);
   if (inverted) *inverted = inv;
   return st;
 }
