@@ -111,6 +111,31 @@ def counter_traffic():
     return int(m_tr.group(1))
 
 
+ASSEMBLY_FILE = os.path.join(ROOT, "profiles", "assembly_large_counters.md")
+ASSEMBLY_SOURCES = ["elastic.hip", "assemble.hip", "common.h"]
+
+
+def assembly_counters():
+    """The element and row-assembly kernels' HBM and VALU figures from the
+    committed counter summary (JSON on its `assembly_kernels:` line), or None
+    when their sources changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        txt = open(ASSEMBLY_FILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in ASSEMBLY_SOURCES:
+        with open(os.path.join(ROOT, "paper_2512_12151_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    m_sha = re.search(r"^kernel_sources_sha256: ([0-9a-f]+)", txt, re.M)
+    m_js = re.search(r"^assembly_kernels: (\{.*\})$", txt, re.M)
+    if not (m_sha and m_js) or m_sha.group(1) != h.hexdigest():
+        return None
+    return json.loads(m_js.group(1))
+
+
 def cpu_baseline(sc, gpu_iters, frac):
     """The FP64 oracle on a bounded sample of the workload, one thread.
 
@@ -150,11 +175,23 @@ def cpu_baseline(sc, gpu_iters, frac):
         oracle.block_jacobi_pcg(st.H, st.G, 0.0, max_iter=24)
         t_b = time.perf_counter() - t0
     t_it = max(t_b - t_a, 0.0) / 20.0
-    ms = (t_asm + t_it * gpu_iters) / frac * 1e3
+    # the FP64 oracle PCG's own iteration count at this tolerance on this
+    # workload, recorded with its reference solution; else the GPU's
+    iters, src = gpu_iters, "the GPU's iteration count"
+    try:
+        import scenes
+        with open(os.path.join(ROOT, "tests", "golden", "large_p_ref.json")) as f:
+            meta = json.load(f)
+        if sc.get("name") == "large" and meta["digest"] == scenes.digest(sc):
+            iters = int(meta["fp64_pcg_at_step_tol"]["iterations"])
+            src = "the FP64 oracle PCG's own iteration count to 1e-5 on the full workload"
+    except (OSError, KeyError, ValueError):
+        pass
+    ms = (t_asm + t_it * iters) / frac * 1e3
     return {"value": round(ms, 1), "unit": "ms", "cores": 1, "kind": "oracle",
             "sample": (f"first {frac:.0%} of tets and constraints ({len(sub['tets'])} tets, {npt}+{nee} PT+EE): "
-                       f"oracle assembly {t_asm:.2f} s and FP64 block-Jacobi PCG {t_it * 1e3:.1f} ms/iteration, "
-                       f"each scaled by 1/{frac:g}, PCG x {gpu_iters} GPU iterations")}
+                       f"oracle assembly {t_asm:.2f} s and FP64 block-Jacobi PCG {t_it * 1e3:.1f} ms/iteration "
+                       f"(one thread), each scaled by 1/{frac:g}; PCG x {iters} iterations ({src})")}
 
 
 def serve_trace(server, reqs, arrivals, timeout=600.0):
@@ -571,6 +608,7 @@ def main():
                      "copy_ceiling_gbs": cc["gbs_read_plus_write"],
                      "frac_of_copy_ceiling": round(achieved / cc["gbs_read_plus_write"], 4)},
     }
+    line["assembly_kernels"] = assembly_counters()
     line["abi_end_to_end"] = run_abi_end_to_end(ctx, sc, opts)
     log(f"abi end to end: {line['abi_end_to_end']}")
     if args.subproblem:
