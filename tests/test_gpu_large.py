@@ -123,6 +123,8 @@ def test_large_no_constraints_gradient_and_blocks():
 
 
 @pytest.mark.timeout(600)
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "large_p_ref.npy")),
+                    reason="reference solution not written yet (tests/golden/make_large_reference.py)")
 def test_large_solution_energy_norm(large, gpu):
     """The step against the oracle's reference solution p* in the energy norm
     of the oracle's FP64 H.  The bar is the FP64 oracle PCG's own error at the
