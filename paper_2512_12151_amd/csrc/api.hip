@@ -343,7 +343,7 @@ bf_status bf_footprint_bytes(int32_t n_nodes, int32_t n_tets, int32_t n_constrai
   b += C * (16 + 16 + 12 + 16 + 8);                // ids, lambda/gamma, n, w, factors
   b += N * 4 * 8 + C * 16 + cap * 4 * 2;           // incidence, candidates, pattern
   b += cap * (36 + 36 + 4 + 4 + 8 + 4);            // blocks, scaled blocks, ucol, eslot, transpose index, lsrc
-  b += N * (12 * 6 + 24 * 2 + 24);                 // grad, bhat, r, p (2), q, x, L, L^-1, p out
+  b += N * (12 * (4 + kPRing) + 24 * 2 + 24);      // grad, bhat, r, q, the direction ring, x, L, L^-1, p out
   b += 1 << 20;                                    // partials, scalars, scan scratch
   *out = b;
   return BF_OK;
@@ -375,7 +375,7 @@ void bf_problem_destroy(bf_problem* pb) {
                     &pb->cg, &pb->ch, &pb->viol_part, &pb->vcnt, &pb->vptr, &pb->vinc, &pb->ccount, &pb->cptr,
                     &pb->cand, &pb->ucount, &pb->row_ptr, &pb->col, &pb->eslot, &pb->vals, &pb->grad, &pb->Lf,
                     &pb->Linv, &pb->bhat, &pb->bb_part, &pb->lcnt, &pb->lptr, &pb->lsrc, &pb->sbu, &pb->sbl,
-                    &pb->sblk, &pb->sblk16, &pb->scol, &pb->sent, &pb->xs, &pb->r, &pb->p0, &pb->p1, &pb->q,
+                    &pb->sblk, &pb->sblk16, &pb->scol, &pb->sent, &pb->xs, &pb->r, &pb->pring, &pb->q,
                     &pb->part, &pb->scal, &pb->pout, &pb->flags, &pb->scan_tmp, &pb->scratch_int,
                     &pb->xd, &pb->rd, &pb->zd, &pb->fcg, &pb->rpart, &pb->lin64, &pb->pdir, &pb->xtrial,
                     &pb->epart, &pb->stris, &pb->sedges, &pb->sverts, &pb->xq, &pb->tbox, &pb->tkey, &pb->tkey2,
@@ -583,10 +583,9 @@ bf_status size_constraint_buffers(bf_problem* pb, int n_pt, int n_ee) {
   ALLOC(c, pb->rd, 24LL * N4);   // FP64 residual (replacement, refinement)
   ALLOC(c, pb->rpart, 8LL * (kMaxSpmvParts + 8 + 6 * 256 + 8));
   ALLOC(c, pb->r, 12LL * N4);
-  ALLOC(c, pb->p0, 12LL * N4);
-  ALLOC(c, pb->p1, 12LL * N4);
+  ALLOC(c, pb->pring, 12LL * N4 * kPRing);
   ALLOC(c, pb->q, 12LL * N4);
-  for (DevBuf* b : {&pb->Lf, &pb->Linv, &pb->bhat, &pb->xs, &pb->rd, &pb->r, &pb->p0, &pb->p1, &pb->q})
+  for (DevBuf* b : {&pb->Lf, &pb->Linv, &pb->bhat, &pb->xs, &pb->rd, &pb->r, &pb->pring, &pb->q})
     HIPCHK(c, hipMemsetAsync(b->p, 0, b->bytes, s));
   HIPCHK(c, hipStreamSynchronize(s));
   ALLOC(c, pb->part, 8LL * kPartsPerSystem);
@@ -737,6 +736,7 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
       if (pb->host_sc->iter == 0) {
         HIPCHK(c, hipMemcpyAsync(zd, rd, 8 * n3, hipMemcpyDeviceToDevice, s));   // no progress: steepest descent
       } else {
+        launch_pcg_flush(S16, s);
         HIPCHK(c, hipMemcpyAsync(zd, S16.x, 8 * n3, hipMemcpyDeviceToDevice, s));
       }
       // p = z - sum_j (z.q_j / p_j.q_j) p_j over the window

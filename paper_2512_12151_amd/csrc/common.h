@@ -46,7 +46,16 @@ struct PcgScalars {
   int max_iter;
   int check_every;
   int flags;         // FLAG_* bits
+  int xbase;         // x holds alpha_j p_j for every j < xbase and for every j below the last multiple of kXBatch
+                     // reached by the update kernel (written by the flush kernel only)
+  float alpha_hist[8];   // alpha_j at j % kXBatch (written by workgroup 0 of the update kernel)
 };
+
+// x += alpha_j p_j is applied kXBatch iterations at a time (the update kernel
+// of every kXBatch-th iteration, or a flush before x is read): the directions
+// p_j live in a ring of kPRing buffers until then.
+constexpr int kXBatch = 8;
+constexpr int kPRing = kXBatch + 1;
 
 // Partials of one PCG system: every workgroup writes one FP64 value per sum.
 constexpr int kMaxVecParts = 1024;    // workgroups of the update kernel per system
@@ -81,8 +90,8 @@ struct PcgSystem {
   const float* Lf;
   double* x;         // FP64 solution (AoS [N4][3])
   float* r;
-  float* P0;         // p_k for even k
-  float* P1;         // p_k for odd k
+  float* P;          // ring of kPRing direction buffers: p_k at P + (k % kPRing) * pstride
+  long long pstride; // floats per direction buffer (3 N4)
   float* q;
   double* part;      // kPartsPerSystem
   PcgScalars* sc;
@@ -294,6 +303,8 @@ void launch_pcg_iteration(const PcgSystem& S, bool bf16, hipStream_t s, hipEvent
 // lists them, wg_sys_spmv / wg_sys_vec map each workgroup to its system.
 void launch_pcg_iteration_batched(const PcgSystem* sys, const int* wg_sys_spmv, int nwg_spmv, const int* wg_sys_vec,
                                   int nwg_vec, bool bf16, hipStream_t s);
+// x += the directions the update kernel has not applied yet (before x is read).
+void launch_pcg_flush(const PcgSystem& S, hipStream_t s);
 // p = L^{-T} x in FP64 and the stats (max |p|, max violation).
 void launch_pcg_finish(const PcgSystem& S, const float* Linv, double* pout, const double* viol_part, int nviol,
                        hipStream_t s);

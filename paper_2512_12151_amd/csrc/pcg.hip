@@ -12,11 +12,15 @@
 //   update  alpha = rho_k / p^T q; beta = rho~_{k+1} / rho_k with
 //           rho~_{k+1} = |r - alpha q|^2 = rho_k - 2 alpha r^T q + alpha^2 q^T q
 //           (known before r is updated, so the direction can be formed in the
-//           same pass); x += alpha p, r -= alpha q, p_{k+1} = r_{k+1} +
-//           beta p_k into the other buffer of a pair; rho_{k+1} = r^T r
-//           (FP64, for the next alpha and the convergence test); every
-//           check_every iterations also |L r|^2, the unscaled residual norm
-//           squared.
+//           same pass); r -= alpha q, p_{k+1} = r_{k+1} + beta p_k into the
+//           next buffer of a ring; rho_{k+1} = r^T r (FP64, for the next
+//           alpha and the convergence test); every check_every iterations
+//           also |L r|^2, the unscaled residual norm squared.  The FP64
+//           x += alpha_j p_j is applied every kXBatch iterations for the
+//           last kXBatch directions at once (the same FMAs in the same
+//           order as one per iteration), so x is read and written once per
+//           kXBatch iterations; a flush kernel applies the pending ones
+//           before anything reads x.
 // Every SpMV gather then reads one vector (p) instead of forming r + beta p
 // from two.
 // The upper blocks are stored once, in slices of 64 rows with one lane per row
@@ -325,7 +329,7 @@ template <class BT>
 __device__ inline void spmv_slices(const PcgSystem& S, int lb, int nwg, int k, double& pq, double& rq,
                                    double& qq) {
   const int wave = threadIdx.x / kSlice, lane = threadIdx.x % kSlice;
-  const PView pv{(k & 1) ? S.P1 : S.P0};
+  const PView pv{S.P + (k % kPRing) * S.pstride};
   const BT* __restrict__ blk = static_cast<const BT*>(S.blk);
   for (int sl = lb * kSlicesPerGroup + wave; sl < S.nslices; sl += nwg * kSlicesPerGroup) {
     const int bu = S.sbu[sl], wu = (S.sbu[sl + 1] - bu) / kSlice;
@@ -381,17 +385,25 @@ __global__ void __launch_bounds__(kSpmvBlock) k_spmv_batched(const PcgSystem* __
 }
 
 // Operands of one chunk of 4 * kVecBlock nodes for one thread: three float4
-// of p, q, r and the matching FP64 x, and, on check iterations, the thread's
-// 4 nodes of L (SoA [6][N4]).
+// of p, q, r; on flush iterations the matching FP64 x and the pending
+// directions p_j, j0 <= j < k (at most kXBatch - 1; the slots of absent ones
+// repeat p_k and are not applied); on check iterations the thread's 4 nodes
+// of L (SoA [6][N4]).
 struct UpdateOperands {
   float4 p[3], q[3], r[3], l[6];
   double2 xa[3], xb[3];
+  float4 pj[kXBatch - 1][3];
 };
 
-__device__ __forceinline__ void load_update_operands(const PcgSystem& S, const float4* __restrict__ p4, long long ch,
+// Where the directions of iteration k live, and which of them x still lacks
+// at the update of iteration k: j0 <= j <= k on a flush iteration.
+__device__ __forceinline__ const float* dir_of(const PcgSystem& S, int j) { return S.P + (j % kPRing) * S.pstride; }
+
+__device__ __forceinline__ void load_update_operands(const PcgSystem& S, int k, bool flush, int j0, long long ch,
                                                      bool check, UpdateOperands& o) {
   const int t = threadIdx.x;
   const long long n4 = S.N4, nf4 = 3 * n4 / 4;
+  const float4* __restrict__ p4 = reinterpret_cast<const float4*>(dir_of(S, k));
   const float4* __restrict__ q4 = reinterpret_cast<const float4*>(S.q);
   const double2* __restrict__ x2 = reinterpret_cast<const double2*>(S.x);
   const float4* __restrict__ r4 = reinterpret_cast<const float4*>(S.r);
@@ -403,8 +415,26 @@ __device__ __forceinline__ void load_update_operands(const PcgSystem& S, const f
       o.p[m] = p4[f];
       o.q[m] = q4[f];
       o.r[m] = r4[f];
-      o.xa[m] = x2[2 * f];
-      o.xb[m] = x2[2 * f + 1];
+    }
+  }
+  if (flush) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const long long f = ch * 3 * kVecBlock + m * kVecBlock + t;
+      if (f < nf4) {
+        o.xa[m] = x2[2 * f];
+        o.xb[m] = x2[2 * f + 1];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kXBatch - 1; ++u) {
+      const int j = j0 + u < k ? j0 + u : k;
+      const float4* __restrict__ pj4 = reinterpret_cast<const float4*>(dir_of(S, j));
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const long long f = ch * 3 * kVecBlock + m * kVecBlock + t;
+        if (f < nf4) o.pj[u][m] = pj4[f];
+      }
     }
   }
   const long long v0 = ch * 4 * kVecBlock + 4LL * t;
@@ -413,30 +443,48 @@ __device__ __forceinline__ void load_update_operands(const PcgSystem& S, const f
     for (int m = 0; m < 6; ++m) o.l[m] = l4[(m * n4 + v0) / 4];
 }
 
-// x += alpha p, r -= alpha q, p_{k+1} = r + beta p for one chunk; adds the
-// chunk's r^T r and (on check iterations) |L r|^2 shares.  The new residual is
-// staged in LDS (rs) for the per-node |L r|^2.
+// x += alpha_j p_j for j0 <= j <= k, in order (flush iterations only).
+__device__ __forceinline__ void apply_pending(double2& xa, double2& xb, const float4 p, const UpdateOperands& o, int m,
+                                              int j0, int k, const float* alpha_hist, float alpha) {
+#pragma unroll
+  for (int u = 0; u < kXBatch - 1; ++u) {
+    if (j0 + u < k) {
+      const double a = alpha_hist[(j0 + u) % kXBatch];
+      const float4 pj = o.pj[u][m];
+      xa.x = fma(a, (double)pj.x, xa.x); xa.y = fma(a, (double)pj.y, xa.y);
+      xb.x = fma(a, (double)pj.z, xb.x); xb.y = fma(a, (double)pj.w, xb.y);
+    }
+  }
+  const double ad = alpha;   // the same alpha as the residual update
+  xa.x = fma(ad, (double)p.x, xa.x); xa.y = fma(ad, (double)p.y, xa.y);
+  xb.x = fma(ad, (double)p.z, xb.x); xb.y = fma(ad, (double)p.w, xb.y);
+}
+
+// r -= alpha q, p_{k+1} = r + beta p (and on flush iterations the pending
+// x updates) for one chunk; adds the chunk's r^T r and (on check iterations)
+// |L r|^2 shares.  The new residual is staged in LDS (rs) for the per-node
+// |L r|^2.
 __device__ __forceinline__ void update_chunk(const PcgSystem& S, float4* __restrict__ pn4, long long ch, bool check,
-                                             float alpha, float beta, const UpdateOperands& o, float4* rs,
-                                             double& rr, double& rt) {
+                                             bool flush, int j0, int k, const float* alpha_hist, float alpha,
+                                             float beta, const UpdateOperands& o, float4* rs, double& rr, double& rt) {
   const int t = threadIdx.x;
   const long long n4 = S.N4, nf4 = 3 * n4 / 4;
   double2* __restrict__ x2 = reinterpret_cast<double2*>(S.x);
   float4* __restrict__ r4 = reinterpret_cast<float4*>(S.r);
-  const double ad = alpha;   // the same alpha as the residual update
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
     const long long f = ch * 3 * kVecBlock + m * kVecBlock + t;
     if (f < nf4) {
       const float4 p = o.p[m], q = o.q[m];
       float4 r = o.r[m];
-      double2 xa = o.xa[m], xb = o.xb[m];
-      xa.x = fma(ad, (double)p.x, xa.x); xa.y = fma(ad, (double)p.y, xa.y);
-      xb.x = fma(ad, (double)p.z, xb.x); xb.y = fma(ad, (double)p.w, xb.y);
+      if (flush) {
+        double2 xa = o.xa[m], xb = o.xb[m];
+        apply_pending(xa, xb, p, o, m, j0, k, alpha_hist, alpha);
+        x2[2 * f] = xa;
+        x2[2 * f + 1] = xb;
+      }
       r.x = __fmaf_rn(-alpha, q.x, r.x); r.y = __fmaf_rn(-alpha, q.y, r.y);
       r.z = __fmaf_rn(-alpha, q.z, r.z); r.w = __fmaf_rn(-alpha, q.w, r.w);
-      x2[2 * f] = xa;
-      x2[2 * f + 1] = xb;
       r4[f] = r;
       pn4[f] = make_float4(__fmaf_rn(beta, p.x, r.x), __fmaf_rn(beta, p.y, r.y), __fmaf_rn(beta, p.z, r.z),
                            __fmaf_rn(beta, p.w, r.w));
@@ -466,7 +514,7 @@ __device__ __forceinline__ void update_chunk(const PcgSystem& S, float4* __restr
   }
 }
 
-// alpha and beta, then x += alpha p, r -= alpha q, p_{k+1} = r + beta p over
+// alpha and beta, then r -= alpha q, p_{k+1} = r + beta p (and x on flush iterations) over
 // the nodes of workgroup lb of nwg, in chunks of 4 * kVecBlock nodes whose
 // three vectors' float4s are contiguous (every load and store is one
 // contiguous run per wavefront).  The operands of the workgroup's first chunk
@@ -479,11 +527,15 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
   const bool check = ((k + 1) % sc->check_every) == 0;
   double* part = S.part;
   __shared__ float4 rs[3 * kVecBlock];
-  const float4* __restrict__ p4 = reinterpret_cast<const float4*>((k & 1) ? S.P1 : S.P0);
-  float4* __restrict__ pn4 = reinterpret_cast<float4*>((k & 1) ? S.P0 : S.P1);
+  __shared__ float alpha_hist[kXBatch];
+  float4* __restrict__ pn4 = reinterpret_cast<float4*>(const_cast<float*>(dir_of(S, k + 1)));
   const long long nchunk = (S.N4 + 4 * kVecBlock - 1) / (4 * kVecBlock);
+  // x takes alpha_j p_j, j0 <= j <= k, on every kXBatch-th iteration
+  const bool flush = ((k + 1) % kXBatch) == 0;
+  const int j0 = max(sc->xbase, k + 1 - kXBatch);
+  if (flush && threadIdx.x < kXBatch) alpha_hist[threadIdx.x] = sc->alpha_hist[threadIdx.x];
   UpdateOperands o;
-  if (lb < nchunk) load_update_operands(S, p4, lb, check, o);
+  if (lb < nchunk) load_update_operands(S, k, flush, j0, lb, check, o);
   double rho, pq, rq, qq;
   sum_parts4<kVecBlock>(part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg, part + kPartPQ, S.spmv_nwg,
                         part + kPartRQ, S.spmv_nwg, part + kPartQQ, S.spmv_nwg, rho, pq, rq, qq);
@@ -502,10 +554,11 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
   const double rho_next = rho - 2.0 * ad * rq + ad * ad * qq;
   const float beta = rho_next > 0.0 ? (float)(rho_next / rho) : 0.f;
   double rr = 0.0, rt = 0.0;
-  if (lb < nchunk) update_chunk(S, pn4, lb, check, alpha, beta, o, rs, rr, rt);
+  __syncthreads();   // alpha_hist staged
+  if (lb < nchunk) update_chunk(S, pn4, lb, check, flush, j0, k, alpha_hist, alpha, beta, o, rs, rr, rt);
   for (long long ch = lb + S.vec_nwg; ch < nchunk; ch += S.vec_nwg) {
-    load_update_operands(S, p4, ch, check, o);
-    update_chunk(S, pn4, ch, check, alpha, beta, o, rs, rr, rt);
+    load_update_operands(S, k, flush, j0, ch, check, o);
+    update_chunk(S, pn4, ch, check, flush, j0, k, alpha_hist, alpha, beta, o, rs, rr, rt);
   }
   const double srr = block_sum_all<kVecBlock>(rr);
   const double srt = block_sum_all<kVecBlock>(rt);
@@ -513,7 +566,10 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
     part[kPartRR + ((k + 1) & 1) * kMaxVecParts + lb] = srr;
     part[kPartRT + lb] = srt;
   }
-  if (leader) sc->iter = k + 1;
+  if (leader) {
+    sc->alpha_hist[k % kXBatch] = alpha;
+    sc->iter = k + 1;
+  }
 }
 
 __global__ void __launch_bounds__(kVecBlock) k_update(PcgSystem S) { update_nodes(S, blockIdx.x); }
@@ -557,6 +613,7 @@ k_init_scalars(const double* __restrict__ bb_part, int nbb, PcgScalars* sc, doub
     sc->check_every = check_every > 0 ? check_every : 1;
     sc->flags = 0;
     sc->brk = 0;
+    sc->xbase = 0;
     sc->done = (bb == 0.0) ? 1 : (max_iter <= 0 ? 2 : 0);
   }
 }
@@ -705,6 +762,27 @@ k_init_from64(int n3, const double* __restrict__ rd, double* __restrict__ x, flo
   if (threadIdx.x == 0) part[kPartRR + blockIdx.x] = s;
 }
 
+// x += alpha_j p_j for the directions the update kernel has not applied yet
+// (j from the last multiple of kXBatch, or xbase, up to iter - 1), in
+// order; then xbase = iter.  Runs before anything reads x.
+__global__ void __launch_bounds__(kVecBlock) k_flush_x(PcgSystem S) {
+  PcgScalars* sc = S.sc;
+  const int n = sc->iter;
+  const int j0 = max(sc->xbase, n - n % kXBatch);
+  const long long n3 = 3LL * S.N4;
+  for (long long i = (long long)blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += (long long)gridDim.x * kVecBlock) {
+    double x = S.x[i];
+    for (int j = j0; j < n; ++j) x = fma((double)sc->alpha_hist[j % kXBatch], (double)dir_of(S, j)[i], x);
+    S.x[i] = x;
+  }
+}
+
+// Marks the flushed directions (after k_flush_x, in a kernel of its own so
+// that no workgroup of the flush reads a changed xbase).
+__global__ void k_flush_mark(PcgScalars* sc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) sc->xbase = sc->iter;
+}
+
 // Residual replacement, second half: r = (float) rd over this workgroup's
 // chunk with its r^T r partial, the |L rd|^2 partials of k_residual64 folded
 // into workgroup 0's slot, the reference and the replaced iteration recorded,
@@ -745,8 +823,8 @@ __global__ void __launch_bounds__(kVecBlock) k_replace_dir(PcgSystem S) {
   sum_parts3<kVecBlock>(S.part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg,
                         S.part + kPartRR + ((k + 1) & 1) * kMaxVecParts, S.vec_nwg, S.part, 0, rho, rho_old, unused);
   const float beta = rho_old > 0.0 ? (float)(rho / rho_old) : 0.f;
-  float* __restrict__ pk = (k & 1) ? S.P1 : S.P0;
-  const float* __restrict__ pold = (k & 1) ? S.P0 : S.P1;
+  float* __restrict__ pk = const_cast<float*>(dir_of(S, k));
+  const float* __restrict__ pold = dir_of(S, k - 1);
   const long long n3 = 3LL * S.N4;
   for (long long i = (long long)blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += (long long)gridDim.x * kVecBlock)
     pk[i] = __fmaf_rn(beta, pold[i], S.r[i]);
@@ -804,12 +882,18 @@ int pcg_vec_groups(int N) {
 
 void launch_pcg_init(const PcgSystem& S, const float* bhat, const double* bb_part, int nbb, double tol, int max_iter,
                      int check_every, bool replace, hipStream_t s) {
-  hipLaunchKernelGGL(k_init, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, bhat, S.x, S.r, S.P0, S.part);
+  hipLaunchKernelGGL(k_init, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, bhat, S.x, S.r, S.P, S.part);
   hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kBlock), 0, s, bb_part, nbb, S.sc, tol, max_iter, check_every,
                      replace ? 1 : 0);
 }
 
+void launch_pcg_flush(const PcgSystem& S, hipStream_t s) {
+  hipLaunchKernelGGL(k_flush_x, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, S);
+  hipLaunchKernelGGL(k_flush_mark, dim3(1), dim3(64), 0, s, S.sc);
+}
+
 void launch_pcg_replace(const PcgSystem& S, const float* bhat, double* rd, double* rpart, hipStream_t s) {
+  launch_pcg_flush(S, s);
   hipLaunchKernelGGL(k_residual64, dim3(S.spmv_nwg), dim3(kSpmvBlock), 0, s, S, bhat, (const double*)S.x, rd, rpart);
   hipLaunchKernelGGL(k_replace_fold, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, S, (const double*)rd,
                      (const double*)rpart, S.spmv_nwg);
@@ -843,6 +927,7 @@ void launch_pcg_iteration_batched(const PcgSystem* sys, const int* wg_sys_spmv, 
 void launch_pcg_finish(const PcgSystem& S, const float* Linv, double* pout, const double* viol_part, int nviol,
                        hipStream_t s) {
   const int g = pcg_vec_groups(S.N);
+  launch_pcg_flush(S, s);
   // the max |p| partials reuse the p^T q slots, which the solve no longer needs
   double* part = S.part + kPartPQ;
   hipLaunchKernelGGL(k_finish<double>, dim3(g), dim3(kVecBlock), 0, s, S.N, S.N4, Linv, (const double*)S.x, pout,
@@ -852,7 +937,7 @@ void launch_pcg_finish(const PcgSystem& S, const float* Linv, double* pout, cons
 
 void launch_pcg_init_from64(const PcgSystem& S, const double* rd, const double* rpart, int nparts, double tol,
                             int max_iter, int check_every, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_from64, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, rd, S.x, S.r, S.P0, S.part);
+  hipLaunchKernelGGL(k_init_from64, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, rd, S.x, S.r, S.P, S.part);
   hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kBlock), 0, s, rpart, nparts, S.sc, tol, max_iter, check_every,
                      0);
 }

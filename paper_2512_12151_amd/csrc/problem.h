@@ -47,7 +47,7 @@ struct bf_problem {
   DevBuf vcnt, vptr, vinc;
   DevBuf ccount, cptr, cand, ucount, row_ptr, col, eslot;
   DevBuf vals, grad, Lf, Linv, bhat, bb_part, lcnt, lptr, lsrc, sbu, sbl, sblk, sblk16, scol, sent;
-  DevBuf xs, r, p0, p1, q, part, scal, pout, flags, scan_tmp, scratch_int;
+  DevBuf xs, r, pring, q, part, scal, pout, flags, scan_tmp, scratch_int;
   DevBuf xd, rd, zd, fcg, rpart;   // refinement: FP64 solution, residual, inner solution, directions, partials
   DevBuf lin64;                    // FP64 linearization of the constraints, SoA [8][n]
   DevBuf pdir, xtrial, epart;      // subproblem: Newton direction, line-search trial state, partials
@@ -131,8 +131,8 @@ inline PcgSystem system_of(bf_problem* pb) {
   S.Lf = pb->Lf.as<float>();
   S.x = pb->xs.as<double>();
   S.r = pb->r.as<float>();
-  S.P0 = pb->p0.as<float>();
-  S.P1 = pb->p1.as<float>();
+  S.P = pb->pring.as<float>();
+  S.pstride = 3LL * S.N4;
   S.q = pb->q.as<float>();
   S.part = pb->part.as<double>();
   S.sc = pb->scal.as<PcgScalars>();

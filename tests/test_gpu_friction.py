@@ -290,3 +290,24 @@ def test_momentum_conservation_with_friction(ctx, bf):
               flush=True)
     assert v[~up].mean(0)[0] > 0.005          # friction dragged the lower cube along
     assert max(errs) <= 1e-6
+
+
+def test_friction_stiffer_than_fp32_blocks_reports_not_spd(ctx, bf):
+    """The documented limit of FP32 blocks: a sticking stiffness 2 coef /
+    (eps_v h) = 1e11 against nodal masses of a few kg leaves FP32 rounding
+    residues (~6e-8 x 4 x 1e11) far above the smallest stiffness of the
+    assembled matrix, which is then indefinite.  The step must say so
+    (BF_ERR_NOT_SPD from a diagonal block's factorization or a PCG breakdown)
+    instead of returning a direction; the same problem with friction off
+    still solves.  The computation is bitwise deterministic, so the outcome
+    is the same on every run."""
+    sc, _ = sliding(3)
+    sc = dict(sc, lam=np.full(len(sc["lam"]), 1e6))
+    pb = bf.Problem.from_scene(ctx, sc)
+    pb.set_friction(0.5, 1e-3)
+    with pytest.raises(bf.BfalError) as e:
+        pb.newton_step(tol=1e-7, max_iter=20000)
+    assert e.value.status == -6   # BF_ERR_NOT_SPD
+    pb.set_friction(0.0)
+    _, _, status = pb.newton_step(tol=1e-7, max_iter=20000)
+    assert status in (bf.BF_OK, bf.BF_WARN_PCG_MAXITER)
