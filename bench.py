@@ -51,12 +51,14 @@ def spmv_design_bytes(N, nnzb):
     return 48 * n_off + 8 * (N + 1) + 36 * N
 
 
-def pcg_iteration_bytes(N, nnzb, check_every=1):
-    """The SpMV's design bytes + the update kernel (p, q and r read, 36 B/node;
-    the FP64 x read and written, 48 B/node; r and the next p written,
-    24 B/node: 108 B/node, and the factor L, 24 B/node, on the iterations that
-    test |L r|)."""
-    return spmv_design_bytes(N, nnzb) + (108 + 24.0 / check_every) * N
+def pcg_iteration_bytes(N, nnzb, check_every=1, x_batch=8):
+    """The SpMV's design bytes + the update kernel: p, q and r read (36 B/node),
+    r and the next p written (24 B/node); every x_batch-th iteration also
+    applies the pending x += alpha_j p_j, reading the other x_batch - 1
+    directions (12 B/node each) and the FP64 x, and writing x (48 B/node),
+    spread over the x_batch iterations; and the factor L (24 B/node) on the
+    iterations that test |L r|."""
+    return spmv_design_bytes(N, nnzb) + (60 + (48 + 12.0 * (x_batch - 1)) / x_batch + 24.0 / check_every) * N
 
 
 def copy_ceiling():

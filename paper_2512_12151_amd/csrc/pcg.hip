@@ -277,33 +277,45 @@ struct PView {
 
 // Accumulates one row's slots as pairs (upper slot k: B p_c with the column
 // from scol; lower slot k: B^T p_r with block and source row from sent),
-// kPairs pairs per step with all their loads issued before any is used.  A
-// step may run past the row's widths: those slots are still read (the slot
-// arrays are padded, so every index read is in range) but not added, which
-// keeps the step free of branches.  The sum runs in pair order.
+// kPairs pairs per step with all their loads issued before any is used.  The
+// next step's indices are loaded before this step's products (a scheduling
+// barrier keeps them there), so each step waits for one memory round trip
+// instead of an index load followed by the loads it addresses.  A step may
+// run past the row's widths: those slots are still read (the slot arrays are
+// padded, so every index read is in range) but not added, which keeps the
+// step free of branches.  The sum runs in pair order.
 template <class BT>
 __device__ inline void accumulate_pairs(int ubase, int wu, int lbase, int wl, const int* __restrict__ scol,
                                         const int2* __restrict__ sent, const BT* __restrict__ blk, const PView& pv,
                                         float& a0, float& a1, float& a2) {
   const int w = wu > wl ? wu : wl;
-  for (int k = 0; k < w; k += kPairs) {
-    int ub[kPairs], uc[kPairs], lb[kPairs], lc[kPairs];
+  int uc[kPairs], lb[kPairs], lc[kPairs];
 #pragma unroll
-    for (int u = 0; u < kPairs; ++u) {
-      ub[u] = ubase + (k + u) * kSlice;
-      uc[u] = scol[ub[u]];
-      const int2 t = sent[lbase + (k + u) * kSlice];
-      lb[u] = t.x;
-      lc[u] = t.y;
-    }
+  for (int u = 0; u < kPairs; ++u) {
+    uc[u] = scol[ubase + u * kSlice];
+    const int2 t = sent[lbase + u * kSlice];
+    lb[u] = t.x;
+    lc[u] = t.y;
+  }
+  for (int k = 0; k < w; k += kPairs) {
     float bu[kPairs][9], pu[kPairs][3], bl[kPairs][9], pl[kPairs][3];
 #pragma unroll
     for (int u = 0; u < kPairs; ++u) {
-      load_block(blk, ub[u], bu[u]);
+      load_block(blk, ubase + (k + u) * kSlice, bu[u]);
       pv.at(uc[u], pu[u][0], pu[u][1], pu[u][2]);
       load_block(blk, lb[u], bl[u]);
       pv.at(lc[u], pl[u][0], pl[u][1], pl[u][2]);
     }
+    // indices of the next step (inside the slot arrays' read-ahead padding), in flight during this step's products
+    const int kn = k + kPairs < w ? k + kPairs : k;
+#pragma unroll
+    for (int u = 0; u < kPairs; ++u) {
+      uc[u] = scol[ubase + (kn + u) * kSlice];
+      const int2 t = sent[lbase + (kn + u) * kSlice];
+      lb[u] = t.x;
+      lc[u] = t.y;
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < kPairs; ++u) {
       const bool vu = k + u < wu, vl = k + u < wl;
