@@ -29,9 +29,10 @@
 // part.  On a structured mesh the rows of a slice have the same stencil, so the
 // lower references of slot k point at consecutive slots of the source slice
 // and the p gathers of a slot are consecutive nodes: every access of the SpMV
-// is a contiguous run per wavefront.  Workgroups are mapped so each XCD owns
-// one contiguous range of slices; the whole upper matrix of the large workload
-// (~150 MB) fits the 256 MB Infinity Cache.
+// is a contiguous run per wavefront.  Workgroups are mapped so that in each
+// round of the slice loop every XCD works on one contiguous window of slices;
+// the whole upper matrix of the large workload (~150 MB) fits the 256 MB
+// Infinity Cache.
 //
 // Residual replacement (reliable updating): x is kept in FP64, and when the
 // recursive residual has fallen 100x since the last replacement, or claims
