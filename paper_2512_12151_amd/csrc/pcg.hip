@@ -748,12 +748,13 @@ __global__ void __launch_bounds__(kBlock) k_dots_sum(const double* __restrict__ 
   }
 }
 
-// y += alpha x (FP64), or y = x (FP32 source) when x32 is set.
+// y += alpha x (FP64).
 __global__ void __launch_bounds__(kVecBlock)
 k_axpy_d(int n3, double alpha, const double* __restrict__ x, double* __restrict__ y) {
   for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) y[i] += alpha * x[i];
 }
 
+// y = x widened from FP32 to FP64.
 __global__ void __launch_bounds__(kVecBlock)
 k_copy_f2d(int n3, const float* __restrict__ x, double* __restrict__ y) {
   for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) y[i] = (double)x[i];
