@@ -111,7 +111,7 @@ typedef struct {
   int32_t check_every;   /* the true residual norm is formed every this many iterations */
   int32_t time_spmv;     /* >0: time the SpMV launches of the first this-many PCG iterations
                             with HIP events (reported in bf_step_stats); 0: no per-kernel events */
-  int32_t max_sweeps;    /* BF16 mode: at most this many inner solves (0 means 30) */
+  int32_t max_sweeps;    /* BF16 mode: at most this many inner solves (0 means 100) */
 } bf_solve_opts;
 
 typedef struct {
@@ -193,8 +193,9 @@ bf_status bf_get_nnzb(bf_problem* pb, int64_t* nnzb);
  * vertex id is larger); diag [n_nodes] slot of (v,v).  Any pointer may be NULL. */
 bf_status bf_get_pattern(bf_problem* pb, int32_t* row_ptr, int32_t* col, int32_t* emap, int32_t* cmap,
                          int32_t* diag);
-/* Assembled (unscaled) blocks after DBC, [nnzb][3][3] row-major FP32. */
-bf_status bf_get_blocks(bf_problem* pb, float* vals);
+/* Assembled (unscaled) blocks after DBC, [nnzb][3][3] row-major FP64 (the solver stores the
+ * symmetrically scaled blocks rounded once to FP32). */
+bf_status bf_get_blocks(bf_problem* pb, double* vals);
 
 /* Device bytes a problem of this size holds (mesh, state, constraints,
  * pattern, blocks and solver vectors), for admission control. */

@@ -408,7 +408,7 @@ class Problem:
         return row_ptr, col, emap, cmap[: self.n_c], diag
 
     def blocks(self):
-        v = np.empty((self.nnzb(), 3, 3), np.float32)
+        v = np.empty((self.nnzb(), 3, 3), np.float64)
         self.ctx.check(lib().bf_get_blocks(self.h, v.ctypes.data))
         return v
 

@@ -89,7 +89,7 @@ bf_status problem_init(bf_context* c, bf_problem* pb, const bf_mesh_desc* m, int
   ALLOC(c, pb->vol, 4LL * T);
   ALLOC(c, pb->mu, 4LL * T);
   ALLOC(c, pb->lam, 4LL * T);
-  ALLOC(c, pb->mass, 4LL * N);
+  ALLOC(c, pb->mass, 8LL * N);
   ALLOC(c, pb->flags, 64);
   HIPCHK(c, hipMemcpyAsync(pb->tets.p, m->tets, 16LL * T, kind_in(mem), s));
   HIPCHK(c, hipMemcpyAsync(pb->rest.p, m->rest, 24LL * N, kind_in(mem), s));
@@ -161,8 +161,8 @@ bf_status problem_init(bf_context* c, bf_problem* pb, const bf_mesh_desc* m, int
   launch_slot_fill(pb->emap.as<int>(), 10LL * T, ecptr, scnt, pb->elist.as<int>(), s);
   sort_segments(pb->elist.as<int>(), ecptr, nnzb_e, s);
   launch_inverse_positions(pb->elist.as<int>(), 10LL * T, pb->epos.as<int>(), s);
-  launch_mass(ecptr, pb->elist.as<int>(), erow, pb->vol.as<float>(), pb->rho.as<double>(), N, pb->mass.as<float>(), s);
-  ALLOC(c, pb->staging, 360LL * T);
+  launch_mass(ecptr, pb->elist.as<int>(), erow, pb->vol.as<float>(), pb->rho.as<double>(), N, pb->mass.as<double>(), s);
+  ALLOC(c, pb->staging, 720LL * T);   // FP64: ten 3x3 blocks (the diagonal ones with the gradient) per tet
   r0 = read_flags(pb, &hflags);
   if (r0 != BF_OK) return r0;
   if (hflags) return flags_to_status(c, hflags);
@@ -194,9 +194,8 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
   // (1) constraint linearization at x and AL factors at x_hat
   fill_int(reinterpret_cast<int*>(pb->viol_part.p), 0, 2, s);
   launch_contact_lin(ids, pb->n_pt, n, pb->x.as<double>(), pb->xh.as<double>(), pb->clam.as<double>(),
-                     pb->cgam.as<double>(), pb->kappa, pb->delta, pb->cn.as<float>(), pb->cw.as<float>(),
-                     pb->cg.as<float>(), pb->ch.as<float>(), pb->lin64.as<double>(), pb->viol_part.as<double>(), flags,
-                     s);
+                     pb->cgam.as<double>(), pb->kappa, pb->delta, pb->cg.as<double>(), pb->ch.as<double>(),
+                     pb->lin64.as<double>(), pb->viol_part.as<double>(), flags, s);
   HIPCHK(c, hipEventRecord(pb->ev[1], s));
   // (2) merged pattern: vertex -> constraint incidence, candidates, unique rows.
   // Its stencils: the constraints, then the friction contacts that match no
@@ -239,17 +238,17 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
   HIPCHK(c, hipEventRecord(pb->ev[2], s));
   // (3) assembly (friction terms at x_hat first)
   launch_friction_terms(pb->fids.as<int4>(), nf, pb->xh.as<double>(), pb->fx0.as<double>(), pb->f64.as<double>(),
-                        pb->fric_e, pb->fgk.as<float>(), s);
-  const float h2 = (float)(pb->dt * pb->dt);
+                        pb->fric_e, pb->fgk.as<double>(), s);
+  const double h2 = pb->dt * pb->dt;
   launch_elastic(pb->tets.as<int4>(), T, pb->rest.as<double>(), pb->xh.as<double>(), pb->Dminv9.as<double>(),
                  pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), h2, pb->epos.as<int>(),
-                 pb->staging.as<float>(), pb->has_mat ? pb->mat.as<int>() : nullptr, flags, s);
-  launch_assemble_rows(N, row_ptr, pb->col.as<int>(), pb->eslot.as<int>(), pb->ecptr.as<int>(), pb->staging.as<float>(),
-                       vptr, pb->vinc.as<int>(), pids, n, pb->cn.as<float>(), pb->cw.as<float>(), pb->cg.as<float>(),
-                       pb->ch.as<float>(), nf, pb->fgk.as<float>(), pb->cfr.as<int>(), pb->fext.as<int>(),
-                       pb->mass.as<float>(), pb->xh.as<double>(), pb->xt.as<double>(),
-                       pb->fixed.as<uint8_t>(), pb->vals.as<float>(), pb->grad.as<float>(), pb->Lf.as<float>(),
-                       pb->Linv.as<float>(), pb->bhat.as<float>(), pb->bb_part.as<double>(), flags, s);
+                 pb->staging.as<double>(), pb->has_mat ? pb->mat.as<int>() : nullptr, flags, s);
+  launch_assemble_rows(N, row_ptr, pb->col.as<int>(), pb->eslot.as<int>(), pb->ecptr.as<int>(),
+                       pb->staging.as<double>(), vptr, pb->vinc.as<int>(), pids, n, pb->lin64.as<double>(),
+                       pb->cg.as<double>(), pb->ch.as<double>(), nf, pb->fgk.as<double>(), pb->cfr.as<int>(),
+                       pb->fext.as<int>(), pb->mass.as<double>(), pb->xh.as<double>(), pb->xt.as<double>(),
+                       pb->fixed.as<uint8_t>(), pb->vals.as<double>(), pb->grad.as<float>(), pb->Lf.as<float>(),
+                       pb->Linv.as<double>(), pb->bhat.as<float>(), pb->bb_part.as<double>(), flags, s);
   // sliced storage of the scaled matrix: per column the source rows of its
   // upper blocks, slot counts per slice, then the slots themselves
   int* lcnt = pb->lcnt.as<int>();
@@ -286,7 +285,7 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
   if (bf16) HIPCHK(c, hipMemsetAsync(pb->sblk16.as<char>() + 20LL * tot[0], 0, 20LL * (nu_alloc - tot[0]), s));
   HIPCHK(c, hipMemsetAsync(pb->scol.as<char>() + 4LL * tot[0], 0, 4LL * (nu_alloc - tot[0]), s));
   HIPCHK(c, hipMemsetAsync(pb->sent.as<char>() + 8LL * tot[1], 0, 8LL * (nl_alloc - tot[1]), s));
-  launch_sell_fill(N, nslices, row_ptr, pb->col.as<int>(), pb->vals.as<float>(), pb->Linv.as<float>(), lptr,
+  launch_sell_fill(N, nslices, row_ptr, pb->col.as<int>(), pb->vals.as<double>(), pb->Linv.as<double>(), lptr,
                    pb->lsrc.as<int>(), sbu, sbl, pb->sblk.as<float>(), bf16 ? pb->sblk16.as<uint32_t>() : nullptr,
                    pb->scol.as<int>(),
                    pb->sent.as<int2>(), s);
@@ -337,13 +336,13 @@ bf_status bf_footprint_bytes(int32_t n_nodes, int32_t n_tets, int32_t n_constrai
   const size_t nnzb_e = N + 6 * T;                 // upper bound on the static pattern
   const size_t cap = nnzb_e + 6 * C;
   size_t b = 0;
-  b += T * (16 + 3 * 8 + 72 + 12 + 40 * 3 + 360);  // tets, E/nu/rho, Dm^-1 (FP64), vol/mu/lam, emap/epos/elist, staging
-  b += nnzb_e * (4 + 4) + N * (4 * 3 + 24 + 4 + 1);
+  b += T * (16 + 3 * 8 + 72 + 12 + 40 * 3 + 720);  // tets, E/nu/rho, Dm^-1, vol/mu/lam, emap/epos/elist, FP64 staging
+  b += nnzb_e * (4 + 4) + N * (4 * 3 + 24 + 8 + 1);
   b += N * 24 * 3;                                 // x, x_hat, x_tilde
-  b += C * (16 + 16 + 12 + 16 + 8);                // ids, lambda/gamma, n, w, factors
+  b += C * (16 + 16 + 64 + 16);                    // ids, lambda/gamma, the FP64 linearization, AL factors
   b += N * 4 * 8 + C * 16 + cap * 4 * 2;           // incidence, candidates, pattern
-  b += cap * (36 + 36 + 4 + 4 + 8 + 4);            // blocks, scaled blocks, ucol, eslot, transpose index, lsrc
-  b += N * (12 * (4 + kPRing) + 24 * 2 + 24);      // grad, bhat, r, q, the direction ring, x, L, L^-1, p out
+  b += cap * (72 + 36 + 4 + 4 + 8 + 4);            // FP64 blocks, FP32 scaled blocks, ucol, eslot, transpose index, lsrc
+  b += N * (12 * (4 + kPRing) + 24 + 24 + 48 + 24);   // grad, bhat, r, q, the direction ring, x, L, L^-1, p out
   b += 1 << 20;                                    // partials, scalars, scan scratch
   *out = b;
   return BF_OK;
@@ -371,7 +370,7 @@ void bf_problem_destroy(bf_problem* pb) {
   if (pb->ctx) (void)hipStreamSynchronize(pb->ctx->stream);
   DevBuf* bufs[] = {&pb->tets, &pb->rest, &pb->E, &pb->nu, &pb->rho, &pb->fixed, &pb->Dminv9, &pb->vol, &pb->mu,
                     &pb->lam, &pb->mass, &pb->erow_ptr, &pb->ecol, &pb->emap, &pb->ecptr, &pb->elist, &pb->epos,
-                    &pb->staging, &pb->x, &pb->xh, &pb->xt, &pb->cids, &pb->clam, &pb->cgam, &pb->cn, &pb->cw,
+                    &pb->staging, &pb->x, &pb->xh, &pb->xt, &pb->cids, &pb->clam, &pb->cgam,
                     &pb->cg, &pb->ch, &pb->viol_part, &pb->vcnt, &pb->vptr, &pb->vinc, &pb->ccount, &pb->cptr,
                     &pb->cand, &pb->ucount, &pb->row_ptr, &pb->col, &pb->eslot, &pb->vals, &pb->grad, &pb->Lf,
                     &pb->Linv, &pb->bhat, &pb->bb_part, &pb->lcnt, &pb->lptr, &pb->lsrc, &pb->sbu, &pb->sbl,
@@ -505,7 +504,7 @@ bf_status bf_set_friction(bf_problem* pb, double mu_f, double eps_v) {
   if (nf > 0) {
     ALLOC(c, pb->fids, 16LL * nf);
     ALLOC(c, pb->f64, 64LL * nf);
-    ALLOC(c, pb->fgk, 52LL * nf);
+    ALLOC(c, pb->fgk, 104LL * nf);
     ALLOC(c, pb->fx0, 24LL * pb->N);
     HIPCHK(c, hipMemcpyAsync(pb->fids.p, pb->cids.p, 16LL * nf, hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipMemcpyAsync(pb->fx0.p, pb->x.p, 24LL * pb->N, hipMemcpyDeviceToDevice, s));
@@ -536,10 +535,8 @@ bf_status size_constraint_buffers(bf_problem* pb, int n_pt, int n_ee) {
   const long long cap = (long long)pb->nnzb_e + 6LL * np;
   const long long capc = (long long)pb->nnzb_e - N + 6LL * np + 16;
   ALLOC(c, pb->lin64, 64LL * n + 64);
-  ALLOC(c, pb->cn, 12LL * n + 16);
-  ALLOC(c, pb->cw, 16LL * n + 16);
-  ALLOC(c, pb->cg, 4LL * n + 16);
-  ALLOC(c, pb->ch, 4LL * n + 16);
+  ALLOC(c, pb->cg, 8LL * n + 16);
+  ALLOC(c, pb->ch, 8LL * n + 16);
   ALLOC(c, pb->viol_part, 8LL * (div_up(n, kBlock) + 1));
   ALLOC(c, pb->vcnt, 4LL * (N + 1));
   ALLOC(c, pb->vptr, 4LL * (N + 1));
@@ -559,7 +556,7 @@ bf_status size_constraint_buffers(bf_problem* pb, int n_pt, int n_ee) {
   ALLOC(c, pb->row_ptr, 4LL * (N + 1));
   ALLOC(c, pb->col, 4LL * cap);
   ALLOC(c, pb->eslot, 4LL * cap);
-  ALLOC(c, pb->vals, 36LL * cap);
+  ALLOC(c, pb->vals, 72LL * cap);   // FP64 assembled blocks
   ALLOC(c, pb->lcnt, 4LL * (N + 1));
   ALLOC(c, pb->lptr, 4LL * (N + 1));
   ALLOC(c, pb->lsrc, 4LL * cap);
@@ -576,7 +573,7 @@ bf_status size_constraint_buffers(bf_problem* pb, int n_pt, int n_ee) {
   const long long N4 = (N + 3) & ~3LL;
   ALLOC(c, pb->grad, 12LL * N);
   ALLOC(c, pb->Lf, 24LL * N4);
-  ALLOC(c, pb->Linv, 24LL * N4);
+  ALLOC(c, pb->Linv, 48LL * N4);   // FP64 L^{-1} per node (6 entries)
   ALLOC(c, pb->bhat, 12LL * N4);
   ALLOC(c, pb->bb_part, 8LL * (div_up(N, kBlock) + 1));
   ALLOC(c, pb->xs, 24LL * N4);   // FP64 solution
@@ -681,7 +678,7 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
                     o->check_every, true, s);
     bf_status r0 = run_solve(S, false);
     if (r0 != BF_OK) return r0;
-    launch_pcg_finish(S, pb->Linv.as<float>(), pb->pout.as<double>(), pb->viol_part.as<double>(), nviol, s);
+    launch_pcg_finish(S, pb->Linv.as<double>(), pb->pout.as<double>(), pb->viol_part.as<double>(), nviol, s);
   } else {
     // Flexible CG on the FP32-stored system in FP64 vectors (the refinement):
     // every sweep forms the true residual r = b_hat - H_hat x in FP64, solves
@@ -768,7 +765,7 @@ bf_status bf_newton_step(bf_problem* pb, const bf_solve_opts* o, double* p_out, 
       ++sweeps;
     }
     pb->host_sc->bb = bb;
-    launch_pcg_finish64(S, pb->Linv.as<float>(), pb->xd.as<double>(), pb->pout.as<double>(),
+    launch_pcg_finish64(S, pb->Linv.as<double>(), pb->xd.as<double>(), pb->pout.as<double>(),
                         pb->viol_part.as<double>(), nviol, s);
   }
   HIPCHK(c, hipEventRecord(pb->ev[4], s));
@@ -883,12 +880,12 @@ bf_status bf_get_pattern(bf_problem* pb, int32_t* row_ptr, int32_t* col, int32_t
   return BF_OK;
 }
 
-bf_status bf_get_blocks(bf_problem* pb, float* vals) {
+bf_status bf_get_blocks(bf_problem* pb, double* vals) {
   if (!pb) return BF_ERR_INVALID_ARG;
   bf_context* c = pb->ctx;
   if (!vals) return fail(c, BF_ERR_INVALID_ARG, "vals is NULL");
   if (!pb->stepped) return fail(c, BF_ERR_STATE, "no Newton step has been run");
-  HIPCHK(c, hipMemcpyAsync(vals, pb->vals.p, 36LL * pb->nnzb_last, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(vals, pb->vals.p, 72LL * pb->nnzb_last, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return BF_OK;
 }
@@ -984,11 +981,11 @@ bf_status bf_mu_init(bf_problem* pb, double C, double* mu_out) {
   // the elastic Hessian at x, the state the time step starts from, into the
   // staging buffer (the next Newton step overwrites it)
   launch_elastic(pb->tets.as<int4>(), T, pb->rest.as<double>(), pb->x.as<double>(), pb->Dminv9.as<double>(),
-                 pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), (float)(pb->dt * pb->dt),
-                 pb->epos.as<int>(), pb->staging.as<float>(), pb->has_mat ? pb->mat.as<int>() : nullptr, flags, s);
+                 pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), pb->dt * pb->dt,
+                 pb->epos.as<int>(), pb->staging.as<double>(), pb->has_mat ? pb->mat.as<int>() : nullptr, flags, s);
   const int np = diag_max_parts(N);
   ALLOC(c, pb->epart, 8LL * (np + 8));
-  launch_diag_max(N, pb->erow_ptr.as<int>(), pb->ecptr.as<int>(), pb->staging.as<float>(), pb->mass.as<float>(),
+  launch_diag_max(N, pb->erow_ptr.as<int>(), pb->ecptr.as<int>(), pb->staging.as<double>(), pb->mass.as<double>(),
                   pb->epart.as<double>(), s);
   std::vector<double> hp(np);
   HIPCHK(c, hipMemcpyAsync(hp.data(), pb->epart.p, 8LL * np, hipMemcpyDeviceToHost, s));

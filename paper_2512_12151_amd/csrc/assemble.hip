@@ -39,40 +39,42 @@ __device__ inline int find_slot(const int* __restrict__ col, int lo, int hi, int
 // Friction contact fi at vertex slot a of its stencil t, into row r's
 // diagonal d, gradient g and upper blocks.
 __device__ inline void add_friction(int fi, int a, const int4& t, int r, int o, int n, int n_f,
-                                    const float* __restrict__ fgk, const int* __restrict__ col, float* vals,
-                                    float d[6], float g[3]) {
-  float K[6], w[4];
+                                    const double* __restrict__ fgk, const int* __restrict__ col, double* vals,
+                                    double d[6], double g[3]) {
+  double K[6], w[4];
 #pragma unroll
   for (int k = 0; k < 6; ++k) K[k] = fgk[(3LL + k) * n_f + fi];
 #pragma unroll
   for (int k = 0; k < 4; ++k) w[k] = fgk[(9LL + k) * n_f + fi];
-  const float wa = w[a];
+  const double wa = w[a];
 #pragma unroll
   for (int k = 0; k < 3; ++k) g[k] += wa * fgk[(long long)k * n_f + fi];
-  const float saa = wa * wa;
+  const double saa = wa * wa;
 #pragma unroll
   for (int k = 0; k < 6; ++k) d[k] += saa * K[k];
   for (int b = 0; b < 4; ++b) {
     const int vb = vtx(t, b);
     if (b == a || vb < r) continue;
     const int s = find_slot(col, o + 1, o + n - 1, vb);
-    const float sab = wa * w[b];
-    float* v = vals + 9LL * s;
+    const double sab = wa * w[b];
+    double* v = vals + 9LL * s;
     v[0] += sab * K[0]; v[1] += sab * K[1]; v[2] += sab * K[2];
     v[3] += sab * K[1]; v[4] += sab * K[3]; v[5] += sab * K[4];
     v[6] += sab * K[2]; v[7] += sab * K[4]; v[8] += sab * K[5];
   }
 }
 
+// All sums, the factor L and the right-hand side in FP64; the blocks stay
+// FP64 (vals) until the sliced storage rounds the scaled ones once.
 __global__ void __launch_bounds__(kBlock)
 k_assemble_rows(int N, const int* __restrict__ row_ptr, const int* __restrict__ col, const int* __restrict__ eslot,
-                const int* __restrict__ ecptr, const float* __restrict__ staging, const int* __restrict__ vptr,
-                const int* __restrict__ vinc, const int4* __restrict__ ids, int n_c, const float* __restrict__ cn,
-                const float* __restrict__ cw, const float* __restrict__ cg, const float* __restrict__ ch, int n_f,
-                const float* __restrict__ fgk, const int* __restrict__ cfr, const int* __restrict__ fext,
-                const float* __restrict__ mass, const double* __restrict__ xh, const double* __restrict__ xt,
-                const uint8_t* __restrict__ fixed, float* __restrict__ vals, float* __restrict__ grad,
-                float* __restrict__ Lf, float* __restrict__ Linv, float* __restrict__ bhat,
+                const int* __restrict__ ecptr, const double* __restrict__ staging, const int* __restrict__ vptr,
+                const int* __restrict__ vinc, const int4* __restrict__ ids, int n_c, const double* __restrict__ lin64,
+                const double* __restrict__ cg, const double* __restrict__ ch, int n_f,
+                const double* __restrict__ fgk, const int* __restrict__ cfr, const int* __restrict__ fext,
+                const double* __restrict__ mass, const double* __restrict__ xh, const double* __restrict__ xt,
+                const uint8_t* __restrict__ fixed, double* __restrict__ vals, float* __restrict__ grad,
+                float* __restrict__ Lf, double* __restrict__ Linv, float* __restrict__ bhat,
                 double* __restrict__ bb_part, int* flags) {
   __shared__ double red[kBlock / kWave];
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -80,11 +82,11 @@ k_assemble_rows(int N, const int* __restrict__ row_ptr, const int* __restrict__ 
   if (r < N) {
     const int o = row_ptr[r], n = row_ptr[r + 1] - o;
     // diagonal: elastic sum (symmetric 6 + gradient 3 per contribution)
-    float d[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, g[3] = {0.f, 0.f, 0.f};
+    double d[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, g[3] = {0.0, 0.0, 0.0};
     {
       const int es = eslot[o];
       for (int j = ecptr[es]; j < ecptr[es + 1]; ++j) {
-        const float* s = staging + 9LL * j;
+        const double* s = staging + 9LL * j;
 #pragma unroll
         for (int k = 0; k < 6; ++k) d[k] += s[k];
 #pragma unroll
@@ -93,24 +95,24 @@ k_assemble_rows(int N, const int* __restrict__ row_ptr, const int* __restrict__ 
     }
     // off-diagonal elastic sums
     for (int j = 1; j < n; ++j) {
-      float b[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      double b[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       const int es = eslot[o + j];
       if (es >= 0) {
         for (int q = ecptr[es]; q < ecptr[es + 1]; ++q) {
-          const float* s = staging + 9LL * q;
+          const double* s = staging + 9LL * q;
 #pragma unroll
           for (int k = 0; k < 9; ++k) b[k] += s[k];
         }
       }
-      float* v = vals + 9LL * (o + j);
+      double* v = vals + 9LL * (o + j);
 #pragma unroll
       for (int k = 0; k < 9; ++k) v[k] = b[k];
     }
     // inertia
-    const float m = mass[r];
+    const double m = mass[r];
     d[0] += m; d[3] += m; d[5] += m;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) g[k] += m * (float)(xh[3LL * r + k] - xt[3LL * r + k]);
+    for (int k = 0; k < 3; ++k) g[k] += m * (xh[3LL * r + k] - xt[3LL * r + k]);
     // AL contact terms of the incident constraints, then friction terms
     for (int j = vptr[r]; j < vptr[r + 1]; ++j) {
       const int ci = vinc[j] >> 2, a = vinc[j] & 3;
@@ -123,20 +125,22 @@ k_assemble_rows(int N, const int* __restrict__ row_ptr, const int* __restrict__ 
         const int fi = cfr[ci];
         if (fi >= 0) add_friction(fi, a, t, r, o, n, n_f, fgk, col, vals, d, g);
       }
-      const float n0 = cn[ci], n1 = cn[n_c + ci], n2 = cn[2LL * n_c + ci];
-      const float w[4] = {cw[ci], cw[n_c + ci], cw[2LL * n_c + ci], cw[3LL * n_c + ci]};
-      const float gf = cg[ci], hf = ch[ci];
-      const float wa = w[a];
+      // normal n and weights w from the linearization (SoA rows 1-3 and 4-7)
+      const double n0 = lin64[1LL * n_c + ci], n1 = lin64[2LL * n_c + ci], n2 = lin64[3LL * n_c + ci];
+      const double w[4] = {lin64[4LL * n_c + ci], lin64[5LL * n_c + ci], lin64[6LL * n_c + ci],
+                           lin64[7LL * n_c + ci]};
+      const double gf = cg[ci], hf = ch[ci];
+      const double wa = w[a];
       g[0] += gf * wa * n0; g[1] += gf * wa * n1; g[2] += gf * wa * n2;
-      const float saa = hf * wa * wa;
+      const double saa = hf * wa * wa;
       d[0] += saa * n0 * n0; d[1] += saa * n0 * n1; d[2] += saa * n0 * n2;
       d[3] += saa * n1 * n1; d[4] += saa * n1 * n2; d[5] += saa * n2 * n2;
       for (int b = 0; b < 4; ++b) {
         const int vb = vtx(t, b);
         if (b == a || vb < r) continue;
         const int s = find_slot(col, o + 1, o + n - 1, vb);
-        const float sab = hf * wa * w[b];
-        float* v = vals + 9LL * s;
+        const double sab = hf * wa * w[b];
+        double* v = vals + 9LL * s;
         v[0] += sab * n0 * n0; v[1] += sab * n0 * n1; v[2] += sab * n0 * n2;
         v[3] += sab * n1 * n0; v[4] += sab * n1 * n1; v[5] += sab * n1 * n2;
         v[6] += sab * n2 * n0; v[7] += sab * n2 * n1; v[8] += sab * n2 * n2;
@@ -145,49 +149,49 @@ k_assemble_rows(int N, const int* __restrict__ row_ptr, const int* __restrict__ 
     // moving-boundary elimination
     const bool fr = fixed[r] != 0;
     if (fr) {
-      g[0] = g[1] = g[2] = 0.f;
-      d[1] = d[2] = d[4] = 0.f;
+      g[0] = g[1] = g[2] = 0.0;
+      d[1] = d[2] = d[4] = 0.0;
     }
     for (int j = 1; j < n; ++j) {
       if (fr || fixed[col[o + j]]) {
-        float* v = vals + 9LL * (o + j);
+        double* v = vals + 9LL * (o + j);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) v[k] = 0.f;
+        for (int k = 0; k < 9; ++k) v[k] = 0.0;
       }
     }
-    float* v = vals + 9LL * o;
+    double* v = vals + 9LL * o;
     v[0] = d[0]; v[1] = d[1]; v[2] = d[2];
     v[3] = d[1]; v[4] = d[3]; v[5] = d[4];
     v[6] = d[2]; v[7] = d[4]; v[8] = d[5];
-    grad[3LL * r] = g[0]; grad[3LL * r + 1] = g[1]; grad[3LL * r + 2] = g[2];
-    bb = (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
+    grad[3LL * r] = (float)g[0]; grad[3LL * r + 1] = (float)g[1]; grad[3LL * r + 2] = (float)g[2];
+    bb = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
     // Cholesky D = L L^T and M = L^{-1} (both lower triangular, 6 entries)
-    const float q00 = d[0];
-    bool ok = q00 > 0.f;
-    const float L00 = ok ? sqrtf(q00) : 1.f;
-    const float L10 = d[1] / L00, L20 = d[2] / L00;
-    const float q11 = d[3] - L10 * L10;
-    ok = ok && q11 > 0.f;
-    const float L11 = q11 > 0.f ? sqrtf(q11) : 1.f;
-    const float L21 = (d[4] - L20 * L10) / L11;
-    const float q22 = d[5] - L20 * L20 - L21 * L21;
-    ok = ok && q22 > 0.f;
-    const float L22 = q22 > 0.f ? sqrtf(q22) : 1.f;
+    const double q00 = d[0];
+    bool ok = q00 > 0.0;
+    const double L00 = ok ? sqrt(q00) : 1.0;
+    const double L10 = d[1] / L00, L20 = d[2] / L00;
+    const double q11 = d[3] - L10 * L10;
+    ok = ok && q11 > 0.0;
+    const double L11 = q11 > 0.0 ? sqrt(q11) : 1.0;
+    const double L21 = (d[4] - L20 * L10) / L11;
+    const double q22 = d[5] - L20 * L20 - L21 * L21;
+    ok = ok && q22 > 0.0;
+    const double L22 = q22 > 0.0 ? sqrt(q22) : 1.0;
     if (!ok) atomicOr(flags, FLAG_NOT_SPD);
-    const float M00 = 1.f / L00, M11 = 1.f / L11, M22 = 1.f / L22;
-    const float M10 = -L10 * M00 * M11;
-    const float M21 = -L21 * M11 * M22;
-    const float M20 = -(L20 * M00 + L21 * M10) * M22;
-    // L as SoA [6][N4] for the solver's residual check
+    const double M00 = 1.0 / L00, M11 = 1.0 / L11, M22 = 1.0 / L22;
+    const double M10 = -L10 * M00 * M11;
+    const double M21 = -L21 * M11 * M22;
+    const double M20 = -(L20 * M00 + L21 * M10) * M22;
+    // L as FP32 SoA [6][N4] for the solver's residual norm
     const long long N4 = (N + 3) & ~3;
-    Lf[r] = L00; Lf[N4 + r] = L10; Lf[2 * N4 + r] = L11; Lf[3 * N4 + r] = L20; Lf[4 * N4 + r] = L21;
-    Lf[5 * N4 + r] = L22;
-    float* li = Linv + 6LL * r;
+    Lf[r] = (float)L00; Lf[N4 + r] = (float)L10; Lf[2 * N4 + r] = (float)L11; Lf[3 * N4 + r] = (float)L20;
+    Lf[4 * N4 + r] = (float)L21; Lf[5 * N4 + r] = (float)L22;
+    double* li = Linv + 6LL * r;
     li[0] = M00; li[1] = M10; li[2] = M11; li[3] = M20; li[4] = M21; li[5] = M22;
-    // b_hat = L^{-1} b with b = -G
-    bhat[3LL * r] = -(M00 * g[0]);
-    bhat[3LL * r + 1] = -(M10 * g[0] + M11 * g[1]);
-    bhat[3LL * r + 2] = -(M20 * g[0] + M21 * g[1] + M22 * g[2]);
+    // b_hat = L^{-1} b with b = -G, rounded once to FP32
+    bhat[3LL * r] = (float)(-(M00 * g[0]));
+    bhat[3LL * r + 1] = (float)(-(M10 * g[0] + M11 * g[1]));
+    bhat[3LL * r + 2] = (float)(-(M20 * g[0] + M21 * g[1] + M22 * g[2]));
   }
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) bb += __shfl_xor(bb, off, kWave);
@@ -218,11 +222,11 @@ __global__ void k_lower_fill(int N, const int* __restrict__ row_ptr, const int* 
   }
 }
 
-__device__ inline void scaled_block(const float* __restrict__ mr, const float* __restrict__ b,
-                                    const float* __restrict__ mc, float out[3][3]) {
-  const float R[3][3] = {{mr[0], 0.f, 0.f}, {mr[1], mr[2], 0.f}, {mr[3], mr[4], mr[5]}};
-  const float Cm[3][3] = {{mc[0], 0.f, 0.f}, {mc[1], mc[2], 0.f}, {mc[3], mc[4], mc[5]}};
-  float T1[3][3];
+__device__ inline void scaled_block(const double* __restrict__ mr, const double* __restrict__ b,
+                                    const double* __restrict__ mc, double out[3][3]) {
+  const double R[3][3] = {{mr[0], 0.0, 0.0}, {mr[1], mr[2], 0.0}, {mr[3], mr[4], mr[5]}};
+  const double Cm[3][3] = {{mc[0], 0.0, 0.0}, {mc[1], mc[2], 0.0}, {mc[3], mc[4], mc[5]}};
+  double T1[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -271,7 +275,7 @@ __global__ void k_slice_widths(int N, int nslices, const int* __restrict__ row_p
 // off-diagonal block, FP32 row-major 9 floats per slot, and when blk16 is set a
 // BF16 copy (10 half-words packed two per word, the last one zero).
 __global__ void k_sell_upper(int N, int nslices, const int* __restrict__ row_ptr, const int* __restrict__ col,
-                             const float* __restrict__ vals, const float* __restrict__ Linv,
+                             const double* __restrict__ vals, const double* __restrict__ Linv,
                              const int* __restrict__ sbu, float* __restrict__ blk, uint32_t* __restrict__ blk16,
                              int* __restrict__ scol) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -280,16 +284,22 @@ __global__ void k_sell_upper(int N, int nslices, const int* __restrict__ row_ptr
   const int base = sbu[sl], wu = (sbu[sl + 1] - base) / kSlice;
   const int o = r < N ? row_ptr[r] : 0;
   const int nu = r < N ? row_ptr[r + 1] - o - 1 : 0;
-  const float* mr = Linv + 6LL * (r < N ? r : 0);
+  const double* mr = Linv + 6LL * (r < N ? r : 0);
   for (int k = 0; k < wu; ++k) {
     const long long e = base + (long long)k * kSlice + lane;
-    float h[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    double hd[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     int c = r < N ? r : N - 1;
     if (k < nu) {   // decreasing column order
       const int sk = o + nu - k;
       c = col[sk];
-      scaled_block(mr, vals + 9LL * sk, Linv + 6LL * c, h);
+      scaled_block(mr, vals + 9LL * sk, Linv + 6LL * c, hd);
     }
+    // the scaled block rounded once to FP32 (and from there to BF16)
+    float h[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) h[i][m] = (float)hd[i][m];
     float* d = blk + 9 * e;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -345,13 +355,13 @@ __global__ void k_row_diag_slots(int N, const int* __restrict__ row_ptr, int* di
 }  // namespace
 
 void launch_assemble_rows(int N, const int* row_ptr, const int* col, const int* eslot, const int* ecptr,
-                          const float* staging, const int* vptr, const int* vinc, const int4* ids, int n_c,
-                          const float* cn, const float* cw, const float* cg, const float* ch, int n_f,
-                          const float* fgk, const int* cfr, const int* fext, const float* mass, const double* xh,
-                          const double* xt, const uint8_t* fixed, float* vals, float* grad, float* Lf, float* Linv,
-                          float* bhat, double* bb_part, int* flags, hipStream_t s) {
+                          const double* staging, const int* vptr, const int* vinc, const int4* ids, int n_c,
+                          const double* lin64, const double* cg, const double* ch, int n_f, const double* fgk,
+                          const int* cfr, const int* fext, const double* mass, const double* xh, const double* xt,
+                          const uint8_t* fixed, double* vals, float* grad, float* Lf, double* Linv, float* bhat,
+                          double* bb_part, int* flags, hipStream_t s) {
   hipLaunchKernelGGL(k_assemble_rows, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, eslot, ecptr,
-                     staging, vptr, vinc, ids, n_c, cn, cw, cg, ch, n_f, fgk, cfr, fext, mass, xh, xt, fixed, vals,
+                     staging, vptr, vinc, ids, n_c, lin64, cg, ch, n_f, fgk, cfr, fext, mass, xh, xt, fixed, vals,
                      grad, Lf, Linv, bhat, bb_part, flags);
 }
 
@@ -370,7 +380,7 @@ void launch_slice_widths(int N, int nslices, const int* row_ptr, const int* lptr
                      cl, wmax);
 }
 
-void launch_sell_fill(int N, int nslices, const int* row_ptr, const int* col, const float* vals, const float* Linv,
+void launch_sell_fill(int N, int nslices, const int* row_ptr, const int* col, const double* vals, const double* Linv,
                       const int* lptr, const int* lsrc, const int* sbu, const int* sbl, float* blk, uint32_t* blk16,
                       int* scol, int2* sent, hipStream_t s) {
   const int g = div_up((long long)nslices * kSlice, kBlock);

@@ -143,15 +143,17 @@ void launch_slot_count(const int* map, long long n, int* cnt, hipStream_t s);
 void launch_slot_fill(const int* map, long long n, const int* ptr, int* cursor, int* list, hipStream_t s);
 void launch_inverse_positions(const int* list, long long n, int* pos, hipStream_t s);
 void launch_mass(const int* ecptr, const int* elist, const int* erow_ptr, const float* vol,
-                 const double* rho, int N, float* mass, hipStream_t s);
+                 const double* rho, int N, double* mass, hipStream_t s);
 
 // contact.hip: per-step constraint work
 void launch_check_constraints(const int4* ids, int n_c, int N, const double* lam, const double* gam,
                               int* flags, hipStream_t s);
-// lin64 receives the FP64 linearization, SoA [8][n_c]: d, n (3), w (4).
+// lin64 receives the linearization, SoA [8][n_c]: d, n (3), w (4); cg and ch
+// the gradient factor kappa gamma (c - lambda / kappa - s) and the Hessian
+// factor kappa gamma of each constraint.
 void launch_contact_lin(const int4* ids, int n_pt, int n_c, const double* x, const double* xh,
                         const double* lam, const double* gam, double kappa, double delta,
-                        float* cn, float* cw, float* cg, float* ch, double* lin64, double* viol_part, int* flags,
+                        double* cg, double* ch, double* lin64, double* viol_part, int* flags,
                         hipStream_t s);
 void launch_vertex_incidence_count(const int4* ids, int n_c, int* cnt, hipStream_t s);
 void launch_vertex_incidence_fill(const int4* ids, int n_c, const int* ptr, int* cursor, int* inc,
@@ -227,18 +229,18 @@ void launch_inversion_bound(int T, const int4* tets, const double* x, const doub
 void launch_blend(int n3, double* x, const double* xh, double alpha, hipStream_t s);
 void launch_velocity(int n3, const double* x, const double* x0, double inv_h, double* v, hipStream_t s);
 int diag_max_parts(int N);
-void launch_diag_max(int N, const int* erow_ptr, const int* ecptr, const float* staging, const float* mass,
+void launch_diag_max(int N, const int* erow_ptr, const int* ecptr, const double* staging, const double* mass,
                      double* part, hipStream_t s);
 void launch_dual_update(const int4* ids, int n_c, const double* lin64, const double* xlin, const double* xh,
                         double kappa, double delta, double decay, double* lam, double* gam, double* part,
                         hipStream_t s);
 
 // contact.hip: semi-implicit friction (capture at x^t into FP64 SoA [8][n_f];
-// per-step terms at x_hat into FP32 SoA [13][n_f])
+// per-step terms at x_hat into FP64 SoA [13][n_f])
 void launch_friction_capture(const int4* ids, int n_pt, int n_f, const double* x, const double* lam, double kappa,
                              double delta, double mu_f, double* f64, hipStream_t s);
 void launch_friction_terms(const int4* ids, int n_f, const double* xh, const double* x0, const double* f64, double e,
-                           float* fgk, hipStream_t s);
+                           double* fgk, hipStream_t s);
 // Friction contact -> constraint with the same stencil: table insert of the
 // constraint rows (tab filled with -1 first, mask = capacity - 1), match
 // (cfr[ci] = fi, cfr filled with -1 first; extra[fi] = 1 when unmatched), and
@@ -251,16 +253,16 @@ void launch_friction_extra(const int4* fids, int n_f, const int* extra, const in
 
 // elastic.hip
 void launch_elastic(const int4* tets, int T, const double* rest, const double* xh, const double* Dminv9,
-                    const float* vol, const float* mu, const float* lam, float h2, const int* epos,
-                    float* staging, const int* mat, int* flags, hipStream_t s);
+                    const float* vol, const float* mu, const float* lam, double h2, const int* epos,
+                    double* staging, const int* mat, int* flags, hipStream_t s);
 
 // assemble.hip
 void launch_assemble_rows(int N, const int* row_ptr, const int* col, const int* eslot, const int* ecptr,
-                          const float* staging, const int* vptr, const int* vinc, const int4* ids, int n_c,
-                          const float* cn, const float* cw, const float* cg, const float* ch, int n_f,
-                          const float* fgk, const int* cfr, const int* fext, const float* mass, const double* xh,
-                          const double* xt, const uint8_t* fixed, float* vals, float* grad, float* Lf, float* Linv,
-                          float* bhat, double* bb_part, int* flags, hipStream_t s);
+                          const double* staging, const int* vptr, const int* vinc, const int4* ids, int n_c,
+                          const double* lin64, const double* cg, const double* ch, int n_f, const double* fgk,
+                          const int* cfr, const int* fext, const double* mass, const double* xh, const double* xt,
+                          const uint8_t* fixed, double* vals, float* grad, float* Lf, double* Linv, float* bhat,
+                          double* bb_part, int* flags, hipStream_t s);
 // Sliced storage of the scaled matrix: lower_count / lower_fill /
 // sort_segments give, per column, the source rows of its upper blocks;
 // slice_widths gives the slot counts per slice (64 x the widest row), whose
@@ -276,7 +278,7 @@ void launch_slice_widths(int N, int nslices, const int* row_ptr, const int* lptr
 // the slot arrays carry that much zeroed padding after their last slot.
 constexpr int kPairs = 2;
 inline long long slot_padding(int wmax_other) { return (long long)(wmax_other + kPairs + 1) * kSlice; }
-void launch_sell_fill(int N, int nslices, const int* row_ptr, const int* col, const float* vals, const float* Linv,
+void launch_sell_fill(int N, int nslices, const int* row_ptr, const int* col, const double* vals, const double* Linv,
                       const int* lptr, const int* lsrc, const int* sbu, const int* sbl, float* blk, uint32_t* blk16,
                       int* scol, int2* sent, hipStream_t s);
 void launch_row_diag_slots(int N, const int* row_ptr, int* diag, hipStream_t s);
@@ -306,7 +308,7 @@ void launch_pcg_iteration_batched(const PcgSystem* sys, const int* wg_sys_spmv, 
 // x += the directions the update kernel has not applied yet (before x is read).
 void launch_pcg_flush(const PcgSystem& S, hipStream_t s);
 // p = L^{-T} x in FP64 and the stats (max |p|, max violation).
-void launch_pcg_finish(const PcgSystem& S, const float* Linv, double* pout, const double* viol_part, int nviol,
+void launch_pcg_finish(const PcgSystem& S, const double* Linv, double* pout, const double* viol_part, int nviol,
                        hipStream_t s);
 // Iterative refinement around BF16 inner solves: rd = b_hat - H_hat xd in FP64
 // with the FP32 blocks (S.blk must be the FP32 storage), partials of |L rd|^2
@@ -326,7 +328,7 @@ void launch_dots64(int n3, const double* a, const double* const* b, int nb, doub
                    hipStream_t s);
 void launch_axpy_d(int n3, double alpha, const double* x, double* y, hipStream_t s);
 void launch_copy_f2d(int n3, const float* x, double* y, hipStream_t s);
-void launch_pcg_finish64(const PcgSystem& S, const float* Linv, const double* xd, double* pout,
+void launch_pcg_finish64(const PcgSystem& S, const double* Linv, const double* xd, double* pout,
                          const double* viol_part, int nviol, hipStream_t s);
 
 }  // namespace bfal

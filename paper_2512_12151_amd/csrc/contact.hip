@@ -125,8 +125,7 @@ __global__ void k_check_constraints(const int4* __restrict__ ids, int n_c, int N
 __global__ void __launch_bounds__(kBlock)
 k_contact_lin(const int4* __restrict__ ids, int n_pt, int n_c, const double* __restrict__ x,
               const double* __restrict__ xh, const double* __restrict__ lam, const double* __restrict__ gam,
-              double kappa, double delta, float* __restrict__ cn, float* __restrict__ cw,
-              float* __restrict__ cg, float* __restrict__ ch, double* __restrict__ lin64,
+              double kappa, double delta, double* __restrict__ cg, double* __restrict__ ch, double* __restrict__ lin64,
               double* __restrict__ viol_part, int* flags) {
   __shared__ double red[kBlock / kWave];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -141,9 +140,7 @@ k_contact_lin(const int4* __restrict__ ids, int n_pt, int n_c, const double* __r
     const double d = sqrt(dot(diff, diff));
     if (degenerate || !(d > 0.0)) {
       atomicOr(flags, FLAG_DEGENERATE);
-      cn[i] = cn[n_c + i] = cn[2LL * n_c + i] = 0.f;
-      cw[i] = cw[n_c + i] = cw[2LL * n_c + i] = cw[3LL * n_c + i] = 0.f;
-      cg[i] = ch[i] = 0.f;
+      cg[i] = ch[i] = 0.0;
       for (int m = 0; m < 8; ++m) lin64[(long long)m * n_c + i] = 0.0;
     } else {
       const d3 n = mul(diff, 1.0 / d);
@@ -154,11 +151,9 @@ k_contact_lin(const int4* __restrict__ ids, int n_pt, int n_c, const double* __r
       const double s = fmax(0.0, c - l / kappa);                 // slack
       const double gfac = kappa * g * (c - l / kappa - s);       // zero when s > 0
       viol = fmax(0.0, -c);
-      cn[i] = (float)n.x; cn[n_c + i] = (float)n.y; cn[2LL * n_c + i] = (float)n.z;
-      cw[i] = (float)w0; cw[n_c + i] = (float)w1; cw[2LL * n_c + i] = (float)w2; cw[3LL * n_c + i] = (float)w3;
-      cg[i] = (float)gfac;
-      ch[i] = (float)(kappa * g);
-      // the FP64 linearization, for the energy and the multiplier update: SoA [8][n]
+      cg[i] = gfac;
+      ch[i] = kappa * g;
+      // the linearization, for the assembly, the energy and the multiplier update: SoA [8][n]
       const double lv[8] = {d, n.x, n.y, n.z, w0, w1, w2, w3};
 #pragma unroll
       for (int m = 0; m < 8; ++m) lin64[(long long)m * n_c + i] = lv[m];
@@ -442,12 +437,11 @@ k_friction_capture(const int4* __restrict__ ids, int n_pt, int n_f, const double
 // f_1(y)/y = 1/y and f_1' = 0 for y >= e, 2/e - y/e^2 and 2/e - 2y/e^2 below.
 // Its eigenvalues coef f_1/y (tangent, across t), coef f_1' (along t) and 0
 // (normal) are never negative, so the SPD projection leaves it unchanged.
-// Computed in FP64, stored FP32 SoA [13][n_f]: gradient (3), Hessian (6:
-// xx xy xz yy yz zz), weights (4).
+// FP64 SoA [13][n_f]: gradient (3), Hessian (6: xx xy xz yy yz zz), weights (4).
 __global__ void __launch_bounds__(kBlock)
 k_friction_terms(const int4* __restrict__ ids, int n_f, const double* __restrict__ xh,
                  const double* __restrict__ x0, const double* __restrict__ f64, double e,
-                 float* __restrict__ fgk) {
+                 double* __restrict__ fgk) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_f) return;
   const int4 t4 = ids[i];
@@ -468,17 +462,17 @@ k_friction_terms(const int4* __restrict__ ids, int n_f, const double* __restrict
   const double g[3] = {coef * f1y * u.x, coef * f1y * u.y, coef * f1y * u.z};
   const double nn[3] = {n.x, n.y, n.z}, tv[3] = {tt.x, tt.y, tt.z};
   const int ri[6] = {0, 0, 0, 1, 1, 2}, ci[6] = {0, 1, 2, 1, 2, 2};
-  float out[13];
+  double out[13];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) out[k] = (float)g[k];
+  for (int k = 0; k < 3; ++k) out[k] = g[k];
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     const int r = ri[k], c = ci[k];
     const double P = (r == c ? 1.0 : 0.0) - nn[r] * nn[c];
-    out[3 + k] = (float)(coef * (f1y * P + (f1p - f1y) * tv[r] * tv[c]));
+    out[3 + k] = coef * (f1y * P + (f1p - f1y) * tv[r] * tv[c]);
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a) out[9 + a] = (float)fv[3 + a];
+  for (int a = 0; a < 4; ++a) out[9 + a] = fv[3 + a];
 #pragma unroll
   for (int m = 0; m < 13; ++m) fgk[(long long)m * n_f + i] = out[m];
 }
@@ -493,11 +487,11 @@ void launch_check_constraints(const int4* ids, int n_c, int N, const double* lam
 }
 
 void launch_contact_lin(const int4* ids, int n_pt, int n_c, const double* x, const double* xh, const double* lam,
-                        const double* gam, double kappa, double delta, float* cn, float* cw, float* cg, float* ch,
-                        double* lin64, double* viol_part, int* flags, hipStream_t s) {
+                        const double* gam, double kappa, double delta, double* cg, double* ch, double* lin64,
+                        double* viol_part, int* flags, hipStream_t s) {
   if (n_c > 0)
     hipLaunchKernelGGL(k_contact_lin, dim3(div_up(n_c, kBlock)), dim3(kBlock), 0, s, ids, n_pt, n_c, x, xh, lam,
-                       gam, kappa, delta, cn, cw, cg, ch, lin64, viol_part, flags);
+                       gam, kappa, delta, cg, ch, lin64, viol_part, flags);
 }
 
 void launch_vertex_incidence_count(const int4* ids, int n_c, int* cnt, hipStream_t s) {
@@ -561,7 +555,7 @@ void launch_friction_extra(const int4* fids, int n_f, const int* extra, const in
 }
 
 void launch_friction_terms(const int4* ids, int n_f, const double* xh, const double* x0, const double* f64, double e,
-                           float* fgk, hipStream_t s) {
+                           double* fgk, hipStream_t s) {
   if (n_f > 0)
     hipLaunchKernelGGL(k_friction_terms, dim3(div_up(n_f, kBlock)), dim3(kBlock), 0, s, ids, n_f, xh, x0, f64, e,
                        fgk);

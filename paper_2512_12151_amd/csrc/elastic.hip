@@ -1,11 +1,10 @@
 // Hyperelastic element kernel (Neo-Hookean, stable Neo-Hookean or corotated
 // linear per tet): one thread per tet.
 //
-// Per tet it forms G = F - I and the stress P in FP64 (from the FP64
+// Per tet it forms, all in FP64, G = F - I and the stress P (from the FP64
 // displacement differences and the FP64 rows of D_m^{-1}), the element
-// gradient h^2 V P A_a^T (rounded to FP32 at the end), and, in FP32, the ten
-// upper 3x3 blocks of the SPD-projected element Hessian by the vertex-block
-// identity of Section 5.1:
+// gradient h^2 V P A_a^T, and the ten upper 3x3 blocks of the SPD-projected
+// element Hessian by the vertex-block identity of Section 5.1:
 //
 //   H_ab = h^2 V  U [ sum_k omega_k^+ D_k (A_a V)^T (A_b V) D_k^T ] U^T
 //
@@ -15,8 +14,15 @@
 // diag(e_k)), three twist and three flip modes (D = (E_ij -+ E_ji)/sqrt 2).
 // Exploiting the sparsity of D_k, the bracket is the Hadamard product of the
 // projected 3x3 scaling Hessian with (A_a V)^T (A_b V), plus four terms per
-// singular-value pair.  Blocks are written to the fixed assembly order
-// (staging position of each (tet, pair)), so no atomics touch the matrix.
+// singular-value pair.  Blocks are written in FP64 to the fixed assembly
+// order (staging position of each (tet, pair)), so no atomics touch the
+// matrix.  The Hessian is FP64 because the blocks of one element sum to zero
+// along every row and column (A_0 = -(A_1 + A_2 + A_3)): the assembled
+// matrix leaves rigid translations to inertia and contact alone, and
+// rounding each element's blocks to FP32 breaks that cancellation by about
+// 1e-7 of the element stiffness, which on a stiff, finely meshed scene is a
+// large relative error in those soft directions.  The row sums assemble the
+// FP64 blocks and round the finished matrix once.
 //
 // Energies (readings of the paper, which names its materials in Table 2
 // without printing them); the first two are Psi = mu/2 (tr F^T F - 3) + g(J):
@@ -52,36 +58,36 @@ __constant__ int c_pb[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
 
 // Cyclic Jacobi eigen-decomposition of a symmetric 3x3 matrix (A is destroyed).
 // On return A's diagonal holds the eigenvalues and V's columns the eigenvectors.
-__device__ inline void jacobi3(float A[3][3], float V[3][3]) {
+__device__ inline void jacobi3(double A[3][3], double V[3][3]) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? 1.f : 0.f;
-  for (int sweep = 0; sweep < 8; ++sweep) {
-    const float off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
-    const float dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
-    if (off <= 1e-14f * dia || off == 0.f) break;
+    for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 10; ++sweep) {
+    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (off <= 1e-32 * dia || off == 0.0) break;
 #pragma unroll
     for (int pq = 0; pq < 3; ++pq) {
       const int p = pq == 2 ? 1 : 0;
       const int q = pq == 0 ? 1 : 2;
-      const float apq = A[p][q];
-      if (apq == 0.f) continue;
-      const float theta = (A[q][q] - A[p][p]) / (2.f * apq);
-      const float t = copysignf(1.f, theta) / (fabsf(theta) + sqrtf(theta * theta + 1.f));
-      const float c = 1.f / sqrtf(t * t + 1.f), s = t * c;
+      const double apq = A[p][q];
+      if (apq == 0.0) continue;
+      const double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+      const double t = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
       const int r = 3 - p - q;
-      const float arp = A[r][p], arq = A[r][q];
+      const double arp = A[r][p], arq = A[r][q];
       A[p][p] -= t * apq;
       A[q][q] += t * apq;
-      A[p][q] = A[q][p] = 0.f;
-      A[r][p] = A[p][r] = c * arp - s * arq;
-      A[r][q] = A[q][r] = s * arp + c * arq;
+      A[p][q] = A[q][p] = 0.0;
+      A[r][p] = A[p][r] = c * arp - sn * arq;
+      A[r][q] = A[q][r] = sn * arp + c * arq;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const float vkp = V[k][p], vkq = V[k][q];
-        V[k][p] = c * vkp - s * vkq;
-        V[k][q] = s * vkp + c * vkq;
+        const double vkp = V[k][p], vkq = V[k][q];
+        V[k][p] = c * vkp - sn * vkq;
+        V[k][q] = sn * vkp + c * vkq;
       }
     }
   }
@@ -104,25 +110,20 @@ __device__ inline void cof3d(const double M[3][3], double C[3][3]) {
   C[2][2] = M[0][0] * M[1][1] - M[0][1] * M[1][0];
 }
 
-__device__ inline float det3(const float M[3][3]) {
-  return M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
-         M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
-}
-
 // Rotation-preserving SVD F = U diag(S) V^T with det U = det V = +1 (S[2]
 // carries the sign of det F).  V from the Jacobi eigenvectors of F^T F, U and
 // S from a Givens QR of F V (McAdams et al. 2011, "Computing the singular
 // value decomposition of 3x3 matrices with minimal branching and elementary
 // floating point operations", steps: symmetric eigenanalysis, sorting, QR).
-__device__ inline void svd3(const float F[3][3], float U[3][3], float S[3], float V[3][3]) {
-  float A[3][3];
+__device__ inline void svd3(const double F[3][3], double U[3][3], double S[3], double V[3][3]) {
+  double A[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) A[i][j] = F[0][i] * F[0][j] + F[1][i] * F[1][j] + F[2][i] * F[2][j];
-  float W[3][3];
+  double W[3][3];
   jacobi3(A, W);
-  float ev[3] = {A[0][0], A[1][1], A[2][2]};
+  const double ev[3] = {A[0][0], A[1][1], A[2][2]};
   int o[3] = {0, 1, 2};
   // sort eigenvalues descending
   if (ev[o[0]] < ev[o[1]]) { int t = o[0]; o[0] = o[1]; o[1] = t; }
@@ -132,33 +133,33 @@ __device__ inline void svd3(const float F[3][3], float U[3][3], float S[3], floa
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int k = 0; k < 3; ++k) V[i][k] = W[i][o[k]];
-  if (det3(V) < 0.f) {
+  if (det3d(V) < 0.0) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) V[i][2] = -V[i][2];
   }
-  float B[3][3];
+  double B[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int k = 0; k < 3; ++k) B[i][k] = F[i][0] * V[0][k] + F[i][1] * V[1][k] + F[i][2] * V[2][k];
   // Q^T accumulates the Givens rotations: Q^T B = R
-  float Qt[3][3] = {{1.f, 0.f, 0.f}, {0.f, 1.f, 0.f}, {0.f, 0.f, 1.f}};
+  double Qt[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
   const int gi[3] = {0, 0, 1}, gj[3] = {1, 2, 2}, gc[3] = {0, 0, 1};
 #pragma unroll
   for (int g = 0; g < 3; ++g) {
     const int i = gi[g], j = gj[g], col = gc[g];
-    const float a = B[i][col], b = B[j][col];
-    const float r = sqrtf(a * a + b * b);
-    float c = 1.f, s = 0.f;
-    if (r > 0.f) { c = a / r; s = b / r; }
+    const double a = B[i][col], b = B[j][col];
+    const double r = sqrt(a * a + b * b);
+    double c = 1.0, sn = 0.0;
+    if (r > 0.0) { c = a / r; sn = b / r; }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const float bi = B[i][k], bj = B[j][k];
-      B[i][k] = c * bi + s * bj;
-      B[j][k] = -s * bi + c * bj;
-      const float qi = Qt[i][k], qj = Qt[j][k];
-      Qt[i][k] = c * qi + s * qj;
-      Qt[j][k] = -s * qi + c * qj;
+      const double bi = B[i][k], bj = B[j][k];
+      B[i][k] = c * bi + sn * bj;
+      B[j][k] = -sn * bi + c * bj;
+      const double qi = Qt[i][k], qj = Qt[j][k];
+      Qt[i][k] = c * qi + sn * qj;
+      Qt[j][k] = -sn * qi + c * qj;
     }
   }
 #pragma unroll
@@ -169,7 +170,7 @@ __device__ inline void svd3(const float F[3][3], float U[3][3], float S[3], floa
   // make S[0], S[1] non-negative, pushing signs into column 2 to keep det U = +1
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    if (S[k] < 0.f) {
+    if (S[k] < 0.0) {
       S[k] = -S[k]; S[2] = -S[2];
 #pragma unroll
       for (int i = 0; i < 3; ++i) { U[i][k] = -U[i][k]; U[i][2] = -U[i][2]; }
@@ -180,13 +181,13 @@ __device__ inline void svd3(const float F[3][3], float U[3][3], float S[3], floa
 __global__ void __launch_bounds__(kBlock)
 k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest, const double* __restrict__ xh,
           const double* __restrict__ Dminv9, const float* __restrict__ vol, const float* __restrict__ mu_,
-          const float* __restrict__ lam_, float h2, const int* __restrict__ epos, float* __restrict__ staging,
+          const float* __restrict__ lam_, double h2, const int* __restrict__ epos, double* __restrict__ staging,
           const int* __restrict__ mat, int* flags) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= T) return;
   const int4 t = tets[e];
   const int v[4] = {t.x, t.y, t.z, t.w};
-  // G = F - I in FP64 from the displacement differences and the FP64 rows of D_m^{-1}
+  // G = F - I from the displacement differences and the rows of D_m^{-1}
   double u0[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) u0[i] = xh[3LL * v[0] + i] - rest[3LL * v[0] + i];
@@ -200,110 +201,95 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) Dm[i][j] = Dminv9[(long long)(3 * i + j) * T + e];
-  double Gd[3][3], Fd[3][3];
-  float F[3][3];
+  double Gd[3][3], F[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       Gd[i][j] = Du[i][0] * Dm[0][j] + Du[i][1] * Dm[1][j] + Du[i][2] * Dm[2][j];
-      Fd[i][j] = Gd[i][j] + (i == j ? 1.0 : 0.0);
-      F[i][j] = (float)Fd[i][j];
+      F[i][j] = Gd[i][j] + (i == j ? 1.0 : 0.0);
     }
-  // C - I = G + G^T + G^T G (the strain, FP64)
+  // C - I = G + G^T + G^T G (the strain)
   double CmI[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       CmI[i][j] = Gd[i][j] + Gd[j][i] + Gd[0][i] * Gd[0][j] + Gd[1][i] * Gd[1][j] + Gd[2][i] * Gd[2][j];
-  const double trGd = Gd[0][0] + Gd[1][1] + Gd[2][2];
-  double trG2d = 0.0;
+  const double trG = Gd[0][0] + Gd[1][1] + Gd[2][2];
+  double trG2 = 0.0;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) trG2d += Gd[i][j] * Gd[j][i];
-  const double Jm1d = trGd + 0.5 * (trGd * trGd - trG2d) + det3d(Gd);
-  const double Jd = 1.0 + Jm1d;
-  const float Jm1 = (float)Jm1d;
-  const float J = (float)Jd;
-  const float w = h2 * vol[e];
+    for (int j = 0; j < 3; ++j) trG2 += Gd[i][j] * Gd[j][i];
+  const double Jm1 = trG + 0.5 * (trG * trG - trG2) + det3d(Gd);
+  const double J = 1.0 + Jm1;
+  const double w = h2 * (double)vol[e];
   const long long pbase = 10LL * e;
-  if (!(Jd > 0.0) || !(J > 0.f)) {
+  if (!(J > 0.0)) {
     atomicOr(flags, FLAG_INVERTED);
     for (int k = 0; k < 10; ++k) {
-      float* o = staging + 9LL * epos[pbase + k];
+      double* o = staging + 9LL * epos[pbase + k];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) o[q] = 0.f;
+      for (int q = 0; q < 9; ++q) o[q] = 0.0;
     }
     return;
   }
-  const float mu = mu_[e], lam = lam_[e];
-  const double mud = mu, lamd = lam;
+  const double mu = mu_[e], lam = lam_[e];
   const int code = mat != nullptr ? mat[e] : 0;
-  // rows A_a (A_1..A_3 = rows of Dm^{-1}, A_0 = -their sum): FP64 for the
-  // gradient, FP32 for the Hessian blocks
-  double Ad[4][3];
-  float A[4][3];
+  // rows A_a (A_1..A_3 = rows of Dm^{-1}, A_0 = -their sum)
+  double A[4][3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    Ad[1][j] = Dm[0][j]; Ad[2][j] = Dm[1][j]; Ad[3][j] = Dm[2][j];
-    Ad[0][j] = -(Dm[0][j] + Dm[1][j] + Dm[2][j]);
+    A[1][j] = Dm[0][j]; A[2][j] = Dm[1][j]; A[3][j] = Dm[2][j];
+    A[0][j] = -(Dm[0][j] + Dm[1][j] + Dm[2][j]);
   }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) A[a][j] = (float)Ad[a][j];
   // SVD, then per material the stress, the 3x3 Hessian in the singular values
   // (Ah) and the twist / flip eigenvalues of the pairs (0,1), (0,2), (1,2)
-  float U[3][3], S[3], V[3][3];
+  double U[3][3], S[3], V[3][3];
   svd3(F, U, S, V);
   const int pi[3] = {0, 0, 1}, pj[3] = {1, 2, 2};
-  double Pd[3][3];
-  float Ah[3][3], wt[3], wf[3];
+  double P[3][3], Ah[3][3], wt[3], wf[3];
   bool clamp;
   if (code == 2) {
     // corotated linear: Psi = mu sum (S_k - 1)^2 + lam/2 (sum S_k - 3)^2.  S_k - 1 without
-    // cancellation: e_k = S_k^2 - 1 is the Rayleigh quotient of F^T F - I (FP64) along V_k
-    // (stationary in V_k, so the FP32 singular vectors suffice), and S_k - 1 = e_k / (1 + sqrt(1 + e_k)).
-    double dd[3];
-    float d[3];
+    // cancellation: e_k = S_k^2 - 1 is the Rayleigh quotient of F^T F - I along V_k
+    // (stationary in V_k), and S_k - 1 = e_k / (1 + sqrt(1 + e_k)).
+    double d[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       double ek = 0.0;
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) ek += (double)V[i][k] * CmI[i][j] * (double)V[j][k];
-      dd[k] = ek / (1.0 + sqrt(fmax(1.0 + ek, 0.0)));
-      d[k] = (float)dd[k];
+        for (int j = 0; j < 3; ++j) ek += V[i][k] * CmI[i][j] * V[j][k];
+      d[k] = ek / (1.0 + sqrt(fmax(1.0 + ek, 0.0)));
     }
-    const double tr = dd[0] + dd[1] + dd[2];
+    const double tr = d[0] + d[1] + d[2];
     double dpsi[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) dpsi[k] = 2.0 * mud * dd[k] + lamd * tr;
+    for (int k = 0; k < 3; ++k) dpsi[k] = 2.0 * mu * d[k] + lam * tr;
     // P = U diag(dPsi/dS) V^T = 2 mu (F - R) + lam tr(S - I) R
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j)
-        Pd[i][j] = (double)U[i][0] * dpsi[0] * V[j][0] + (double)U[i][1] * dpsi[1] * V[j][1] +
-                   (double)U[i][2] * dpsi[2] * V[j][2];
+        P[i][j] = U[i][0] * dpsi[0] * V[j][0] + U[i][1] * dpsi[1] * V[j][1] + U[i][2] * dpsi[2] * V[j][2];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) Ah[i][j] = (i == j ? 2.f * mu : 0.f) + lam;
-    clamp = lam < 0.f;   // 2 mu I + lam 1 1^T is PSD for lam >= 0
+      for (int j = 0; j < 3; ++j) Ah[i][j] = (i == j ? 2.0 * mu : 0.0) + lam;
+    clamp = lam < 0.0;   // 2 mu I + lam 1 1^T is PSD for lam >= 0
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int i = pi[k], j = pj[k];
-      wt[k] = (float)((dpsi[i] + dpsi[j]) / (2.0 + dd[i] + dd[j]));
-      wf[k] = 2.f * mu;   // (dPsi_i - dPsi_j) / (S_i - S_j)
+      wt[k] = (dpsi[i] + dpsi[j]) / (2.0 + d[i] + d[j]);
+      wf[k] = 2.0 * mu;   // (dPsi_i - dPsi_j) / (S_i - S_j)
     }
   } else {
     double C[3][3];
-    cof3d(Fd, C);
-    float q, r, rq;
+    cof3d(F, C);
+    double q, r, rq;
     if (code == 1) {
       double Cg[3][3];
       cof3d(Gd, Cg);
@@ -311,24 +297,23 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-          Pd[i][j] = mud * (Gd[i][j] + Gd[j][i] - (i == j ? trGd : 0.0) - Cg[i][j]) + lamd * Jm1d * C[i][j];
+          P[i][j] = mu * (Gd[i][j] + Gd[j][i] - (i == j ? trG : 0.0) - Cg[i][j]) + lam * Jm1 * C[i][j];
       q = J * (lam * Jm1 - mu);
       r = lam * J * J;
       rq = r + q;
     } else {
-      const double lnJd = log1p(Jm1d);
-      const float lnJ = (float)lnJd;
+      const double lnJ = log1p(Jm1);
       // P = F^{-T} Sp with Sp = mu (C - I) + lam lnJ I; F^{-T} = cof(F) / J
       double Sp[3][3];
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) Sp[i][j] = mud * CmI[i][j] + (i == j ? lamd * lnJd : 0.0);
-      const double iJ = 1.0 / Jd;
+        for (int j = 0; j < 3; ++j) Sp[i][j] = mu * CmI[i][j] + (i == j ? lam * lnJ : 0.0);
+      const double iJ = 1.0 / J;
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) Pd[i][j] = (C[i][0] * Sp[0][j] + C[i][1] * Sp[1][j] + C[i][2] * Sp[2][j]) * iJ;
+        for (int j = 0; j < 3; ++j) P[i][j] = (C[i][0] * Sp[0][j] + C[i][1] * Sp[1][j] + C[i][2] * Sp[2][j]) * iJ;
       q = lam * lnJ - mu;
       r = mu + lam - lam * lnJ;
       rq = lam;
@@ -338,36 +323,36 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
 #pragma unroll
       for (int j = 0; j < 3; ++j) Ah[i][j] = (i == j) ? mu + r / (S[i] * S[i]) : rq / (S[i] * S[j]);
     // Ah = mu I + diag(1/S) (-q I + (r + q) 1 1^T) diag(1/S) is PSD when -q >= 0 and r + q >= 0
-    clamp = q > 0.f || rq < 0.f;
+    clamp = q > 0.0 || rq < 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const float ss = S[pi[k]] * S[pj[k]];
+      const double ss = S[pi[k]] * S[pj[k]];
       wt[k] = mu + q / ss;
       wf[k] = mu - q / ss;
     }
   }
   if (clamp) {
     // Ah may be indefinite: clamp its eigenvalues
-    float E3[3][3], Q[3][3];
+    double E3[3][3], Q[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) E3[i][j] = Ah[i][j];
     jacobi3(E3, Q);
-    const float l0 = fmaxf(E3[0][0], 0.f), l1 = fmaxf(E3[1][1], 0.f), l2 = fmaxf(E3[2][2], 0.f);
+    const double l0 = fmax(E3[0][0], 0.0), l1 = fmax(E3[1][1], 0.0), l2 = fmax(E3[2][2], 0.0);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) Ah[i][j] = l0 * Q[i][0] * Q[j][0] + l1 * Q[i][1] * Q[j][1] + l2 * Q[i][2] * Q[j][2];
   }
-  float c1[3], c2[3];
+  double c1[3], c2[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const float t = fmaxf(wt[k], 0.f), f = fmaxf(wf[k], 0.f);
-    c1[k] = 0.5f * (t + f);
-    c2[k] = 0.5f * (f - t);
+    const double tk = fmax(wt[k], 0.0), fk = fmax(wf[k], 0.0);
+    c1[k] = 0.5 * (tk + fk);
+    c2[k] = 0.5 * (fk - tk);
   }
-  float AV[4][3];
+  double AV[4][3];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -375,7 +360,7 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
 
   for (int pr = 0; pr < 10; ++pr) {
     const int a = c_pa[pr], b = c_pb[pr];
-    float Sm[3][3];
+    double Sm[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -388,7 +373,7 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
       Sm[i][j] += c2[k] * AV[a][j] * AV[b][i];
       Sm[j][i] += c2[k] * AV[a][i] * AV[b][j];
     }
-    float T1[3][3], Hb[3][3];
+    double T1[3][3], Hb[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -397,18 +382,17 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) Hb[i][j] = w * (T1[i][0] * U[j][0] + T1[i][1] * U[j][1] + T1[i][2] * U[j][2]);
-    float* o = staging + 9LL * epos[pbase + pr];
+    double* o = staging + 9LL * epos[pbase + pr];
     if (a == b) {
       // symmetric diagonal block: 6 entries, then the vertex gradient h^2 V P A_a^T
       o[0] = Hb[0][0];
-      o[1] = 0.5f * (Hb[0][1] + Hb[1][0]);
-      o[2] = 0.5f * (Hb[0][2] + Hb[2][0]);
+      o[1] = 0.5 * (Hb[0][1] + Hb[1][0]);
+      o[2] = 0.5 * (Hb[0][2] + Hb[2][0]);
       o[3] = Hb[1][1];
-      o[4] = 0.5f * (Hb[1][2] + Hb[2][1]);
+      o[4] = 0.5 * (Hb[1][2] + Hb[2][1]);
       o[5] = Hb[2][2];
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
-        o[6 + i] = (float)((double)w * (Pd[i][0] * Ad[a][0] + Pd[i][1] * Ad[a][1] + Pd[i][2] * Ad[a][2]));
+      for (int i = 0; i < 3; ++i) o[6 + i] = w * (P[i][0] * A[a][0] + P[i][1] * A[a][1] + P[i][2] * A[a][2]);
     } else if (v[a] < v[b]) {
 #pragma unroll
       for (int i = 0; i < 3; ++i)
@@ -426,7 +410,7 @@ k_elastic(const int4* __restrict__ tets, int T, const double* __restrict__ rest,
 }  // namespace
 
 void launch_elastic(const int4* tets, int T, const double* rest, const double* xh, const double* Dminv9,
-                    const float* vol, const float* mu, const float* lam, float h2, const int* epos, float* staging,
+                    const float* vol, const float* mu, const float* lam, double h2, const int* epos, double* staging,
                     const int* mat, int* flags, hipStream_t s) {
   if (T > 0)
     hipLaunchKernelGGL(k_elastic, dim3(div_up(T, kBlock)), dim3(kBlock), 0, s, tets, T, rest, xh, Dminv9, vol, mu,

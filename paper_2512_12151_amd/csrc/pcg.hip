@@ -634,15 +634,15 @@ k_init_scalars(const double* __restrict__ bb_part, int nbb, PcgScalars* sc, doub
 // p = L^{-T} x in FP64 (x FP32 or FP64, AoS [N4][3]) and the per-workgroup max |p|.
 template <class XT>
 __global__ void __launch_bounds__(kVecBlock)
-k_finish(int N, int N4, const float* __restrict__ Linv, const XT* __restrict__ x, double* __restrict__ pout,
+k_finish(int N, int N4, const double* __restrict__ Linv, const XT* __restrict__ x, double* __restrict__ pout,
          double* __restrict__ part) {
   double m = 0.0;
   for (int v = blockIdx.x * kVecBlock + threadIdx.x; v < N; v += gridDim.x * kVecBlock) {
-    const float* l = Linv + 6LL * v;
+    const double* l = Linv + 6LL * v;
     const double x0 = x[3LL * v], x1 = x[3LL * v + 1], x2 = x[3LL * v + 2];
-    const double p0 = (double)l[0] * x0 + (double)l[1] * x1 + (double)l[3] * x2;
-    const double p1 = (double)l[2] * x1 + (double)l[4] * x2;
-    const double p2 = (double)l[5] * x2;
+    const double p0 = l[0] * x0 + l[1] * x1 + l[3] * x2;
+    const double p1 = l[2] * x1 + l[4] * x2;
+    const double p2 = l[5] * x2;
     pout[3LL * v] = p0;
     pout[3LL * v + 1] = p1;
     pout[3LL * v + 2] = p2;
@@ -938,7 +938,7 @@ void launch_pcg_iteration_batched(const PcgSystem* sys, const int* wg_sys_spmv, 
   hipLaunchKernelGGL(k_update_batched, dim3(nwg_vec), dim3(kVecBlock), 0, s, sys, wg_sys_vec);
 }
 
-void launch_pcg_finish(const PcgSystem& S, const float* Linv, double* pout, const double* viol_part, int nviol,
+void launch_pcg_finish(const PcgSystem& S, const double* Linv, double* pout, const double* viol_part, int nviol,
                        hipStream_t s) {
   const int g = pcg_vec_groups(S.N);
   launch_pcg_flush(S, s);
@@ -994,7 +994,7 @@ void launch_axpy64(const PcgSystem& S, double* xd, hipStream_t s) {
   hipLaunchKernelGGL(k_axpy64, dim3(S.vec_nwg), dim3(kVecBlock), 0, s, 3 * S.N4, (const double*)S.x, xd);
 }
 
-void launch_pcg_finish64(const PcgSystem& S, const float* Linv, const double* xd, double* pout,
+void launch_pcg_finish64(const PcgSystem& S, const double* Linv, const double* xd, double* pout,
                          const double* viol_part, int nviol, hipStream_t s) {
   const int g = pcg_vec_groups(S.N);
   double* part = S.part + kPartPQ;

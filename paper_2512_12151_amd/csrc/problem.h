@@ -43,7 +43,7 @@ struct bf_problem {
   DevBuf fids, f64, fx0, fgk, pids;
   DevBuf ftab, cfr, fextra, fpos, fext;   // per step: friction contact <-> constraint with the same stencil
   // per-step buffers
-  DevBuf cn, cw, cg, ch, viol_part;
+  DevBuf cg, ch, viol_part;   // AL factors per constraint (FP64)
   DevBuf vcnt, vptr, vinc;
   DevBuf ccount, cptr, cand, ucount, row_ptr, col, eslot;
   DevBuf vals, grad, Lf, Linv, bhat, bb_part, lcnt, lptr, lsrc, sbu, sbl, sblk, sblk16, scol, sent;

@@ -258,7 +258,7 @@ void retire(bf_server* sv, int si, const int* stat) {
   std::string msg;
   const int n = pb->n_c;
   pb->ctx = c;
-  launch_pcg_finish(sl.S, pb->Linv.as<float>(), pb->pout.as<double>(), pb->viol_part.as<double>(),
+  launch_pcg_finish(sl.S, pb->Linv.as<double>(), pb->pout.as<double>(), pb->viol_part.as<double>(),
                     div_up(n, kBlock) > 0 ? div_up(n, kBlock) : 1, s);
   r->p.resize(3LL * pb->N);
   int nnzb = 0;

@@ -164,7 +164,7 @@ __global__ void k_inverse_positions(const int* __restrict__ list, long long n, i
 // exactly the (tet, local diagonal pair) entries of its incident tets.
 __global__ void k_mass(const int* __restrict__ ecptr, const int* __restrict__ elist,
                        const int* __restrict__ erow_ptr, const float* __restrict__ vol,
-                       const double* __restrict__ rho, int N, float* mass) {
+                       const double* __restrict__ rho, int N, double* mass) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
   const int d = erow_ptr[v];
@@ -173,7 +173,7 @@ __global__ void k_mass(const int* __restrict__ ecptr, const int* __restrict__ el
     const int e = elist[j] / 10;
     m += rho[e] * (double)vol[e] * 0.25;
   }
-  mass[v] = (float)m;
+  mass[v] = m;
 }
 
 }  // namespace
@@ -227,7 +227,7 @@ void launch_inverse_positions(const int* list, long long n, int* pos, hipStream_
 }
 
 void launch_mass(const int* ecptr, const int* elist, const int* erow_ptr, const float* vol, const double* rho,
-                 int N, float* mass, hipStream_t s) {
+                 int N, double* mass, hipStream_t s) {
   hipLaunchKernelGGL(k_mass, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, ecptr, elist, erow_ptr, vol, rho, N,
                      mass);
 }

@@ -265,21 +265,21 @@ k_dual_update(const int4* __restrict__ ids, int n_c, const double* __restrict__ 
 // workgroup: the diagonal block of row r is the sum of its staging range (the
 // static pattern holds the diagonal first in each row), plus the lumped mass.
 __global__ void __launch_bounds__(kEBlock)
-k_diag_max(int N, const int* __restrict__ erow_ptr, const int* __restrict__ ecptr, const float* __restrict__ staging,
-           const float* __restrict__ mass, double* __restrict__ part) {
+k_diag_max(int N, const int* __restrict__ erow_ptr, const int* __restrict__ ecptr, const double* __restrict__ staging,
+           const double* __restrict__ mass, double* __restrict__ part) {
   const int r = blockIdx.x * kEBlock + threadIdx.x;
   double m = 0.0;
   if (r < N) {
     const int es = erow_ptr[r];
-    float d0 = 0.f, d1 = 0.f, d2 = 0.f;
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
     for (int j = ecptr[es]; j < ecptr[es + 1]; ++j) {
-      const float* st = staging + 9LL * j;   // symmetric 6 (xx, xy, xz, yy, yz, zz), then the gradient
+      const double* st = staging + 9LL * j;   // symmetric 6 (xx, xy, xz, yy, yz, zz), then the gradient
       d0 += st[0];
       d1 += st[3];
       d2 += st[5];
     }
-    const float mv = mass[r];
-    m = (double)fmaxf(fmaxf(d0 + mv, d1 + mv), d2 + mv);
+    const double mv = mass[r];
+    m = fmax(fmax(d0 + mv, d1 + mv), d2 + mv);
   }
   __shared__ double red[kEBlock / kWave];
 #pragma unroll
@@ -321,7 +321,7 @@ int energy_parts(int T, int n_c, int n_f) { return div_up(T, kEBlock) + div_up(n
 
 int diag_max_parts(int N) { return div_up(N, kEBlock); }
 
-void launch_diag_max(int N, const int* erow_ptr, const int* ecptr, const float* staging, const float* mass,
+void launch_diag_max(int N, const int* erow_ptr, const int* ecptr, const double* staging, const double* mass,
                      double* part, hipStream_t s) {
   hipLaunchKernelGGL(k_diag_max, dim3(div_up(N, kEBlock)), dim3(kEBlock), 0, s, N, erow_ptr, ecptr, staging, mass,
                      part);

@@ -5,10 +5,10 @@ FP64 oracle assembled at full size (about a minute of CPU).
 Bars: the merged BSR pattern and its maps bit-exact; the FP32 gradient and
 blocks within 1e-5 relative, globally and per node / per block against the
 summed magnitude of their terms (term_scales.py), also with the constraint set
-emptied (the elastic and inertia terms alone); the returned step within the
-FP64 solver's own error at the same tolerance, in the energy norm of the
-oracle's H against the oracle's reference solution (tests/golden/
-large_p_ref.npy: FP64 block-Jacobi PCG to 1e-12); its residual, measured in
+emptied (the elastic and inertia terms alone); the returned step within twice
+the FP64 solver's own error at the same tolerance plus the FP32-storage floor,
+in the energy norm of the oracle's H against the oracle's reference solution
+(tests/golden/large_p_ref.npy: FP64 block-Jacobi PCG to 1e-12); its residual, measured in
 FP64 with the oracle's H, within 1.5e-5 of |G| (the PCG tolerance is 1e-5 on
 the FP32-stored system); the FP64 stats exact to rounding."""
 import json
@@ -127,9 +127,12 @@ def test_large_no_constraints_gradient_and_blocks():
                     reason="reference solution not written yet (tests/golden/make_large_reference.py)")
 def test_large_solution_energy_norm(large, gpu):
     """The step against the oracle's reference solution p* in the energy norm
-    of the oracle's FP64 H.  The bar is the FP64 oracle PCG's own error at the
-    same tolerance (x0 = 0, |r| <= 1e-5 |b|; recorded with p* by the script
-    that wrote it), doubled, plus 1e-5; both iteration counts are printed."""
+    of the oracle's FP64 H.  The bar adds what the two sides of the comparison
+    cannot avoid: the FP64 oracle PCG's own error at the same tolerance
+    (x0 = 0, |r| <= 1e-5 |b|), doubled for FP32 recurrences, and the distance
+    between p* and the exact solution of the FP32-stored system (a lower bound,
+    so the bar errs on the strict side); both recorded with p* by the script
+    that wrote it, from the oracle alone.  Iteration counts are printed."""
     sc, st = large
     with open(os.path.join(GOLDEN, "large_p_ref.json")) as f:
         meta = json.load(f)
@@ -137,10 +140,13 @@ def test_large_solution_energy_norm(large, gpu):
     p_ref = np.load(os.path.join(GOLDEN, "large_p_ref.npy")).astype(np.float64)
     err = oracle.energy_norm_rel(st.H, gpu["p"], p_ref)
     ref64 = meta["fp64_pcg_at_step_tol"]
+    floor32 = meta["float32_storage_floor"]["energy_norm_lower_bound"]
+    bar = 2.0 * ref64["energy_norm_error"] + floor32 + 1e-5
     print(f"large: energy-norm error {err:.3e} after {gpu['stats']['pcg_iters']} FP32 PCG iterations | FP64 "
           f"oracle PCG at tol {ref64['tol']:g}: {ref64['energy_norm_error']:.3e} after {ref64['iterations']} "
-          f"iterations | p* storage {meta['float32_storage_energy_norm_error']:.1e}", flush=True)
-    assert err <= 2.0 * ref64["energy_norm_error"] + 1e-5
+          f"iterations | FP32-storage floor >= {floor32:.2e} | bar {bar:.3e} | p* storage "
+          f"{meta['float32_storage_energy_norm_error']:.1e}", flush=True)
+    assert err <= bar
 
 
 @pytest.mark.timeout(600)
