@@ -1,8 +1,9 @@
 /* libbfal host rules: the parts of the library that need no device.
  *
  * Argument validation of the descriptors the device entry points take, the
- * penalty stall rule of the time step (Section 5.2) and the admission policy
- * of the serving engine.  bf_problem_create, bf_set_state,
+ * penalty stall rule of the time step (Section 5.2), the admission policy of
+ * the serving engine and the SpMV's plan of which wavefront takes which
+ * slice.  bf_problem_create, bf_set_state,
  * bf_set_constraints, bf_newton_step, bf_time_step and the bf_server_* calls
  * apply exactly these functions; they are exported so that a caller can apply
  * them ahead of a call (a serving front end validating a request before it
@@ -95,6 +96,30 @@ bf_status bf_admission_release(bf_admission* a, int32_t slot, uint64_t footprint
 uint64_t bf_admission_used(const bf_admission* a);
 int32_t bf_admission_waiting(const bf_admission* a);
 int32_t bf_admission_active(const bf_admission* a);
+
+/* ------------------------------------------------------ SpMV slice plan --
+ * Which slices of the sliced matrix storage each SpMV wavefront processes.
+ * The SpMV gives one 64-row slice at a time to a wavefront; its workgroups
+ * are spread over the device's 8 XCDs (accelerator complex dies), each with
+ * its own L2, workgroup w of `nparts / 4` on XCD w / (nparts / 32) and wave v
+ * of it taking part 4 w + v.  A slice's cost is ceil(max(wu, wl) / pairs) + 1
+ * steps, wu and wl its upper and lower slot widths ((slot_u[s+1] - slot_u[s])
+ * / 64 and the same for slot_l, the exclusive scans of 64 x the widths).
+ * The plan keeps the slices that are read together on one XCD and balances
+ * the parts: the slices are cut into rounds of nparts consecutive slices,
+ * each round into 8 consecutive windows of equal cost (window x to XCD x),
+ * and inside an XCD every slice, in increasing order, goes to the part with
+ * the least cost so far (the lowest index on ties).  Output as lists:
+ * part p takes wave_slices[wave_ptr[p] .. wave_ptr[p+1]), increasing.
+ *   nslices >= 1; slot_u, slot_l: [nslices + 1] nondecreasing multiples of 64;
+ *   pairs >= 1 (upper/lower pairs per SpMV step); nparts: a positive multiple
+ *   of 8; wave_ptr: [nparts + 1]; wave_slices: [nslices] (caller-owned).
+ * Returns BF_ERR_INVALID_ARG for a NULL array, a size out of range or slot
+ * offsets that are not nondecreasing multiples of 64 (nothing written then),
+ * BF_ERR_OOM if the host cannot allocate the per-part costs, else BF_OK.
+ * Every slice is listed exactly once. */
+bf_status bf_slice_plan(int32_t nslices, const int32_t* slot_u, const int32_t* slot_l, int32_t pairs,
+                        int32_t nparts, int32_t* wave_ptr, int32_t* wave_slices);
 
 #ifdef __cplusplus
 }

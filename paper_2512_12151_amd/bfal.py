@@ -169,6 +169,7 @@ _PROTOS = [
     ("bf_admission_used", C.c_uint64, [C.c_void_p]),
     ("bf_admission_waiting", C.c_int32, [C.c_void_p]),
     ("bf_admission_active", C.c_int32, [C.c_void_p]),
+    ("bf_slice_plan", C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
 ]
 
 EXPORTED = [p[0] for p in _PROTOS]
@@ -487,6 +488,19 @@ class StallRule:
         if fired < 0:
             raise BfalError(-1, "bf_stall_step: bad argument")
         return bool(fired), k.value, d.value
+
+
+def slice_plan(slot_u, slot_l, pairs, nparts):
+    """bf_slice_plan: (status, wave_ptr [nparts + 1], wave_slices [nslices]) for
+    the slot offsets slot_u, slot_l ([nslices + 1] each)."""
+    su = np.ascontiguousarray(slot_u, dtype=np.int32)
+    sl = np.ascontiguousarray(slot_l, dtype=np.int32)
+    n = len(su) - 1
+    ptr = np.full(max(int(nparts), 0) + 1, -7, np.int32)
+    out = np.full(max(n, 0), -7, np.int32)
+    st = lib().bf_slice_plan(int(n), su.ctypes.data, sl.ctypes.data, int(pairs), int(nparts), ptr.ctypes.data,
+                             out.ctypes.data)
+    return int(st), ptr, out
 
 
 class Admission:

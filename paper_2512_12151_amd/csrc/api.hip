@@ -267,13 +267,28 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
   launch_slice_widths(N, nslices, row_ptr, lptr, sbu, sbl, wmax, s);
   scan_exclusive(sbu, sbu, nslices, sbu + nslices, tmp, s);
   scan_exclusive(sbl, sbl, nslices, sbl + nslices, tmp, s);
+  // the slot offsets come to the host for the SpMV's slice plan (bf_slice_plan)
   int tot[4] = {0, 0, 0, 0};
-  HIPCHK(c, hipMemcpyAsync(&tot[0], sbu + nslices, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(&tot[1], sbl + nslices, sizeof(int), hipMemcpyDeviceToHost, s));
+  pb->h_sbu.resize(nslices + 1);
+  pb->h_sbl.resize(nslices + 1);
+  HIPCHK(c, hipMemcpyAsync(pb->h_sbu.data(), sbu, 4LL * (nslices + 1), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(pb->h_sbl.data(), sbl, 4LL * (nslices + 1), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipMemcpyAsync(&tot[2], wmax, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
+  tot[0] = pb->h_sbu[nslices];
+  tot[1] = pb->h_sbl[nslices];
   pb->nslot_u = tot[0];
   pb->nslot_l = tot[1];
+  const int nparts = kSpmvWaves * pcg_spmv_groups(N, c->num_cu);
+  pb->h_wptr.resize(nparts + 1);
+  pb->h_wsl.resize(nslices);
+  if (bf_slice_plan(nslices, pb->h_sbu.data(), pb->h_sbl.data(), kPairs, nparts, pb->h_wptr.data(),
+                    pb->h_wsl.data()) != BF_OK)
+    return fail(c, BF_ERR_INVALID_ARG, "the slice plan rejected the slot offsets");
+  ALLOC(c, pb->wplan_ptr, 4LL * (nparts + 1));
+  ALLOC(c, pb->wplan_sl, 4LL * nslices);
+  HIPCHK(c, hipMemcpyAsync(pb->wplan_ptr.p, pb->h_wptr.data(), 4LL * (nparts + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(pb->wplan_sl.p, pb->h_wsl.data(), 4LL * nslices, hipMemcpyHostToDevice, s));
   // slot arrays with the zero block (upper) and the SpMV's read-ahead padding
   const long long nu_alloc = tot[0] + slot_padding(tot[3]);
   const long long nl_alloc = tot[1] + slot_padding(tot[2]);
@@ -343,7 +358,8 @@ bf_status bf_footprint_bytes(int32_t n_nodes, int32_t n_tets, int32_t n_constrai
   b += N * 4 * 8 + C * 16 + cap * 4 * 2;           // incidence, candidates, pattern
   b += cap * (72 + 36 + 4 + 4 + 8 + 4);            // FP64 blocks, FP32 scaled blocks, ucol, eslot, transpose index, lsrc
   b += N * (12 * (4 + kPRing) + 24 + 24 + 48 + 24);   // grad, bhat, r, q, the direction ring, x, L, L^-1, p out
-  b += 1 << 20;                                    // partials, scalars, scan scratch
+  b += 1 << 20;                                    // partials, scalars, scan scratch, the SpMV slice plan
+  b += 4 * (N / 64 + 1);
   *out = b;
   return BF_OK;
 }
@@ -374,7 +390,7 @@ void bf_problem_destroy(bf_problem* pb) {
                     &pb->cg, &pb->ch, &pb->viol_part, &pb->vcnt, &pb->vptr, &pb->vinc, &pb->ccount, &pb->cptr,
                     &pb->cand, &pb->ucount, &pb->row_ptr, &pb->col, &pb->eslot, &pb->vals, &pb->grad, &pb->Lf,
                     &pb->Linv, &pb->bhat, &pb->bb_part, &pb->lcnt, &pb->lptr, &pb->lsrc, &pb->sbu, &pb->sbl,
-                    &pb->sblk, &pb->sblk16, &pb->scol, &pb->sent, &pb->xs, &pb->r, &pb->pring, &pb->q,
+                    &pb->wplan_ptr, &pb->wplan_sl,                    &pb->sblk, &pb->sblk16, &pb->scol, &pb->sent, &pb->xs, &pb->r, &pb->pring, &pb->q,
                     &pb->part, &pb->scal, &pb->pout, &pb->flags, &pb->scan_tmp, &pb->scratch_int,
                     &pb->xd, &pb->rd, &pb->zd, &pb->fcg, &pb->rpart, &pb->lin64, &pb->pdir, &pb->xtrial,
                     &pb->epart, &pb->stris, &pb->sedges, &pb->sverts, &pb->xq, &pb->tbox, &pb->tkey, &pb->tkey2,

@@ -84,6 +84,8 @@ struct PcgSystem {
   int N, N4, nslices;
   const int* sbu;    // [nslices + 1]
   const int* sbl;    // [nslices + 1]
+  const int* wave_ptr;     // SpMV slice plan (bf_slice_plan for 4 * spmv_nwg parts): part p takes
+  const int* wave_slices;  // wave_slices[wave_ptr[p] .. wave_ptr[p + 1])
   const int* scol;
   const void* blk;
   const int2* sent;
@@ -277,6 +279,7 @@ void launch_slice_widths(int N, int nslices, const int* row_ptr, const int* lptr
 // up to (max width + kPairs) * kSlice slots past the end of a slice's range;
 // the slot arrays carry that much zeroed padding after their last slot.
 constexpr int kPairs = 2;
+constexpr int kSpmvWaves = 4;   // wavefronts (slices in flight) per SpMV workgroup
 inline long long slot_padding(int wmax_other) { return (long long)(wmax_other + kPairs + 1) * kSlice; }
 void launch_sell_fill(int N, int nslices, const int* row_ptr, const int* col, const double* vals, const double* Linv,
                       const int* lptr, const int* lsrc, const int* sbu, const int* sbl, float* blk, uint32_t* blk16,

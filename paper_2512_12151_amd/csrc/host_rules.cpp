@@ -1,7 +1,7 @@
 // Host rules of libbfal (include/bfal_host.h): argument validation, the
-// penalty stall rule of Section 5.2 and the serving admission policy.  Plain
-// C++ without HIP, built with the host compiler, so the same object serves
-// the library and a CPU-only (sanitizer) build.
+// penalty stall rule of Section 5.2, the serving admission policy and the
+// SpMV's slice plan.  Plain C++ without HIP, built with the host compiler, so
+// the same object serves the library and a CPU-only (sanitizer) build.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -190,6 +190,63 @@ bf_status bf_admission_release(bf_admission* a, int32_t slot, uint64_t footprint
   a->slot_bytes[slot] = 0;
   a->used -= footprint;
   a->free_slots.push_back(slot);
+  return BF_OK;
+}
+
+bf_status bf_slice_plan(int32_t nslices, const int32_t* slot_u, const int32_t* slot_l, int32_t pairs,
+                        int32_t nparts, int32_t* wave_ptr, int32_t* wave_slices) {
+  if (!slot_u || !slot_l || !wave_ptr || !wave_slices || nslices < 1 || pairs < 1 || nparts < 8 || nparts % 8)
+    return BF_ERR_INVALID_ARG;
+  for (int32_t s = 0; s <= nslices; ++s)
+    if (slot_u[s] % 64 || slot_l[s] % 64 || (s > 0 && (slot_u[s] < slot_u[s - 1] || slot_l[s] < slot_l[s - 1])))
+      return BF_ERR_INVALID_ARG;
+  const int32_t per_x = nparts / 8;
+  std::vector<int64_t> load;
+  std::vector<int32_t> cost, part_of, cur;
+  try {
+    load.assign(nparts, 0);
+    cost.resize(nslices);
+    part_of.resize(nslices);
+    cur.resize(nparts);
+  } catch (...) {
+    return BF_ERR_OOM;
+  }
+  for (int32_t s = 0; s < nslices; ++s) {
+    const int32_t wu = (slot_u[s + 1] - slot_u[s]) / 64, wl = (slot_l[s + 1] - slot_l[s]) / 64;
+    const int32_t w = wu > wl ? wu : wl;
+    cost[s] = (w + pairs - 1) / pairs + 1;
+  }
+  for (int32_t r0 = 0; r0 < nslices; r0 += nparts) {
+    const int32_t r1 = r0 + nparts < nslices ? r0 + nparts : nslices;
+    int64_t tot = 0;
+    for (int32_t s = r0; s < r1; ++s) tot += cost[s];
+    // window x starts at the first slice whose cost prefix in the round reaches x / 8 of it
+    int32_t start[9];
+    start[0] = r0;
+    int32_t x = 1;
+    int64_t acc = 0;
+    for (int32_t s = r0; s < r1 && x < 8; ++s) {
+      while (x < 8 && 8 * acc >= x * tot) start[x++] = s;
+      acc += cost[s];
+    }
+    while (x < 8) start[x++] = r1;
+    start[8] = r1;
+    for (x = 0; x < 8; ++x) {
+      int64_t* lx = load.data() + (int64_t)x * per_x;
+      for (int32_t s = start[x]; s < start[x + 1]; ++s) {
+        int32_t best = 0;
+        for (int32_t p = 1; p < per_x; ++p)
+          if (lx[p] < lx[best]) best = p;
+        lx[best] += cost[s];
+        part_of[s] = x * per_x + best;
+      }
+    }
+  }
+  for (int32_t p = 0; p <= nparts; ++p) wave_ptr[p] = 0;
+  for (int32_t s = 0; s < nslices; ++s) ++wave_ptr[part_of[s] + 1];
+  for (int32_t p = 0; p < nparts; ++p) wave_ptr[p + 1] += wave_ptr[p];
+  for (int32_t p = 0; p < nparts; ++p) cur[p] = wave_ptr[p];
+  for (int32_t s = 0; s < nslices; ++s) wave_slices[cur[part_of[s]]++] = s;
   return BF_OK;
 }
 

@@ -69,6 +69,7 @@ namespace {
 
 constexpr int kSpmvBlock = 256;                    // threads per SpMV workgroup (4 slices)
 constexpr int kSlicesPerGroup = kSpmvBlock / kSlice;
+static_assert(kSlicesPerGroup == kSpmvWaves, "the slice plan's parts are the SpMV's wavefronts");
 constexpr int kVecBlock = 256;                     // threads per update workgroup (4 nodes per thread)
 
 // Sum of v over a workgroup of NT threads, returned to every thread (fixed shuffle/LDS order).
@@ -336,15 +337,21 @@ __device__ inline void accumulate_pairs(int ubase, int wu, int lbase, int wl, co
   }
 }
 
-// q = H_hat p_k for the slices of workgroup lb (of nwg) of one system; adds
-// this thread's shares of p^T q, r^T q and q^T q.
+// q = H_hat p_k for the slices the system's plan gives wave `threadIdx.x / 64`
+// of its workgroup lb (bf_slice_plan: on each XCD consecutive windows of
+// slices, balanced in cost across the waves); adds this thread's shares of
+// p^T q, r^T q and q^T q.  The next slice's number is loaded one slice ahead.
 template <class BT>
-__device__ inline void spmv_slices(const PcgSystem& S, int lb, int nwg, int k, double& pq, double& rq,
-                                   double& qq) {
+__device__ inline void spmv_slices(const PcgSystem& S, int lb, int k, double& pq, double& rq, double& qq) {
   const int wave = threadIdx.x / kSlice, lane = threadIdx.x % kSlice;
   const PView pv{S.P + (k % kPRing) * S.pstride};
   const BT* __restrict__ blk = static_cast<const BT*>(S.blk);
-  for (int sl = lb * kSlicesPerGroup + wave; sl < S.nslices; sl += nwg * kSlicesPerGroup) {
+  const int part = lb * kSlicesPerGroup + wave;
+  const int j0 = S.wave_ptr[part], j1 = S.wave_ptr[part + 1];
+  int sl_next = j0 < j1 ? S.wave_slices[j0] : 0;
+  for (int j = j0; j < j1; ++j) {
+    const int sl = sl_next;
+    sl_next = j + 1 < j1 ? S.wave_slices[j + 1] : 0;
     const int bu = S.sbu[sl], wu = (S.sbu[sl + 1] - bu) / kSlice;
     const int bl = S.sbl[sl], wl = (S.sbl[sl + 1] - bl) / kSlice;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
@@ -370,7 +377,7 @@ __global__ void __launch_bounds__(kSpmvBlock) k_spmv(PcgSystem S) {
   int k;
   if (!spmv_scalars(S, lb == 0 && threadIdx.x == 0, k)) return;
   double pq = 0.0, rq = 0.0, qq = 0.0;
-  spmv_slices<BT>(S, lb, gridDim.x, k, pq, rq, qq);
+  spmv_slices<BT>(S, lb, k, pq, rq, qq);
   block_sum3<kSpmvBlock>(pq, rq, qq);
   if (threadIdx.x == 0) {
     S.part[kPartPQ + lb] = pq;
@@ -388,7 +395,7 @@ __global__ void __launch_bounds__(kSpmvBlock) k_spmv_batched(const PcgSystem* __
   int k;
   if (!spmv_scalars(S, lb == 0 && threadIdx.x == 0, k)) return;
   double pq = 0.0, rq = 0.0, qq = 0.0;
-  spmv_slices<BT>(S, lb, S.spmv_nwg, k, pq, rq, qq);
+  spmv_slices<BT>(S, lb, k, pq, rq, qq);
   block_sum3<kSpmvBlock>(pq, rq, qq);
   if (threadIdx.x == 0) {
     S.part[kPartPQ + lb] = pq;

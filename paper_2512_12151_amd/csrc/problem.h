@@ -47,6 +47,8 @@ struct bf_problem {
   DevBuf vcnt, vptr, vinc;
   DevBuf ccount, cptr, cand, ucount, row_ptr, col, eslot;
   DevBuf vals, grad, Lf, Linv, bhat, bb_part, lcnt, lptr, lsrc, sbu, sbl, sblk, sblk16, scol, sent;
+  DevBuf wplan_ptr, wplan_sl;                  // the SpMV's slice plan of the current step
+  std::vector<int> h_sbu, h_sbl, h_wptr, h_wsl;  // host copies for planning (kept for the async upload)
   DevBuf xs, r, pring, q, part, scal, pout, flags, scan_tmp, scratch_int;
   DevBuf xd, rd, zd, fcg, rpart;   // refinement: FP64 solution, residual, inner solution, directions, partials
   DevBuf lin64;                    // FP64 linearization of the constraints, SoA [8][n]
@@ -125,6 +127,8 @@ inline PcgSystem system_of(bf_problem* pb) {
   S.nslices = div_up(pb->N, kSlice);
   S.sbu = pb->sbu.as<int>();
   S.sbl = pb->sbl.as<int>();
+  S.wave_ptr = pb->wplan_ptr.as<int>();
+  S.wave_slices = pb->wplan_sl.as<int>();
   S.scol = pb->scol.as<int>();
   S.blk = pb->sblk.p;
   S.sent = pb->sent.as<int2>();

@@ -113,6 +113,33 @@ int main() {
   EXPECT(bf_admission_active(a) >= 0 && bf_admission_waiting(a) >= 0);
   bf_admission_destroy(a);
   bf_admission_destroy(nullptr);
+  // slice plan: random widths, every slice listed once, lists increasing
+  for (int trial = 0; trial < 20; ++trial) {
+    seed = seed * 6364136223846793005ULL + 1442695040888963407ULL;
+    const int32_t ns = 1 + (int32_t)((seed >> 33) % 3000), nparts = 8 * (1 + (int32_t)((seed >> 20) % 64));
+    std::vector<int32_t> su(ns + 1, 0), sl(ns + 1, 0), ptr(nparts + 1), ws(ns);
+    for (int32_t s = 0; s < ns; ++s) {
+      seed = seed * 6364136223846793005ULL + 1442695040888963407ULL;
+      su[s + 1] = su[s] + 64 * (int32_t)((seed >> 40) % 20);
+      sl[s + 1] = sl[s] + 64 * (int32_t)((seed >> 50) % 20);
+    }
+    EXPECT(bf_slice_plan(ns, su.data(), sl.data(), 2, nparts, ptr.data(), ws.data()) == BF_OK);
+    std::vector<int> seen(ns, 0);
+    EXPECT(ptr[0] == 0 && ptr[nparts] == ns);
+    for (int32_t p = 0; p < nparts; ++p)
+      for (int32_t j = ptr[p]; j < ptr[p + 1]; ++j) {
+        EXPECT(ws[j] >= 0 && ws[j] < ns);
+        if (ws[j] >= 0 && ws[j] < ns) ++seen[ws[j]];
+        if (j > ptr[p]) EXPECT(ws[j] > ws[j - 1]);
+      }
+    for (int32_t s = 0; s < ns; ++s) EXPECT(seen[s] == 1);
+  }
+  {
+    std::vector<int32_t> su = {0, 64, 100}, sl = {0, 64, 128}, ptr(9), ws(2);
+    EXPECT(bf_slice_plan(2, su.data(), sl.data(), 2, 8, ptr.data(), ws.data()) == BF_ERR_INVALID_ARG);
+    EXPECT(bf_slice_plan(2, sl.data(), sl.data(), 2, 12, ptr.data(), ws.data()) == BF_ERR_INVALID_ARG);
+    EXPECT(bf_slice_plan(2, sl.data(), sl.data(), 2, 8, nullptr, ws.data()) == BF_ERR_INVALID_ARG);
+  }
   if (failures) return 1;
   std::printf("host rules: all checks passed\n");
   return 0;

@@ -239,3 +239,81 @@ def test_admission_release_is_checked():
     assert adm.release(0, 99) == INVALID      # not the footprint admitted there
     assert adm.release(0, 100) == OK
     assert adm.release(0, 100) == INVALID     # already free
+
+
+# ------------------------------------------------------------- slice plan
+
+def plan_reference(wu, wl, pairs, nparts):
+    """The plan restated in Python: rounds of nparts slices, eight windows of
+    equal cost per round (by the cost prefix), least-loaded part per XCD."""
+    cost = (np.maximum(wu, wl) + pairs - 1) // pairs + 1
+    ns, per_x = len(cost), nparts // 8
+    load = np.zeros(nparts, np.int64)
+    part_of = np.empty(ns, np.int64)
+    for r0 in range(0, ns, nparts):
+        r1 = min(ns, r0 + nparts)
+        c = cost[r0:r1]
+        before = np.concatenate([[0], np.cumsum(c)[:-1]])   # cost of the round's slices before each one
+        tot = int(c.sum())
+        win = [r0] + [r0 + int(np.argmax(8 * before >= x * tot)) if (8 * before >= x * tot).any() else r1
+                      for x in range(1, 8)] + [r1]
+        for x in range(8):
+            for s in range(win[x], win[x + 1]):
+                lx = load[x * per_x:(x + 1) * per_x]
+                b = int(np.argmin(lx))
+                lx[b] += cost[s]
+                part_of[s] = x * per_x + b
+    return part_of, load
+
+
+@pytest.mark.parametrize("ns,nparts,seed", [(1, 8, 0), (37, 32, 1), (700, 1024, 2), (6300, 1024, 3), (5000, 64, 4)])
+def test_slice_plan_lists_every_slice_once_in_its_window(ns, nparts, seed):
+    rng = np.random.default_rng(seed)
+    wu = rng.integers(0, 9, ns)
+    wl = rng.integers(0, 9, ns)
+    hot = rng.random(ns) < 0.05            # clustered wide (contact) slices
+    wu[hot] += 20
+    slot_u = np.concatenate([[0], np.cumsum(64 * wu)])
+    slot_l = np.concatenate([[0], np.cumsum(64 * wl)])
+    st, ptr, out = bfal.slice_plan(slot_u, slot_l, 2, nparts)
+    assert st == OK
+    assert ptr[0] == 0 and ptr[-1] == ns and np.all(np.diff(ptr) >= 0)
+    assert np.array_equal(np.sort(out), np.arange(ns))            # every slice exactly once
+    part_of, load = plan_reference(wu, wl, 2, nparts)
+    for p in range(nparts):
+        lst = out[ptr[p]:ptr[p + 1]]
+        assert np.all(np.diff(lst) > 0)                           # increasing, the order it is processed in
+        assert np.all(part_of[lst] == p)                          # the restated rule's assignment
+    # balance: no part exceeds the even share by more than one slice's cost
+    cost = (np.maximum(wu, wl) + 1) // 2 + 1
+    per_x = nparts // 8
+    for x in range(8):
+        lx = load[x * per_x:(x + 1) * per_x]
+        assert lx.max() - lx.min() <= cost.max()
+
+
+def test_slice_plan_balances_better_than_round_robin():
+    """Clustered wide slices (contact interfaces) as on the large workload:
+    the plan's heaviest part carries less than round-robin's."""
+    ns, nparts = 6300, 1024
+    wu = np.full(ns, 7)
+    for c in (1220, 2480, 3740, 5000):
+        wu[c:c + 80] = 25
+    slot = np.concatenate([[0], np.cumsum(64 * wu)])
+    st, ptr, out = bfal.slice_plan(slot, slot, 2, nparts)
+    assert st == OK
+    cost = (wu + 1) // 2 + 1
+    plan_max = max(cost[out[ptr[p]:ptr[p + 1]]].sum() for p in range(nparts))
+    rr_max = max(cost[p::nparts].sum() for p in range(nparts))
+    assert plan_max < rr_max
+    assert plan_max <= cost.sum() / nparts + cost.max()
+
+
+def test_slice_plan_argument_errors():
+    good = np.arange(0, 64 * 5, 64)
+    assert bfal.slice_plan(good, good, 2, 12)[0] == INVALID          # not a multiple of 8
+    assert bfal.slice_plan(good, good, 0, 8)[0] == INVALID           # pairs < 1
+    assert bfal.slice_plan(good + 1, good, 2, 8)[0] == INVALID       # not multiples of 64
+    assert bfal.slice_plan(good[::-1].copy(), good, 2, 8)[0] == INVALID   # decreasing
+    st, ptr, out = bfal.slice_plan(good[::-1].copy(), good, 2, 8)
+    assert np.all(ptr == -7) and np.all(out == -7)                 # nothing written on an error
