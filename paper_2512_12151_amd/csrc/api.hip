@@ -243,8 +243,9 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
   launch_elastic(pb->tets.as<int4>(), T, pb->rest.as<double>(), pb->xh.as<double>(), pb->Dminv9.as<double>(),
                  pb->vol.as<float>(), pb->mu.as<float>(), pb->lam.as<float>(), h2, pb->epos.as<int>(),
                  pb->staging.as<double>(), pb->has_mat ? pb->mat.as<int>() : nullptr, flags, s);
-  launch_assemble_rows(N, row_ptr, pb->col.as<int>(), pb->eslot.as<int>(), pb->ecptr.as<int>(),
-                       pb->staging.as<double>(), vptr, pb->vinc.as<int>(), pids, n, pb->lin64.as<double>(),
+  launch_assemble_rows(N, pb->cap_nnzb, row_ptr, pb->col.as<int>(), pb->eslot.as<int>(), pb->erow_ptr.as<int>(),
+                       pb->ecol.as<int>(), pb->ecptr.as<int>(), pb->staging.as<double>(), vptr, pb->vinc.as<int>(),
+                       pids, n, pb->lin64.as<double>(),
                        pb->cg.as<double>(), pb->ch.as<double>(), nf, pb->fgk.as<double>(), pb->cfr.as<int>(),
                        pb->fext.as<int>(), pb->mass.as<double>(), pb->xh.as<double>(), pb->xt.as<double>(),
                        pb->fixed.as<uint8_t>(), pb->vals.as<double>(), pb->grad.as<float>(), pb->Lf.as<float>(),

@@ -64,6 +64,35 @@ __device__ inline void add_friction(int fi, int a, const int4& t, int r, int o, 
   }
 }
 
+// Elastic sums of the merged pattern's off-diagonal slots, one thread per
+// slot: the slot's range of (tet, pair) contributions in FP64, in that order,
+// written to vals before the row owners add the contact and friction terms
+// (so every block is summed in the same order as by its row owner alone); a
+// slot without a static elastic part (contact only) starts at zero.  A static
+// slot es is a diagonal one, left to the row owner, when erow_ptr[ecol[es]]
+// == es (the static pattern holds each row's diagonal first).  Threads beyond
+// the merged pattern's row_ptr[N] slots return.
+__global__ void __launch_bounds__(kBlock)
+k_offdiag_sums(int N, long long cap, const int* __restrict__ row_ptr, const int* __restrict__ eslot,
+               const int* __restrict__ erow_ptr, const int* __restrict__ ecol, const int* __restrict__ ecptr,
+               const double* __restrict__ staging, double* __restrict__ vals) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cap || j >= row_ptr[N]) return;
+  const int es = eslot[j];
+  if (es >= 0 && erow_ptr[ecol[es]] == es) return;
+  double b[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (es >= 0) {
+    for (int q = ecptr[es]; q < ecptr[es + 1]; ++q) {
+      const double* st = staging + 9LL * q;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) b[k] += st[k];
+    }
+  }
+  double* v = vals + 9 * j;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) v[k] = b[k];
+}
+
 // All sums, the factor L and the right-hand side in FP64; the blocks stay
 // FP64 (vals) until the sliced storage rounds the scaled ones once.
 __global__ void __launch_bounds__(kBlock)
@@ -93,21 +122,7 @@ k_assemble_rows(int N, const int* __restrict__ row_ptr, const int* __restrict__ 
         for (int k = 0; k < 3; ++k) g[k] += s[6 + k];
       }
     }
-    // off-diagonal elastic sums
-    for (int j = 1; j < n; ++j) {
-      double b[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-      const int es = eslot[o + j];
-      if (es >= 0) {
-        for (int q = ecptr[es]; q < ecptr[es + 1]; ++q) {
-          const double* s = staging + 9LL * q;
-#pragma unroll
-          for (int k = 0; k < 9; ++k) b[k] += s[k];
-        }
-      }
-      double* v = vals + 9LL * (o + j);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) v[k] = b[k];
-    }
+    // (the off-diagonal elastic sums are in vals already: k_offdiag_sums)
     // inertia
     const double m = mass[r];
     d[0] += m; d[3] += m; d[5] += m;
@@ -354,12 +369,15 @@ __global__ void k_row_diag_slots(int N, const int* __restrict__ row_ptr, int* di
 
 }  // namespace
 
-void launch_assemble_rows(int N, const int* row_ptr, const int* col, const int* eslot, const int* ecptr,
-                          const double* staging, const int* vptr, const int* vinc, const int4* ids, int n_c,
-                          const double* lin64, const double* cg, const double* ch, int n_f, const double* fgk,
-                          const int* cfr, const int* fext, const double* mass, const double* xh, const double* xt,
+void launch_assemble_rows(int N, long long cap, const int* row_ptr, const int* col, const int* eslot,
+                          const int* erow_ptr, const int* ecol, const int* ecptr, const double* staging,
+                          const int* vptr, const int* vinc, const int4* ids, int n_c, const double* lin64,
+                          const double* cg, const double* ch, int n_f, const double* fgk, const int* cfr,
+                          const int* fext, const double* mass, const double* xh, const double* xt,
                           const uint8_t* fixed, double* vals, float* grad, float* Lf, double* Linv, float* bhat,
                           double* bb_part, int* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_offdiag_sums, dim3(div_up(cap, kBlock)), dim3(kBlock), 0, s, N, cap, row_ptr, eslot, erow_ptr,
+                     ecol, ecptr, staging, vals);
   hipLaunchKernelGGL(k_assemble_rows, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, eslot, ecptr,
                      staging, vptr, vinc, ids, n_c, lin64, cg, ch, n_f, fgk, cfr, fext, mass, xh, xt, fixed, vals,
                      grad, Lf, Linv, bhat, bb_part, flags);
