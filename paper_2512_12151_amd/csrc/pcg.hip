@@ -29,10 +29,11 @@
 // part.  On a structured mesh the rows of a slice have the same stencil, so the
 // lower references of slot k point at consecutive slots of the source slice
 // and the p gathers of a slot are consecutive nodes: every access of the SpMV
-// is a contiguous run per wavefront.  Workgroups are mapped so that in each
-// round of the slice loop every XCD works on one contiguous window of slices;
-// the whole upper matrix of the large workload (~150 MB) fits the 256 MB
-// Infinity Cache.
+// is a contiguous run per wavefront.  Workgroups are mapped so that each XCD
+// holds one contiguous range of them, and a per-step plan (bf_slice_plan)
+// gives every XCD consecutive windows of slices and balances their cost over
+// its wavefronts; the whole upper matrix of the large workload (~150 MB) fits
+// the 256 MB Infinity Cache.
 //
 // Residual replacement (reliable updating): x is kept in FP64, and when the
 // recursive residual has fallen 100x since the last replacement, or claims
@@ -882,9 +883,9 @@ k_finish_scalars(const double* __restrict__ part, int n, const double* __restric
 // CU can keep in flight, so a CU holding two workgroups would take twice as
 // long as the others (measured on the large workload: 1576 workgroups, 6 or 7
 // per CU, 44.5 us; 256, one per CU with 6 or 7 slices per wave, 42.6 us; 264
-// or 320, 54 and 65 us).  Each workgroup then walks its slices in rounds, and
-// in a round the 4 * num_cu slices in flight are consecutive per XCD, so the
-// lower-half reads of a block mostly follow its upper-half read closely.
+// or 320, 54 and 65 us).  Each wavefront then walks the slices the plan gives
+// it, consecutive windows per XCD, so the lower-half reads of a block mostly
+// follow its upper-half read closely and on the same XCD.
 int pcg_spmv_groups(int N, int num_cu) {
   const int nslices = div_up(N, kSlice);
   int g = div_up(nslices, kSlicesPerGroup);
