@@ -235,6 +235,9 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
   scan_exclusive(pb->ucount.as<int>(), row_ptr, N, row_ptr + N, tmp, s);
   launch_merged_write(pb->cand.as<int>(), cptr, row_ptr, pb->erow_ptr.as<int>(), pb->ecol.as<int>(), N,
                       pb->col.as<int>(), pb->eslot.as<int>(), s);
+  // slots of every stencil's ten vertex pairs in the merged pattern, for the row assembly
+  ALLOC(c, pb->cslot, 40LL * npat + 16);
+  launch_cmap(pids, npat, row_ptr, pb->col.as<int>(), pb->cslot.as<int>(), s);
   HIPCHK(c, hipEventRecord(pb->ev[2], s));
   // (3) assembly (friction terms at x_hat first)
   launch_friction_terms(pb->fids.as<int4>(), nf, pb->xh.as<double>(), pb->fx0.as<double>(), pb->f64.as<double>(),
@@ -245,7 +248,7 @@ bf_status step_assemble(bf_problem* pb, bool bf16) {
                  pb->staging.as<double>(), pb->has_mat ? pb->mat.as<int>() : nullptr, flags, s);
   launch_assemble_rows(N, pb->cap_nnzb, row_ptr, pb->col.as<int>(), pb->eslot.as<int>(), pb->erow_ptr.as<int>(),
                        pb->ecol.as<int>(), pb->ecptr.as<int>(), pb->staging.as<double>(), vptr, pb->vinc.as<int>(),
-                       pids, n, pb->lin64.as<double>(),
+                       pids, pb->cslot.as<int>(), n, pb->lin64.as<double>(),
                        pb->cg.as<double>(), pb->ch.as<double>(), nf, pb->fgk.as<double>(), pb->cfr.as<int>(),
                        pb->fext.as<int>(), pb->mass.as<double>(), pb->xh.as<double>(), pb->xt.as<double>(),
                        pb->fixed.as<uint8_t>(), pb->vals.as<double>(), pb->grad.as<float>(), pb->Lf.as<float>(),
@@ -355,7 +358,7 @@ bf_status bf_footprint_bytes(int32_t n_nodes, int32_t n_tets, int32_t n_constrai
   b += T * (16 + 3 * 8 + 72 + 12 + 40 * 3 + 720);  // tets, E/nu/rho, Dm^-1, vol/mu/lam, emap/epos/elist, FP64 staging
   b += nnzb_e * (4 + 4) + N * (4 * 3 + 24 + 8 + 1);
   b += N * 24 * 3;                                 // x, x_hat, x_tilde
-  b += C * (16 + 16 + 64 + 16);                    // ids, lambda/gamma, the FP64 linearization, AL factors
+  b += C * (16 + 16 + 64 + 16 + 40);               // ids, lambda/gamma, FP64 linearization, AL factors, pair slots
   b += N * 4 * 8 + C * 16 + cap * 4 * 2;           // incidence, candidates, pattern
   b += cap * (72 + 36 + 4 + 4 + 8 + 4);            // FP64 blocks, FP32 scaled blocks, ucol, eslot, transpose index, lsrc
   b += N * (12 * (4 + kPRing) + 24 + 24 + 48 + 24);   // grad, bhat, r, q, the direction ring, x, L, L^-1, p out
@@ -401,7 +404,7 @@ void bf_problem_destroy(bf_problem* pb) {
                     &pb->sort_tmp, &pb->ctmp, &pb->htable, &pb->tvmin, &pb->keepn[0], &pb->keepn[1], &pb->posn[0],
                     &pb->posn[1], &pb->keepc, &pb->posc, &pb->nids, &pb->nlam, &pb->ngam, &pb->mpart,
                     &pb->xstart, &pb->xprev, &pb->vout, &pb->mat, &pb->fids, &pb->f64, &pb->fx0, &pb->fgk,
-                    &pb->pids, &pb->ftab, &pb->cfr, &pb->fextra, &pb->fpos, &pb->fext};
+                    &pb->pids, &pb->cslot, &pb->ftab, &pb->cfr, &pb->fextra, &pb->fpos, &pb->fext};
   for (DevBuf* b : bufs) b->release();
   for (auto& e : pb->ev)
     if (e) (void)hipEventDestroy(e);

@@ -36,11 +36,14 @@ __device__ inline int find_slot(const int* __restrict__ col, int lo, int hi, int
   return lo;
 }
 
-// Friction contact fi at vertex slot a of its stencil t, into row r's
-// diagonal d, gradient g and upper blocks.
-__device__ inline void add_friction(int fi, int a, const int4& t, int r, int o, int n, int n_f,
-                                    const double* __restrict__ fgk, const int* __restrict__ col, double* vals,
-                                    double d[6], double g[3]) {
+// Slot index of the local vertex pair (i, j), i < j, in a stencil's ten
+// pairs (0,0),(0,1),(0,2),(0,3),(1,1),(1,2),(1,3),(2,2),(2,3),(3,3).
+__device__ inline int pair_index(int i, int j) { return (i == 0 ? 0 : i == 1 ? 4 : i == 2 ? 7 : 9) + (j - i); }
+
+// Friction contact fi at vertex slot a of its stencil t (whose ten pair
+// slots are cs), into row r's diagonal d, gradient g and upper blocks.
+__device__ inline void add_friction(int fi, int a, const int4& t, int r, const int* __restrict__ cs, int n_f,
+                                    const double* __restrict__ fgk, double* vals, double d[6], double g[3]) {
   double K[6], w[4];
 #pragma unroll
   for (int k = 0; k < 6; ++k) K[k] = fgk[(3LL + k) * n_f + fi];
@@ -55,7 +58,7 @@ __device__ inline void add_friction(int fi, int a, const int4& t, int r, int o, 
   for (int b = 0; b < 4; ++b) {
     const int vb = vtx(t, b);
     if (b == a || vb < r) continue;
-    const int s = find_slot(col, o + 1, o + n - 1, vb);
+    const int s = cs[pair_index(min(a, b), max(a, b))];
     const double sab = wa * w[b];
     double* v = vals + 9LL * s;
     v[0] += sab * K[0]; v[1] += sab * K[1]; v[2] += sab * K[2];
@@ -98,7 +101,8 @@ k_offdiag_sums(int N, long long cap, const int* __restrict__ row_ptr, const int*
 __global__ void __launch_bounds__(kBlock)
 k_assemble_rows(int N, const int* __restrict__ row_ptr, const int* __restrict__ col, const int* __restrict__ eslot,
                 const int* __restrict__ ecptr, const double* __restrict__ staging, const int* __restrict__ vptr,
-                const int* __restrict__ vinc, const int4* __restrict__ ids, int n_c, const double* __restrict__ lin64,
+                const int* __restrict__ vinc, const int4* __restrict__ ids, const int* __restrict__ cslot, int n_c,
+                const double* __restrict__ lin64,
                 const double* __restrict__ cg, const double* __restrict__ ch, int n_f,
                 const double* __restrict__ fgk, const int* __restrict__ cfr, const int* __restrict__ fext,
                 const double* __restrict__ mass, const double* __restrict__ xh, const double* __restrict__ xt,
@@ -132,13 +136,14 @@ k_assemble_rows(int N, const int* __restrict__ row_ptr, const int* __restrict__ 
     for (int j = vptr[r]; j < vptr[r + 1]; ++j) {
       const int ci = vinc[j] >> 2, a = vinc[j] & 3;
       const int4 t = ids[ci];
+      const int* cs = cslot + 10LL * ci;
       if (ci >= n_c) {
-        add_friction(fext[ci - n_c], a, t, r, o, n, n_f, fgk, col, vals, d, g);
+        add_friction(fext[ci - n_c], a, t, r, cs, n_f, fgk, vals, d, g);
         continue;
       }
       if (n_f > 0) {
         const int fi = cfr[ci];
-        if (fi >= 0) add_friction(fi, a, t, r, o, n, n_f, fgk, col, vals, d, g);
+        if (fi >= 0) add_friction(fi, a, t, r, cs, n_f, fgk, vals, d, g);
       }
       // normal n and weights w from the linearization (SoA rows 1-3 and 4-7)
       const double n0 = lin64[1LL * n_c + ci], n1 = lin64[2LL * n_c + ci], n2 = lin64[3LL * n_c + ci];
@@ -153,7 +158,7 @@ k_assemble_rows(int N, const int* __restrict__ row_ptr, const int* __restrict__ 
       for (int b = 0; b < 4; ++b) {
         const int vb = vtx(t, b);
         if (b == a || vb < r) continue;
-        const int s = find_slot(col, o + 1, o + n - 1, vb);
+        const int s = cs[pair_index(min(a, b), max(a, b))];
         const double sab = hf * wa * w[b];
         double* v = vals + 9LL * s;
         v[0] += sab * n0 * n0; v[1] += sab * n0 * n1; v[2] += sab * n0 * n2;
@@ -371,7 +376,8 @@ __global__ void k_row_diag_slots(int N, const int* __restrict__ row_ptr, int* di
 
 void launch_assemble_rows(int N, long long cap, const int* row_ptr, const int* col, const int* eslot,
                           const int* erow_ptr, const int* ecol, const int* ecptr, const double* staging,
-                          const int* vptr, const int* vinc, const int4* ids, int n_c, const double* lin64,
+                          const int* vptr, const int* vinc, const int4* ids, const int* cslot, int n_c,
+                          const double* lin64,
                           const double* cg, const double* ch, int n_f, const double* fgk, const int* cfr,
                           const int* fext, const double* mass, const double* xh, const double* xt,
                           const uint8_t* fixed, double* vals, float* grad, float* Lf, double* Linv, float* bhat,
@@ -379,7 +385,7 @@ void launch_assemble_rows(int N, long long cap, const int* row_ptr, const int* c
   hipLaunchKernelGGL(k_offdiag_sums, dim3(div_up(cap, kBlock)), dim3(kBlock), 0, s, N, cap, row_ptr, eslot, erow_ptr,
                      ecol, ecptr, staging, vals);
   hipLaunchKernelGGL(k_assemble_rows, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, row_ptr, col, eslot, ecptr,
-                     staging, vptr, vinc, ids, n_c, lin64, cg, ch, n_f, fgk, cfr, fext, mass, xh, xt, fixed, vals,
+                     staging, vptr, vinc, ids, cslot, n_c, lin64, cg, ch, n_f, fgk, cfr, fext, mass, xh, xt, fixed, vals,
                      grad, Lf, Linv, bhat, bb_part, flags);
 }
 

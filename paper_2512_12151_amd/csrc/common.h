@@ -263,7 +263,8 @@ void launch_elastic(const int4* tets, int T, const double* rest, const double* x
 // >= its slot count), then the row owners (one thread per row).
 void launch_assemble_rows(int N, long long cap, const int* row_ptr, const int* col, const int* eslot,
                           const int* erow_ptr, const int* ecol, const int* ecptr, const double* staging,
-                          const int* vptr, const int* vinc, const int4* ids, int n_c, const double* lin64,
+                          const int* vptr, const int* vinc, const int4* ids, const int* cslot, int n_c,
+                          const double* lin64,
                           const double* cg, const double* ch, int n_f, const double* fgk, const int* cfr,
                           const int* fext, const double* mass, const double* xh, const double* xt,
                           const uint8_t* fixed, double* vals, float* grad, float* Lf, double* Linv, float* bhat,

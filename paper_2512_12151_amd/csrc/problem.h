@@ -48,6 +48,7 @@ struct bf_problem {
   DevBuf ccount, cptr, cand, ucount, row_ptr, col, eslot;
   DevBuf vals, grad, Lf, Linv, bhat, bb_part, lcnt, lptr, lsrc, sbu, sbl, sblk, sblk16, scol, sent;
   DevBuf wplan_ptr, wplan_sl;                  // the SpMV's slice plan of the current step
+  DevBuf cslot;                                // merged-pattern slots of each stencil's ten vertex pairs
   std::vector<int> h_sbu, h_sbl, h_wptr, h_wsl;  // host copies for planning (kept for the async upload)
   DevBuf xs, r, pring, q, part, scal, pout, flags, scan_tmp, scratch_int;
   DevBuf xd, rd, zd, fcg, rpart;   // refinement: FP64 solution, residual, inner solution, directions, partials
