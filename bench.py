@@ -6,9 +6,11 @@ Workload (default "large"): five 50x50x30-cell Kuhn blocks (2.25M tets,
 point-triangle + 400k edge-edge constraints, kappa = 1e5; synthetic, seeded.
 
 One "step" is one bf_newton_step call with the state already in HBM:
-constraint linearization, merged BSR pattern, elastic/contact assembly,
-preconditioner, PCG to a relative residual of 1e-5, FP64 stats.  Prints one
-JSON line (see the fields below); progress goes to stderr.
+constraint linearization, merged BSR pattern, elastic/contact assembly (FP64),
+preconditioner and FP32 sliced storage, PCG to a relative residual of 1e-5
+(FP32 vectors, FP64 reductions and solution), FP64 stats.  `dtype` names the
+PCG's arithmetic, where the step spends its time.  Prints one JSON line (see
+the fields below); progress goes to stderr.
 """
 from __future__ import annotations
 
