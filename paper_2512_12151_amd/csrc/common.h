@@ -126,7 +126,7 @@ struct DevBuf {
 // receives the sum.  tmp must hold scan_tmp_ints(n) ints.
 size_t scan_tmp_ints(long long n);
 void scan_exclusive(const int* in, int* out, long long n, int* total, int* tmp, hipStream_t s);
-// Sort every segment [ptr[i], ptr[i+1]) of keys ascending (thread per segment).
+// Sort every segment [ptr[i], ptr[i+1]) of keys ascending (a wavefront per segment; stable).
 void sort_segments(int* keys, const int* ptr, int nseg, hipStream_t s);
 void fill_int(int* a, int v, long long n, hipStream_t s);
 

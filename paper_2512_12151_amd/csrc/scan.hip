@@ -54,15 +54,41 @@ __global__ void k_add_tile_offsets(int* out, long long n, const int* __restrict_
   if (i < n) out[i] += tile_off[i / kScanTile];
 }
 
-__global__ void k_sort_segments(int* keys, const int* __restrict__ ptr, int nseg) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nseg) return;
-  const int b = ptr[i], e = ptr[i + 1];
-  for (int j = b + 1; j < e; ++j) {          // insertion sort: segments are short
-    int key = keys[j];
-    int k = j - 1;
-    while (k >= b && keys[k] > key) { keys[k + 1] = keys[k]; --k; }
-    keys[k + 1] = key;
+// Sorts every segment [ptr[i], ptr[i+1]) of keys ascending, one wavefront
+// per segment: the segment is staged in LDS and each key is written to the
+// position given by its rank (the smaller keys, and the equal ones before
+// it), so no element waits for another.  A segment longer than kSortCap keys (rare: a
+// vertex in very many constraints) is insertion-sorted by one lane.
+constexpr int kSortWaves = 4;
+constexpr int kSortCap = 256;
+
+__global__ void __launch_bounds__(kSortWaves * 64) k_sort_segments(int* keys, const int* __restrict__ ptr, int nseg) {
+  __shared__ int buf[kSortWaves][kSortCap];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int sg = blockIdx.x * kSortWaves + wave;
+  const int b = sg < nseg ? ptr[sg] : 0;
+  const int n = sg < nseg ? ptr[sg + 1] - b : 0;
+  const bool staged = n > 1 && n <= kSortCap;
+  if (staged)
+    for (int i = lane; i < n; i += 64) buf[wave][i] = keys[b + i];
+  __syncthreads();
+  if (staged) {
+    for (int i = lane; i < n; i += 64) {
+      const int key = buf[wave][i];
+      int rank = 0;
+      for (int j = 0; j < n; ++j) {
+        const int kj = buf[wave][j];
+        rank += (kj < key || (kj == key && j < i)) ? 1 : 0;   // equal keys keep their order
+      }
+      keys[b + rank] = key;
+    }
+  } else if (n > kSortCap && lane == 0) {
+    for (int j = b + 1; j < b + n; ++j) {
+      const int key = keys[j];
+      int k = j - 1;
+      while (k >= b && keys[k] > key) { keys[k + 1] = keys[k]; --k; }
+      keys[k + 1] = key;
+    }
   }
 }
 
@@ -102,7 +128,7 @@ void scan_exclusive(const int* in, int* out, long long n, int* total, int* tmp, 
 
 void sort_segments(int* keys, const int* ptr, int nseg, hipStream_t s) {
   if (nseg <= 0) return;
-  hipLaunchKernelGGL(k_sort_segments, dim3(div_up(nseg, kBlock)), dim3(kBlock), 0, s, keys, ptr, nseg);
+  hipLaunchKernelGGL(k_sort_segments, dim3(div_up(nseg, kSortWaves)), dim3(kSortWaves * 64), 0, s, keys, ptr, nseg);
 }
 
 void fill_int(int* a, int v, long long n, hipStream_t s) {
