@@ -29,25 +29,28 @@ constexpr int kBlock = 256;        // default workgroup size (4 waves)
 
 // Device-resident scalars of one PCG solve (see pcg.hip for who writes what).
 struct PcgScalars {
+  // Control words first, grouped so that each PCG kernel reads its own in one
+  // load and none of them reads a word it writes: the update kernel reads
+  // [ks, done, check_every, xbase], the SpMV [check_every, xbase, iter, brk].
+  int ks;            // iteration index of the last SpMV (written by its workgroup 0)
+  int done;          // 1: converged, 2: max_iter, 4: residual replacement requested
+                     // (written by workgroup 0 of the SpMV; cleared by the replacement)
+  int check_every;
+  int xbase;         // x holds alpha_j p_j for every j < xbase and for every j below the last multiple of kXBatch
+                     // reached by the update kernel (written by the flush kernel only)
+  int iter;          // completed iterations (written by workgroup 0 of the update kernel)
+  int brk;           // 1: breakdown p^T H p <= 0 (written by workgroup 0 of the update kernel)
+  int max_iter;
+  int verified;      // iteration of the last residual replacement (-1: none)
+  int replace_on;    // 1: replace the residual (see pcg.hip), 0: plain recurrences
+  int flags;         // FLAG_* bits
   double rho;        // r^T r of the scaled system (= r^T D^{-1} r of the original)
   double rr_true;    // |L r|^2 = unscaled residual norm squared (when checked)
   double bb;         // |b|^2 (unscaled)
   double tol2;       // tol^2
   double stat_pinf;  // max |p_i| of the result
   double stat_viol;  // max_i max(0, -c_i)
-  int iter;          // completed iterations (written by workgroup 0 of the update kernel)
-  int ks;            // iteration index of the last SpMV (written by its workgroup 0)
   double rt_ref;     // |L r|^2 right after the last residual replacement (or |b|^2)
-  int done;          // 1: converged, 2: max_iter, 4: residual replacement requested
-                     // (written by workgroup 0 of the SpMV; cleared by the replacement)
-  int verified;      // iteration of the last residual replacement (-1: none)
-  int replace_on;    // 1: replace the residual (see pcg.hip), 0: plain recurrences
-  int brk;           // 1: breakdown p^T H p <= 0 (written by workgroup 0 of the update kernel)
-  int max_iter;
-  int check_every;
-  int flags;         // FLAG_* bits
-  int xbase;         // x holds alpha_j p_j for every j < xbase and for every j below the last multiple of kXBatch
-                     // reached by the update kernel (written by the flush kernel only)
   float alpha_hist[8];   // alpha_j at j % kXBatch (written by workgroup 0 of the update kernel)
 };
 

@@ -141,9 +141,9 @@ __device__ __forceinline__ double thread_parts(const double* __restrict__ a, int
     const int k = threadIdx.x + u * NT;
     v[u] = k < n ? a[k] : 0.0;
   }
-  double s = 0.0;
+  double s = v[0];
 #pragma unroll
-  for (int u = 0; u < kPer; ++u) s += v[u];
+  for (int u = 1; u < kPer; ++u) s += v[u];
   return s;
 }
 
@@ -236,17 +236,135 @@ __device__ inline void load_block(const uint32_t* __restrict__ u, int j, float b
   b[8] = __uint_as_float(w[4] << 16);
 }
 
-// Scalars at the start of SpMV k: returns false when the system is finished
-// (converged, capped) and the workgroup must return.  Called by the whole workgroup.
-__device__ inline bool spmv_scalars(const PcgSystem& S, bool leader, int& k) {
+// Vector entries of p_k at node c (AoS [N4][3]: one 12-byte load per node).
+struct PView {
+  const float* __restrict__ p;
+  __device__ inline void at(int c, float& p0, float& p1, float& p2) const {
+    const float* pc = p + 3LL * c;
+    p0 = pc[0];
+    p1 = pc[1];
+    p2 = pc[2];
+  }
+};
+
+// Index loads of one step of a row's pairs: upper slot columns from scol,
+// lower block slots and source rows from sent.
+__device__ __forceinline__ void load_step_indices(const int* __restrict__ scol, const int2* __restrict__ sent,
+                                                  int ubase, int lbase, int uc[kPairs], int lb[kPairs],
+                                                  int lc[kPairs]) {
+#pragma unroll
+  for (int u = 0; u < kPairs; ++u) {
+    uc[u] = scol[ubase + u * kSlice];
+    const int2 t = sent[lbase + u * kSlice];
+    lb[u] = t.x;
+    lc[u] = t.y;
+  }
+}
+
+// One step of a row's pairs (upper slot k + u: B p_c with the column from
+// scol; lower slot k + u: B^T p_r with block and source row from sent), with
+// all its loads issued before any is used.  The step's indices arrive loaded
+// (uc, lb, lc); the next step's are loaded before this step's products (a
+// scheduling barrier keeps them there), from the next slice's first step
+// (bases nub, nlb) after the row's last step.  A step may run past the row's
+// widths: those slots are still read (the slot arrays are padded, so every
+// index read is in range) but not added, which keeps the step free of
+// branches.
+template <class BT>
+__device__ __forceinline__ void pair_step(int k, int wu, int wl, int w, int ubase, int lbase, int nub, int nlb,
+                                          const int* __restrict__ scol, const int2* __restrict__ sent,
+                                          const BT* __restrict__ blk, const PView& pv, int uc[kPairs],
+                                          int lb[kPairs], int lc[kPairs], float& a0, float& a1, float& a2) {
+  float bu[kPairs][9], pu[kPairs][3], bl[kPairs][9], pl[kPairs][3];
+#pragma unroll
+  for (int u = 0; u < kPairs; ++u) {
+    load_block(blk, ubase + (k + u) * kSlice, bu[u]);
+    pv.at(uc[u], pu[u][0], pu[u][1], pu[u][2]);
+    load_block(blk, lb[u], bl[u]);
+    pv.at(lc[u], pl[u][0], pl[u][1], pl[u][2]);
+  }
+  const bool more = k + kPairs < w;
+  load_step_indices(scol, sent, more ? ubase + (k + kPairs) * kSlice : nub, more ? lbase + (k + kPairs) * kSlice : nlb,
+                    uc, lb, lc);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < kPairs; ++u) {
+    const bool vu = k + u < wu, vl = k + u < wl;
+    const float y0 = bu[u][0] * pu[u][0] + bu[u][1] * pu[u][1] + bu[u][2] * pu[u][2];
+    const float y1 = bu[u][3] * pu[u][0] + bu[u][4] * pu[u][1] + bu[u][5] * pu[u][2];
+    const float y2 = bu[u][6] * pu[u][0] + bu[u][7] * pu[u][1] + bu[u][8] * pu[u][2];
+    a0 += vu ? y0 : 0.f;
+    a1 += vu ? y1 : 0.f;
+    a2 += vu ? y2 : 0.f;
+    const float z0 = bl[u][0] * pl[u][0] + bl[u][3] * pl[u][1] + bl[u][6] * pl[u][2];
+    const float z1 = bl[u][1] * pl[u][0] + bl[u][4] * pl[u][1] + bl[u][7] * pl[u][2];
+    const float z2 = bl[u][2] * pl[u][0] + bl[u][5] * pl[u][1] + bl[u][8] * pl[u][2];
+    a0 += vl ? z0 : 0.f;
+    a1 += vl ? z1 : 0.f;
+    a2 += vl ? z2 : 0.f;
+  }
+}
+
+// A wavefront's place in its slice list (bf_slice_plan): its range [j0, j1),
+// the current slice and the next two, the slot offsets of the current and the
+// next slice, and the indices of the current slice's first step.
+struct SliceCursor {
+  int j0, j1, sl, sl1, sl2, bu, eu, bl, el, nbu, neu, nbl, nel;
+  int uc[kPairs], lb[kPairs], lc[kPairs];
+};
+
+// Start of SpMV k, in one pass of loads: the solver scalars and the partials
+// of r^T r and |L r|^2 (which decide whether the system goes on) are loaded
+// together with the wavefront's first slices, their offsets and first
+// indices, which do not depend on the iteration.  Returns false when the
+// system is finished (converged, capped, broken down, or a residual
+// replacement is due) and the workgroup must return.  Called by the whole
+// workgroup.
+__device__ inline bool spmv_begin(const PcgSystem& S, int lb, bool leader, int& k, SliceCursor& c) {
+  const int wave = threadIdx.x / kSlice, lane = threadIdx.x % kSlice;
   PcgScalars* sc = S.sc;
-  if (sc->brk) return false;
+  const int every = sc->check_every, brk = sc->brk;
   k = sc->iter;
-  const double* part = S.part;
-  const bool check = k > 0 && (k % sc->check_every) == 0;
-  double rho, rt, unused;
-  sum_parts3<kSpmvBlock>(part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg, part + kPartRT,
-                         check ? S.vec_nwg : 0, part, 0, rho, rt, unused);
+  const int part = lb * kSlicesPerGroup + wave;
+  c.j0 = S.wave_ptr[part];
+  c.j1 = S.wave_ptr[part + 1];
+  // r^T r and |L r|^2 partials (the latter used on check iterations only);
+  // every load is issued (indices past the count re-read the last entry and
+  // are not added), so later waits count the loads in order
+  constexpr int kPer = (kMaxVecParts + kSpmvBlock - 1) / kSpmvBlock;
+  const int nv = S.vec_nwg;
+  double va[kPer], vb[kPer];
+  {
+    const double* pa = S.part + kPartRR + (k & 1) * kMaxVecParts;
+    const double* pb = S.part + kPartRT;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int i = min((int)threadIdx.x + u * kSpmvBlock, nv - 1);
+      va[u] = pa[i];
+      vb[u] = pb[i];
+    }
+  }
+  // an empty range reads slice 0 and is not walked
+  const int jf = c.j0 < c.j1 ? c.j0 : 0, jl = c.j0 < c.j1 ? c.j1 - 1 : 0;
+  c.sl = S.wave_slices[jf];
+  c.sl1 = S.wave_slices[min(jf + 1, jl)];
+  c.sl2 = S.wave_slices[min(jf + 2, jl)];
+  c.bu = S.sbu[c.sl]; c.eu = S.sbu[c.sl + 1]; c.bl = S.sbl[c.sl]; c.el = S.sbl[c.sl + 1];
+  c.nbu = S.sbu[c.sl1]; c.neu = S.sbu[c.sl1 + 1]; c.nbl = S.sbl[c.sl1]; c.nel = S.sbl[c.sl1 + 1];
+  load_step_indices(S.scol, S.sent, c.bu + lane, c.bl + lane, c.uc, c.lb, c.lc);
+  const bool first = (int)threadIdx.x < nv;
+  double a = first ? va[0] : 0.0, b = first ? vb[0] : 0.0;
+#pragma unroll
+  for (int u = 1; u < kPer; ++u) {
+    const bool in = (int)threadIdx.x + u * kSpmvBlock < nv;
+    a += in ? va[u] : 0.0;
+    b += in ? vb[u] : 0.0;
+  }
+  double unused = 0.0;
+  block_sum3<kSpmvBlock>(a, b, unused);
+  const bool check = (k > 0) & ((k % every) == 0);
+  const double rho = a, rt = check ? b : 0.0;
+  if (brk) return false;
   if (k > 0) {
     const bool converged = (check && rt <= sc->tol2 * sc->bb) || rho == 0.0;
     const bool capped = k >= sc->max_iter;
@@ -267,108 +385,49 @@ __device__ inline bool spmv_scalars(const PcgSystem& S, bool leader, int& k) {
   return true;
 }
 
-// Vector entries of p_k at node c (AoS [N4][3]: one 12-byte load per node).
-struct PView {
-  const float* __restrict__ p;
-  __device__ inline void at(int c, float& p0, float& p1, float& p2) const {
-    const float* pc = p + 3LL * c;
-    p0 = pc[0];
-    p1 = pc[1];
-    p2 = pc[2];
-  }
-};
-
-// Accumulates one row's slots as pairs (upper slot k: B p_c with the column
-// from scol; lower slot k: B^T p_r with block and source row from sent),
-// kPairs pairs per step with all their loads issued before any is used.  The
-// next step's indices are loaded before this step's products (a scheduling
-// barrier keeps them there), so each step waits for one memory round trip
-// instead of an index load followed by the loads it addresses.  A step may
-// run past the row's widths: those slots are still read (the slot arrays are
-// padded, so every index read is in range) but not added, which keeps the
-// step free of branches.  The sum runs in pair order.
+// q = H_hat p_k for the slices of the cursor (bf_slice_plan: on each XCD
+// consecutive windows of slices, balanced in cost across the waves); adds
+// this thread's shares of p^T q, r^T q and q^T q.  The slices are pipelined
+// so that a change of slice costs no extra memory round trip: the slot
+// offsets are loaded two slices ahead and the slice numbers three ahead, a
+// slice's own p and r entries are loaded before its first step, and its last
+// step loads the next slice's first indices.  Every slice takes at least one
+// step.
 template <class BT>
-__device__ inline void accumulate_pairs(int ubase, int wu, int lbase, int wl, const int* __restrict__ scol,
-                                        const int2* __restrict__ sent, const BT* __restrict__ blk, const PView& pv,
-                                        float& a0, float& a1, float& a2) {
-  const int w = wu > wl ? wu : wl;
-  int uc[kPairs], lb[kPairs], lc[kPairs];
-#pragma unroll
-  for (int u = 0; u < kPairs; ++u) {
-    uc[u] = scol[ubase + u * kSlice];
-    const int2 t = sent[lbase + u * kSlice];
-    lb[u] = t.x;
-    lc[u] = t.y;
-  }
-  for (int k = 0; k < w; k += kPairs) {
-    float bu[kPairs][9], pu[kPairs][3], bl[kPairs][9], pl[kPairs][3];
-#pragma unroll
-    for (int u = 0; u < kPairs; ++u) {
-      load_block(blk, ubase + (k + u) * kSlice, bu[u]);
-      pv.at(uc[u], pu[u][0], pu[u][1], pu[u][2]);
-      load_block(blk, lb[u], bl[u]);
-      pv.at(lc[u], pl[u][0], pl[u][1], pl[u][2]);
-    }
-    // indices of the next step (inside the slot arrays' read-ahead padding), in flight during this step's products
-    const int kn = k + kPairs < w ? k + kPairs : k;
-#pragma unroll
-    for (int u = 0; u < kPairs; ++u) {
-      uc[u] = scol[ubase + (kn + u) * kSlice];
-      const int2 t = sent[lbase + (kn + u) * kSlice];
-      lb[u] = t.x;
-      lc[u] = t.y;
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int u = 0; u < kPairs; ++u) {
-      const bool vu = k + u < wu, vl = k + u < wl;
-      const float y0 = bu[u][0] * pu[u][0] + bu[u][1] * pu[u][1] + bu[u][2] * pu[u][2];
-      const float y1 = bu[u][3] * pu[u][0] + bu[u][4] * pu[u][1] + bu[u][5] * pu[u][2];
-      const float y2 = bu[u][6] * pu[u][0] + bu[u][7] * pu[u][1] + bu[u][8] * pu[u][2];
-      a0 += vu ? y0 : 0.f;
-      a1 += vu ? y1 : 0.f;
-      a2 += vu ? y2 : 0.f;
-      const float z0 = bl[u][0] * pl[u][0] + bl[u][3] * pl[u][1] + bl[u][6] * pl[u][2];
-      const float z1 = bl[u][1] * pl[u][0] + bl[u][4] * pl[u][1] + bl[u][7] * pl[u][2];
-      const float z2 = bl[u][2] * pl[u][0] + bl[u][5] * pl[u][1] + bl[u][8] * pl[u][2];
-      a0 += vl ? z0 : 0.f;
-      a1 += vl ? z1 : 0.f;
-      a2 += vl ? z2 : 0.f;
-    }
-  }
-}
-
-// q = H_hat p_k for the slices the system's plan gives wave `threadIdx.x / 64`
-// of its workgroup lb (bf_slice_plan: on each XCD consecutive windows of
-// slices, balanced in cost across the waves); adds this thread's shares of
-// p^T q, r^T q and q^T q.  The next slice's number is loaded one slice ahead.
-template <class BT>
-__device__ inline void spmv_slices(const PcgSystem& S, int lb, int k, double& pq, double& rq, double& qq) {
-  const int wave = threadIdx.x / kSlice, lane = threadIdx.x % kSlice;
+__device__ inline void spmv_slices(const PcgSystem& S, int k, SliceCursor& c, double& pq, double& rq, double& qq) {
+  const int lane = threadIdx.x % kSlice;
   const PView pv{S.P + (k % kPRing) * S.pstride};
   const BT* __restrict__ blk = static_cast<const BT*>(S.blk);
-  const int part = lb * kSlicesPerGroup + wave;
-  const int j0 = S.wave_ptr[part], j1 = S.wave_ptr[part + 1];
-  int sl_next = j0 < j1 ? S.wave_slices[j0] : 0;
-  for (int j = j0; j < j1; ++j) {
-    const int sl = sl_next;
-    sl_next = j + 1 < j1 ? S.wave_slices[j + 1] : 0;
-    const int bu = S.sbu[sl], wu = (S.sbu[sl + 1] - bu) / kSlice;
-    const int bl = S.sbl[sl], wl = (S.sbl[sl + 1] - bl) / kSlice;
+  const int jl = c.j1 - 1;
+  for (int j = c.j0; j < c.j1; ++j) {
+    const int sl3 = S.wave_slices[min(j + 3, jl)];
+    const int b2u = S.sbu[c.sl2], e2u = S.sbu[c.sl2 + 1], b2l = S.sbl[c.sl2], e2l = S.sbl[c.sl2 + 1];
+    const int row = c.sl * kSlice + lane;
+    const bool live = row < S.N;
+    // read unconditionally (a pad row reads row N - 1 and is not used), so no
+    // branch forces a wait on the loads in flight
+    const int rowc = live ? row : S.N - 1;
+    float s0, s1, s2;
+    pv.at(rowc, s0, s1, s2);
+    const float* rr = S.r + 3LL * rowc;
+    const float r0 = rr[0], r1 = rr[1], r2 = rr[2];
+    const int wu = (c.eu - c.bu) / kSlice, wl = (c.el - c.bl) / kSlice, w = wu > wl ? wu : wl;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-    accumulate_pairs<BT>(bu + lane, wu, bl + lane, wl, S.scol, S.sent, blk, pv, a0, a1, a2);
-    const int row = sl * kSlice + lane;
-    if (row < S.N) {
-      float s0, s1, s2;
-      pv.at(row, s0, s1, s2);
-      const float* rr = S.r + 3LL * row;
-      const float r0 = rr[0], r1 = rr[1], r2 = rr[2];
+    pair_step<BT>(0, wu, wl, w, c.bu + lane, c.bl + lane, c.nbu + lane, c.nbl + lane, S.scol, S.sent, blk, pv, c.uc,
+                  c.lb, c.lc, a0, a1, a2);
+    for (int kk = kPairs; kk < w; kk += kPairs)
+      pair_step<BT>(kk, wu, wl, w, c.bu + lane, c.bl + lane, c.nbu + lane, c.nbl + lane, S.scol, S.sent, blk, pv,
+                    c.uc, c.lb, c.lc, a0, a1, a2);
+    if (live) {
       const float q0 = s0 + a0, q1 = s1 + a1, q2 = s2 + a2;
       S.q[3LL * row] = q0; S.q[3LL * row + 1] = q1; S.q[3LL * row + 2] = q2;
       pq += (double)s0 * q0 + (double)s1 * q1 + (double)s2 * q2;
       rq += (double)r0 * q0 + (double)r1 * q1 + (double)r2 * q2;
       qq += (double)q0 * q0 + (double)q1 * q1 + (double)q2 * q2;
     }
+    c.sl = c.sl1; c.sl1 = c.sl2; c.sl2 = sl3;
+    c.bu = c.nbu; c.eu = c.neu; c.bl = c.nbl; c.el = c.nel;
+    c.nbu = b2u; c.neu = e2u; c.nbl = b2l; c.nel = e2l;
   }
 }
 
@@ -376,9 +435,10 @@ template <class BT>
 __global__ void __launch_bounds__(kSpmvBlock) k_spmv(PcgSystem S) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   int k;
-  if (!spmv_scalars(S, lb == 0 && threadIdx.x == 0, k)) return;
+  SliceCursor c;
+  if (!spmv_begin(S, lb, lb == 0 && threadIdx.x == 0, k, c)) return;
   double pq = 0.0, rq = 0.0, qq = 0.0;
-  spmv_slices<BT>(S, lb, k, pq, rq, qq);
+  spmv_slices<BT>(S, k, c, pq, rq, qq);
   block_sum3<kSpmvBlock>(pq, rq, qq);
   if (threadIdx.x == 0) {
     S.part[kPartPQ + lb] = pq;
@@ -394,9 +454,10 @@ __global__ void __launch_bounds__(kSpmvBlock) k_spmv_batched(const PcgSystem* __
   const PcgSystem S = sys[wg_sys[b]];
   const int lb = b - S.spmv_wg0;
   int k;
-  if (!spmv_scalars(S, lb == 0 && threadIdx.x == 0, k)) return;
+  SliceCursor c;
+  if (!spmv_begin(S, lb, lb == 0 && threadIdx.x == 0, k, c)) return;
   double pq = 0.0, rq = 0.0, qq = 0.0;
-  spmv_slices<BT>(S, lb, k, pq, rq, qq);
+  spmv_slices<BT>(S, k, c, pq, rq, qq);
   block_sum3<kSpmvBlock>(pq, rq, qq);
   if (threadIdx.x == 0) {
     S.part[kPartPQ + lb] = pq;
@@ -543,9 +604,11 @@ __device__ __forceinline__ void update_chunk(const PcgSystem& S, float4* __restr
 // reduction (a workgroup usually owns one chunk).
 __device__ inline void update_nodes(const PcgSystem& S, int lb) {
   PcgScalars* sc = S.sc;
-  if (sc->done) return;
-  const int k = sc->ks;
-  const bool check = ((k + 1) % sc->check_every) == 0;
+  // the control words are read together, and `done` is tested once the
+  // operand loads are on their way (a finished system's loads stay in range
+  // and are dropped)
+  const int done = sc->done, k = sc->ks, every = sc->check_every, xbase = sc->xbase;
+  const bool check = ((k + 1) % every) == 0;
   double* part = S.part;
   __shared__ float4 rs[3 * kVecBlock];
   __shared__ float alpha_hist[kXBatch];
@@ -553,10 +616,11 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
   const long long nchunk = (S.N4 + 4 * kVecBlock - 1) / (4 * kVecBlock);
   // x takes alpha_j p_j, j0 <= j <= k, on every kXBatch-th iteration
   const bool flush = ((k + 1) % kXBatch) == 0;
-  const int j0 = max(sc->xbase, k + 1 - kXBatch);
-  if (flush && threadIdx.x < kXBatch) alpha_hist[threadIdx.x] = sc->alpha_hist[threadIdx.x];
+  const int j0 = max(xbase, k + 1 - kXBatch);
   UpdateOperands o;
   if (lb < nchunk) load_update_operands(S, k, flush, j0, lb, check, o);
+  if (done) return;
+  const float ah = sc->alpha_hist[threadIdx.x % kXBatch];
   double rho, pq, rq, qq;
   sum_parts4<kVecBlock>(part + kPartRR + (k & 1) * kMaxVecParts, S.vec_nwg, part + kPartPQ, S.spmv_nwg,
                         part + kPartRQ, S.spmv_nwg, part + kPartQQ, S.spmv_nwg, rho, pq, rq, qq);
@@ -575,6 +639,7 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
   const double rho_next = rho - 2.0 * ad * rq + ad * ad * qq;
   const float beta = rho_next > 0.0 ? (float)(rho_next / rho) : 0.f;
   double rr = 0.0, rt = 0.0;
+  if (flush && threadIdx.x < kXBatch) alpha_hist[threadIdx.x] = ah;
   __syncthreads();   // alpha_hist staged
   if (lb < nchunk) update_chunk(S, pn4, lb, check, flush, j0, k, alpha_hist, alpha, beta, o, rs, rr, rt);
   for (long long ch = lb + S.vec_nwg; ch < nchunk; ch += S.vec_nwg) {
