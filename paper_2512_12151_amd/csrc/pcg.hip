@@ -604,9 +604,8 @@ __device__ __forceinline__ void update_chunk(const PcgSystem& S, float4* __restr
 // reduction (a workgroup usually owns one chunk).
 __device__ inline void update_nodes(const PcgSystem& S, int lb) {
   PcgScalars* sc = S.sc;
-  // the control words are read together, and `done` is tested once the
-  // operand loads are on their way (a finished system's loads stay in range
-  // and are dropped)
+  // the control words are read together (k, every and xbase are also used
+  // after the test of `done`, so their loads stay with it)
   const int done = sc->done, k = sc->ks, every = sc->check_every, xbase = sc->xbase;
   const bool check = ((k + 1) % every) == 0;
   double* part = S.part;
@@ -618,7 +617,7 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
   const bool flush = ((k + 1) % kXBatch) == 0;
   const int j0 = max(xbase, k + 1 - kXBatch);
   UpdateOperands o;
-  if (lb < nchunk) load_update_operands(S, k, flush, j0, lb, check, o);
+  if (!done && lb < nchunk) load_update_operands(S, k, flush, j0, lb, check, o);
   if (done) return;
   const float ah = sc->alpha_hist[threadIdx.x % kXBatch];
   double rho, pq, rq, qq;
@@ -646,11 +645,11 @@ __device__ inline void update_nodes(const PcgSystem& S, int lb) {
     load_update_operands(S, k, flush, j0, ch, check, o);
     update_chunk(S, pn4, ch, check, flush, j0, k, alpha_hist, alpha, beta, o, rs, rr, rt);
   }
-  const double srr = block_sum_all<kVecBlock>(rr);
-  const double srt = block_sum_all<kVecBlock>(rt);
+  double unused = 0.0;
+  block_sum3<kVecBlock>(rr, rt, unused);   // one LDS round for both sums
   if (threadIdx.x == 0) {
-    part[kPartRR + ((k + 1) & 1) * kMaxVecParts + lb] = srr;
-    part[kPartRT + lb] = srt;
+    part[kPartRR + ((k + 1) & 1) * kMaxVecParts + lb] = rr;
+    part[kPartRT + lb] = rt;
   }
   if (leader) {
     sc->alpha_hist[k % kXBatch] = alpha;
