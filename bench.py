@@ -87,7 +87,8 @@ def copy_ceiling():
 
 
 COUNTER_FILE = os.path.join(ROOT, "profiles", "k_spmv_large_hbm_counters.md")
-KERNEL_SOURCES = ["pcg.hip", "assemble.hip", "common.h"]
+# the SpMV and update kernels, and the host rule that plans which slices each SpMV wavefront takes
+KERNEL_SOURCES = ["pcg.hip", "assemble.hip", "common.h", "host_rules.cpp"]
 
 
 def kernel_sources_sha256():

@@ -106,10 +106,13 @@ int32_t bf_admission_active(const bf_admission* a);
  * steps, wu and wl its upper and lower slot widths ((slot_u[s+1] - slot_u[s])
  * / 64 and the same for slot_l, the exclusive scans of 64 x the widths).
  * The plan keeps the slices that are read together on one XCD and balances
- * the parts: the slices are cut into rounds of nparts consecutive slices,
- * each round into 8 consecutive windows of equal cost (window x to XCD x),
- * and inside an XCD every slice, in increasing order, goes to the part with
- * the least cost so far (the lowest index on ties).  Output as lists:
+ * the parts: the slices are cut into 8 consecutive windows of equal cost
+ * (window x to XCD x; window x starts at the first slice whose cost prefix
+ * reaches x / 8 of the total); each window is taken in consecutive blocks of
+ * 2 nparts / 8 slices, and inside a block the slices, costliest first (ties
+ * in slice order), go one by one to the part of that XCD with the least cost
+ * so far (the lowest index on ties).  Each XCD thus sweeps its window from
+ * start to end, two slices per part per block.  Output as lists:
  * part p takes wave_slices[wave_ptr[p] .. wave_ptr[p+1]), increasing.
  *   nslices >= 1; slot_u, slot_l: [nslices + 1] nondecreasing multiples of 64;
  *   pairs >= 1 (upper/lower pairs per SpMV step); nparts: a positive multiple

@@ -2,6 +2,7 @@
 // penalty stall rule of Section 5.2, the serving admission policy and the
 // SpMV's slice plan.  Plain C++ without HIP, built with the host compiler, so
 // the same object serves the library and a CPU-only (sanitizer) build.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -202,12 +203,13 @@ bf_status bf_slice_plan(int32_t nslices, const int32_t* slot_u, const int32_t* s
       return BF_ERR_INVALID_ARG;
   const int32_t per_x = nparts / 8;
   std::vector<int64_t> load;
-  std::vector<int32_t> cost, part_of, cur;
+  std::vector<int32_t> cost, part_of, cur, blk;
   try {
     load.assign(nparts, 0);
     cost.resize(nslices);
     part_of.resize(nslices);
     cur.resize(nparts);
+    blk.reserve(2 * (size_t)per_x);
   } catch (...) {
     return BF_ERR_OOM;
   }
@@ -216,24 +218,31 @@ bf_status bf_slice_plan(int32_t nslices, const int32_t* slot_u, const int32_t* s
     const int32_t w = wu > wl ? wu : wl;
     cost[s] = (w + pairs - 1) / pairs + 1;
   }
-  for (int32_t r0 = 0; r0 < nslices; r0 += nparts) {
-    const int32_t r1 = r0 + nparts < nslices ? r0 + nparts : nslices;
-    int64_t tot = 0;
-    for (int32_t s = r0; s < r1; ++s) tot += cost[s];
-    // window x starts at the first slice whose cost prefix in the round reaches x / 8 of it
-    int32_t start[9];
-    start[0] = r0;
-    int32_t x = 1;
-    int64_t acc = 0;
-    for (int32_t s = r0; s < r1 && x < 8; ++s) {
-      while (x < 8 && 8 * acc >= x * tot) start[x++] = s;
-      acc += cost[s];
-    }
-    while (x < 8) start[x++] = r1;
-    start[8] = r1;
-    for (x = 0; x < 8; ++x) {
-      int64_t* lx = load.data() + (int64_t)x * per_x;
-      for (int32_t s = start[x]; s < start[x + 1]; ++s) {
+  int64_t tot = 0;
+  for (int32_t s = 0; s < nslices; ++s) tot += cost[s];
+  // window x starts at the first slice whose cost prefix reaches x / 8 of the total
+  int32_t start[9];
+  start[0] = 0;
+  int32_t x = 1;
+  int64_t acc = 0;
+  for (int32_t s = 0; s < nslices && x < 8; ++s) {
+    while (x < 8 && 8 * acc >= x * tot) start[x++] = s;
+    acc += cost[s];
+  }
+  while (x < 8) start[x++] = nslices;
+  start[8] = nslices;
+  // each window in blocks of two slices per part, taken in order; inside a
+  // block the costliest slices go first (ties in slice order), each to the
+  // part with the least cost so far
+  const int32_t bsize = 2 * per_x;
+  for (x = 0; x < 8; ++x) {
+    int64_t* lx = load.data() + (int64_t)x * per_x;
+    for (int32_t b0 = start[x]; b0 < start[x + 1]; b0 += bsize) {
+      const int32_t b1 = std::min(start[x + 1], b0 + bsize);
+      blk.clear();
+      for (int32_t s = b0; s < b1; ++s) blk.push_back(s);
+      std::stable_sort(blk.begin(), blk.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+      for (const int32_t s : blk) {
         int32_t best = 0;
         for (int32_t p = 1; p < per_x; ++p)
           if (lx[p] < lx[best]) best = p;

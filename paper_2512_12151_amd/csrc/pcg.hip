@@ -31,8 +31,8 @@
 // and the p gathers of a slot are consecutive nodes: every access of the SpMV
 // is a contiguous run per wavefront.  Workgroups are mapped so that each XCD
 // holds one contiguous range of them, and a per-step plan (bf_slice_plan)
-// gives every XCD consecutive windows of slices and balances their cost over
-// its wavefronts; the whole upper matrix of the large workload (~150 MB) fits
+// gives every XCD one contiguous window of slices, which its wavefronts sweep
+// together, and balances their cost; the whole upper matrix of the large workload (~150 MB) fits
 // the 256 MB Infinity Cache.
 //
 // Residual replacement (reliable updating): x is kept in FP64, and when the
@@ -385,8 +385,8 @@ __device__ inline bool spmv_begin(const PcgSystem& S, int lb, bool leader, int& 
   return true;
 }
 
-// q = H_hat p_k for the slices of the cursor (bf_slice_plan: on each XCD
-// consecutive windows of slices, balanced in cost across the waves); adds
+// q = H_hat p_k for the slices of the cursor (bf_slice_plan: each XCD sweeps
+// one window of slices, balanced in cost across its waves); adds
 // this thread's shares of p^T q, r^T q and q^T q.  The slices are pipelined
 // so that a change of slice costs no extra memory round trip: the slot
 // offsets are loaded two slices ahead and the slice numbers three ahead, a
@@ -948,8 +948,9 @@ k_finish_scalars(const double* __restrict__ part, int n, const double* __restric
 // long as the others (measured on the large workload: 1576 workgroups, 6 or 7
 // per CU, 44.5 us; 256, one per CU with 6 or 7 slices per wave, 42.6 us; 264
 // or 320, 54 and 65 us).  Each wavefront then walks the slices the plan gives
-// it, consecutive windows per XCD, so the lower-half reads of a block mostly
-// follow its upper-half read closely and on the same XCD.
+// it, one window per XCD swept by all its wavefronts together, so the
+// lower-half reads of a block mostly follow its upper-half read closely and
+// on the same XCD.
 int pcg_spmv_groups(int N, int num_cu) {
   const int nslices = div_up(N, kSlice);
   int g = div_up(nslices, kSlicesPerGroup);

@@ -244,22 +244,23 @@ def test_admission_release_is_checked():
 # ------------------------------------------------------------- slice plan
 
 def plan_reference(wu, wl, pairs, nparts):
-    """The plan restated in Python: rounds of nparts slices, eight windows of
-    equal cost per round (by the cost prefix), least-loaded part per XCD."""
+    """The plan restated in Python: eight windows of equal cost (by the cost
+    prefix); each window in blocks of two slices per part, and inside a block
+    the costliest slices first (stable), each to the least-loaded part of the
+    XCD."""
     cost = (np.maximum(wu, wl) + pairs - 1) // pairs + 1
     ns, per_x = len(cost), nparts // 8
     load = np.zeros(nparts, np.int64)
     part_of = np.empty(ns, np.int64)
-    for r0 in range(0, ns, nparts):
-        r1 = min(ns, r0 + nparts)
-        c = cost[r0:r1]
-        before = np.concatenate([[0], np.cumsum(c)[:-1]])   # cost of the round's slices before each one
-        tot = int(c.sum())
-        win = [r0] + [r0 + int(np.argmax(8 * before >= x * tot)) if (8 * before >= x * tot).any() else r1
-                      for x in range(1, 8)] + [r1]
-        for x in range(8):
-            for s in range(win[x], win[x + 1]):
-                lx = load[x * per_x:(x + 1) * per_x]
+    before = np.concatenate([[0], np.cumsum(cost)[:-1]])   # cost of the slices before each one
+    tot = int(cost.sum())
+    win = [0] + [int(np.argmax(8 * before >= x * tot)) if (8 * before >= x * tot).any() else ns
+                 for x in range(1, 8)] + [ns]
+    for x in range(8):
+        lx = load[x * per_x:(x + 1) * per_x]
+        for b0 in range(win[x], win[x + 1], 2 * per_x):
+            blk = np.arange(b0, min(b0 + 2 * per_x, win[x + 1]))
+            for s in blk[np.argsort(-cost[blk], kind="stable")]:
                 b = int(np.argmin(lx))
                 lx[b] += cost[s]
                 part_of[s] = x * per_x + b
